@@ -1,0 +1,692 @@
+/*
+ * ctu_oracle.c -- plain, slow FP64 CPU reference of the unsplit CTU/PPM
+ * Godunov advance of an ideal gamma-law gas.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the package smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the HIP path.
+ *
+ * What the method computes: the paper states that Castro's main hydrodynamics
+ * scheme is an unsplit piecewise parabolic method, advanced box by box on a
+ * block-structured grid with coarse levels advanced first, fine levels
+ * subcycled and the levels then synchronised (section 3 and section 3.2).  The
+ * paper gives no further detail, so every step below follows the published
+ * method it names, in this reading:
+ *   - PPM reconstruction, limiter and flattening: Colella & Woodward 1984
+ *     (CW84), JCP 54:174, section 1 and appendix;
+ *   - corner-transport-upwind (unsplit) coupling and characteristic tracing:
+ *     Colella 1990, JCP 87:171; Saltzman 1994, JCP 115:153; Miller & Colella
+ *     2002, JCP 183:26;
+ *   - HLLC Riemann flux with Davis wave-speed bounds: Toro, Spruce & Speares
+ *     1994, Shock Waves 4:25; Davis 1988, SIAM J. Sci. Stat. Comput. 9:445;
+ *   - two-level refluxing: Berger & Colella 1989, JCP 82:64.
+ * Steps are coded in the order the method takes them, on whole arrays, one
+ * stage after another.  Floating-point expressions are written exactly as the
+ * stated formulas parenthesise them and are compiled without contraction
+ * (-ffp-contract=off) and without fast-math.
+ *
+ * Layouts.  A box of n = (nx, ny, nz) valid cells is stored "grown" by 4 ghost
+ * cells: U[c][k][j][i], c in 0..4 = (rho, rho u, rho v, rho w, rho E), i fastest,
+ * cell (i,j,k) of the box at offset ((c*(nz+8)+k+4)*(ny+8)+j+4)*(nx+8)+i+4.
+ * Stage arrays use the "halo-1" geometry, indices -1..n in every direction,
+ * offset ((c*(nz+2)+k+1)*(ny+2)+j+1)*(nx+2)+i+1.  A face array for direction d
+ * stores face f (between cells f-1 and f along d) at index f along d.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NV 5
+#define NG 4
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_INFLOW = 3 };
+
+/* counters: 0 density floor in cons->prim, 1 pressure floor in cons->prim,
+ * 2 floors on traced states, 3 transverse fall-backs, 4 update failures */
+#define NCNT 5
+
+typedef struct {
+    double gamma, cfl, small_dens, small_pres, grav_z;
+    double dx[3];
+    int bc_lo[3], bc_hi[3];
+    double inflow[5]; /* rho, u, v, w, p */
+} orc_params;
+
+/* optional stage outputs (NULL entries are allocated internally) */
+typedef struct {
+    double *q;        /* 6 x grown: rho,u,v,w,p,c */
+    double *phi;      /* 1 x halo-1 */
+    double *ql[3];    /* 5 x halo-1, permuted primitives, left state of face */
+    double *qr[3];    /* 5 x halo-1, right state of face */
+    double *fn[3];    /* 5 x halo-1, normal fluxes (conserved order) */
+    double *f1[6];    /* 5 x halo-1, stage-1 fluxes, pair index 2a+(b==(a+1)%3?0:1) */
+    double *ff[3];    /* 5 x halo-1, final fluxes */
+} orc_stages;
+
+static double omin(double a, double b) { return a < b ? a : b; }
+static double omax(double a, double b) { return a > b ? a : b; }
+
+/* ---------------------------------------------------------------- indexing */
+
+typedef struct { int n[3]; long gx, gy, gz, hx, hy, hz; } geom;
+
+static geom mkgeom(const int n[3]) {
+    geom g;
+    for (int d = 0; d < 3; ++d) g.n[d] = n[d];
+    g.gx = n[0] + 2 * NG; g.gy = n[1] + 2 * NG; g.gz = n[2] + 2 * NG;
+    g.hx = n[0] + 2; g.hy = n[1] + 2; g.hz = n[2] + 2;
+    return g;
+}
+static long gidx(const geom *g, int c, int i, int j, int k) {
+    return ((c * g->gz + (k + NG)) * g->gy + (j + NG)) * g->gx + (i + NG);
+}
+static long hidx(const geom *g, int c, int i, int j, int k) {
+    return ((c * g->hz + (k + 1)) * g->hy + (j + 1)) * g->hx + (i + 1);
+}
+static long gsize(const geom *g) { return g->gx * g->gy * g->gz; }
+static long hsize(const geom *g) { return g->hx * g->hy * g->hz; }
+
+/* tangential directions of a sweep along d: x:(y,z) y:(z,x) z:(x,y) */
+static int t1of(int d) { return (d + 1) % 3; }
+static int t2of(int d) { return (d + 2) % 3; }
+
+/* ---------------------------------------------------- state conversions (O1, O3) */
+
+/* Conserved -> primitive for a cell (rho,u,v,w,p,c), with the density and
+ * pressure floors; the kinetic energy sums u^2+v^2 first, then w^2. */
+static void cons_to_prim_cell(const double U[5], const orc_params *P, double q[6], long long *cnt) {
+    const double gm1 = P->gamma - 1.0;
+    double rho = U[0];
+    if (rho < P->small_dens) { rho = P->small_dens; cnt[0]++; }
+    double u = U[1] / rho, v = U[2] / rho, w = U[3] / rho;
+    double ke = 0.5 * rho * ((u * u + v * v) + w * w);
+    double p = gm1 * (U[4] - ke);
+    if (p < P->small_pres) { p = P->small_pres; cnt[1]++; }
+    q[0] = rho; q[1] = u; q[2] = v; q[3] = w; q[4] = p;
+    q[5] = sqrt(P->gamma * p / rho);
+}
+
+/* Permuted primitive state of a sweep along d (rho, u_n, u_t1, u_t2, p) to the
+ * conserved state in global component order. */
+static void perm_prim_to_cons(const double s[5], int d, const orc_params *P, double U[5]) {
+    const double rgm1 = 1.0 / (P->gamma - 1.0);
+    double rho = s[0];
+    U[0] = rho;
+    U[1 + d] = rho * s[1];
+    U[1 + t1of(d)] = rho * s[2];
+    U[1 + t2of(d)] = rho * s[3];
+    U[4] = s[4] * rgm1 + 0.5 * rho * ((s[1] * s[1] + s[2] * s[2]) + s[3] * s[3]);
+}
+
+/* Conserved (global order) to the permuted primitive state of a sweep along d,
+ * without floors (the caller decides what a non-physical result means). */
+static void cons_to_perm_prim(const double U[5], int d, const orc_params *P, double s[5]) {
+    const double gm1 = P->gamma - 1.0;
+    double rho = U[0];
+    double un = U[1 + d] / rho, ut1 = U[1 + t1of(d)] / rho, ut2 = U[1 + t2of(d)] / rho;
+    double ke = 0.5 * rho * ((un * un + ut1 * ut1) + ut2 * ut2);
+    s[0] = rho; s[1] = un; s[2] = ut1; s[3] = ut2;
+    s[4] = gm1 * (U[4] - ke);
+}
+
+/* ------------------------------------------------------------ HLLC flux (O7) */
+
+/* HLLC flux (Toro, Spruce & Speares 1994) with Davis (1988) speed bounds
+ * S_L = min(u_L-c_L, u_R-c_R), S_R = max(u_L+c_L, u_R+c_R).  L and R are
+ * permuted primitives of a sweep along d; the flux is returned in global
+ * conserved order. */
+void orc_hllc(const double L[5], const double R[5], int d, const orc_params *P, double Fg[5]) {
+    const double g = P->gamma, rgm1 = 1.0 / (g - 1.0);
+    const double rL = L[0], uL = L[1], vL = L[2], wL = L[3], pL = L[4];
+    const double rR = R[0], uR = R[1], vR = R[2], wR = R[3], pR = R[4];
+    const double cL = sqrt(g * pL / rL), cR = sqrt(g * pR / rR);
+    const double SL = omin(uL - cL, uR - cR);
+    const double SR = omax(uL + cL, uR + cR);
+    const double EL = pL * rgm1 + 0.5 * rL * ((uL * uL + vL * vL) + wL * wL);
+    const double ER = pR * rgm1 + 0.5 * rR * ((uR * uR + vR * vR) + wR * wR);
+    double F[5];
+    if (SL >= 0.0) {
+        double m = rL * uL;
+        F[0] = m; F[1] = m * uL + pL; F[2] = m * vL; F[3] = m * wL; F[4] = uL * (EL + pL);
+    } else {
+        const double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
+                          (rL * (SL - uL) - rR * (SR - uR));
+        if (Ss >= 0.0 || SR > 0.0) {
+            /* one star region: K = L if S* >= 0, else K = R */
+            const int left = (Ss >= 0.0);
+            const double rK = left ? rL : rR, uK = left ? uL : uR, vK = left ? vL : vR;
+            const double wK = left ? wL : wR, pK = left ? pL : pR, EK = left ? EL : ER;
+            const double SK = left ? SL : SR;
+            const double m = rK * uK;
+            double FK[5], UK[5], Us[5];
+            FK[0] = m; FK[1] = m * uK + pK; FK[2] = m * vK; FK[3] = m * wK; FK[4] = uK * (EK + pK);
+            UK[0] = rK; UK[1] = m; UK[2] = rK * vK; UK[3] = rK * wK; UK[4] = EK;
+            const double fac = rK * (SK - uK) / (SK - Ss);
+            Us[0] = fac;
+            Us[1] = fac * Ss;
+            Us[2] = fac * vK;
+            Us[3] = fac * wK;
+            Us[4] = fac * (EK / rK + (Ss - uK) * (Ss + pK / (rK * (SK - uK))));
+            for (int c = 0; c < 5; ++c) F[c] = FK[c] + SK * (Us[c] - UK[c]);
+        } else {
+            double m = rR * uR;
+            F[0] = m; F[1] = m * uR + pR; F[2] = m * vR; F[3] = m * wR; F[4] = uR * (ER + pR);
+        }
+    }
+    Fg[0] = F[0];
+    Fg[1 + d] = F[1];
+    Fg[1 + t1of(d)] = F[2];
+    Fg[1 + t2of(d)] = F[3];
+    Fg[4] = F[4];
+}
+
+/* ------------------------------------------------------ PPM pieces (O5, O6) */
+
+/* Monotonised-central slope (CW84 eq. 1.7-1.8). */
+static double mc_slope(double am, double a0, double ap) {
+    double dm = a0 - am, dp = ap - a0, dc = 0.5 * (ap - am);
+    if (dm * dp > 0.0) {
+        double lim = omin(fabs(dc), omin(2.0 * fabs(dm), 2.0 * fabs(dp)));
+        return copysign(lim, dc);
+    }
+    return 0.0;
+}
+
+/* Interface value between cells with averages a0, a1 and slopes s0, s1
+ * (CW84 eq. 1.6 with the MC slopes). */
+static double ppm_edge(double a0, double a1, double s0, double s1) {
+    return 0.5 * (a0 + a1) - (1.0 / 6.0) * (s1 - s0);
+}
+
+/* Full reconstruction of one cell from the five-cell stencil a[0..4] (cell at
+ * a[2]) and flattening coefficient phi: interface values, flattening, CW84
+ * monotonicity (eq. 1.10), then the parabola's (aL, aR, da, a6). */
+void orc_ppm_cell(const double a[5], double phi, double out[4]) {
+    const double C6 = 1.0 / 6.0;
+    double sm = mc_slope(a[0], a[1], a[2]);
+    double s0 = mc_slope(a[1], a[2], a[3]);
+    double sp = mc_slope(a[2], a[3], a[4]);
+    double ai = a[2];
+    double aL = ppm_edge(a[1], a[2], sm, s0);
+    double aR = ppm_edge(a[2], a[3], s0, sp);
+    aL = phi * aL + (1.0 - phi) * ai;
+    aR = phi * aR + (1.0 - phi) * ai;
+    if ((aR - ai) * (ai - aL) <= 0.0) {
+        aL = ai; aR = ai;
+    } else {
+        double dd = aR - aL;
+        double m = ai - 0.5 * (aL + aR);
+        if (dd * m > C6 * (dd * dd)) aL = 3.0 * ai - 2.0 * aR;
+        else if (-C6 * (dd * dd) > dd * m) aR = 3.0 * ai - 2.0 * aL;
+    }
+    out[0] = aL;
+    out[1] = aR;
+    out[2] = aR - aL;
+    out[3] = 6.0 * (ai - 0.5 * (aL + aR));
+}
+
+/* Average of the parabola over the domain of dependence of the right edge
+ * (I+) and of the left edge (I-) for a wave travelling sigma cells per dt. */
+double orc_iplus(double aR, double da, double a6, double sig) {
+    const double C23 = 2.0 / 3.0;
+    return aR - 0.5 * sig * (da - (1.0 - C23 * sig) * a6);
+}
+double orc_iminus(double aL, double da, double a6, double sig) {
+    const double C23 = 2.0 / 3.0;
+    return aL + 0.5 * sig * (da + (1.0 - C23 * sig) * a6);
+}
+
+/* Characteristic tracing of one cell to t + dt/2 (CW84 section 3, reference
+ * state form; Colella 1990).  par[m] = (aL, aR, da, a6) of permuted component m,
+ * rho, un, c are the cell's centre values.  Returns the left state of the
+ * upper face (qL) and the right state of the lower face (qR), before floors. */
+void orc_trace_cell(const double par[5][4], double rho, double un, double c, double dtdx,
+                    double qL[5], double qR[5]) {
+    const double lam[3] = {un - c, un, un + c};
+    double I[3][5];
+    const double csq = c * c;
+    /* upper face: waves with lam > 0 reach it */
+    for (int nu = 0; nu < 3; ++nu) {
+        double sig = fabs(lam[nu]) * dtdx;
+        for (int m = 0; m < 5; ++m)
+            I[nu][m] = lam[nu] > 0.0 ? orc_iplus(par[m][1], par[m][2], par[m][3], sig) : par[m][1];
+    }
+    {
+        const double *ref = I[2];
+        double bm = -(rho / (2.0 * c)) * (ref[1] - I[0][1]) + (ref[4] - I[0][4]) / (2.0 * csq);
+        double b0 = (ref[0] - I[1][0]) - (ref[4] - I[1][4]) / csq;
+        double bt1 = ref[2] - I[1][2];
+        double bt2 = ref[3] - I[1][3];
+        for (int m = 0; m < 5; ++m) qL[m] = ref[m];
+        if (lam[0] > 0.0) {
+            qL[0] = qL[0] - bm;
+            qL[1] = qL[1] - bm * (-(c / rho));
+            qL[4] = qL[4] - bm * csq;
+        }
+        if (lam[1] > 0.0) {
+            qL[0] = qL[0] - b0;
+            qL[2] = qL[2] - bt1;
+            qL[3] = qL[3] - bt2;
+        }
+    }
+    /* lower face: waves with lam < 0 reach it */
+    for (int nu = 0; nu < 3; ++nu) {
+        double sig = fabs(lam[nu]) * dtdx;
+        for (int m = 0; m < 5; ++m)
+            I[nu][m] = lam[nu] < 0.0 ? orc_iminus(par[m][0], par[m][2], par[m][3], sig) : par[m][0];
+    }
+    {
+        const double *ref = I[0];
+        double bp = (rho / (2.0 * c)) * (ref[1] - I[2][1]) + (ref[4] - I[2][4]) / (2.0 * csq);
+        double b0 = (ref[0] - I[1][0]) - (ref[4] - I[1][4]) / csq;
+        double bt1 = ref[2] - I[1][2];
+        double bt2 = ref[3] - I[1][3];
+        for (int m = 0; m < 5; ++m) qR[m] = ref[m];
+        if (lam[2] < 0.0) {
+            qR[0] = qR[0] - bp;
+            qR[1] = qR[1] - bp * (c / rho);
+            qR[4] = qR[4] - bp * csq;
+        }
+        if (lam[1] < 0.0) {
+            qR[0] = qR[0] - b0;
+            qR[2] = qR[2] - bt1;
+            qR[3] = qR[3] - bt2;
+        }
+    }
+}
+
+/* ------------------------------------------------------------ flattening (O4) */
+
+/* CW84 appendix: shock indicator f~ of cell i along d with eps = 0.33,
+ * omega1 = 0.75, omega2 = 10. */
+static double ftilde(const double *q, const geom *g, int d, const int c[3]) {
+    int e[3] = {0, 0, 0};
+    e[d] = 1;
+#define QAT(comp, s) q[gidx(g, comp, c[0] + (s) * e[0], c[1] + (s) * e[1], c[2] + (s) * e[2])]
+    double dp1 = QAT(4, 1) - QAT(4, -1);
+    double dp2 = QAT(4, 2) - QAT(4, -2);
+    double f = 0.0;
+    if (fabs(dp1) > 0.33 * omin(QAT(4, 1), QAT(4, -1)) && QAT(1 + d, -1) - QAT(1 + d, 1) > 0.0) {
+        f = omin(1.0, omax(0.0, 10.0 * (fabs(dp1) / omax(fabs(dp2), 1e-300) - 0.75)));
+    }
+    return f;
+#undef QAT
+}
+
+static double flatten_cell(const double *q, const geom *g, const int c[3]) {
+    double phi = 1.0;
+    for (int d = 0; d < 3; ++d) {
+        int e[3] = {0, 0, 0};
+        e[d] = 1;
+        double dp1 = q[gidx(g, 4, c[0] + e[0], c[1] + e[1], c[2] + e[2])] -
+                     q[gidx(g, 4, c[0] - e[0], c[1] - e[1], c[2] - e[2])];
+        int s = dp1 > 0.0 ? 1 : -1;
+        int cs[3] = {c[0] - s * e[0], c[1] - s * e[1], c[2] - s * e[2]};
+        double fd = omax(ftilde(q, g, d, c), ftilde(q, g, d, cs));
+        double v = 1.0 - fd;
+        phi = d == 0 ? v : omin(phi, v);
+    }
+    return phi;
+}
+
+/* ---------------------------------------------------------- the box advance */
+
+static double *xalloc(long n) {
+    double *p = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    return p;
+}
+
+/* Advance one grown box (ghost cells already filled) by dt.  Unew receives the
+ * new valid cells (grown layout; ghosts untouched).  Stage arrays may be
+ * supplied through st (for inspection); the rest are allocated here. */
+int orc_advance_box(const double *U, const int n[3], const orc_params *P, double dt,
+                    double *Unew, long long *cnt, orc_stages *st) {
+    const geom G = mkgeom(n);
+    const geom *g = &G;
+    const long gs = gsize(g), hs = hsize(g);
+    orc_stages S;
+    memset(&S, 0, sizeof(S));
+    if (st) S = *st;
+    double *own[32];
+    int nown = 0;
+#define NEED(ptr, count)                         \
+    do {                                         \
+        if (!(ptr)) { ptr = xalloc(count); own[nown++] = ptr; } \
+    } while (0)
+    NEED(S.q, 6 * gs);
+    NEED(S.phi, hs);
+    for (int d = 0; d < 3; ++d) { NEED(S.ql[d], 5 * hs); NEED(S.qr[d], 5 * hs); NEED(S.fn[d], 5 * hs); NEED(S.ff[d], 5 * hs); }
+    for (int p = 0; p < 6; ++p) NEED(S.f1[p], 5 * hs);
+#undef NEED
+    for (int i = 0; i < nown; ++i) if (!own[i]) return -2;
+
+    const double dtdx[3] = {dt / P->dx[0], dt / P->dx[1], dt / P->dx[2]};
+    double c3[3], c2[3];
+    for (int d = 0; d < 3; ++d) { c3[d] = dtdx[d] / 3.0; c2[d] = 0.5 * dtdx[d]; }
+    const double hdtg = 0.5 * dt * P->grav_z;
+    long long c0 = 0, c1 = 0, c2cnt = 0, c3cnt = 0, c4 = 0;
+
+    /* (a3) primitive state on every grown cell */
+#pragma omp parallel for reduction(+ : c0, c1) schedule(static)
+    for (int k = -NG; k < n[2] + NG; ++k)
+        for (int j = -NG; j < n[1] + NG; ++j)
+            for (int i = -NG; i < n[0] + NG; ++i) {
+                double Uc[5], q[6];
+                long long lc[NCNT] = {0, 0, 0, 0, 0};
+                for (int c = 0; c < 5; ++c) Uc[c] = U[gidx(g, c, i, j, k)];
+                cons_to_prim_cell(Uc, P, q, lc);
+                c0 += lc[0]; c1 += lc[1];
+                for (int c = 0; c < 6; ++c) S.q[gidx(g, c, i, j, k)] = q[c];
+            }
+
+    /* (a4) flattening coefficient on cells -1..n */
+#pragma omp parallel for schedule(static)
+    for (int k = -1; k <= n[2]; ++k)
+        for (int j = -1; j <= n[1]; ++j)
+            for (int i = -1; i <= n[0]; ++i) {
+                int c[3] = {i, j, k};
+                S.phi[hidx(g, 0, i, j, k)] = flatten_cell(S.q, g, c);
+            }
+
+    /* (a5, a6) reconstruction and tracing along each direction, cells -1..n */
+    for (int d = 0; d < 3; ++d) {
+        const int t1 = t1of(d), t2 = t2of(d);
+        const int comp[5] = {0, 1 + d, 1 + t1, 1 + t2, 4};
+        const int zpos = 1 + (2 - d + 3) % 3; /* permuted position of the z velocity */
+#pragma omp parallel for reduction(+ : c2cnt) schedule(static)
+        for (int k = -1; k <= n[2]; ++k)
+            for (int j = -1; j <= n[1]; ++j)
+                for (int i = -1; i <= n[0]; ++i) {
+                    int c[3] = {i, j, k};
+                    int e[3] = {0, 0, 0};
+                    e[d] = 1;
+                    double par[5][4], a[5];
+                    double phi = S.phi[hidx(g, 0, i, j, k)];
+                    for (int m = 0; m < 5; ++m) {
+                        for (int s = -2; s <= 2; ++s)
+                            a[s + 2] = S.q[gidx(g, comp[m], i + s * e[0], j + s * e[1], k + s * e[2])];
+                        orc_ppm_cell(a, phi, par[m]);
+                    }
+                    double rho = S.q[gidx(g, 0, i, j, k)];
+                    double un = S.q[gidx(g, 1 + d, i, j, k)];
+                    double cs = S.q[gidx(g, 5, i, j, k)];
+                    double qL[5], qR[5];
+                    orc_trace_cell(par, rho, un, cs, dtdx[d], qL, qR);
+                    /* floors, gravity predictor; keep the left state of the
+                     * upper face (faces 0..n) and the right state of the lower face */
+                    double *both[2] = {qL, qR};
+                    const int keep[2] = {c[d] <= n[d] - 1, c[d] >= 0};
+                    for (int b = 0; b < 2; ++b) {
+                        if (!keep[b]) continue;
+                        double *s = both[b];
+                        if (s[0] < P->small_dens) { s[0] = P->small_dens; c2cnt++; }
+                        if (s[4] < P->small_pres) { s[4] = P->small_pres; c2cnt++; }
+                        if (P->grav_z != 0.0) s[zpos] = s[zpos] + hdtg;
+                    }
+                    if (keep[0])
+                        for (int m = 0; m < 5; ++m)
+                            S.ql[d][hidx(g, m, i + e[0], j + e[1], k + e[2])] = qL[m];
+                    if (keep[1])
+                        for (int m = 0; m < 5; ++m) S.qr[d][hidx(g, m, i, j, k)] = qR[m];
+                }
+    }
+
+    /* (a7) normal fluxes: faces 0..n along d, cells -1..n across */
+    for (int d = 0; d < 3; ++d) {
+#pragma omp parallel for schedule(static)
+        for (int k = -1; k <= n[2]; ++k)
+            for (int j = -1; j <= n[1]; ++j)
+                for (int i = -1; i <= n[0]; ++i) {
+                    int c[3] = {i, j, k};
+                    if (c[d] < 0) continue;
+                    double L[5], R[5], F[5];
+                    for (int m = 0; m < 5; ++m) {
+                        L[m] = S.ql[d][hidx(g, m, i, j, k)];
+                        R[m] = S.qr[d][hidx(g, m, i, j, k)];
+                    }
+                    orc_hllc(L, R, d, P, F);
+                    for (int m = 0; m < 5; ++m) S.fn[d][hidx(g, m, i, j, k)] = F[m];
+                }
+    }
+
+    /* (a8) stage 1: states along a corrected by dt/(3 dx_b) times the
+     * difference of the normal b-fluxes of their owner cell, then HLLC. */
+    for (int a = 0; a < 3; ++a)
+        for (int which = 0; which < 2; ++which) {
+            const int b = which == 0 ? t1of(a) : t2of(a);
+            const int cdir = which == 0 ? t2of(a) : t1of(a);
+            const int pidx = 2 * a + which;
+            long long lfb = 0;
+#pragma omp parallel for reduction(+ : lfb) schedule(static)
+            for (int k = -1; k <= n[2]; ++k)
+                for (int j = -1; j <= n[1]; ++j)
+                    for (int i = -1; i <= n[0]; ++i) {
+                        int c[3] = {i, j, k};
+                        if (c[a] < 0) continue;              /* a faces 0..n */
+                        if (c[b] < 0 || c[b] >= n[b]) continue; /* b cells 0..n-1 */
+                        (void)cdir;                          /* c cells -1..n */
+                        int ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0};
+                        ea[a] = 1; eb[b] = 1;
+                        double st2[2][5];
+                        for (int side = 0; side < 2; ++side) {
+                            const double *src = side == 0 ? S.ql[a] : S.qr[a];
+                            int o[3] = {i - (side == 0 ? ea[0] : 0), j - (side == 0 ? ea[1] : 0),
+                                        k - (side == 0 ? ea[2] : 0)};
+                            double s0[5], Uc[5], s1[5];
+                            for (int m = 0; m < 5; ++m) s0[m] = src[hidx(g, m, i, j, k)];
+                            perm_prim_to_cons(s0, a, P, Uc);
+                            for (int m = 0; m < 5; ++m)
+                                Uc[m] = Uc[m] - c3[b] * (S.fn[b][hidx(g, m, o[0] + eb[0], o[1] + eb[1], o[2] + eb[2])] -
+                                                         S.fn[b][hidx(g, m, o[0], o[1], o[2])]);
+                            cons_to_perm_prim(Uc, a, P, s1);
+                            if (s1[0] < P->small_dens || s1[4] < P->small_pres) {
+                                for (int m = 0; m < 5; ++m) s1[m] = s0[m];
+                                lfb++;
+                            }
+                            for (int m = 0; m < 5; ++m) st2[side][m] = s1[m];
+                        }
+                        double F[5];
+                        orc_hllc(st2[0], st2[1], a, P, F);
+                        for (int m = 0; m < 5; ++m) S.f1[pidx][hidx(g, m, i, j, k)] = F[m];
+                    }
+            c3cnt += lfb;
+        }
+
+    /* (a9) stage 2: states along a corrected by dt/(2 dx_b) dF^{b|c} and
+     * dt/(2 dx_c) dF^{c|b}, with (b, c) the cyclic successors of a; final HLLC. */
+    for (int a = 0; a < 3; ++a) {
+        const int b = t1of(a), cdir = t2of(a);
+        const int pbc = 2 * b + (cdir == t1of(b) ? 0 : 1); /* F^{b|c} */
+        const int pcb = 2 * cdir + (b == t1of(cdir) ? 0 : 1); /* F^{c|b} */
+        long long lfb = 0;
+#pragma omp parallel for reduction(+ : lfb) schedule(static)
+        for (int k = 0; k <= n[2]; ++k)
+            for (int j = 0; j <= n[1]; ++j)
+                for (int i = 0; i <= n[0]; ++i) {
+                    int c[3] = {i, j, k};
+                    if (c[b] >= n[b] || c[cdir] >= n[cdir]) continue; /* a faces 0..n, others 0..n-1 */
+                    int ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0}, ec[3] = {0, 0, 0};
+                    ea[a] = 1; eb[b] = 1; ec[cdir] = 1;
+                    double st2[2][5];
+                    for (int side = 0; side < 2; ++side) {
+                        const double *src = side == 0 ? S.ql[a] : S.qr[a];
+                        int o[3] = {i - (side == 0 ? ea[0] : 0), j - (side == 0 ? ea[1] : 0),
+                                    k - (side == 0 ? ea[2] : 0)};
+                        double s0[5], Uc[5], s1[5];
+                        for (int m = 0; m < 5; ++m) s0[m] = src[hidx(g, m, i, j, k)];
+                        perm_prim_to_cons(s0, a, P, Uc);
+                        for (int m = 0; m < 5; ++m)
+                            Uc[m] = Uc[m] - c2[b] * (S.f1[pbc][hidx(g, m, o[0] + eb[0], o[1] + eb[1], o[2] + eb[2])] -
+                                                     S.f1[pbc][hidx(g, m, o[0], o[1], o[2])]);
+                        for (int m = 0; m < 5; ++m)
+                            Uc[m] = Uc[m] - c2[cdir] * (S.f1[pcb][hidx(g, m, o[0] + ec[0], o[1] + ec[1], o[2] + ec[2])] -
+                                                        S.f1[pcb][hidx(g, m, o[0], o[1], o[2])]);
+                        cons_to_perm_prim(Uc, a, P, s1);
+                        if (s1[0] < P->small_dens || s1[4] < P->small_pres) {
+                            for (int m = 0; m < 5; ++m) s1[m] = s0[m];
+                            lfb++;
+                        }
+                        for (int m = 0; m < 5; ++m) st2[side][m] = s1[m];
+                    }
+                    double F[5];
+                    orc_hllc(st2[0], st2[1], a, P, F);
+                    for (int m = 0; m < 5; ++m) S.ff[a][hidx(g, m, i, j, k)] = F[m];
+                }
+        c3cnt += lfb;
+    }
+
+    /* (a10) conservative update, gravity corrector and failure check */
+    const double gm1 = P->gamma - 1.0;
+#pragma omp parallel for reduction(+ : c4) schedule(static)
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                double Un[5];
+                for (int m = 0; m < 5; ++m) {
+                    double du = dtdx[0] * (S.ff[0][hidx(g, m, i, j, k)] - S.ff[0][hidx(g, m, i + 1, j, k)]);
+                    du = du + dtdx[1] * (S.ff[1][hidx(g, m, i, j, k)] - S.ff[1][hidx(g, m, i, j + 1, k)]);
+                    du = du + dtdx[2] * (S.ff[2][hidx(g, m, i, j, k)] - S.ff[2][hidx(g, m, i, j, k + 1)]);
+                    Un[m] = U[gidx(g, m, i, j, k)] + du;
+                }
+                if (P->grav_z != 0.0) {
+                    Un[3] = Un[3] + hdtg * (U[gidx(g, 0, i, j, k)] + Un[0]);
+                    Un[4] = Un[4] + hdtg * (U[gidx(g, 3, i, j, k)] + Un[3]);
+                }
+                int bad = 0;
+                for (int m = 0; m < 5; ++m) if (!isfinite(Un[m])) bad = 1;
+                if (Un[0] < P->small_dens) bad = 1;
+                if (!bad) {
+                    double u = Un[1] / Un[0], v = Un[2] / Un[0], w = Un[3] / Un[0];
+                    double ke = 0.5 * Un[0] * ((u * u + v * v) + w * w);
+                    if (gm1 * (Un[4] - ke) < P->small_pres) bad = 1;
+                }
+                c4 += bad;
+                for (int m = 0; m < 5; ++m) Unew[gidx(g, m, i, j, k)] = Un[m];
+            }
+
+    if (cnt) { cnt[0] += c0; cnt[1] += c1; cnt[2] += c2cnt; cnt[3] += c3cnt; cnt[4] += c4; }
+    for (int i = 0; i < nown; ++i) free(own[i]);
+    return 0;
+}
+
+/* ------------------------------------------------------- ghost fill (O11) */
+
+/* Conserved state of the inflow primitive (rho, u, v, w, p). */
+static void inflow_cons(const orc_params *P, double U[5]) {
+    const double rgm1 = 1.0 / (P->gamma - 1.0);
+    const double *s = P->inflow;
+    U[0] = s[0];
+    U[1] = s[0] * s[1];
+    U[2] = s[0] * s[2];
+    U[3] = s[0] * s[3];
+    U[4] = s[4] * rgm1 + 0.5 * s[0] * ((s[1] * s[1] + s[2] * s[2]) + s[3] * s[3]);
+}
+
+/* Fill the ghost cells of a whole-domain grown array: first every ghost cell
+ * whose periodic image is a valid cell, then the physical boundaries of the
+ * non-periodic directions in the order x, y, z, each over the full grown extent
+ * of the other two directions. */
+void orc_fill_domain(double *U, const int n[3], const orc_params *P) {
+    const geom G = mkgeom(n);
+    const geom *g = &G;
+#pragma omp parallel for schedule(static)
+    for (int k = -NG; k < n[2] + NG; ++k)
+        for (int j = -NG; j < n[1] + NG; ++j)
+            for (int i = -NG; i < n[0] + NG; ++i) {
+                int c[3] = {i, j, k}, s[3];
+                int valid = 1, ok = 1;
+                for (int d = 0; d < 3; ++d) {
+                    if (c[d] >= 0 && c[d] < n[d]) { s[d] = c[d]; continue; }
+                    valid = 0;
+                    if (P->bc_lo[d] == BC_PERIODIC) s[d] = ((c[d] % n[d]) + n[d]) % n[d];
+                    else ok = 0;
+                }
+                if (valid || !ok) continue;
+                for (int m = 0; m < 5; ++m) U[gidx(g, m, i, j, k)] = U[gidx(g, m, s[0], s[1], s[2])];
+            }
+    for (int d = 0; d < 3; ++d) {
+        if (P->bc_lo[d] == BC_PERIODIC) continue;
+        for (int side = 0; side < 2; ++side) {
+            const int bc = side == 0 ? P->bc_lo[d] : P->bc_hi[d];
+            double Uin[5];
+            inflow_cons(P, Uin);
+            for (int k = -NG; k < n[2] + NG; ++k)
+                for (int j = -NG; j < n[1] + NG; ++j)
+                    for (int i = -NG; i < n[0] + NG; ++i) {
+                        int c[3] = {i, j, k};
+                        if (side == 0 ? c[d] >= 0 : c[d] < n[d]) continue;
+                        int s[3] = {i, j, k};
+                        if (bc == BC_OUTFLOW) s[d] = side == 0 ? 0 : n[d] - 1;
+                        else if (bc == BC_REFLECT) s[d] = side == 0 ? -c[d] - 1 : 2 * n[d] - 1 - c[d];
+                        for (int m = 0; m < 5; ++m) {
+                            double v;
+                            if (bc == BC_INFLOW) v = Uin[m];
+                            else {
+                                v = U[gidx(g, m, s[0], s[1], s[2])];
+                                if (bc == BC_REFLECT && m == 1 + d) v = -v;
+                            }
+                            U[gidx(g, m, i, j, k)] = v;
+                        }
+                    }
+        }
+    }
+}
+
+/* --------------------------------------------------------------- dt (O2) */
+
+/* Largest signal speed over valid cells: max over cells and directions of
+ * (|u_d| + c) / dx_d, using the floored primitive state. */
+double orc_signal_speed(const double *U, const int n[3], const orc_params *P) {
+    const geom G = mkgeom(n);
+    const geom *g = &G;
+    const double rdx[3] = {1.0 / P->dx[0], 1.0 / P->dx[1], 1.0 / P->dx[2]};
+    double smax = 0.0;
+#pragma omp parallel for reduction(max : smax) schedule(static)
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                double Uc[5], q[6];
+                long long lc[NCNT] = {0, 0, 0, 0, 0};
+                for (int m = 0; m < 5; ++m) Uc[m] = U[gidx(g, m, i, j, k)];
+                cons_to_prim_cell(Uc, P, q, lc);
+                for (int d = 0; d < 3; ++d) {
+                    double s = (fabs(q[1 + d]) + q[5]) * rdx[d];
+                    if (s > smax) smax = s;
+                }
+            }
+    return smax;
+}
+
+/* One single-level step on a whole-domain grown array: fill ghosts, dt from
+ * the CFL condition (unless dt_fixed > 0), advance.  Returns dt via dt_used. */
+int orc_step(double *U, const int n[3], const orc_params *P, double dt_fixed, double *dt_used,
+             long long *cnt) {
+    const geom G = mkgeom(n);
+    const long gs = gsize(&G);
+    orc_fill_domain(U, n, P);
+    double dt = dt_fixed;
+    if (!(dt_fixed > 0.0)) {
+        double s = orc_signal_speed(U, n, P);
+        dt = P->cfl / s;
+    }
+    double *Un = xalloc(NV * gs);
+    if (!Un) return -2;
+    memcpy(Un, U, sizeof(double) * NV * gs);
+    int rc = orc_advance_box(U, n, P, dt, Un, cnt, NULL);
+    if (rc == 0) memcpy(U, Un, sizeof(double) * NV * gs);
+    free(Un);
+    if (dt_used) *dt_used = dt;
+    return rc;
+}
+
+int orc_run(double *U, const int n[3], const orc_params *P, int nsteps, double dt_fixed,
+            double *dts, long long *cnt) {
+    for (int s = 0; s < nsteps; ++s) {
+        double dt;
+        int rc = orc_step(U, n, P, dt_fixed, &dt, cnt);
+        if (rc) return rc;
+        if (dts) dts[s] = dt;
+    }
+    return 0;
+}

@@ -1,0 +1,331 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the bench.
+
+This module holds no step of the hydro scheme.  It evaluates initial
+conditions at cell centres, turns the primitive initial fields into the
+conserved state with the ideal-gas energy relation (E = p/(gamma-1) + kinetic
+energy), and cuts index-space domains into boxes.  Random numbers come from
+numpy's PCG64 (``numpy.random.default_rng(seed)``) and are drawn over the global
+index space in C order (k, j, i), so a box decomposition never changes an
+initial condition.
+
+The workloads stand in for the paper's own problems (Sedov with a stellar
+equation of state, white-dwarf mergers, X-ray bursts; section 4), whose inputs
+are not available: their shapes follow the paper's description of block
+structured grids (boxes of unequal size, a refined patch over several coarse
+boxes; section 3, Figure 1).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+NVAR = 5
+NGHOST = 4
+
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_INFLOW = 0, 1, 2, 3
+
+Box = Tuple[Tuple[int, int, int], Tuple[int, int, int]]  # (lo, hi) inclusive, (i, j, k)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One hydro problem on a level-0 index space [0, n) with its boxes."""
+
+    name: str
+    n: Tuple[int, int, int]                 # cells (nx, ny, nz)
+    gamma: float
+    U0: np.ndarray                          # conserved state, shape (5, nz, ny, nx)
+    boxes: List[Box]
+    bc_lo: Tuple[int, int, int] = (BC_PERIODIC,) * 3
+    bc_hi: Tuple[int, int, int] = (BC_PERIODIC,) * 3
+    cfl: float = 0.5
+    grav_z: float = 0.0
+    inflow: Tuple[float, float, float, float, float] = (1.0, 0.0, 0.0, 0.0, 1.0)
+    prob_lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    prob_hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    steps: int = 10
+    small_dens: float = 1e-12
+    small_pres: float = 1e-12
+    # two-level problems only
+    fine_boxes: Optional[List[Box]] = None   # fine-level index space
+    U0_fine: Optional[np.ndarray] = None     # (5, nzf, nyf, nxf) over the fine bounding region
+    fine_lo: Optional[Tuple[int, int, int]] = None  # fine index of U0_fine[..., 0, 0, 0]
+
+    @property
+    def dx(self) -> Tuple[float, float, float]:
+        return tuple((self.prob_hi[d] - self.prob_lo[d]) / self.n[d] for d in range(3))
+
+    @property
+    def zones(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+
+# ----------------------------------------------------------------------------
+# geometry helpers
+# ----------------------------------------------------------------------------
+
+def cell_centres(n: Sequence[int], lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), offset=(0, 0, 0)):
+    """Cell-centre coordinates (x, y, z), each shaped (nz, ny, nx)."""
+    axes = []
+    for d in range(3):
+        dx = (hi[d] - lo[d]) / n[d]
+        axes.append(lo[d] + (np.arange(offset[d], offset[d] + n[d], dtype=np.float64) + 0.5) * dx)
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return x, y, z
+
+
+def conserved(gamma, rho, u, v, w, p) -> np.ndarray:
+    """Ideal-gas conserved state (rho, rho u, rho v, rho w, rho E) of primitive fields."""
+    rho = np.asarray(rho, dtype=np.float64)
+    shape = np.broadcast_shapes(np.shape(rho), np.shape(u), np.shape(v), np.shape(w), np.shape(p))
+    U = np.empty((NVAR,) + shape, dtype=np.float64)
+    rho = np.broadcast_to(rho, shape)
+    u = np.broadcast_to(np.asarray(u, np.float64), shape)
+    v = np.broadcast_to(np.asarray(v, np.float64), shape)
+    w = np.broadcast_to(np.asarray(w, np.float64), shape)
+    p = np.broadcast_to(np.asarray(p, np.float64), shape)
+    U[0] = rho
+    U[1] = rho * u
+    U[2] = rho * v
+    U[3] = rho * w
+    U[4] = p / (gamma - 1.0) + 0.5 * rho * ((u * u + v * v) + w * w)
+    return U
+
+
+def regular_boxes(n: Sequence[int], edge: Sequence[int], origin=(0, 0, 0)) -> List[Box]:
+    """Cut [origin, origin+n) into boxes of the given edge (must divide n)."""
+    for d in range(3):
+        if n[d] % edge[d]:
+            raise ValueError("box edge must divide the domain")
+    out = []
+    for k in range(0, n[2], edge[2]):
+        for j in range(0, n[1], edge[1]):
+            for i in range(0, n[0], edge[0]):
+                lo = (origin[0] + i, origin[1] + j, origin[2] + k)
+                hi = (lo[0] + edge[0] - 1, lo[1] + edge[1] - 1, lo[2] + edge[2] - 1)
+                out.append((lo, hi))
+    return out
+
+
+EDGE_SET = (16, 24, 32, 48, 64)
+
+
+def _composition(rng: np.random.Generator, total: int, edges=EDGE_SET) -> List[int]:
+    """Split ``total`` into edges from ``edges``; every draw leaves 0 or >= 16."""
+    out = []
+    rem = total
+    while rem > 0:
+        allowed = [e for e in edges if e <= rem and (rem - e == 0 or rem - e >= min(edges))]
+        if not allowed:
+            raise ValueError(f"cannot compose {total} from {edges}")
+        e = allowed[int(rng.integers(len(allowed)))]
+        out.append(e)
+        rem -= e
+    return out
+
+
+def uneven_boxes(n: Sequence[int], seed: int, edges=EDGE_SET) -> List[Box]:
+    """Hierarchical compositions: z slabs, then per slab y rows, then per row x boxes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    z0 = 0
+    for ez in _composition(rng, n[2], edges):
+        y0 = 0
+        for ey in _composition(rng, n[1], edges):
+            x0 = 0
+            for ex in _composition(rng, n[0], edges):
+                out.append(((x0, y0, z0), (x0 + ex - 1, y0 + ey - 1, z0 + ez - 1)))
+                x0 += ex
+            y0 += ey
+        z0 += ez
+    return out
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+
+def sod(n=32, axis=0, gamma=1.4, boxes_edge=None, steps=20, flip=False) -> Problem:
+    """Sod shock tube along ``axis``: left (rho, p) = (1, 1), right (0.125, 0.1)."""
+    nn = [n, n, n] if np.isscalar(n) else list(n)
+    x = cell_centres(nn)[axis]
+    left = x < 0.5
+    if flip:
+        left = ~left
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    U = conserved(gamma, rho, 0.0, 0.0, 0.0, p)
+    bc = [BC_PERIODIC] * 3
+    bc[axis] = BC_OUTFLOW
+    edge = boxes_edge or nn
+    if np.isscalar(edge):
+        edge = [edge] * 3
+    return Problem("sod", tuple(nn), gamma, U, regular_boxes(nn, edge), tuple(bc), tuple(bc),
+                   cfl=0.5, steps=steps)
+
+
+def kelvin_helmholtz(n=256, box=64, seed=20260102, gamma=5.0 / 3.0, steps=100) -> Problem:
+    """Periodic shear layer: rho=2, u_x=+0.5 in |y-0.5|<0.25; rho=1, u_x=-0.5 outside;
+    p=2.5; u_y = 0.01 (2r-1) with r ~ U[0,1) per cell."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    x, y, z = cell_centres(nn)
+    rng = np.random.default_rng(seed)
+    r = rng.random((nn[2], nn[1], nn[0]))
+    inside = np.abs(y - 0.5) < 0.25
+    rho = np.where(inside, 2.0, 1.0)
+    u = np.where(inside, 0.5, -0.5)
+    v = 0.01 * (2.0 * r - 1.0)
+    U = conserved(gamma, rho, u, v, 0.0, 2.5)
+    be = (box, box, box) if np.isscalar(box) else tuple(box)
+    return Problem("kh", nn, gamma, U, regular_boxes(nn, be), cfl=0.5, steps=steps)
+
+
+def rayleigh_taylor(n=384, seed=20260103, box_seed=None, gamma=1.4, steps=200, boxes=None) -> Problem:
+    """Heavy over light in g_z = -1: rho=2 for z>0.5 else 1, p = 2.5 - rho (z-0.5),
+    u_z = 0.01 (2r-1) (1+cos(4 pi (z-0.5)))/2 for |z-0.5| < 0.25; periodic x, y,
+    reflecting z; boxes from seeded hierarchical compositions."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    x, y, z = cell_centres(nn)
+    rng = np.random.default_rng(seed)
+    r = rng.random((nn[2], nn[1], nn[0]))
+    rho = np.where(z > 0.5, 2.0, 1.0)
+    p = 2.5 - rho * (z - 0.5)
+    window = np.abs(z - 0.5) < 0.25
+    w = np.where(window, 0.01 * (2.0 * r - 1.0) * 0.5 * (1.0 + np.cos(4.0 * np.pi * (z - 0.5))), 0.0)
+    U = conserved(gamma, rho, 0.0, 0.0, w, p)
+    if boxes is None:
+        boxes = uneven_boxes(nn, seed if box_seed is None else box_seed)
+    return Problem("rt", nn, gamma, U, boxes, (BC_PERIODIC, BC_PERIODIC, BC_REFLECT),
+                   (BC_PERIODIC, BC_PERIODIC, BC_REFLECT), cfl=0.5, grav_z=-1.0, steps=steps)
+
+
+def _fourier_field(rng: np.random.Generator, x, y, z, modes=8):
+    ks = [k for k in np.ndindex(5, 5, 5) if k != (2, 2, 2)]
+    f = np.zeros_like(x)
+    amps = rng.uniform(0.5, 1.0, size=modes)
+    phases = rng.uniform(0.0, 2.0 * np.pi, size=modes)
+    picks = rng.integers(len(ks), size=modes)
+    for m in range(modes):
+        kx, ky, kz = (c - 2 for c in ks[int(picks[m])])
+        f = f + amps[m] * np.sin(2.0 * np.pi * (kx * x + ky * y + kz * z) + phases[m])
+    return f / amps.sum()
+
+
+SERVING_SIZES = (32, 48, 64, 96, 128)
+
+
+def serving_request(seed: int, n: Optional[int] = None, gamma=1.4, steps=50) -> Problem:
+    """One serving request: a periodic N^3 box with a smooth random state
+    (rho = 1 + 0.1 f, p = 1 + 0.1 f, u_d = 0.3 sqrt(gamma) f; 8 Fourier modes each)."""
+    rng = np.random.default_rng(seed)
+    if n is None:
+        n = SERVING_SIZES[int(rng.integers(len(SERVING_SIZES)))]
+    nn = (n, n, n)
+    x, y, z = cell_centres(nn)
+    rho = 1.0 + 0.1 * _fourier_field(rng, x, y, z)
+    p = 1.0 + 0.1 * _fourier_field(rng, x, y, z)
+    a = 0.3 * math.sqrt(gamma)
+    u = a * _fourier_field(rng, x, y, z)
+    v = a * _fourier_field(rng, x, y, z)
+    w = a * _fourier_field(rng, x, y, z)
+    U = conserved(gamma, rho, u, v, w, p)
+    return Problem(f"serve{n}", nn, gamma, U, [((0, 0, 0), (n - 1, n - 1, n - 1))], cfl=0.5, steps=steps)
+
+
+def smooth_wave(n=32, gamma=1.4, box=None, amp=0.2) -> Problem:
+    """rho = 1 + amp sin(2 pi (x+y+z)), u=v=w=1, p=1, periodic (advected entropy wave)."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    x, y, z = cell_centres(nn)
+    rho = 1.0 + amp * np.sin(2.0 * np.pi * (x + y + z))
+    U = conserved(gamma, rho, 1.0, 1.0, 1.0, 1.0)
+    be = box or nn
+    if np.isscalar(be):
+        be = (be, be, be)
+    return Problem("wave", nn, gamma, U, regular_boxes(nn, be), cfl=0.5)
+
+
+def uniform(n=16, gamma=1.4, rho=1.3, vel=(0.3, -0.2, 0.1), p=0.9, box=None, bc=BC_PERIODIC,
+            grav_z=0.0) -> Problem:
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    U = conserved(gamma, np.full((nn[2], nn[1], nn[0]), rho), vel[0], vel[1], vel[2], p)
+    be = box or nn
+    if np.isscalar(be):
+        be = (be, be, be)
+    return Problem("uniform", nn, gamma, U, regular_boxes(nn, be), (bc,) * 3, (bc,) * 3, grav_z=grav_z)
+
+
+def cloud_wind(n=256, box=64, fine_box=32, fine_region=None, gamma=5.0 / 3.0, steps=100) -> Problem:
+    """Dense cloud (rho 10, radius 0.1, at rest, pressure-matched p=1) in a Mach-2
+    wind (rho 1, p 1, u_x = 2 sqrt(gamma)); inflow x-lo, outflow x-hi, periodic y, z.
+    Two levels: the fine level (ratio 2) covers coarse cells ``fine_region``
+    (default: the central half of the domain)."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    wind = 2.0 * math.sqrt(gamma)
+
+    def state(x, y, z):
+        r2 = (x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2
+        inc = r2 < 0.01
+        rho = np.where(inc, 10.0, 1.0)
+        u = np.where(inc, 0.0, wind)
+        return conserved(gamma, rho, u, 0.0, 0.0, 1.0)
+
+    x, y, z = cell_centres(nn)
+    U = state(x, y, z)
+    if fine_region is None:
+        fine_region = (tuple(v // 4 for v in nn), tuple(3 * v // 4 for v in nn))
+    clo, chi = fine_region
+    flo = tuple(2 * c for c in clo)
+    fn = tuple(2 * (chi[d] - clo[d]) for d in range(3))
+    nf = tuple(2 * v for v in nn)
+    # fine cell centres: (i + 0.5) / (2 n)
+    axes = [(np.arange(flo[d], flo[d] + fn[d], dtype=np.float64) + 0.5) / nf[d] for d in range(3)]
+    zf, yf, xf = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    Uf = state(xf, yf, zf)
+    be = (box, box, box) if np.isscalar(box) else tuple(box)
+    fbe = (fine_box,) * 3 if np.isscalar(fine_box) else tuple(fine_box)
+    prob = Problem("cloud", nn, gamma, U, regular_boxes(nn, be),
+                   (BC_INFLOW, BC_PERIODIC, BC_PERIODIC), (BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC),
+                   cfl=0.5, inflow=(1.0, wind, 0.0, 0.0, 1.0), steps=steps)
+    prob.fine_boxes = regular_boxes(fn, fbe, origin=flo)
+    prob.U0_fine = Uf
+    prob.fine_lo = flo
+    return prob
+
+
+# ----------------------------------------------------------------------------
+# per-box views
+# ----------------------------------------------------------------------------
+
+def box_shape(box: Box) -> Tuple[int, int, int]:
+    lo, hi = box
+    return tuple(hi[d] - lo[d] + 1 for d in range(3))
+
+
+def grown_fab(U: np.ndarray, box: Box, origin=(0, 0, 0), fill=np.nan) -> np.ndarray:
+    """Grown (5, nz+8, ny+8, nx+8) array of one box with valid cells copied from the
+    level array ``U`` (whose [..., 0, 0, 0] is index ``origin``); ghosts = ``fill``."""
+    lo, hi = box
+    nx, ny, nz = box_shape(box)
+    g = NGHOST
+    out = np.full((NVAR, nz + 2 * g, ny + 2 * g, nx + 2 * g), fill, dtype=np.float64)
+    sl = (slice(None),
+          slice(lo[2] - origin[2], hi[2] + 1 - origin[2]),
+          slice(lo[1] - origin[1], hi[1] + 1 - origin[1]),
+          slice(lo[0] - origin[0], hi[0] + 1 - origin[0]))
+    out[:, g:g + nz, g:g + ny, g:g + nx] = U[sl]
+    return out
+
+
+def gather_valid(fabs: Sequence[np.ndarray], boxes: Sequence[Box], n, origin=(0, 0, 0)) -> np.ndarray:
+    """Inverse of grown_fab over a box list: assemble the level's valid cells."""
+    out = np.full((NVAR, n[2], n[1], n[0]), np.nan, dtype=np.float64)
+    g = NGHOST
+    for f, b in zip(fabs, boxes):
+        lo, hi = b
+        nx, ny, nz = box_shape(b)
+        out[:, lo[2] - origin[2]:hi[2] + 1 - origin[2], lo[1] - origin[1]:hi[1] + 1 - origin[1],
+            lo[0] - origin[0]:hi[0] + 1 - origin[0]] = np.asarray(f)[:, g:g + nz, g:g + ny, g:g + nx]
+    return out
