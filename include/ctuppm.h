@@ -1,0 +1,152 @@
+/*
+ * ctuppm.h -- C ABI of the MI355X (gfx950) unsplit CTU/PPM hydro library.
+ *
+ * The calls follow the paper's statement of the problem: a block-structured
+ * grid is a list of boxes per level, each box holding its conserved state with
+ * ghost cells and handed to the compute kernels box by box (section 3; section
+ * 4, the box iterator that passes each box's data pointer to a kernel); the
+ * state advances one step at a time with dt from the CFL condition, using an
+ * unsplit piecewise parabolic method (section 3.2); coarse and fine levels are
+ * advanced with subcycling and then synchronised (section 3 and section 3.2).
+ *
+ * Conventions for every call:
+ *   - All functions are extern "C", return an int status (CTUPPM_OK = 0, < 0 on
+ *     error) and never throw; ctuppm_last_error() gives the message of the last
+ *     failure on a context.
+ *   - Device memory for the state and the stage workspace is owned by the
+ *     caller (the Python binding allocates it with PyTorch).  The library keeps
+ *     the raw pointers and never frees them.  The library itself allocates only
+ *     small device metadata tables (box records, work lists, problem records)
+ *     and frees them in ctuppm_problem_destroy / ctuppm_ctx_destroy.
+ *   - Work is enqueued asynchronously on the context's HIP stream (caller's);
+ *     only ctuppm_get_dt, ctuppm_status and ctuppm_stage_times synchronise it.
+ *   - One context per host thread.
+ *
+ * State layout: one "fab" per box, FP64, [comp][k][j][i] over the box grown by
+ * CTUPPM_NGHOST cells on every side, i fastest; components
+ * (rho, rho u, rho v, rho w, rho E).  A box (nx, ny, nz) has
+ * 5 (nx+8)(ny+8)(nz+8) doubles.  Each box has two fabs, A and B; steps
+ * alternate between them and ctuppm_current_state() tells which holds the
+ * current state.
+ */
+#ifndef CTUPPM_H
+#define CTUPPM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CTUPPM_OK = 0,
+  CTUPPM_EINVAL = -1,  /* bad argument (shapes, overlapping boxes, unknown id) */
+  CTUPPM_ENOMEM = -2,  /* workspace smaller than ctuppm_workspace_bytes() */
+  CTUPPM_EHIP = -3,    /* a HIP runtime call failed; see ctuppm_last_error */
+  CTUPPM_ESTATE = -4   /* call out of order (e.g. step before bind) */
+};
+enum { CTUPPM_BC_PERIODIC = 0, CTUPPM_BC_OUTFLOW = 1, CTUPPM_BC_REFLECT = 2, CTUPPM_BC_INFLOW = 3 };
+/* Step forms: one launch per stage per box; one persistent launch per stage
+ * over the boxes of every problem stepped; the batched launches replayed from
+ * a captured hipGraph. */
+enum { CTUPPM_FORM_PER_BOX = 0, CTUPPM_FORM_BATCHED = 1, CTUPPM_FORM_GRAPH = 2 };
+
+#define CTUPPM_NVAR 5
+#define CTUPPM_NGHOST 4
+
+/* A box: inclusive valid cell range in its level's index space. */
+typedef struct {
+  int lo[3];
+  int hi[3];
+} ctuppm_box;
+
+/* Problem parameters (level 0).  Level l has cell size dx / 2^l. */
+typedef struct {
+  double gamma;        /* ideal-gas ratio of specific heats, > 1 */
+  double cfl;          /* Courant number for dt = cfl / max_cells max_d (|u_d|+c)/dx_d */
+  double small_dens;   /* density floor */
+  double small_pres;   /* pressure floor */
+  double grav_z;       /* constant gravitational acceleration along z (0: none) */
+  double dx[3];        /* level-0 cell size */
+  int domain_lo[3];    /* level-0 index space of the domain, inclusive */
+  int domain_hi[3];
+  int bc_lo[3];        /* CTUPPM_BC_* per direction and side; periodic on both */
+  int bc_hi[3];        /*   sides or neither */
+  double inflow[5];    /* (rho, u, v, w, p) written by CTUPPM_BC_INFLOW */
+} ctuppm_params;
+
+typedef struct ctuppm_ctx ctuppm_ctx;
+
+/* Create a context that enqueues on `hip_stream` (a hipStream_t owned by the
+ * caller; NULL = the null stream).  *out receives the context. */
+int ctuppm_ctx_create(void* hip_stream, ctuppm_ctx** out);
+/* Destroy a context, its problems, graphs and metadata tables. */
+int ctuppm_ctx_destroy(ctuppm_ctx* ctx);
+/* Message of the last error on ctx (static storage of the context). */
+const char* ctuppm_last_error(ctuppm_ctx* ctx);
+
+/* Define a problem: nlevels (1 or 2; refinement ratio 2), boxes[l] an array of
+ * nboxes[l] boxes of level l.  Boxes of a level must not overlap, must lie in
+ * the level's domain, and periodic domain extents must be >= CTUPPM_NGHOST.
+ * A fine level must lie at least 3 coarse cells inside the domain (section 3.2,
+ * subcycled levels synchronised by refluxing).  *pid_out receives the id. */
+int ctuppm_problem_create(ctuppm_ctx* ctx, const ctuppm_params* params, int nlevels,
+                          const ctuppm_box* const* boxes, const int* nboxes, int* pid_out);
+int ctuppm_problem_destroy(ctuppm_ctx* ctx, int pid);
+
+/* Doubles in one fab of a box: 5 (nx+8)(ny+8)(nz+8). */
+int ctuppm_fab_elems(const ctuppm_box* box, long long* elems);
+
+/* Bytes of stage workspace a problem needs in a form (the batched and graph
+ * forms need scratch for all boxes at once, the per-box form for the largest). */
+int ctuppm_workspace_bytes(ctuppm_ctx* ctx, int pid, int form, size_t* bytes);
+
+/* Hand the library the device pointers of level `level`: U_a[b], U_b[b] are
+ * the two fabs of box b (CTUPPM state layout), 8-byte aligned, caller-owned.
+ * The state is taken to be in the A fabs. */
+int ctuppm_bind_state(ctuppm_ctx* ctx, int pid, int level, double* const* U_a, double* const* U_b);
+/* Hand the library the problem's workspace (device, 256-byte aligned). */
+int ctuppm_bind_workspace(ctuppm_ctx* ctx, int pid, void* workspace, size_t bytes);
+
+/* Use a fixed dt (> 0) instead of the CFL time step; dt <= 0 restores CFL. */
+int ctuppm_set_fixed_dt(ctuppm_ctx* ctx, int pid, double dt);
+
+/* Advance each listed problem by one (coarse) step with its own dt: ghost
+ * fill, dt from the CFL condition, cons->prim, flattening, PPM + tracing,
+ * normal HLLC fluxes, the two transverse (CTU) stages, conservative update.
+ * Two-level problems subcycle the fine level twice, then average down and
+ * reflux.  Asynchronous. */
+int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
+
+/* Which fab (0 = A, 1 = B) holds the current state of problem pid. */
+int ctuppm_current_state(ctuppm_ctx* ctx, int pid, int* which);
+/* dt of the last step (synchronises the stream). */
+int ctuppm_get_dt(ctuppm_ctx* ctx, int pid, double* dt_host);
+/* Counters (synchronises): [0] density floors, [1] pressure floors in
+ * cons->prim, [2] floors on traced states, [3] transverse fall-backs,
+ * [4] cells whose new state failed (rho < small_dens, p < small_pres or
+ * non-finite), [5] steps taken. */
+int ctuppm_status(ctuppm_ctx* ctx, int pid, long long counters[6]);
+
+/* Per-stage timing of eager launches: enable (1) or disable (0).  While on,
+ * every stage launch of the per-box and batched forms is bracketed by HIP
+ * events on the context stream. */
+int ctuppm_set_timing(ctuppm_ctx* ctx, int on);
+/* Accumulated milliseconds and launch counts per stage (synchronises), for
+ * n <= ctuppm_num_stages() stages; resets the accumulators. */
+int ctuppm_stage_times(ctuppm_ctx* ctx, double* ms, long long* launches, int n);
+int ctuppm_num_stages(void);
+const char* ctuppm_stage_name(int stage);
+
+/* Algorithmic HBM bytes of one stage for one step of problem pid (each input
+ * read once, each output written once, over that stage's regions). */
+int ctuppm_stage_bytes(ctuppm_ctx* ctx, int pid, int stage, double* bytes);
+
+/* Tuning of the batched form: blocks per CU of the persistent launches
+ * (0 = one block per chunk). */
+int ctuppm_set_blocks_per_cu(ctuppm_ctx* ctx, int blocks_per_cu);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,804 @@
+// Host runtime of the CTU/PPM library: problems and boxes, ghost-fill tags,
+// per-stage work lists, the per-box / batched / graph step forms, timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ctuppm.h"
+#include "ctuppm_internal.h"
+
+using namespace ctu;
+
+namespace {
+
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  hipError_t upload(const void* src, size_t bytes, void** out) {
+    *out = nullptr;
+    if (bytes == 0) return hipSuccess;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
+    *out = p;
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct Level {
+  std::vector<ctuppm_box> boxes;
+  std::vector<double*> Ua, Ub;
+  bool bound = false;
+};
+
+struct Problem {
+  int id = -1;
+  ctuppm_params prm{};
+  int nlevels = 1;
+  Level lev[2];
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  ProbDev* dP = nullptr;  // device record (library-allocated)
+  int cur = 0;            // host mirror of the parity
+  long long steps = 0;
+};
+
+// Work lists of one set of problems stepped together in one form.
+struct StepSet {
+  std::vector<int> pids;
+  int form = 0;
+  int nboxes = 0;
+  BoxRec* boxes = nullptr;
+  Chunk* chunks[kNumRegions] = {};
+  int nch[kNumRegions] = {};
+  std::vector<int> box_beg[kNumRegions], box_cnt[kNumRegions];
+  FillTag* ftags = nullptr;
+  Chunk* fchunks = nullptr;
+  int nfch = 0;
+  std::vector<int> fbox_beg, fbox_cnt;
+  BcTag* btags[3] = {};
+  Chunk* bchunks[3] = {};
+  int nbch[3] = {};
+  std::vector<int> bbox_beg[3], bbox_cnt[3];
+  ProbDev** probs = nullptr;
+  int nprobs = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  DevAlloc mem;
+  ~StepSet() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    mem.release();
+  }
+};
+
+struct TimedLaunch {
+  int stage;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ctuppm_ctx {
+  hipStream_t stream = nullptr;
+  hipStream_t capture = nullptr;
+  std::string err;
+  std::map<int, std::unique_ptr<Problem>> probs;
+  int next_id = 1;
+  std::map<std::pair<std::vector<int>, int>, std::unique_ptr<StepSet>> sets;
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  double acc_ms[kNumStages] = {};
+  long long acc_n[kNumStages] = {};
+  int num_cus = 256;
+  int blocks_per_cu = 8;
+};
+
+namespace {
+
+int fail(ctuppm_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess) return fail(ctx, CTUPPM_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+int box_n(const ctuppm_box& b, int d) { return b.hi[d] - b.lo[d] + 1; }
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t box_scratch_bytes(const ctuppm_box& b) {
+  const int n[3] = {box_n(b, 0), box_n(b, 1), box_n(b, 2)};
+  return align256(size_t(scratch_doubles(n)) * sizeof(double));
+}
+
+Problem* get_problem(ctuppm_ctx* c, int pid) {
+  auto it = c->probs.find(pid);
+  return it == c->probs.end() ? nullptr : it->second.get();
+}
+
+void level_domain(const ctuppm_params& p, int level, int lo[3], int hi[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const int r = 1 << level;
+    lo[d] = p.domain_lo[d] * r;
+    hi[d] = (p.domain_hi[d] + 1) * r - 1;
+  }
+}
+
+bool overlap(const ctuppm_box& a, const ctuppm_box& b) {
+  for (int d = 0; d < 3; ++d)
+    if (a.hi[d] < b.lo[d] || b.hi[d] < a.lo[d]) return false;
+  return true;
+}
+
+// Intersection of [alo, ahi] and [blo, bhi] per direction; false if empty.
+bool intersect(const int alo[3], const int ahi[3], const int blo[3], const int bhi[3], int lo[3], int hi[3]) {
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = std::max(alo[d], blo[d]);
+    hi[d] = std::min(ahi[d], bhi[d]);
+    if (lo[d] > hi[d]) return false;
+  }
+  return true;
+}
+
+void chunk_region(std::vector<Chunk>& out, int box, long long items) {
+  for (long long s = 0; s < items; s += kBlock) out.push_back(Chunk{box, int(s)});
+}
+
+int grid_for(const ctuppm_ctx* c, int nchunks, bool persistent) {
+  int g = (nchunks + 7) / 8 * 8;
+  if (persistent && c->blocks_per_cu > 0) g = std::min(g, c->blocks_per_cu * c->num_cus);
+  return std::max(8, g);
+}
+
+hipEvent_t take_event(ctuppm_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch one stage over a chunk range (or a fill/bc tag range) with optional timing.
+int run_stage(ctuppm_ctx* c, hipStream_t s, int stage, const BoxRec* boxes, const void* tags,
+              const Chunk* chunks, int nchunks, bool persistent, bool timed) {
+  if (nchunks <= 0) return CTUPPM_OK;
+  Launch L{boxes, tags, chunks, nchunks, grid_for(c, nchunks, persistent), s};
+  hipEvent_t a = nullptr, b = nullptr;
+  if (timed) {
+    a = take_event(c);
+    b = take_event(c);
+    if (!a || !b) return fail(c, CTUPPM_EHIP, "hipEventCreate failed");
+    HIPCHK(c, hipEventRecord(a, s));
+  }
+  hipError_t e = launch_stage(stage, L);
+  if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "launch of %s: %s", stage_name(stage), hipGetErrorString(e));
+  if (timed) {
+    HIPCHK(c, hipEventRecord(b, s));
+    c->timed.push_back(TimedLaunch{stage, a, b});
+  }
+  return CTUPPM_OK;
+}
+
+// Build the work lists for a set of single-level problems in one form.
+int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** out) {
+  auto key = std::make_pair(pids, form == CTUPPM_FORM_GRAPH ? CTUPPM_FORM_BATCHED : form);
+  auto it = c->sets.find(key);
+  if (it != c->sets.end()) {
+    *out = it->second.get();
+    return CTUPPM_OK;
+  }
+  std::unique_ptr<StepSet> S(new StepSet);
+  S->pids = pids;
+  S->form = key.second;
+  std::vector<BoxRec> boxes;
+  std::vector<Chunk> ch[kNumRegions];
+  std::vector<FillTag> ftags;
+  std::vector<Chunk> fch;
+  std::vector<BcTag> btags[3];
+  std::vector<Chunk> bch[3];
+  std::vector<ProbDev*> probs;
+  for (int pid : pids) {
+    Problem* P = get_problem(c, pid);
+    if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+    if (P->nlevels != 1) return fail(c, CTUPPM_EINVAL, "problem %d: multi-level stepping is not built", pid);
+    const Level& L = P->lev[0];
+    if (!L.bound || !P->ws) return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
+    size_t need = 0;
+    if (ctuppm_workspace_bytes(c, pid, S->form, &need) != CTUPPM_OK) return CTUPPM_EINVAL;
+    if (P->ws_bytes < need)
+      return fail(c, CTUPPM_ENOMEM, "problem %d: workspace %zu < %zu bytes", pid, P->ws_bytes, need);
+    probs.push_back(P->dP);
+    const int base = int(boxes.size());
+    size_t off = 0;
+    int dlo[3], dhi[3];
+    level_domain(P->prm, 0, dlo, dhi);
+    for (size_t b = 0; b < L.boxes.size(); ++b) {
+      const ctuppm_box& bx = L.boxes[b];
+      BoxRec r{};
+      r.U[0] = L.Ua[b];
+      r.U[1] = L.Ub[b];
+      r.scr = (double*)((char*)P->ws + (S->form == CTUPPM_FORM_PER_BOX ? 0 : off));
+      off += box_scratch_bytes(bx);
+      r.P = P->dP;
+      for (int d = 0; d < 3; ++d) {
+        r.n[d] = box_n(bx, d);
+        r.lo[d] = bx.lo[d];
+      }
+      boxes.push_back(r);
+    }
+    const int nb = int(L.boxes.size());
+    // same-level ghost copies, periodic images included
+    int shifts[3][3];
+    int nsh[3];
+    for (int d = 0; d < 3; ++d) {
+      const int len = dhi[d] - dlo[d] + 1;
+      nsh[d] = 0;
+      shifts[d][nsh[d]++] = 0;
+      if (P->prm.bc_lo[d] == CTUPPM_BC_PERIODIC) {
+        shifts[d][nsh[d]++] = len;
+        shifts[d][nsh[d]++] = -len;
+      }
+    }
+    for (int db = 0; db < nb; ++db) {
+      const ctuppm_box& D = L.boxes[db];
+      int glo[3], ghi[3];
+      for (int d = 0; d < 3; ++d) {
+        glo[d] = D.lo[d] - kNG;
+        ghi[d] = D.hi[d] + kNG;
+      }
+      for (int sb = 0; sb < nb; ++sb) {
+        const ctuppm_box& Sx = L.boxes[sb];
+        for (int a = 0; a < nsh[0]; ++a)
+          for (int bb = 0; bb < nsh[1]; ++bb)
+            for (int cc = 0; cc < nsh[2]; ++cc) {
+              const int sh[3] = {shifts[0][a], shifts[1][bb], shifts[2][cc]};
+              if (sb == db && sh[0] == 0 && sh[1] == 0 && sh[2] == 0) continue;
+              // image of the source's valid cells, in the destination's frame
+              int slo[3], shi[3], lo[3], hi[3];
+              for (int d = 0; d < 3; ++d) {
+                slo[d] = Sx.lo[d] - sh[d];
+                shi[d] = Sx.hi[d] - sh[d];
+              }
+              if (!intersect(glo, ghi, slo, shi, lo, hi)) continue;
+              FillTag t{};
+              t.dst = base + db;
+              t.src = base + sb;
+              long long vol = 1;
+              for (int d = 0; d < 3; ++d) {
+                t.lo[d] = lo[d] - D.lo[d];
+                t.ext[d] = hi[d] - lo[d] + 1;
+                t.off[d] = D.lo[d] + sh[d] - Sx.lo[d];
+                vol *= t.ext[d];
+              }
+              ftags.push_back(t);
+              (void)vol;
+            }
+      }
+    }
+    // physical boundaries, one list per direction
+    const double rgm1 = 1.0 / (P->prm.gamma - 1.0);
+    const double* s = P->prm.inflow;
+    double inflow_cons[5];
+    inflow_cons[0] = s[0];
+    inflow_cons[1] = s[0] * s[1];
+    inflow_cons[2] = s[0] * s[2];
+    inflow_cons[3] = s[0] * s[3];
+    inflow_cons[4] = s[4] * rgm1 + 0.5 * s[0] * ((s[1] * s[1] + s[2] * s[2]) + s[3] * s[3]);
+    for (int d = 0; d < 3; ++d) {
+      if (P->prm.bc_lo[d] == CTUPPM_BC_PERIODIC) continue;
+      for (int b = 0; b < nb; ++b) {
+        const ctuppm_box& B = L.boxes[b];
+        for (int side = 0; side < 2; ++side) {
+          BcTag t{};
+          t.box = base + b;
+          t.dir = d;
+          t.side = side;
+          t.bc = side == 0 ? P->prm.bc_lo[d] : P->prm.bc_hi[d];
+          t.dom_lo = dlo[d];
+          t.dom_hi = dhi[d];
+          for (int m = 0; m < 5; ++m) t.inflow[m] = inflow_cons[m];
+          bool any = true;
+          for (int e = 0; e < 3; ++e) {
+            int lo = -kNG, hi = box_n(B, e) + kNG - 1;  // box-local grown range
+            if (e == d) {
+              if (side == 0) hi = std::min(hi, dlo[d] - 1 - B.lo[d]);
+              else lo = std::max(lo, dhi[d] + 1 - B.lo[d]);
+            }
+            if (lo > hi) any = false;
+            t.lo[e] = lo;
+            t.ext[e] = hi - lo + 1;
+          }
+          if (any) btags[d].push_back(t);
+        }
+      }
+    }
+  }
+  S->nboxes = int(boxes.size());
+  S->nprobs = int(probs.size());
+  // chunk lists per region, per box in order
+  for (int k = 0; k < kNumRegions; ++k) {
+    S->box_beg[k].resize(S->nboxes);
+    S->box_cnt[k].resize(S->nboxes);
+    for (int b = 0; b < S->nboxes; ++b) {
+      int org[3], ext[3];
+      region_of(k, boxes[b].n, org, ext);
+      S->box_beg[k][b] = int(ch[k].size());
+      chunk_region(ch[k], b, (long long)ext[0] * ext[1] * ext[2]);
+      S->box_cnt[k][b] = int(ch[k].size()) - S->box_beg[k][b];
+    }
+    S->nch[k] = int(ch[k].size());
+  }
+  // fill tags sorted by destination box so a box's tags are contiguous
+  std::stable_sort(ftags.begin(), ftags.end(), [](const FillTag& a, const FillTag& b) { return a.dst < b.dst; });
+  S->fbox_beg.assign(S->nboxes, 0);
+  S->fbox_cnt.assign(S->nboxes, 0);
+  for (size_t t = 0; t < ftags.size(); ++t) {
+    const FillTag& T = ftags[t];
+    const int before = int(fch.size());
+    chunk_region(fch, int(t), (long long)T.ext[0] * T.ext[1] * T.ext[2]);
+    if (S->fbox_cnt[T.dst] == 0) S->fbox_beg[T.dst] = before;
+    S->fbox_cnt[T.dst] += int(fch.size()) - before;
+  }
+  S->nfch = int(fch.size());
+  for (int d = 0; d < 3; ++d) {
+    S->bbox_beg[d].assign(S->nboxes, 0);
+    S->bbox_cnt[d].assign(S->nboxes, 0);
+    for (size_t t = 0; t < btags[d].size(); ++t) {
+      const BcTag& T = btags[d][t];
+      const int before = int(bch[d].size());
+      chunk_region(bch[d], int(t), (long long)T.ext[0] * T.ext[1] * T.ext[2]);
+      if (S->bbox_cnt[d][T.box] == 0) S->bbox_beg[d][T.box] = before;
+      S->bbox_cnt[d][T.box] += int(bch[d].size()) - before;
+    }
+    S->nbch[d] = int(bch[d].size());
+  }
+  void* p = nullptr;
+  HIPCHK(c, S->mem.upload(boxes.data(), boxes.size() * sizeof(BoxRec), &p));
+  S->boxes = (BoxRec*)p;
+  for (int k = 0; k < kNumRegions; ++k) {
+    HIPCHK(c, S->mem.upload(ch[k].data(), ch[k].size() * sizeof(Chunk), &p));
+    S->chunks[k] = (Chunk*)p;
+  }
+  HIPCHK(c, S->mem.upload(ftags.data(), ftags.size() * sizeof(FillTag), &p));
+  S->ftags = (FillTag*)p;
+  HIPCHK(c, S->mem.upload(fch.data(), fch.size() * sizeof(Chunk), &p));
+  S->fchunks = (Chunk*)p;
+  for (int d = 0; d < 3; ++d) {
+    HIPCHK(c, S->mem.upload(btags[d].data(), btags[d].size() * sizeof(BcTag), &p));
+    S->btags[d] = (BcTag*)p;
+    HIPCHK(c, S->mem.upload(bch[d].data(), bch[d].size() * sizeof(Chunk), &p));
+    S->bchunks[d] = (Chunk*)p;
+  }
+  HIPCHK(c, S->mem.upload(probs.data(), probs.size() * sizeof(ProbDev*), &p));
+  S->probs = (ProbDev**)p;
+  *out = S.get();
+  c->sets[key] = std::move(S);
+  return CTUPPM_OK;
+}
+
+const int kCellStages[] = {kStC2P, kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
+                           kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate};
+const int kCellRegion[] = {kGrown, kCells1, kCells1, kCells1, kCells1, kFace0, kFace1, kFace2,
+                           kFace0, kFace1, kFace2, kFin0, kFin1, kFin2, kValid};
+
+// Enqueue one step of a set on stream s.
+int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
+  const bool per_box = S->form == CTUPPM_FORM_PER_BOX;
+  int rc;
+  if (per_box) {
+    for (int b = 0; b < S->nboxes; ++b)
+      if ((rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks + S->fbox_beg[b], S->fbox_cnt[b], false, timed)))
+        return rc;
+    for (int d = 0; d < 3; ++d)
+      for (int b = 0; b < S->nboxes; ++b)
+        if ((rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d] + S->bbox_beg[d][b],
+                            S->bbox_cnt[d][b], false, timed)))
+          return rc;
+    for (int b = 0; b < S->nboxes; ++b)
+      if ((rc = run_stage(c, s, kStCfl, S->boxes, nullptr, S->chunks[kValid] + S->box_beg[kValid][b],
+                          S->box_cnt[kValid][b], false, timed)))
+        return rc;
+  } else {
+    if ((rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks, S->nfch, true, timed))) return rc;
+    for (int d = 0; d < 3; ++d)
+      if ((rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d], S->nbch[d], true, timed))) return rc;
+    if ((rc = run_stage(c, s, kStCfl, S->boxes, nullptr, S->chunks[kValid], S->nch[kValid], true, timed))) return rc;
+  }
+  {
+    hipError_t e = launch_dt(S->probs, S->nprobs, s);
+    if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "dt launch: %s", hipGetErrorString(e));
+  }
+  const int nst = int(sizeof(kCellStages) / sizeof(int));
+  if (per_box) {
+    for (int b = 0; b < S->nboxes; ++b)
+      for (int q = 0; q < nst; ++q) {
+        const int k = kCellRegion[q];
+        if ((rc = run_stage(c, s, kCellStages[q], S->boxes, nullptr, S->chunks[k] + S->box_beg[k][b],
+                            S->box_cnt[k][b], false, timed)))
+          return rc;
+      }
+  } else {
+    for (int q = 0; q < nst; ++q) {
+      const int k = kCellRegion[q];
+      if ((rc = run_stage(c, s, kCellStages[q], S->boxes, nullptr, S->chunks[k], S->nch[k], true, timed))) return rc;
+    }
+  }
+  hipError_t e = launch_flip(S->probs, S->nprobs, s);
+  if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "flip launch: %s", hipGetErrorString(e));
+  return CTUPPM_OK;
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+
+extern "C" {
+
+int ctuppm_ctx_create(void* hip_stream, ctuppm_ctx** out) {
+  if (!out) return CTUPPM_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<ctuppm_ctx> c(new ctuppm_ctx);
+  c->stream = (hipStream_t)hip_stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CTUPPM_EHIP;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    c->num_cus = cus;
+  if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) return CTUPPM_EHIP;
+  *out = c.release();
+  return CTUPPM_OK;
+}
+
+int ctuppm_ctx_destroy(ctuppm_ctx* c) {
+  if (!c) return CTUPPM_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  c->sets.clear();
+  for (auto& kv : c->probs)
+    if (kv.second->dP) (void)hipFree(kv.second->dP);
+  c->probs.clear();
+  for (auto& t : c->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->capture) (void)hipStreamDestroy(c->capture);
+  delete c;
+  return CTUPPM_OK;
+}
+
+const char* ctuppm_last_error(ctuppm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int ctuppm_fab_elems(const ctuppm_box* b, long long* elems) {
+  if (!b || !elems) return CTUPPM_EINVAL;
+  long long v = kNV;
+  for (int d = 0; d < 3; ++d) {
+    const int n = b->hi[d] - b->lo[d] + 1;
+    if (n < 1) return CTUPPM_EINVAL;
+    v *= n + 2 * kNG;
+  }
+  *elems = v;
+  return CTUPPM_OK;
+}
+
+int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, const ctuppm_box* const* boxes,
+                          const int* nboxes, int* pid_out) {
+  if (!c || !prm || !boxes || !nboxes || !pid_out) return CTUPPM_EINVAL;
+  if (nlevels != 1 && nlevels != 2) return fail(c, CTUPPM_EINVAL, "nlevels must be 1 or 2");
+  if (!(prm->gamma > 1.0)) return fail(c, CTUPPM_EINVAL, "gamma must be > 1");
+  for (int d = 0; d < 3; ++d) {
+    if (!(prm->dx[d] > 0.0)) return fail(c, CTUPPM_EINVAL, "dx must be > 0");
+    if (prm->domain_hi[d] < prm->domain_lo[d]) return fail(c, CTUPPM_EINVAL, "empty domain");
+    const bool plo = prm->bc_lo[d] == CTUPPM_BC_PERIODIC, phi = prm->bc_hi[d] == CTUPPM_BC_PERIODIC;
+    if (plo != phi) return fail(c, CTUPPM_EINVAL, "direction %d periodic on one side only", d);
+    if (plo && prm->domain_hi[d] - prm->domain_lo[d] + 1 < kNG)
+      return fail(c, CTUPPM_EINVAL, "periodic extent along %d below %d cells", d, kNG);
+    for (int s = 0; s < 2; ++s) {
+      const int bc = s ? prm->bc_hi[d] : prm->bc_lo[d];
+      if (bc < 0 || bc > 3) return fail(c, CTUPPM_EINVAL, "unknown boundary condition %d", bc);
+    }
+  }
+  std::unique_ptr<Problem> P(new Problem);
+  P->prm = *prm;
+  P->nlevels = nlevels;
+  for (int l = 0; l < nlevels; ++l) {
+    if (nboxes[l] < 1 || !boxes[l]) return fail(c, CTUPPM_EINVAL, "level %d has no boxes", l);
+    int dlo[3], dhi[3];
+    level_domain(*prm, l, dlo, dhi);
+    for (int b = 0; b < nboxes[l]; ++b) {
+      const ctuppm_box& B = boxes[l][b];
+      for (int d = 0; d < 3; ++d)
+        if (B.lo[d] > B.hi[d] || B.lo[d] < dlo[d] || B.hi[d] > dhi[d])
+          return fail(c, CTUPPM_EINVAL, "level %d box %d outside the domain or empty", l, b);
+      for (int o = 0; o < b; ++o)
+        if (overlap(B, boxes[l][o])) return fail(c, CTUPPM_EINVAL, "level %d boxes %d and %d overlap", l, o, b);
+      P->lev[l].boxes.push_back(B);
+    }
+  }
+  ProbDev h{};
+  h.gamma = prm->gamma;
+  h.gm1 = prm->gamma - 1.0;
+  h.rgm1 = 1.0 / (prm->gamma - 1.0);
+  h.cfl = prm->cfl;
+  h.small_dens = prm->small_dens;
+  h.small_pres = prm->small_pres;
+  h.grav_z = prm->grav_z;
+  for (int d = 0; d < 3; ++d) {
+    h.dx[d] = prm->dx[d];
+    h.rdx[d] = 1.0 / prm->dx[d];
+  }
+  h.nlevels = nlevels;
+  HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
+  HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
+  P->id = c->next_id++;
+  *pid_out = P->id;
+  c->probs[P->id] = std::move(P);
+  return CTUPPM_OK;
+}
+
+int ctuppm_problem_destroy(ctuppm_ctx* c, int pid) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto it = c->sets.begin(); it != c->sets.end();) {
+    const auto& v = it->first.first;
+    if (std::find(v.begin(), v.end(), pid) != v.end()) it = c->sets.erase(it);
+    else ++it;
+  }
+  if (P->dP) (void)hipFree(P->dP);
+  c->probs.erase(pid);
+  return CTUPPM_OK;
+}
+
+int ctuppm_workspace_bytes(ctuppm_ctx* c, int pid, int form, size_t* bytes) {
+  if (!c || !bytes) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  size_t total = 0, mx = 0;
+  for (int l = 0; l < P->nlevels; ++l)
+    for (const auto& b : P->lev[l].boxes) {
+      const size_t s = box_scratch_bytes(b);
+      total += s;
+      mx = std::max(mx, s);
+    }
+  if (form == CTUPPM_FORM_PER_BOX) *bytes = mx;
+  else if (form == CTUPPM_FORM_BATCHED || form == CTUPPM_FORM_GRAPH) *bytes = total;
+  else return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
+  return CTUPPM_OK;
+}
+
+int ctuppm_bind_state(ctuppm_ctx* c, int pid, int level, double* const* Ua, double* const* Ub) {
+  if (!c || !Ua || !Ub) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (level < 0 || level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "bad level %d", level);
+  Level& L = P->lev[level];
+  L.Ua.assign(Ua, Ua + L.boxes.size());
+  L.Ub.assign(Ub, Ub + L.boxes.size());
+  for (size_t b = 0; b < L.boxes.size(); ++b)
+    if (!L.Ua[b] || !L.Ub[b] || ((uintptr_t)L.Ua[b] & 7) || ((uintptr_t)L.Ub[b] & 7))
+      return fail(c, CTUPPM_EINVAL, "box %zu: null or misaligned fab pointer", b);
+  L.bound = true;
+  P->cur = 0;
+  for (auto it = c->sets.begin(); it != c->sets.end();) {
+    const auto& v = it->first.first;
+    if (std::find(v.begin(), v.end(), pid) != v.end()) it = c->sets.erase(it);
+    else ++it;
+  }
+  // parity back to A
+  int zero = 0;
+  HIPCHK(c, hipMemcpyAsync(&P->dP->cur, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CTUPPM_OK;
+}
+
+int ctuppm_bind_workspace(ctuppm_ctx* c, int pid, void* ws, size_t bytes) {
+  if (!c || !ws) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if ((uintptr_t)ws & 255) return fail(c, CTUPPM_EINVAL, "workspace must be 256-byte aligned");
+  P->ws = ws;
+  P->ws_bytes = bytes;
+  for (auto it = c->sets.begin(); it != c->sets.end();) {
+    const auto& v = it->first.first;
+    if (std::find(v.begin(), v.end(), pid) != v.end()) it = c->sets.erase(it);
+    else ++it;
+  }
+  return CTUPPM_OK;
+}
+
+int ctuppm_set_fixed_dt(ctuppm_ctx* c, int pid, double dt) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  const double v = dt > 0.0 ? dt : 0.0;
+  HIPCHK(c, hipMemcpyAsync(&P->dP->fixed_dt, &v, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return CTUPPM_OK;
+}
+
+int ctuppm_step(ctuppm_ctx* c, const int* pids, int npids, int form) {
+  if (!c || !pids || npids < 1) return CTUPPM_EINVAL;
+  if (form < CTUPPM_FORM_PER_BOX || form > CTUPPM_FORM_GRAPH) return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
+  std::vector<int> v(pids, pids + npids);
+  for (size_t i = 0; i < v.size(); ++i)
+    for (size_t j = 0; j < i; ++j)
+      if (v[i] == v[j]) return fail(c, CTUPPM_EINVAL, "problem %d listed twice", v[i]);
+  StepSet* S = nullptr;
+  int rc = build_set(c, v, form, &S);
+  if (rc) return rc;
+  if (form == CTUPPM_FORM_GRAPH) {
+    if (!S->exec) {
+      HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_step(c, S, c->capture, false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->capture, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "graph capture: %s", hipGetErrorString(e));
+      S->graph = g;
+      HIPCHK(c, hipGraphInstantiate(&S->exec, g, nullptr, nullptr, 0));
+    }
+    HIPCHK(c, hipGraphLaunch(S->exec, c->stream));
+  } else {
+    rc = enqueue_step(c, S, c->stream, c->timing);
+    if (rc) return rc;
+  }
+  for (int pid : v) {
+    Problem* P = get_problem(c, pid);
+    P->cur ^= 1;
+    P->steps += 1;
+  }
+  return CTUPPM_OK;
+}
+
+int ctuppm_current_state(ctuppm_ctx* c, int pid, int* which) {
+  if (!c || !which) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  *which = P->cur;
+  return CTUPPM_OK;
+}
+
+int ctuppm_get_dt(ctuppm_ctx* c, int pid, double* dt) {
+  if (!c || !dt) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(dt, &P->dP->dt, sizeof(double), hipMemcpyDeviceToHost));
+  return CTUPPM_OK;
+}
+
+int ctuppm_status(ctuppm_ctx* c, int pid, long long counters[6]) {
+  if (!c || !counters) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  ProbDev h;
+  HIPCHK(c, hipMemcpy(&h, P->dP, sizeof(ProbDev), hipMemcpyDeviceToHost));
+  for (int i = 0; i < 5; ++i) counters[i] = (long long)h.cnt[i];
+  counters[5] = h.nsteps;
+  return CTUPPM_OK;
+}
+
+int ctuppm_set_timing(ctuppm_ctx* c, int on) {
+  if (!c) return CTUPPM_EINVAL;
+  c->timing = on != 0;
+  return CTUPPM_OK;
+}
+
+int ctuppm_stage_times(ctuppm_ctx* c, double* ms, long long* launches, int n) {
+  if (!c || !ms || !launches || n < 0 || n > kNumStages) return CTUPPM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& t : c->timed) {
+    float v = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&v, t.a, t.b));
+    c->acc_ms[t.stage] += v;
+    c->acc_n[t.stage] += 1;
+    c->event_pool.push_back(t.a);
+    c->event_pool.push_back(t.b);
+  }
+  c->timed.clear();
+  for (int s = 0; s < n; ++s) {
+    ms[s] = c->acc_ms[s];
+    launches[s] = c->acc_n[s];
+    c->acc_ms[s] = 0.0;
+    c->acc_n[s] = 0;
+  }
+  return CTUPPM_OK;
+}
+
+int ctuppm_num_stages(void) { return kNumStages; }
+const char* ctuppm_stage_name(int s) { return stage_name(s); }
+
+int ctuppm_set_blocks_per_cu(ctuppm_ctx* c, int bpc) {
+  if (!c || bpc < 0) return CTUPPM_EINVAL;
+  c->blocks_per_cu = bpc;
+  for (auto& kv : c->sets) {
+    StepSet* S = kv.second.get();
+    if (S->exec) {
+      (void)hipGraphExecDestroy(S->exec);
+      S->exec = nullptr;
+    }
+    if (S->graph) {
+      (void)hipGraphDestroy(S->graph);
+      S->graph = nullptr;
+    }
+  }
+  return CTUPPM_OK;
+}
+
+int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
+  if (!c || !bytes) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  double tot = 0.0;
+  const double W = 8.0;  // bytes per double
+  for (const auto& bx : P->lev[0].boxes) {
+    const double n0 = box_n(bx, 0), n1 = box_n(bx, 1), n2 = box_n(bx, 2);
+    const double nn[3] = {n0, n1, n2};
+    const double valid = n0 * n1 * n2;
+    const double grown = (n0 + 8) * (n1 + 8) * (n2 + 8);
+    const double cells1 = (n0 + 2) * (n1 + 2) * (n2 + 2);
+    auto face = [&](int d) { return cells1 / (nn[d] + 2) * (nn[d] + 1); };           // faces 0..n x -1..n
+    auto fin = [&](int d) { return valid / nn[d] * (nn[d] + 1); };                    // faces 0..n x 0..n-1
+    auto half = [&](int a, int b) { return face(a) / (nn[b] + 2) * nn[b]; };         // F^{a|b} region
+    switch (stage) {
+      case kStFill: tot += 2 * 5 * W * (grown - valid); break;
+      case kStCfl: tot += 5 * W * valid; break;
+      case kStC2P: tot += (5 + 6) * W * grown; break;
+      case kStFlatten: tot += 4 * W * cells1 + W * cells1; break;
+      case kStTraceX: case kStTraceY: case kStTraceZ: {
+        const int d = stage - kStTraceX;
+        tot += 6 * W * cells1 / (nn[d] + 2) * (nn[d] + 6) + W * cells1 + 2 * 5 * W * face(d);
+        break;
+      }
+      case kStRiemX: case kStRiemY: case kStRiemZ: tot += 3 * 5 * W * face(stage - kStRiemX); break;
+      case kStT1X: case kStT1Y: case kStT1Z: {
+        const int a = stage - kStT1X, b = (a + 1) % 3, cc = (a + 2) % 3;
+        tot += 2 * 5 * W * face(a) + 5 * W * face(b) + 5 * W * face(cc) + 5 * W * (half(a, b) + half(a, cc));
+        break;
+      }
+      case kStT2X: case kStT2Y: case kStT2Z: {
+        const int a = stage - kStT2X, b = (a + 1) % 3, cc = (a + 2) % 3;
+        tot += 2 * 5 * W * fin(a) + 5 * W * half(b, cc) + 5 * W * half(cc, b) + 5 * W * fin(a);
+        break;
+      }
+      case kStUpdate: tot += 2 * 5 * W * valid + 5 * W * (fin(0) + fin(1) + fin(2)); break;
+      default: break;
+    }
+  }
+  *bytes = tot;
+  return CTUPPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal host/device structures of the CTU/PPM library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ctu {
+
+constexpr int kNV = 5;     // rho, rho u, rho v, rho w, rho E
+constexpr int kNG = 4;     // ghost layers
+constexpr int kBlock = 256;  // threads per block = items per chunk
+
+// Work regions of a box (n valid cells per direction), as (origin, extent):
+//   kValid  cells [0, n)            kGrown cells [-4, n+4)   kCells1 cells [-1, n]
+//   kFaceD  faces [0, n] along D, cells [-1, n] across
+//   kFinD   faces [0, n] along D, cells [0, n) across
+enum Region : int { kValid = 0, kGrown, kCells1, kFace0, kFace1, kFace2, kFin0, kFin1, kFin2, kNumRegions };
+
+__host__ __device__ inline void region_of(int kind, const int n[3], int org[3], int ext[3]) {
+  for (int d = 0; d < 3; ++d) {
+    switch (kind) {
+      case kValid: org[d] = 0; ext[d] = n[d]; break;
+      case kGrown: org[d] = -kNG; ext[d] = n[d] + 2 * kNG; break;
+      case kCells1: org[d] = -1; ext[d] = n[d] + 2; break;
+      case kFace0: case kFace1: case kFace2:
+        if (d == kind - kFace0) { org[d] = 0; ext[d] = n[d] + 1; } else { org[d] = -1; ext[d] = n[d] + 2; }
+        break;
+      default:
+        if (d == kind - kFin0) { org[d] = 0; ext[d] = n[d] + 1; } else { org[d] = 0; ext[d] = n[d]; }
+        break;
+    }
+  }
+}
+
+// Per-problem device record: constants, then the state the kernels update.
+struct ProbDev {
+  double gamma, gm1, rgm1, cfl, small_dens, small_pres, grav_z;
+  double dx[3], rdx[3];
+  double fixed_dt;                 // > 0: use this dt instead of the CFL one
+  double dt;                       // dt of the current/last step
+  unsigned long long smax_bits;    // running max of the signal speed (bit pattern, >= 0)
+  unsigned long long smax_fine_bits;  // fine-level signal speed (two-level problems)
+  unsigned long long cnt[5];       // dens floor, pres floor, traced floors, transverse fall-backs, failures
+  int cur;                         // which of U[0], U[1] holds the current state
+  int nsteps;
+  int nlevels;
+  int pad;
+};
+
+// One box of a step set.
+struct BoxRec {
+  double* U[2];     // grown fabs [5][nz+8][ny+8][nx+8], caller-owned
+  double* scr;      // stage scratch of this box
+  ProbDev* P;       // problem the box belongs to
+  int n[3];         // valid cells
+  int lo[3];        // level index of valid cell (0,0,0)
+  int level;
+  int pad;
+};
+
+struct Chunk { int box; int start; };  // box (or tag) index, first item
+
+// Same-level ghost copy: dst-local cells [lo, lo+ext) <- src-local (cell + off).
+struct FillTag { int dst, src; int lo[3]; int ext[3]; int off[3]; int pad; };
+// Physical boundary along dir on one side of the domain, over a box's grown cells.
+struct BcTag { int box; int dir; int side; int bc; int lo[3]; int ext[3]; int dom_lo, dom_hi; double inflow[5]; };
+
+// Scratch layout per box, in doubles: q (6 x grown), phi (1 x halo-1),
+// ql[3], qr[3], fn[3] (5 x halo-1 each), f1[6], ff[3] (5 x halo-1 each).
+__host__ __device__ inline long long grown_cells(const int n[3]) {
+  return (long long)(n[0] + 2 * kNG) * (n[1] + 2 * kNG) * (n[2] + 2 * kNG);
+}
+__host__ __device__ inline long long h1_cells(const int n[3]) {
+  return (long long)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
+}
+__host__ __device__ inline long long scratch_doubles(const int n[3]) {
+  return 6 * grown_cells(n) + 91 * h1_cells(n);
+}
+
+// ---------------------------------------------------------------- launchers
+enum Stage : int {
+  kStFill = 0, kStBcX, kStBcY, kStBcZ, kStCfl, kStDt, kStC2P, kStFlatten,
+  kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
+  kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate, kStFlip, kNumStages
+};
+
+struct Launch {
+  const BoxRec* boxes;
+  const void* tags;    // FillTag / BcTag for fill stages
+  const Chunk* chunks;
+  int nchunks;
+  int grid;            // blocks (multiple of 8)
+  hipStream_t stream;
+};
+
+hipError_t launch_stage(int stage, const Launch& L);
+hipError_t launch_dt(ProbDev* const* probs, int nprobs, hipStream_t s);
+hipError_t launch_flip(ProbDev* const* probs, int nprobs, hipStream_t s);
+const char* stage_name(int stage);
+
+}  // namespace ctu

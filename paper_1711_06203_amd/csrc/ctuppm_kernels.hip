@@ -1,0 +1,604 @@
+// gfx950 kernels of the unsplit CTU/PPM advance, one kernel per stage.
+//
+// Work decomposition: every stage runs over a list of chunks; a chunk is 256
+// consecutive items (cells or faces, i fastest) of one box's region for that
+// stage, so consecutive lanes touch consecutive doubles of every SoA array.
+// The same kernels serve the per-box form (one launch per box over that box's
+// chunks) and the batched form (one persistent launch over the chunks of all
+// boxes of all problems in a step).  Blocks walk their chunks with an
+// XCD-aware mapping: workgroups are dispatched round-robin over the 8 XCDs, so
+// block b runs on XCD b%8 and takes a contiguous eighth of the chunk list,
+// which keeps the y/z stencil neighbours of a chunk in the same XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include "ctuppm_internal.h"
+#include "hydro_device.h"
+
+namespace ctu {
+
+namespace {
+
+template <class F>
+CTU_DEV void for_each_chunk(int nchunks, F&& f) {
+  const int per = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+  const int span = (nchunks + 7) >> 3;
+  const int beg = xcd * span;
+  const int end = beg + span < nchunks ? beg + span : nchunks;
+  for (int c = beg + local; c < end; c += per) f(c);
+}
+
+// Geometry of one box: grown arrays (ghosts -4..n+3) and halo-1 arrays (-1..n).
+struct Geo {
+  int gx, gplane, gcomp;
+  int hx, hplane, hcomp;
+  CTU_DEV explicit Geo(const int n[3]) {
+    gx = n[0] + 2 * kNG;
+    gplane = gx * (n[1] + 2 * kNG);
+    gcomp = gplane * (n[2] + 2 * kNG);
+    hx = n[0] + 2;
+    hplane = hx * (n[1] + 2);
+    hcomp = hplane * (n[2] + 2);
+  }
+  CTU_DEV int g(int i, int j, int k) const { return (k + kNG) * gplane + (j + kNG) * gx + (i + kNG); }
+  CTU_DEV int h(int i, int j, int k) const { return (k + 1) * hplane + (j + 1) * hx + (i + 1); }
+  CTU_DEV int gstride(int d) const { return d == 0 ? 1 : (d == 1 ? gx : gplane); }
+  CTU_DEV int hstride(int d) const { return d == 0 ? 1 : (d == 1 ? hx : hplane); }
+  // scratch sub-arrays
+  CTU_DEV double* q(double* s) const { return s; }
+  CTU_DEV double* phi(double* s) const { return s + 6 * gcomp; }
+  CTU_DEV double* ql(double* s, int d) const { return s + 6 * gcomp + (1 + 5 * d) * hcomp; }
+  CTU_DEV double* qr(double* s, int d) const { return s + 6 * gcomp + (16 + 5 * d) * hcomp; }
+  CTU_DEV double* fn(double* s, int d) const { return s + 6 * gcomp + (31 + 5 * d) * hcomp; }
+  CTU_DEV double* f1(double* s, int p) const { return s + 6 * gcomp + (46 + 5 * p) * hcomp; }
+  CTU_DEV double* ff(double* s, int d) const { return s + 6 * gcomp + (76 + 5 * d) * hcomp; }
+};
+
+// Decode item t of a region into box-local (i, j, k); false past the end.
+CTU_DEV bool decode(int kind, const int n[3], int t, int& i, int& j, int& k) {
+  int org[3], ext[3];
+  region_of(kind, n, org, ext);
+  if (t >= ext[0] * ext[1] * ext[2]) return false;
+  i = t % ext[0] + org[0];
+  const int r = t / ext[0];
+  j = r % ext[1] + org[1];
+  k = r / ext[1] + org[2];
+  return true;
+}
+
+CTU_DEV void count(unsigned long long* c, unsigned long long v) {
+  if (v) atomicAdd(c, v);
+}
+
+// ---------------------------------------------------------------- ghost fill
+
+__global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxes,
+                                                 const FillTag* __restrict__ tags,
+                                                 const Chunk* __restrict__ chunks, int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const FillTag T = tags[ch.box];
+    const int t = ch.start + threadIdx.x;
+    if (t >= T.ext[0] * T.ext[1] * T.ext[2]) return;
+    const int i = T.lo[0] + t % T.ext[0];
+    const int r = t / T.ext[0];
+    const int j = T.lo[1] + r % T.ext[1];
+    const int k = T.lo[2] + r / T.ext[1];
+    const BoxRec& D = boxes[T.dst];
+    const BoxRec& S = boxes[T.src];
+    const int cur = D.P->cur;
+    const Geo gd(D.n), gs(S.n);
+    const double* __restrict__ src = S.U[cur];
+    double* __restrict__ dst = D.U[cur];
+    const int si = gs.g(i + T.off[0], j + T.off[1], k + T.off[2]);
+    const int di = gd.g(i, j, k);
+#pragma unroll
+    for (int m = 0; m < kNV; ++m) dst[m * gd.gcomp + di] = src[m * gs.gcomp + si];
+  });
+}
+
+// Physical boundary of one direction D: outflow copies the edge cell, reflect
+// mirrors with the normal momentum negated, inflow writes a fixed state.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
+                                               const BcTag* __restrict__ tags,
+                                               const Chunk* __restrict__ chunks, int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BcTag T = tags[ch.box];
+    const int t = ch.start + threadIdx.x;
+    if (t >= T.ext[0] * T.ext[1] * T.ext[2]) return;
+    int x[3];
+    x[0] = T.lo[0] + t % T.ext[0];
+    const int r = t / T.ext[0];
+    x[1] = T.lo[1] + r % T.ext[1];
+    x[2] = T.lo[2] + r / T.ext[1];
+    const BoxRec& B = boxes[T.box];
+    const Geo g(B.n);
+    double* __restrict__ U = B.U[B.P->cur];
+    const int di = g.g(x[0], x[1], x[2]);
+    if (T.bc == 3) {
+#pragma unroll
+      for (int m = 0; m < kNV; ++m) U[m * g.gcomp + di] = T.inflow[m];
+      return;
+    }
+    const int X = B.lo[D] + x[D];  // level index of the ghost cell
+    int Xs;
+    if (T.bc == 1) Xs = T.side == 0 ? T.dom_lo : T.dom_hi;
+    else Xs = T.side == 0 ? 2 * T.dom_lo - X - 1 : 2 * T.dom_hi + 1 - X;
+    int s[3] = {x[0], x[1], x[2]};
+    s[D] = Xs - B.lo[D];
+    const int si = g.g(s[0], s[1], s[2]);
+#pragma unroll
+    for (int m = 0; m < kNV; ++m) {
+      double v = U[m * g.gcomp + si];
+      if (T.bc == 2 && m == 1 + D) v = -v;
+      U[m * g.gcomp + di] = v;
+    }
+  });
+}
+
+// ------------------------------------------------------------------- CFL / dt
+
+CTU_DEV double block_max(double v, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) v = dmax(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double r = lds[0];
+  for (int q = 1; q < kBlock / 64; ++q) r = dmax(r, lds[q]);
+  __syncthreads();
+  return r;
+}
+
+// Largest (|u_d| + c) / dx_d over valid cells, per problem, as a 64-bit
+// atomic max on the bit pattern (non-negative doubles order like integers).
+__global__ __launch_bounds__(kBlock) void k_cfl(const BoxRec* __restrict__ boxes, const Chunk* __restrict__ chunks,
+                                                int nchunks) {
+  __shared__ double lds[kBlock / 64];
+  double m = 0.0;
+  ProbDev* curP = nullptr;
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    ProbDev* P = B.P;
+    if (P != curP) {
+      if (curP) {
+        const double bm = block_max(m, lds);
+        if (threadIdx.x == 0) atomicMax(&curP->smax_bits, (unsigned long long)__double_as_longlong(bm));
+      }
+      m = 0.0;
+      curP = P;
+    }
+    int i, j, k;
+    if (!decode(kValid, B.n, ch.start + threadIdx.x, i, j, k)) return;
+    const Geo g(B.n);
+    const double* __restrict__ U = B.U[P->cur];
+    const int o = g.g(i, j, k);
+    double rho = U[o];
+    if (rho < P->small_dens) rho = P->small_dens;
+    const double u = U[g.gcomp + o] / rho, v = U[2 * g.gcomp + o] / rho, w = U[3 * g.gcomp + o] / rho;
+    const double ke = 0.5 * rho * ((u * u + v * v) + w * w);
+    double p = P->gm1 * (U[4 * g.gcomp + o] - ke);
+    if (p < P->small_pres) p = P->small_pres;
+    const double cs = sqrt(P->gamma * p / rho);
+    const double sx = (fabs(u) + cs) * P->rdx[0];
+    const double sy = (fabs(v) + cs) * P->rdx[1];
+    const double sz = (fabs(w) + cs) * P->rdx[2];
+    m = dmax(m, dmax(sx, dmax(sy, sz)));
+  });
+  if (curP) {
+    const double bm = block_max(m, lds);
+    if (threadIdx.x == 0) atomicMax(&curP->smax_bits, (unsigned long long)__double_as_longlong(bm));
+  }
+}
+
+__global__ void k_dt(ProbDev* const* probs, int nprobs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nprobs) return;
+  ProbDev* P = probs[t];
+  const double s = __longlong_as_double((long long)P->smax_bits);
+  P->dt = P->fixed_dt > 0.0 ? P->fixed_dt : P->cfl / s;
+  P->smax_bits = 0ull;
+}
+
+__global__ void k_flip(ProbDev* const* probs, int nprobs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nprobs) return;
+  ProbDev* P = probs[t];
+  P->cur ^= 1;
+  P->nsteps += 1;
+}
+
+// ------------------------------------------------------------- cons -> prim
+
+__global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes, const Chunk* __restrict__ chunks,
+                                                int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    int i, j, k;
+    if (!decode(kGrown, B.n, ch.start + threadIdx.x, i, j, k)) return;
+    const ProbDev* P = B.P;
+    const Geo g(B.n);
+    const double* __restrict__ U = B.U[P->cur];
+    double* __restrict__ q = g.q(B.scr);
+    const int o = g.g(i, j, k);
+    double rho = U[o];
+    unsigned long long hd = 0, hp = 0;
+    if (rho < P->small_dens) { rho = P->small_dens; hd = 1; }
+    const double u = U[g.gcomp + o] / rho, v = U[2 * g.gcomp + o] / rho, w = U[3 * g.gcomp + o] / rho;
+    const double ke = 0.5 * rho * ((u * u + v * v) + w * w);
+    double p = P->gm1 * (U[4 * g.gcomp + o] - ke);
+    if (p < P->small_pres) { p = P->small_pres; hp = 1; }
+    q[o] = rho;
+    q[g.gcomp + o] = u;
+    q[2 * g.gcomp + o] = v;
+    q[3 * g.gcomp + o] = w;
+    q[4 * g.gcomp + o] = p;
+    q[5 * g.gcomp + o] = sqrt(P->gamma * p / rho);
+    count(&B.P->cnt[0], hd);
+    count(&B.P->cnt[1], hp);
+  });
+}
+
+// ---------------------------------------------------------------- flattening
+
+// CW84 shock indicator of the cell at offset o along stride st (direction d).
+CTU_DEV double shock_ind(const double* __restrict__ p, const double* __restrict__ un, int o, int st) {
+  const double dp1 = p[o + st] - p[o - st];
+  const double dp2 = p[o + 2 * st] - p[o - 2 * st];
+  double f = 0.0;
+  if (fabs(dp1) > 0.33 * dmin(p[o + st], p[o - st]) && un[o - st] - un[o + st] > 0.0)
+    f = dmin(1.0, dmax(0.0, 10.0 * (fabs(dp1) / dmax(fabs(dp2), 1e-300) - 0.75)));
+  return f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flatten(const BoxRec* __restrict__ boxes,
+                                                    const Chunk* __restrict__ chunks, int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    int i, j, k;
+    if (!decode(kCells1, B.n, ch.start + threadIdx.x, i, j, k)) return;
+    const Geo g(B.n);
+    const double* __restrict__ q = g.q(B.scr);
+    const double* __restrict__ p = q + 4 * g.gcomp;
+    const int o = g.g(i, j, k);
+    double phi = 1.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int st = g.gstride(d);
+      const double* __restrict__ un = q + (1 + d) * g.gcomp;
+      const int s = (p[o + st] - p[o - st]) > 0.0 ? 1 : -1;
+      const double fd = dmax(shock_ind(p, un, o, st), shock_ind(p, un, o - s * st, st));
+      const double v = 1.0 - fd;
+      phi = d == 0 ? v : dmin(phi, v);
+    }
+    g.phi(B.scr)[g.h(i, j, k)] = phi;
+  });
+}
+
+// ------------------------------------------------------ PPM + tracing along D
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ boxes, const Chunk* __restrict__ chunks,
+                                                  int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    int x[3];
+    if (!decode(kCells1, B.n, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
+    const ProbDev* P = B.P;
+    const Geo g(B.n);
+    const double* __restrict__ q = g.q(B.scr);
+    const int o = g.g(x[0], x[1], x[2]);
+    const int st = g.gstride(D);
+    const int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
+    const double phi = g.phi(B.scr)[g.h(x[0], x[1], x[2])];
+    Parab par[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const double* a = q + comp[m] * g.gcomp + o;
+      par[m] = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+    }
+    const double dtdx = P->dt / P->dx[D];
+    double up[5], dn[5];
+    trace_cell(par, q[o], q[(1 + D) * g.gcomp + o], q[5 * g.gcomp + o], dtdx, up, dn);
+    const bool keep_up = x[D] <= B.n[D] - 1, keep_dn = x[D] >= 0;
+    const double hdtg = 0.5 * P->dt * P->grav_z;
+    constexpr int zpos = 1 + (2 - D + 3) % 3;
+    unsigned long long floors = 0;
+    const int oh = g.h(x[0], x[1], x[2]);
+    if (keep_up) {
+      if (up[0] < P->small_dens) { up[0] = P->small_dens; ++floors; }
+      if (up[4] < P->small_pres) { up[4] = P->small_pres; ++floors; }
+      if (P->grav_z != 0.0) up[zpos] = up[zpos] + hdtg;
+      double* __restrict__ ql = g.ql(B.scr, D);
+      const int f = oh + g.hstride(D);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) ql[m * g.hcomp + f] = up[m];
+    }
+    if (keep_dn) {
+      if (dn[0] < P->small_dens) { dn[0] = P->small_dens; ++floors; }
+      if (dn[4] < P->small_pres) { dn[4] = P->small_pres; ++floors; }
+      if (P->grav_z != 0.0) dn[zpos] = dn[zpos] + hdtg;
+      double* __restrict__ qr = g.qr(B.scr, D);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
+    }
+    count(&B.P->cnt[2], floors);
+  });
+}
+
+// ------------------------------------------------------------ Riemann fluxes
+
+template <int D>
+CTU_DEV void store_flux(double* __restrict__ F, int hcomp, int o, const double f[5]) {
+  F[o] = f[0];
+  F[(1 + D) * hcomp + o] = f[1];
+  F[(1 + (D + 1) % 3) * hcomp + o] = f[2];
+  F[(1 + (D + 2) % 3) * hcomp + o] = f[3];
+  F[4 * hcomp + o] = f[4];
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ boxes,
+                                                    const Chunk* __restrict__ chunks, int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    int i, j, k;
+    if (!decode(kFace0 + D, B.n, ch.start + threadIdx.x, i, j, k)) return;
+    const ProbDev* P = B.P;
+    const Geo g(B.n);
+    const int o = g.h(i, j, k);
+    const double* __restrict__ ql = g.ql(B.scr, D);
+    const double* __restrict__ qr = g.qr(B.scr, D);
+    double L[5], R[5], f[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      L[m] = ql[m * g.hcomp + o];
+      R[m] = qr[m * g.hcomp + o];
+    }
+    hllc(L, R, P->gamma, P->rgm1, f);
+    store_flux<D>(g.fn(B.scr, D), g.hcomp, o, f);
+  });
+}
+
+// Permuted primitive (sweep along A) -> conserved, global component order.
+template <int A>
+CTU_DEV void to_cons(const double s[5], double rgm1, double U[5]) {
+  const double rho = s[0];
+  U[0] = rho;
+  U[1 + A] = rho * s[1];
+  U[1 + (A + 1) % 3] = rho * s[2];
+  U[1 + (A + 2) % 3] = rho * s[3];
+  U[4] = s[4] * rgm1 + 0.5 * rho * ((s[1] * s[1] + s[2] * s[2]) + s[3] * s[3]);
+}
+
+// Conserved -> permuted primitive of a sweep along A; keeps s0 (and returns 1)
+// when the result has rho < small_dens or p < small_pres.
+template <int A>
+CTU_DEV int to_prim_or_keep(const double U[5], const double s0[5], double gm1, double sd, double sp,
+                            double s[5]) {
+  const double rho = U[0];
+  const double un = U[1 + A] / rho, ut1 = U[1 + (A + 1) % 3] / rho, ut2 = U[1 + (A + 2) % 3] / rho;
+  const double ke = 0.5 * rho * ((un * un + ut1 * ut1) + ut2 * ut2);
+  const double p = gm1 * (U[4] - ke);
+  if (rho < sd || p < sp) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) s[m] = s0[m];
+    return 1;
+  }
+  s[0] = rho; s[1] = un; s[2] = ut1; s[3] = ut2; s[4] = p;
+  return 0;
+}
+
+// Stage 1: face states along A corrected by dt/(3 dx_B) times the normal
+// B-flux difference across their owner cell, for B = the two other
+// directions, then HLLC -> F^{A|B}.
+template <int A>
+__global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ boxes,
+                                                   const Chunk* __restrict__ chunks, int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    int x[3];
+    if (!decode(kFace0 + A, B.n, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
+    const ProbDev* P = B.P;
+    const Geo g(B.n);
+    const int o = g.h(x[0], x[1], x[2]);
+    const int sa = g.hstride(A);
+    const double* __restrict__ ql = g.ql(B.scr, A);
+    const double* __restrict__ qr = g.qr(B.scr, A);
+    double sL[5], sR[5], UL[5], UR[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      sL[m] = ql[m * g.hcomp + o];
+      sR[m] = qr[m * g.hcomp + o];
+    }
+    to_cons<A>(sL, P->rgm1, UL);
+    to_cons<A>(sR, P->rgm1, UR);
+    const double dtdxA = P->dt / P->dx[A];
+    (void)dtdxA;
+    unsigned long long fb = 0;
+#pragma unroll
+    for (int which = 0; which < 2; ++which) {
+      const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
+      const int Cd = which == 0 ? (A + 2) % 3 : (A + 1) % 3;
+      (void)Cd;
+      if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
+      const double c3 = (P->dt / P->dx[Bd]) / 3.0;
+      const int sb = g.hstride(Bd);
+      const double* __restrict__ Fb = g.fn(B.scr, Bd);
+      double VL[5], VR[5], tL[5], tR[5], f[5];
+      const int oL = o - sa, oR = o;  // owner cells of the left and right states
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const double* Fm = Fb + m * g.hcomp;
+        VL[m] = UL[m] - c3 * (Fm[oL + sb] - Fm[oL]);
+        VR[m] = UR[m] - c3 * (Fm[oR + sb] - Fm[oR]);
+      }
+      fb += to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+      fb += to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+      hllc(tL, tR, P->gamma, P->rgm1, f);
+      store_flux<A>(g.f1(B.scr, 2 * A + which), g.hcomp, o, f);
+    }
+    count(&B.P->cnt[3], fb);
+  });
+}
+
+// Stage 2: face states along A corrected by dt/(2 dx_B) dF^{B|C} and
+// dt/(2 dx_C) dF^{C|B} with (B, C) the cyclic successors of A; final HLLC.
+template <int A>
+__global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ boxes,
+                                                   const Chunk* __restrict__ chunks, int nchunks) {
+  constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
+  // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
+  constexpr int pbc = 2 * Bd + (Cd == (Bd + 1) % 3 ? 0 : 1);
+  constexpr int pcb = 2 * Cd + (Bd == (Cd + 1) % 3 ? 0 : 1);
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    int x[3];
+    if (!decode(kFin0 + A, B.n, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
+    const ProbDev* P = B.P;
+    const Geo g(B.n);
+    const int o = g.h(x[0], x[1], x[2]);
+    const int sa = g.hstride(A), sb = g.hstride(Bd), sc = g.hstride(Cd);
+    const double* __restrict__ ql = g.ql(B.scr, A);
+    const double* __restrict__ qr = g.qr(B.scr, A);
+    const double* __restrict__ Fbc = g.f1(B.scr, pbc);
+    const double* __restrict__ Fcb = g.f1(B.scr, pcb);
+    const double c2b = 0.5 * (P->dt / P->dx[Bd]);
+    const double c2c = 0.5 * (P->dt / P->dx[Cd]);
+    double sL[5], sR[5], UL[5], UR[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      sL[m] = ql[m * g.hcomp + o];
+      sR[m] = qr[m * g.hcomp + o];
+    }
+    to_cons<A>(sL, P->rgm1, UL);
+    to_cons<A>(sR, P->rgm1, UR);
+    const int oL = o - sa, oR = o;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const double* F1 = Fbc + m * g.hcomp;
+      const double* F2 = Fcb + m * g.hcomp;
+      UL[m] = UL[m] - c2b * (F1[oL + sb] - F1[oL]);
+      UR[m] = UR[m] - c2b * (F1[oR + sb] - F1[oR]);
+      UL[m] = UL[m] - c2c * (F2[oL + sc] - F2[oL]);
+      UR[m] = UR[m] - c2c * (F2[oR + sc] - F2[oR]);
+    }
+    double tL[5], tR[5], f[5];
+    unsigned long long fb = 0;
+    fb += to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+    fb += to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+    hllc(tL, tR, P->gamma, P->rgm1, f);
+    store_flux<A>(g.ff(B.scr, A), g.hcomp, o, f);
+    count(&B.P->cnt[3], fb);
+  });
+}
+
+// ---------------------------------------------------------------- update
+
+__global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ boxes,
+                                                   const Chunk* __restrict__ chunks, int nchunks) {
+  for_each_chunk(nchunks, [&](int c) {
+    const Chunk ch = chunks[c];
+    const BoxRec& B = boxes[ch.box];
+    int i, j, k;
+    if (!decode(kValid, B.n, ch.start + threadIdx.x, i, j, k)) return;
+    const ProbDev* P = B.P;
+    const Geo g(B.n);
+    const double* __restrict__ U = B.U[P->cur];
+    double* __restrict__ Un = B.U[P->cur ^ 1];
+    const double* __restrict__ Fx = g.ff(B.scr, 0);
+    const double* __restrict__ Fy = g.ff(B.scr, 1);
+    const double* __restrict__ Fz = g.ff(B.scr, 2);
+    const int o = g.h(i, j, k), og = g.g(i, j, k);
+    const double dtdx = P->dt / P->dx[0], dtdy = P->dt / P->dx[1], dtdz = P->dt / P->dx[2];
+    double un[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const int mo = m * g.hcomp + o;
+      double du = dtdx * (Fx[mo] - Fx[mo + 1]);
+      du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
+      du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
+      un[m] = U[m * g.gcomp + og] + du;
+    }
+    if (P->grav_z != 0.0) {
+      const double hdtg = 0.5 * P->dt * P->grav_z;
+      un[3] = un[3] + hdtg * (U[og] + un[0]);
+      un[4] = un[4] + hdtg * (U[3 * g.gcomp + og] + un[3]);
+    }
+    bool bad = false;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) bad = bad || !isfinite(un[m]);
+    if (un[0] < P->small_dens) bad = true;
+    if (!bad) {
+      const double u = un[1] / un[0], v = un[2] / un[0], w = un[3] / un[0];
+      const double ke = 0.5 * un[0] * ((u * u + v * v) + w * w);
+      if (P->gm1 * (un[4] - ke) < P->small_pres) bad = true;
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Un[m * g.gcomp + og] = un[m];
+    count(&B.P->cnt[4], bad ? 1ull : 0ull);
+  });
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+const char* stage_name(int s) {
+  static const char* names[kNumStages] = {
+      "fill", "bc_x", "bc_y", "bc_z", "cfl", "dt", "cons2prim", "flatten",
+      "trace_x", "trace_y", "trace_z", "riemann_x", "riemann_y", "riemann_z",
+      "trans1_x", "trans1_y", "trans1_z", "trans2_x", "trans2_y", "trans2_z", "update", "flip"};
+  return (s >= 0 && s < kNumStages) ? names[s] : "?";
+}
+
+hipError_t launch_stage(int stage, const Launch& L) {
+  if (L.nchunks <= 0) return hipSuccess;
+  const dim3 grid(L.grid), block(kBlock);
+  switch (stage) {
+    case kStFill: k_fill<<<grid, block, 0, L.stream>>>(L.boxes, (const FillTag*)L.tags, L.chunks, L.nchunks); break;
+    case kStBcX: k_bc<0><<<grid, block, 0, L.stream>>>(L.boxes, (const BcTag*)L.tags, L.chunks, L.nchunks); break;
+    case kStBcY: k_bc<1><<<grid, block, 0, L.stream>>>(L.boxes, (const BcTag*)L.tags, L.chunks, L.nchunks); break;
+    case kStBcZ: k_bc<2><<<grid, block, 0, L.stream>>>(L.boxes, (const BcTag*)L.tags, L.chunks, L.nchunks); break;
+    case kStCfl: k_cfl<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStC2P: k_c2p<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStFlatten: k_flatten<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStTraceX: k_trace<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStTraceY: k_trace<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStTraceZ: k_trace<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStRiemX: k_riemann<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStRiemY: k_riemann<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStRiemZ: k_riemann<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStT1X: k_trans1<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStT1Y: k_trans1<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStT1Z: k_trans1<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStT2X: k_trans2<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStT2Y: k_trans2<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStT2Z: k_trans2<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStUpdate: k_update<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dt(ProbDev* const* probs, int nprobs, hipStream_t s) {
+  if (nprobs <= 0) return hipSuccess;
+  k_dt<<<(nprobs + 63) / 64, 64, 0, s>>>(probs, nprobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_flip(ProbDev* const* probs, int nprobs, hipStream_t s) {
+  if (nprobs <= 0) return hipSuccess;
+  k_flip<<<(nprobs + 63) / 64, 64, 0, s>>>(probs, nprobs);
+  return hipGetLastError();
+}
+
+}  // namespace ctu

@@ -1,0 +1,266 @@
+"""Python binding of the C ABI in include/ctuppm.h (ctypes).
+
+Argument marshalling only: PyTorch allocates the device memory (state fabs,
+stage workspace) and provides the HIP stream; every step of the hydro advance
+runs in the HIP kernels of ``libctuppm.so``.  There is no CPU fallback: if the
+library or a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libctuppm.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
+FORM_PER_BOX, FORM_BATCHED, FORM_GRAPH = 0, 1, 2
+FORMS = {"per_box": FORM_PER_BOX, "batched": FORM_BATCHED, "graph": FORM_GRAPH}
+NG = 4
+
+
+class CtuError(RuntimeError):
+    pass
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int * 3), ("hi", ctypes.c_int * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("small_dens", ctypes.c_double),
+                ("small_pres", ctypes.c_double), ("grav_z", ctypes.c_double), ("dx", ctypes.c_double * 3),
+                ("domain_lo", ctypes.c_int * 3), ("domain_hi", ctypes.c_int * 3),
+                ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3), ("inflow", ctypes.c_double * 5)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libctuppm.so (built by paper_1711_06203_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CtuError(f"{LIB_PATH} is missing: build it with python -m paper_1711_06203_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+        llp = ctypes.POINTER(ctypes.c_longlong)
+        sz = ctypes.c_size_t
+        sig = {
+            "ctuppm_ctx_create": [vp, ctypes.POINTER(vp)],
+            "ctuppm_ctx_destroy": [vp],
+            "ctuppm_problem_create": [vp, ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(ctypes.POINTER(Box)),
+                                      ip, ip],
+            "ctuppm_problem_destroy": [vp, ctypes.c_int],
+            "ctuppm_fab_elems": [ctypes.POINTER(Box), llp],
+            "ctuppm_workspace_bytes": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)],
+            "ctuppm_bind_state": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp)],
+            "ctuppm_bind_workspace": [vp, ctypes.c_int, vp, sz],
+            "ctuppm_set_fixed_dt": [vp, ctypes.c_int, ctypes.c_double],
+            "ctuppm_step": [vp, ip, ctypes.c_int, ctypes.c_int],
+            "ctuppm_current_state": [vp, ctypes.c_int, ip],
+            "ctuppm_get_dt": [vp, ctypes.c_int, dp],
+            "ctuppm_status": [vp, ctypes.c_int, llp],
+            "ctuppm_set_timing": [vp, ctypes.c_int],
+            "ctuppm_stage_times": [vp, dp, llp, ctypes.c_int],
+            "ctuppm_num_stages": [],
+            "ctuppm_stage_name": [ctypes.c_int],
+            "ctuppm_stage_bytes": [vp, ctypes.c_int, ctypes.c_int, dp],
+            "ctuppm_set_blocks_per_cu": [vp, ctypes.c_int],
+            "ctuppm_last_error": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.ctuppm_last_error.restype = ctypes.c_char_p
+        L.ctuppm_stage_name.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctuppm_problem_create",
+            "ctuppm_problem_destroy", "ctuppm_fab_elems", "ctuppm_workspace_bytes", "ctuppm_bind_state",
+            "ctuppm_bind_workspace", "ctuppm_set_fixed_dt", "ctuppm_step", "ctuppm_current_state",
+            "ctuppm_get_dt", "ctuppm_status", "ctuppm_set_timing", "ctuppm_stage_times", "ctuppm_num_stages",
+            "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_blocks_per_cu"]
+
+
+class Context:
+    """A library context on the current torch stream of the current device."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise CtuError("no GPU visible: the CTU/PPM library runs on the MI355X only")
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        self._L = lib()
+        self._check(self._L.ctuppm_ctx_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None)
+        self.h = h
+
+    def _check(self, rc, h=-1):
+        if rc != OK:
+            msg = self._L.ctuppm_last_error(self.h if h == -1 else h)
+            raise CtuError(f"ctuppm error {rc}: {msg.decode() if msg else ''}")
+
+    def call(self, name, *args):
+        self._check(getattr(self._L, name)(self.h, *args))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.ctuppm_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- timing
+    def set_timing(self, on: bool):
+        self.call("ctuppm_set_timing", int(bool(on)))
+
+    def stage_times(self) -> Dict[str, tuple]:
+        n = self._L.ctuppm_num_stages()
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_longlong * n)()
+        self.call("ctuppm_stage_times", ms, cnt, n)
+        return {self._L.ctuppm_stage_name(s).decode(): (ms[s], cnt[s]) for s in range(n)}
+
+    def set_blocks_per_cu(self, bpc: int):
+        self.call("ctuppm_set_blocks_per_cu", int(bpc))
+
+    def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1):
+        """Advance several problems together (one batched launch set per step)."""
+        f = FORMS[form] if isinstance(form, str) else int(form)
+        pids = (ctypes.c_int * len(solvers))(*[s.pid for s in solvers])
+        for _ in range(nsteps):
+            self.call("ctuppm_step", pids, len(solvers), f)
+
+
+def stage_names() -> List[str]:
+    L = lib()
+    return [L.ctuppm_stage_name(s).decode() for s in range(L.ctuppm_num_stages())]
+
+
+def _params(prob: W.Problem) -> Params:
+    P = Params()
+    P.gamma, P.cfl, P.small_dens, P.small_pres, P.grav_z = (prob.gamma, prob.cfl, prob.small_dens,
+                                                            prob.small_pres, prob.grav_z)
+    for d in range(3):
+        P.dx[d] = prob.dx[d]
+        P.domain_lo[d] = 0
+        P.domain_hi[d] = prob.n[d] - 1
+        P.bc_lo[d] = prob.bc_lo[d]
+        P.bc_hi[d] = prob.bc_hi[d]
+    for m in range(5):
+        P.inflow[m] = prob.inflow[m]
+    return P
+
+
+class Solver:
+    """One single-level problem resident on the GPU: two fabs per box, one
+    workspace, all allocated with torch and handed to the library."""
+
+    def __init__(self, ctx: Context, prob: W.Problem, form="batched", fixed_dt: Optional[float] = None):
+        torch = ctx.torch
+        self.ctx, self.prob = ctx, prob
+        self.form = FORMS[form] if isinstance(form, str) else int(form)
+        L = lib()
+        boxes = (Box * len(prob.boxes))()
+        for b, (lo, hi) in enumerate(prob.boxes):
+            boxes[b].lo[:] = list(lo)
+            boxes[b].hi[:] = list(hi)
+        self._boxes = boxes
+        ptrs = (ctypes.POINTER(Box) * 1)(ctypes.cast(boxes, ctypes.POINTER(Box)))
+        nb = (ctypes.c_int * 1)(len(prob.boxes))
+        pid = ctypes.c_int()
+        ctx.call("ctuppm_problem_create", ctypes.byref(_params(prob)), 1, ptrs, nb, ctypes.byref(pid))
+        self.pid = pid.value
+        # fab offsets in one tensor per parity, 256-byte aligned
+        self.offsets, self.shapes = [], []
+        off = 0
+        for lo, hi in prob.boxes:
+            n = [hi[d] - lo[d] + 1 for d in range(3)]
+            shape = (5, n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG)
+            self.offsets.append(off)
+            self.shapes.append(shape)
+            off += (int(np.prod(shape)) + 31) // 32 * 32
+        self.total = off
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.UA = torch.full((self.total,), float("nan"), dtype=torch.float64, device=dev)
+        self.UB = torch.full((self.total,), float("nan"), dtype=torch.float64, device=dev)
+        ws = ctypes.c_size_t()
+        best = 0
+        for f in (FORM_PER_BOX, FORM_BATCHED):
+            L.ctuppm_workspace_bytes(ctx.h, self.pid, f, ctypes.byref(ws))
+            best = max(best, ws.value)
+        self.ws = torch.empty((max(best, 256),), dtype=torch.uint8, device=dev)
+        self.upload(prob.U0)
+        ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel())
+        if fixed_dt:
+            ctx.call("ctuppm_set_fixed_dt", self.pid, float(fixed_dt))
+
+    def _bind(self):
+        nb = len(self.prob.boxes)
+        a = (ctypes.c_void_p * nb)(*[self.UA.data_ptr() + 8 * o for o in self.offsets])
+        b = (ctypes.c_void_p * nb)(*[self.UB.data_ptr() + 8 * o for o in self.offsets])
+        self.ctx.call("ctuppm_bind_state", self.pid, 0, a, b)
+
+    def upload(self, Uvalid: np.ndarray):
+        """Copy a level state (5, nz, ny, nx) into the A fabs; ghosts NaN."""
+        host = np.full(self.total, np.nan)
+        for (box, off, shape) in zip(self.prob.boxes, self.offsets, self.shapes):
+            host[off:off + int(np.prod(shape))] = W.grown_fab(Uvalid, box).ravel()
+        self.UA.copy_(self.ctx.torch.from_numpy(host))
+        self.UB.fill_(float("nan"))
+        self._bind()
+
+    def step(self, nsteps: int = 1, form=None):
+        f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
+        self.ctx.step([self], f, nsteps)
+
+    def current(self) -> int:
+        w = ctypes.c_int()
+        self.ctx.call("ctuppm_current_state", self.pid, ctypes.byref(w))
+        return w.value
+
+    def fabs(self) -> List[np.ndarray]:
+        t = (self.UA if self.current() == 0 else self.UB).cpu().numpy()
+        return [t[o:o + int(np.prod(s))].reshape(s) for o, s in zip(self.offsets, self.shapes)]
+
+    def state(self) -> np.ndarray:
+        """Valid cells of the current state, (5, nz, ny, nx)."""
+        return W.gather_valid(self.fabs(), self.prob.boxes, self.prob.n)
+
+    def dt(self) -> float:
+        v = ctypes.c_double()
+        self.ctx.call("ctuppm_get_dt", self.pid, ctypes.byref(v))
+        return v.value
+
+    def counters(self) -> np.ndarray:
+        c = (ctypes.c_longlong * 6)()
+        self.ctx.call("ctuppm_status", self.pid, c)
+        return np.array(c[:])
+
+    def stage_bytes(self) -> Dict[str, float]:
+        out = {}
+        v = ctypes.c_double()
+        for s, name in enumerate(stage_names()):
+            self.ctx.call("ctuppm_stage_bytes", self.pid, s, ctypes.byref(v))
+            out[name] = v.value
+        return out
+
+    def close(self):
+        if getattr(self, "pid", None) is not None and self.ctx.h:
+            self.ctx._L.ctuppm_problem_destroy(self.ctx.h, self.pid)
+            self.pid = None

@@ -96,16 +96,15 @@ def conserved(gamma, rho, u, v, w, p) -> np.ndarray:
 
 
 def regular_boxes(n: Sequence[int], edge: Sequence[int], origin=(0, 0, 0)) -> List[Box]:
-    """Cut [origin, origin+n) into boxes of the given edge (must divide n)."""
-    for d in range(3):
-        if n[d] % edge[d]:
-            raise ValueError("box edge must divide the domain")
+    """Cut [origin, origin+n) into boxes of the given edge; the last box along a
+    direction keeps the remainder (a ragged tail) when the edge does not divide n."""
     out = []
     for k in range(0, n[2], edge[2]):
         for j in range(0, n[1], edge[1]):
             for i in range(0, n[0], edge[0]):
                 lo = (origin[0] + i, origin[1] + j, origin[2] + k)
-                hi = (lo[0] + edge[0] - 1, lo[1] + edge[1] - 1, lo[2] + edge[2] - 1)
+                hi = (origin[0] + min(i + edge[0], n[0]) - 1, origin[1] + min(j + edge[1], n[1]) - 1,
+                      origin[2] + min(k + edge[2], n[2]) - 1)
                 out.append((lo, hi))
     return out
 
