@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--skip-forms", action="store_true", help="time only the requested form")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 10 plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -71,6 +74,15 @@ def main():
     from paper_1711_06203_amd import ctuppm, workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8}))
+        return
     prob = W.kelvin_helmholtz(n=args.n, box=args.box)
     ctx = ctuppm.Context()
     solver = ctuppm.Solver(ctx, prob, form=args.form)
@@ -89,7 +101,7 @@ def main():
     value = zones * args.steps / el
     forms = {args.form: value}
     for f in ("per_box", "batched", "graph"):
-        if f not in forms:
+        if f not in forms and not args.skip_forms:
             k = max(3, args.steps // 5)
             forms[f] = zones * k / timed(f, k, 1)
 
