@@ -87,7 +87,8 @@ const char* ctuppm_last_error(ctuppm_ctx* ctx);
 
 /* Define a problem: nlevels (1 or 2; refinement ratio 2), boxes[l] an array of
  * nboxes[l] boxes of level l.  Boxes of a level must not overlap, must lie in
- * the level's domain, and periodic domain extents must be >= CTUPPM_NGHOST.
+ * the level's domain, have edges of at most 256 cells, and periodic domain
+ * extents must be >= CTUPPM_NGHOST.
  * A fine level must lie at least 3 coarse cells inside the domain (section 3.2,
  * subcycled levels synchronised by refluxing).  *pid_out receives the id. */
 int ctuppm_problem_create(ctuppm_ctx* ctx, const ctuppm_params* params, int nlevels,
@@ -142,9 +143,12 @@ const char* ctuppm_stage_name(int stage);
  * read once, each output written once, over that stage's regions). */
 int ctuppm_stage_bytes(ctuppm_ctx* ctx, int pid, int stage, double* bytes);
 
-/* Tuning of the batched form: blocks per CU of the persistent launches
- * (0 = one block per chunk). */
-int ctuppm_set_blocks_per_cu(ctuppm_ctx* ctx, int blocks_per_cu);
+/* Tuning of the launches: blocks per CU of the persistent batched launches
+ * (0 = one block per work unit), and the z planes one work unit marches
+ * through in the batched/graph forms and in the per-box form (>= 1).  Results
+ * do not depend on the tuning (each cell's arithmetic is the same); graphs are
+ * re-captured and work lists rebuilt on the next step. */
+int ctuppm_set_tuning(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int zseg_per_box);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,77 @@
+"""Autotuner of the launch shapes of the batched form.
+
+Tunables (``ctuppm_set_tuning``): blocks per CU of the launches (0 = one
+block per work unit, else a persistent grid of that many blocks per CU
+walking the units) and the z planes a work unit marches through.  Every
+choice gives bitwise the same results (each cell's arithmetic is fixed), so
+the tuner only times: it runs a few event-timed eager steps per candidate on
+the caller's problems and keeps the fastest.  Choices are cached in a JSON
+file keyed by the workload's box-size signature.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+from . import ctuppm
+
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = ((0, 1), (0, 2), (0, 4), (8, 1), (16, 1), (4, 2), (16, 4))
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+
+
+def signature(solvers: Sequence[ctuppm.Solver]) -> str:
+    """Box-size histogram of the problems stepped together."""
+    hist: Dict[str, int] = {}
+    for s in solvers:
+        for lo, hi in s.prob.boxes:
+            key = "x".join(str(hi[d] - lo[d] + 1) for d in range(3))
+            hist[key] = hist.get(key, 0) + 1
+    return ";".join(f"{k}:{v}" for k, v in sorted(hist.items()))
+
+
+def _time_steps(ctx: ctuppm.Context, solvers, steps: int) -> float:
+    ctx.step(solvers, "batched", 1)
+    ctx.torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.step(solvers, "batched", steps)
+    ctx.set_timing(False)
+    st = ctx.stage_times()
+    return sum(ms for ms, n in st.values()) / steps
+
+
+def tune(ctx: ctuppm.Context, solvers: Sequence[ctuppm.Solver], candidates: Iterable[Tuple[int, int]] = DEFAULT_CANDIDATES,
+         steps: int = 3, cache: Optional[str] = CACHE, use_cache: bool = True) -> dict:
+    """Pick (blocks_per_cu, zseg) for these problems; applies and returns it.
+
+    The problems are advanced by the timing steps (1 + steps per candidate),
+    so callers tune on a copy or before loading the real initial state."""
+    key = signature(solvers)
+    db = {}
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+    if use_cache and key in db:
+        best = db[key]
+        ctx.set_tuning(best["blocks_per_cu"], best["zseg"], 1)
+        return dict(best, cached=True)
+    trials: List[dict] = []
+    for bpc, zseg in candidates:
+        ctx.set_tuning(bpc, zseg, 1)
+        ms = _time_steps(ctx, solvers, steps)
+        trials.append({"blocks_per_cu": bpc, "zseg": zseg, "ms_per_step": ms})
+    best = min(trials, key=lambda t: t["ms_per_step"])
+    ctx.set_tuning(best["blocks_per_cu"], best["zseg"], 1)
+    out = dict(best, trials=trials, signature=key, when=time.strftime("%Y-%m-%dT%H:%M:%S"))
+    if cache:
+        db[key] = {"blocks_per_cu": best["blocks_per_cu"], "zseg": best["zseg"], "ms_per_step": best["ms_per_step"]}
+        try:
+            with open(cache, "w") as f:
+                json.dump(db, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return dict(out, cached=False)

@@ -62,7 +62,7 @@ struct StepSet {
   int form = 0;
   int nboxes = 0;
   BoxRec* boxes = nullptr;
-  Chunk* chunks[kNumRegions] = {};
+  March* units[kNumRegions] = {};
   int nch[kNumRegions] = {};
   std::vector<int> box_beg[kNumRegions], box_cnt[kNumRegions];
   FillTag* ftags = nullptr;
@@ -105,7 +105,9 @@ struct ctuppm_ctx {
   double acc_ms[kNumStages] = {};
   long long acc_n[kNumStages] = {};
   int num_cus = 256;
-  int blocks_per_cu = 8;
+  int blocks_per_cu = 0;  // 0: one block per work unit
+  int zseg_batched = 1;   // planes per march unit, batched / graph forms
+  int zseg_per_box = 1;   // planes per march unit, per-box form
 };
 
 namespace {
@@ -168,6 +170,18 @@ void chunk_region(std::vector<Chunk>& out, int box, long long items) {
   for (long long s = 0; s < items; s += kBlock) out.push_back(Chunk{box, int(s)});
 }
 
+// March units of one box region: z segments of `zseg` planes, each cut into
+// 256-item pieces of the (x, y) plane; ordered (segment, piece) so adjacent
+// units are y neighbours.
+void march_region(std::vector<March>& out, int box, const int org[3], const int ext[3], int zseg) {
+  const long long plane = (long long)ext[0] * ext[1];
+  for (int z0 = 0; z0 < ext[2]; z0 += zseg) {
+    const int z1 = std::min(ext[2], z0 + zseg);
+    for (long long s = 0; s < plane; s += kBlock)
+      out.push_back(March{box, int(s), org[2] + z0, org[2] + z1});
+  }
+}
+
 int grid_for(const ctuppm_ctx* c, int nchunks, bool persistent) {
   int g = (nchunks + 7) / 8 * 8;
   if (persistent && c->blocks_per_cu > 0) g = std::min(g, c->blocks_per_cu * c->num_cus);
@@ -185,11 +199,11 @@ hipEvent_t take_event(ctuppm_ctx* c) {
   return e;
 }
 
-// Launch one stage over a chunk range (or a fill/bc tag range) with optional timing.
+// Launch one stage over a work range (march units, or fill/bc tag chunks) with optional timing.
 int run_stage(ctuppm_ctx* c, hipStream_t s, int stage, const BoxRec* boxes, const void* tags,
-              const Chunk* chunks, int nchunks, bool persistent, bool timed) {
-  if (nchunks <= 0) return CTUPPM_OK;
-  Launch L{boxes, tags, chunks, nchunks, grid_for(c, nchunks, persistent), s};
+              const void* work, int nwork, bool persistent, bool timed) {
+  if (nwork <= 0) return CTUPPM_OK;
+  Launch L{boxes, tags, work, nwork, grid_for(c, nwork, persistent), s};
   hipEvent_t a = nullptr, b = nullptr;
   if (timed) {
     a = take_event(c);
@@ -218,7 +232,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   S->pids = pids;
   S->form = key.second;
   std::vector<BoxRec> boxes;
-  std::vector<Chunk> ch[kNumRegions];
+  std::vector<March> ch[kNumRegions];
   std::vector<FillTag> ftags;
   std::vector<Chunk> fch;
   std::vector<BcTag> btags[3];
@@ -342,7 +356,9 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   }
   S->nboxes = int(boxes.size());
   S->nprobs = int(probs.size());
-  // chunk lists per region, per box in order
+  // march units per region, per box in order; per-box launches use short z
+  // segments so one box still fills the GPU
+  const int zseg = S->form == CTUPPM_FORM_PER_BOX ? c->zseg_per_box : c->zseg_batched;
   for (int k = 0; k < kNumRegions; ++k) {
     S->box_beg[k].resize(S->nboxes);
     S->box_cnt[k].resize(S->nboxes);
@@ -350,7 +366,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
       int org[3], ext[3];
       region_of(k, boxes[b].n, org, ext);
       S->box_beg[k][b] = int(ch[k].size());
-      chunk_region(ch[k], b, (long long)ext[0] * ext[1] * ext[2]);
+      march_region(ch[k], b, org, ext, zseg);
       S->box_cnt[k][b] = int(ch[k].size()) - S->box_beg[k][b];
     }
     S->nch[k] = int(ch[k].size());
@@ -383,8 +399,8 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   HIPCHK(c, S->mem.upload(boxes.data(), boxes.size() * sizeof(BoxRec), &p));
   S->boxes = (BoxRec*)p;
   for (int k = 0; k < kNumRegions; ++k) {
-    HIPCHK(c, S->mem.upload(ch[k].data(), ch[k].size() * sizeof(Chunk), &p));
-    S->chunks[k] = (Chunk*)p;
+    HIPCHK(c, S->mem.upload(ch[k].data(), ch[k].size() * sizeof(March), &p));
+    S->units[k] = (March*)p;
   }
   HIPCHK(c, S->mem.upload(ftags.data(), ftags.size() * sizeof(FillTag), &p));
   S->ftags = (FillTag*)p;
@@ -403,10 +419,15 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   return CTUPPM_OK;
 }
 
-const int kCellStages[] = {kStC2P, kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
+const int kCellStages[] = {kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
                            kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate};
-const int kCellRegion[] = {kGrown, kCells1, kCells1, kCells1, kCells1, kFace0, kFace1, kFace2,
-                           kFace0, kFace1, kFace2, kFin0, kFin1, kFin2, kValid};
+
+int run_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int box, bool timed) {
+  const int k = stage_region(stage);
+  if (box < 0) return run_stage(c, s, stage, S->boxes, nullptr, S->units[k], S->nch[k], true, timed);
+  return run_stage(c, s, stage, S->boxes, nullptr, S->units[k] + S->box_beg[k][box], S->box_cnt[k][box], false,
+                   timed);
+}
 
 // Enqueue one step of a set on stream s.
 int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
@@ -422,14 +443,12 @@ int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
                             S->bbox_cnt[d][b], false, timed)))
           return rc;
     for (int b = 0; b < S->nboxes; ++b)
-      if ((rc = run_stage(c, s, kStCfl, S->boxes, nullptr, S->chunks[kValid] + S->box_beg[kValid][b],
-                          S->box_cnt[kValid][b], false, timed)))
-        return rc;
+      if ((rc = run_cells(c, S, s, kStCfl, b, timed))) return rc;
   } else {
     if ((rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks, S->nfch, true, timed))) return rc;
     for (int d = 0; d < 3; ++d)
       if ((rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d], S->nbch[d], true, timed))) return rc;
-    if ((rc = run_stage(c, s, kStCfl, S->boxes, nullptr, S->chunks[kValid], S->nch[kValid], true, timed))) return rc;
+    if ((rc = run_cells(c, S, s, kStC2P, -1, timed))) return rc;
   }
   {
     hipError_t e = launch_dt(S->probs, S->nprobs, s);
@@ -437,18 +456,14 @@ int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
   }
   const int nst = int(sizeof(kCellStages) / sizeof(int));
   if (per_box) {
-    for (int b = 0; b < S->nboxes; ++b)
-      for (int q = 0; q < nst; ++q) {
-        const int k = kCellRegion[q];
-        if ((rc = run_stage(c, s, kCellStages[q], S->boxes, nullptr, S->chunks[k] + S->box_beg[k][b],
-                            S->box_cnt[k][b], false, timed)))
-          return rc;
-      }
-  } else {
-    for (int q = 0; q < nst; ++q) {
-      const int k = kCellRegion[q];
-      if ((rc = run_stage(c, s, kCellStages[q], S->boxes, nullptr, S->chunks[k], S->nch[k], true, timed))) return rc;
+    for (int b = 0; b < S->nboxes; ++b) {
+      if ((rc = run_cells(c, S, s, kStC2POnly, b, timed))) return rc;
+      for (int q = 0; q < nst; ++q)
+        if ((rc = run_cells(c, S, s, kCellStages[q], b, timed))) return rc;
     }
+  } else {
+    for (int q = 0; q < nst; ++q)
+      if ((rc = run_cells(c, S, s, kCellStages[q], -1, timed))) return rc;
   }
   hipError_t e = launch_flip(S->probs, S->nprobs, s);
   if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "flip launch: %s", hipGetErrorString(e));
@@ -533,9 +548,12 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
     level_domain(*prm, l, dlo, dhi);
     for (int b = 0; b < nboxes[l]; ++b) {
       const ctuppm_box& B = boxes[l][b];
-      for (int d = 0; d < 3; ++d)
+      for (int d = 0; d < 3; ++d) {
         if (B.lo[d] > B.hi[d] || B.lo[d] < dlo[d] || B.hi[d] > dhi[d])
           return fail(c, CTUPPM_EINVAL, "level %d box %d outside the domain or empty", l, b);
+        if (B.hi[d] - B.lo[d] + 1 > 256)
+          return fail(c, CTUPPM_EINVAL, "level %d box %d: edges above 256 cells are not supported", l, b);
+      }
       for (int o = 0; o < b; ++o)
         if (overlap(B, boxes[l][o])) return fail(c, CTUPPM_EINVAL, "level %d boxes %d and %d overlap", l, o, b);
       P->lev[l].boxes.push_back(B);
@@ -740,20 +758,13 @@ int ctuppm_stage_times(ctuppm_ctx* c, double* ms, long long* launches, int n) {
 int ctuppm_num_stages(void) { return kNumStages; }
 const char* ctuppm_stage_name(int s) { return stage_name(s); }
 
-int ctuppm_set_blocks_per_cu(ctuppm_ctx* c, int bpc) {
-  if (!c || bpc < 0) return CTUPPM_EINVAL;
+int ctuppm_set_tuning(ctuppm_ctx* c, int bpc, int zb, int zp) {
+  if (!c || bpc < 0 || zb < 1 || zp < 1) return CTUPPM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->blocks_per_cu = bpc;
-  for (auto& kv : c->sets) {
-    StepSet* S = kv.second.get();
-    if (S->exec) {
-      (void)hipGraphExecDestroy(S->exec);
-      S->exec = nullptr;
-    }
-    if (S->graph) {
-      (void)hipGraphDestroy(S->graph);
-      S->graph = nullptr;
-    }
-  }
+  c->zseg_batched = zb;
+  c->zseg_per_box = zp;
+  c->sets.clear();  // work lists and graphs depend on the tuning
   return CTUPPM_OK;
 }
 
@@ -774,11 +785,13 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
     auto half = [&](int a, int b) { return face(a) / (nn[b] + 2) * nn[b]; };         // F^{a|b} region
     switch (stage) {
       case kStFill: tot += 2 * 5 * W * (grown - valid); break;
+      case kStC2P: case kStC2POnly: tot += (5 + 6) * W * grown; break;
       case kStCfl: tot += 5 * W * valid; break;
-      case kStC2P: tot += (5 + 6) * W * grown; break;
       case kStFlatten: tot += 4 * W * cells1 + W * cells1; break;
       case kStTraceX: case kStTraceY: case kStTraceZ: {
         const int d = stage - kStTraceX;
+        // q over cells -3..n+2 along d (the 5-cell stencils of cells -1..n), phi,
+        // then the left and right states of faces 0..n
         tot += 6 * W * cells1 / (nn[d] + 2) * (nn[d] + 6) + W * cells1 + 2 * 5 * W * face(d);
         break;
       }

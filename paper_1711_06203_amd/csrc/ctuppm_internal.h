@@ -10,6 +10,7 @@ namespace ctu {
 constexpr int kNV = 5;     // rho, rho u, rho v, rho w, rho E
 constexpr int kNG = 4;     // ghost layers
 constexpr int kBlock = 256;  // threads per block = items per chunk
+constexpr int kSlots = 64;   // signal-speed max accumulators per problem (spread atomics)
 
 // Work regions of a box (n valid cells per direction), as (origin, extent):
 //   kValid  cells [0, n)            kGrown cells [-4, n+4)   kCells1 cells [-1, n]
@@ -39,13 +40,14 @@ struct ProbDev {
   double dx[3], rdx[3];
   double fixed_dt;                 // > 0: use this dt instead of the CFL one
   double dt;                       // dt of the current/last step
-  unsigned long long smax_bits;    // running max of the signal speed (bit pattern, >= 0)
-  unsigned long long smax_fine_bits;  // fine-level signal speed (two-level problems)
   unsigned long long cnt[5];       // dens floor, pres floor, traced floors, transverse fall-backs, failures
   int cur;                         // which of U[0], U[1] holds the current state
   int nsteps;
   int nlevels;
   int pad;
+  // running max of the signal speed as bit patterns (>= 0), one 128-byte
+  // line per slot so blocks of one launch do not contend on one address
+  unsigned long long smax[kSlots][16];
 };
 
 // One box of a step set.
@@ -59,7 +61,11 @@ struct BoxRec {
   int pad;
 };
 
-struct Chunk { int box; int start; };  // box (or tag) index, first item
+struct Chunk { int box; int start; };  // tag index, first item (ghost-fill work lists)
+
+// Column-march work unit: items [start, start+256) of the (x, y) plane of a
+// box region, for the box-local planes z in [z0, z1), visited in order.
+struct March { int box; int start; int z0; int z1; };
 
 // Same-level ghost copy: dst-local cells [lo, lo+ext) <- src-local (cell + off).
 struct FillTag { int dst, src; int lo[3]; int ext[3]; int off[3]; int pad; };
@@ -80,16 +86,34 @@ __host__ __device__ inline long long scratch_doubles(const int n[3]) {
 
 // ---------------------------------------------------------------- launchers
 enum Stage : int {
-  kStFill = 0, kStBcX, kStBcY, kStBcZ, kStCfl, kStDt, kStC2P, kStFlatten,
-  kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
-  kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate, kStFlip, kNumStages
+  kStFill = 0, kStBcX, kStBcY, kStBcZ, kStC2P, kStCfl, kStC2POnly, kStDt, kStFlatten,
+  kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ, kStT1X, kStT1Y, kStT1Z,
+  kStT2X, kStT2Y, kStT2Z, kStUpdate, kStFlip, kNumStages
 };
+
+// Region each march stage runs over.
+__host__ __device__ inline int stage_region(int stage) {
+  switch (stage) {
+    case kStC2P: case kStC2POnly: return kGrown;
+    case kStCfl: return kValid;
+    case kStFlatten: return kCells1;
+    case kStTraceX: case kStTraceY: case kStTraceZ: return kCells1;
+    case kStRiemX: case kStT1X: return kFace0;
+    case kStRiemY: case kStT1Y: return kFace1;
+    case kStRiemZ: case kStT1Z: return kFace2;
+    case kStT2X: return kFin0;
+    case kStT2Y: return kFin1;
+    case kStT2Z: return kFin2;
+    case kStUpdate: return kValid;
+    default: return -1;
+  }
+}
 
 struct Launch {
   const BoxRec* boxes;
   const void* tags;    // FillTag / BcTag for fill stages
-  const Chunk* chunks;
-  int nchunks;
+  const void* work;    // Chunk list (fill stages) or March list (cell stages)
+  int nwork;
   int grid;            // blocks (multiple of 8)
   hipStream_t stream;
 };

@@ -1,14 +1,17 @@
 // gfx950 kernels of the unsplit CTU/PPM advance, one kernel per stage.
 //
-// Work decomposition: every stage runs over a list of chunks; a chunk is 256
-// consecutive items (cells or faces, i fastest) of one box's region for that
-// stage, so consecutive lanes touch consecutive doubles of every SoA array.
-// The same kernels serve the per-box form (one launch per box over that box's
-// chunks) and the batched form (one persistent launch over the chunks of all
-// boxes of all problems in a step).  Blocks walk their chunks with an
+// Work decomposition: the cell and face stages run over "march" units: 256
+// consecutive items (cells or faces, i fastest) of one (x, y) plane of a box's
+// region, visited for a run of consecutive z planes.  Lanes touch consecutive
+// doubles of every SoA array, and a z neighbour a stencil reads was read by
+// the same block one or two planes earlier, so it comes from cache rather than
+// HBM.  The same kernels serve the per-box form (one launch per box over that
+// box's units) and the batched form (one persistent launch over the units of
+// all boxes of all problems in a step).  Blocks walk their units with an
 // XCD-aware mapping: workgroups are dispatched round-robin over the 8 XCDs, so
-// block b runs on XCD b%8 and takes a contiguous eighth of the chunk list,
-// which keeps the y/z stencil neighbours of a chunk in the same XCD's L2.
+// block b runs on XCD b%8 and takes a contiguous eighth of the unit list, which
+// keeps the y neighbours of a unit (the adjacent units) in the same XCD's L2.
+// Ghost fills run over 256-item chunks of their copy tags.
 #include <hip/hip_runtime.h>
 
 #include "ctuppm_internal.h"
@@ -26,6 +29,20 @@ CTU_DEV void for_each_chunk(int nchunks, F&& f) {
   const int beg = xcd * span;
   const int end = beg + span < nchunks ? beg + span : nchunks;
   for (int c = beg + local; c < end; c += per) f(c);
+}
+
+// Visit the (i, j, k) items of a march unit in region `kind`; f(i, j, k) is
+// called for the lane's (i, j) at every plane of the unit.  Lanes past the
+// plane's end skip all planes (no barrier inside f).
+template <class F>
+CTU_DEV void march(int kind, const BoxRec& B, const March& M, F&& f) {
+  int org[3], ext[3];
+  region_of(kind, B.n, org, ext);
+  const int t = M.start + threadIdx.x;
+  if (t >= ext[0] * ext[1]) return;
+  const int i = t % ext[0] + org[0];
+  const int j = t / ext[0] + org[1];
+  for (int k = M.z0; k < M.z1; ++k) f(i, j, k);
 }
 
 // Geometry of one box: grown arrays (ghosts -4..n+3) and halo-1 arrays (-1..n).
@@ -53,18 +70,6 @@ struct Geo {
   CTU_DEV double* f1(double* s, int p) const { return s + 6 * gcomp + (46 + 5 * p) * hcomp; }
   CTU_DEV double* ff(double* s, int d) const { return s + 6 * gcomp + (76 + 5 * d) * hcomp; }
 };
-
-// Decode item t of a region into box-local (i, j, k); false past the end.
-CTU_DEV bool decode(int kind, const int n[3], int t, int& i, int& j, int& k) {
-  int org[3], ext[3];
-  region_of(kind, n, org, ext);
-  if (t >= ext[0] * ext[1] * ext[2]) return false;
-  i = t % ext[0] + org[0];
-  const int r = t / ext[0];
-  j = r % ext[1] + org[1];
-  k = r / ext[1] + org[2];
-  return true;
-}
 
 CTU_DEV void count(unsigned long long* c, unsigned long long v) {
   if (v) atomicAdd(c, v);
@@ -138,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
   });
 }
 
-// ------------------------------------------------------------------- CFL / dt
+// ------------------------------------------------------- cons -> prim + CFL
 
 CTU_DEV double block_max(double v, double* lds) {
   for (int off = 32; off > 0; off >>= 1) v = dmax(v, __shfl_xor(v, off, 64));
@@ -151,55 +156,82 @@ CTU_DEV double block_max(double v, double* lds) {
   return r;
 }
 
-// Largest (|u_d| + c) / dx_d over valid cells, per problem, as a 64-bit
-// atomic max on the bit pattern (non-negative doubles order like integers).
-__global__ __launch_bounds__(kBlock) void k_cfl(const BoxRec* __restrict__ boxes, const Chunk* __restrict__ chunks,
-                                                int nchunks) {
+CTU_DEV void flush_max(ProbDev* P, double m, double* lds) {
+  const double bm = block_max(m, lds);
+  if (threadIdx.x == 0) atomicMax(&P->smax[blockIdx.x % kSlots][0], (unsigned long long)__double_as_longlong(bm));
+}
+
+// Primitive state (rho, u, v, w, p, c) with floors (WQ: stored for every
+// grown cell) and the signal speed max_d (|u_d| + c) / dx_d of the valid
+// cells (CFL: reduced per problem by wave shuffles, LDS and a 64-bit atomic
+// max on the bit pattern; non-negative doubles order like unsigned integers,
+// so the max is exact and order-free).  The batched forms do both in one pass;
+// the per-box form, whose boxes share one scratch, reduces first (CFL only)
+// and stores q box by box after dt is known.
+template <bool WQ, bool CFL>
+__global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
+                                                int nunits) {
   __shared__ double lds[kBlock / 64];
-  double m = 0.0;
+  double smax = 0.0;
   ProbDev* curP = nullptr;
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
     ProbDev* P = B.P;
-    if (P != curP) {
-      if (curP) {
-        const double bm = block_max(m, lds);
-        if (threadIdx.x == 0) atomicMax(&curP->smax_bits, (unsigned long long)__double_as_longlong(bm));
-      }
-      m = 0.0;
+    if (P != curP) {  // block-uniform: flush the running max of the previous problem
+      if (CFL && curP) flush_max(curP, smax, lds);
+      smax = 0.0;
       curP = P;
     }
-    int i, j, k;
-    if (!decode(kValid, B.n, ch.start + threadIdx.x, i, j, k)) return;
     const Geo g(B.n);
     const double* __restrict__ U = B.U[P->cur];
-    const int o = g.g(i, j, k);
-    double rho = U[o];
-    if (rho < P->small_dens) rho = P->small_dens;
-    const double u = U[g.gcomp + o] / rho, v = U[2 * g.gcomp + o] / rho, w = U[3 * g.gcomp + o] / rho;
-    const double ke = 0.5 * rho * ((u * u + v * v) + w * w);
-    double p = P->gm1 * (U[4 * g.gcomp + o] - ke);
-    if (p < P->small_pres) p = P->small_pres;
-    const double cs = sqrt(P->gamma * p / rho);
-    const double sx = (fabs(u) + cs) * P->rdx[0];
-    const double sy = (fabs(v) + cs) * P->rdx[1];
-    const double sz = (fabs(w) + cs) * P->rdx[2];
-    m = dmax(m, dmax(sx, dmax(sy, sz)));
+    double* __restrict__ q = g.q(B.scr);
+    const double gamma = P->gamma, gm1 = P->gm1, sd = P->small_dens, sp = P->small_pres;
+    const double rdx = P->rdx[0], rdy = P->rdx[1], rdz = P->rdx[2];
+    unsigned long long hd = 0, hp = 0;
+    march(WQ ? kGrown : kValid, B, M, [&](int i, int j, int k) {
+      const int o = g.g(i, j, k);
+      double rho = U[o];
+      if (rho < sd) { rho = sd; ++hd; }
+      const double u = U[g.gcomp + o] / rho, v = U[2 * g.gcomp + o] / rho, w = U[3 * g.gcomp + o] / rho;
+      const double ke = 0.5 * rho * ((u * u + v * v) + w * w);
+      double p = gm1 * (U[4 * g.gcomp + o] - ke);
+      if (p < sp) { p = sp; ++hp; }
+      const double cs = sqrt(gamma * p / rho);
+      if (WQ) {
+        q[o] = rho;
+        q[g.gcomp + o] = u;
+        q[2 * g.gcomp + o] = v;
+        q[3 * g.gcomp + o] = w;
+        q[4 * g.gcomp + o] = p;
+        q[5 * g.gcomp + o] = cs;
+      }
+      if (CFL && i >= 0 && i < B.n[0] && j >= 0 && j < B.n[1] && k >= 0 && k < B.n[2]) {
+        const double sx = (fabs(u) + cs) * rdx;
+        const double sy = (fabs(v) + cs) * rdy;
+        const double sz = (fabs(w) + cs) * rdz;
+        smax = dmax(smax, dmax(sx, dmax(sy, sz)));
+      }
+    });
+    if (WQ) {
+      count(&P->cnt[0], hd);
+      count(&P->cnt[1], hp);
+    }
   });
-  if (curP) {
-    const double bm = block_max(m, lds);
-    if (threadIdx.x == 0) atomicMax(&curP->smax_bits, (unsigned long long)__double_as_longlong(bm));
-  }
+  if (CFL && curP) flush_max(curP, smax, lds);
 }
 
 __global__ void k_dt(ProbDev* const* probs, int nprobs) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nprobs) return;
   ProbDev* P = probs[t];
-  const double s = __longlong_as_double((long long)P->smax_bits);
+  unsigned long long bits = 0ull;
+  for (int q = 0; q < kSlots; ++q) {
+    bits = P->smax[q][0] > bits ? P->smax[q][0] : bits;
+    P->smax[q][0] = 0ull;
+  }
+  const double s = __longlong_as_double((long long)bits);
   P->dt = P->fixed_dt > 0.0 ? P->fixed_dt : P->cfl / s;
-  P->smax_bits = 0ull;
 }
 
 __global__ void k_flip(ProbDev* const* probs, int nprobs) {
@@ -208,38 +240,6 @@ __global__ void k_flip(ProbDev* const* probs, int nprobs) {
   ProbDev* P = probs[t];
   P->cur ^= 1;
   P->nsteps += 1;
-}
-
-// ------------------------------------------------------------- cons -> prim
-
-__global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes, const Chunk* __restrict__ chunks,
-                                                int nchunks) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
-    int i, j, k;
-    if (!decode(kGrown, B.n, ch.start + threadIdx.x, i, j, k)) return;
-    const ProbDev* P = B.P;
-    const Geo g(B.n);
-    const double* __restrict__ U = B.U[P->cur];
-    double* __restrict__ q = g.q(B.scr);
-    const int o = g.g(i, j, k);
-    double rho = U[o];
-    unsigned long long hd = 0, hp = 0;
-    if (rho < P->small_dens) { rho = P->small_dens; hd = 1; }
-    const double u = U[g.gcomp + o] / rho, v = U[2 * g.gcomp + o] / rho, w = U[3 * g.gcomp + o] / rho;
-    const double ke = 0.5 * rho * ((u * u + v * v) + w * w);
-    double p = P->gm1 * (U[4 * g.gcomp + o] - ke);
-    if (p < P->small_pres) { p = P->small_pres; hp = 1; }
-    q[o] = rho;
-    q[g.gcomp + o] = u;
-    q[2 * g.gcomp + o] = v;
-    q[3 * g.gcomp + o] = w;
-    q[4 * g.gcomp + o] = p;
-    q[5 * g.gcomp + o] = sqrt(P->gamma * p / rho);
-    count(&B.P->cnt[0], hd);
-    count(&B.P->cnt[1], hp);
-  });
 }
 
 // ---------------------------------------------------------------- flattening
@@ -255,83 +255,32 @@ CTU_DEV double shock_ind(const double* __restrict__ p, const double* __restrict_
 }
 
 __global__ __launch_bounds__(kBlock) void k_flatten(const BoxRec* __restrict__ boxes,
-                                                    const Chunk* __restrict__ chunks, int nchunks) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
-    int i, j, k;
-    if (!decode(kCells1, B.n, ch.start + threadIdx.x, i, j, k)) return;
+                                                    const March* __restrict__ units, int nunits) {
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
     const Geo g(B.n);
     const double* __restrict__ q = g.q(B.scr);
     const double* __restrict__ p = q + 4 * g.gcomp;
-    const int o = g.g(i, j, k);
-    double phi = 1.0;
+    double* __restrict__ phiout = g.phi(B.scr);
+    march(kCells1, B, M, [&](int i, int j, int k) {
+      const int o = g.g(i, j, k);
+      double phi = 1.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int st = g.gstride(d);
-      const double* __restrict__ un = q + (1 + d) * g.gcomp;
-      const int s = (p[o + st] - p[o - st]) > 0.0 ? 1 : -1;
-      const double fd = dmax(shock_ind(p, un, o, st), shock_ind(p, un, o - s * st, st));
-      const double v = 1.0 - fd;
-      phi = d == 0 ? v : dmin(phi, v);
-    }
-    g.phi(B.scr)[g.h(i, j, k)] = phi;
+      for (int d = 0; d < 3; ++d) {
+        const int st = g.gstride(d);
+        const double* __restrict__ un = q + (1 + d) * g.gcomp;
+        const int s = (p[o + st] - p[o - st]) > 0.0 ? 1 : -1;
+        const double fd = dmax(shock_ind(p, un, o, st), shock_ind(p, un, o - s * st, st));
+        const double v = 1.0 - fd;
+        phi = d == 0 ? v : dmin(phi, v);
+      }
+      phiout[g.h(i, j, k)] = phi;
+    });
   });
 }
 
 // ------------------------------------------------------ PPM + tracing along D
-
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ boxes, const Chunk* __restrict__ chunks,
-                                                  int nchunks) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
-    int x[3];
-    if (!decode(kCells1, B.n, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
-    const ProbDev* P = B.P;
-    const Geo g(B.n);
-    const double* __restrict__ q = g.q(B.scr);
-    const int o = g.g(x[0], x[1], x[2]);
-    const int st = g.gstride(D);
-    const int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
-    const double phi = g.phi(B.scr)[g.h(x[0], x[1], x[2])];
-    Parab par[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const double* a = q + comp[m] * g.gcomp + o;
-      par[m] = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-    }
-    const double dtdx = P->dt / P->dx[D];
-    double up[5], dn[5];
-    trace_cell(par, q[o], q[(1 + D) * g.gcomp + o], q[5 * g.gcomp + o], dtdx, up, dn);
-    const bool keep_up = x[D] <= B.n[D] - 1, keep_dn = x[D] >= 0;
-    const double hdtg = 0.5 * P->dt * P->grav_z;
-    constexpr int zpos = 1 + (2 - D + 3) % 3;
-    unsigned long long floors = 0;
-    const int oh = g.h(x[0], x[1], x[2]);
-    if (keep_up) {
-      if (up[0] < P->small_dens) { up[0] = P->small_dens; ++floors; }
-      if (up[4] < P->small_pres) { up[4] = P->small_pres; ++floors; }
-      if (P->grav_z != 0.0) up[zpos] = up[zpos] + hdtg;
-      double* __restrict__ ql = g.ql(B.scr, D);
-      const int f = oh + g.hstride(D);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) ql[m * g.hcomp + f] = up[m];
-    }
-    if (keep_dn) {
-      if (dn[0] < P->small_dens) { dn[0] = P->small_dens; ++floors; }
-      if (dn[4] < P->small_pres) { dn[4] = P->small_pres; ++floors; }
-      if (P->grav_z != 0.0) dn[zpos] = dn[zpos] + hdtg;
-      double* __restrict__ qr = g.qr(B.scr, D);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
-    }
-    count(&B.P->cnt[2], floors);
-  });
-}
-
-// ------------------------------------------------------------ Riemann fluxes
 
 template <int D>
 CTU_DEV void store_flux(double* __restrict__ F, int hcomp, int o, const double f[5]) {
@@ -342,27 +291,88 @@ CTU_DEV void store_flux(double* __restrict__ F, int hcomp, int o, const double f
   F[4 * hcomp + o] = f[4];
 }
 
+// One thread per cell of -1..n: parabolas of the five permuted primitives,
+// tracing to both faces along D, floors and the gravity predictor; the left
+// state of the upper face and the right state of the lower face are stored
+// for faces 0..n.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ boxes,
-                                                    const Chunk* __restrict__ chunks, int nchunks) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
-    int i, j, k;
-    if (!decode(kFace0 + D, B.n, ch.start + threadIdx.x, i, j, k)) return;
+__global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
+                                                  int nunits) {
+  constexpr int zpos = 1 + (2 - D + 3) % 3;  // permuted slot of the z velocity
+  constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n);
-    const int o = g.h(i, j, k);
+    const double* __restrict__ q = g.q(B.scr);
+    const double* __restrict__ phiv = g.phi(B.scr);
+    double* __restrict__ ql = g.ql(B.scr, D);
+    double* __restrict__ qr = g.qr(B.scr, D);
+    const int st = g.gstride(D), sth = g.hstride(D);
+    const double dtdx = P->dt / P->dx[D];
+    const double hdtg = 0.5 * P->dt * P->grav_z;
+    const bool grav = P->grav_z != 0.0;
+    const double sd = P->small_dens, sp = P->small_pres;
+    const int nD = B.n[D];
+    unsigned long long floors = 0;
+    march(kCells1, B, M, [&](int i, int j, int k) {
+      const int x[3] = {i, j, k};
+      const int o = g.g(i, j, k), oh = g.h(i, j, k);
+      const double phi = phiv[oh];
+      Parab par[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const double* a = q + comp[m] * g.gcomp + o;
+        par[m] = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+      }
+      const double rho = q[o], un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
+      if (x[D] <= nD - 1) {
+        double up[5];
+        trace_up(par, rho, un, cs, dtdx, up);
+        if (up[0] < sd) { up[0] = sd; ++floors; }
+        if (up[4] < sp) { up[4] = sp; ++floors; }
+        if (grav) up[zpos] = up[zpos] + hdtg;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
+      }
+      if (x[D] >= 0) {
+        double dn[5];
+        trace_dn(par, rho, un, cs, dtdx, dn);
+        if (dn[0] < sd) { dn[0] = sd; ++floors; }
+        if (dn[4] < sp) { dn[4] = sp; ++floors; }
+        if (grav) dn[zpos] = dn[zpos] + hdtg;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
+      }
+    });
+    count(&B.P->cnt[2], floors);
+  });
+}
+
+// Normal HLLC flux of every face 0..n along D (cells -1..n across).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ boxes,
+                                                    const March* __restrict__ units, int nunits) {
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
+    const ProbDev* P = B.P;
+    const Geo g(B.n);
     const double* __restrict__ ql = g.ql(B.scr, D);
     const double* __restrict__ qr = g.qr(B.scr, D);
-    double L[5], R[5], f[5];
+    double* __restrict__ fn = g.fn(B.scr, D);
+    march(kFace0 + D, B, M, [&](int i, int j, int k) {
+      const int o = g.h(i, j, k);
+      double L[5], R[5], f[5];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      L[m] = ql[m * g.hcomp + o];
-      R[m] = qr[m * g.hcomp + o];
-    }
-    hllc(L, R, P->gamma, P->rgm1, f);
-    store_flux<D>(g.fn(B.scr, D), g.hcomp, o, f);
+      for (int m = 0; m < 5; ++m) {
+        L[m] = ql[m * g.hcomp + o];
+        R[m] = qr[m * g.hcomp + o];
+      }
+      hllc(L, R, P->gamma, P->rgm1, f);
+      store_flux<D>(fn, g.hcomp, o, f);
+    });
   });
 }
 
@@ -400,116 +410,128 @@ CTU_DEV int to_prim_or_keep(const double U[5], const double s0[5], double gm1, d
 // directions, then HLLC -> F^{A|B}.
 template <int A>
 __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ boxes,
-                                                   const Chunk* __restrict__ chunks, int nchunks) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
-    int x[3];
-    if (!decode(kFace0 + A, B.n, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
+                                                   const March* __restrict__ units, int nunits) {
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n);
-    const int o = g.h(x[0], x[1], x[2]);
     const int sa = g.hstride(A);
     const double* __restrict__ ql = g.ql(B.scr, A);
     const double* __restrict__ qr = g.qr(B.scr, A);
-    double sL[5], sR[5], UL[5], UR[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      sL[m] = ql[m * g.hcomp + o];
-      sR[m] = qr[m * g.hcomp + o];
-    }
-    to_cons<A>(sL, P->rgm1, UL);
-    to_cons<A>(sR, P->rgm1, UR);
-    const double dtdxA = P->dt / P->dx[A];
-    (void)dtdxA;
     unsigned long long fb = 0;
-#pragma unroll
-    for (int which = 0; which < 2; ++which) {
-      const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
-      const int Cd = which == 0 ? (A + 2) % 3 : (A + 1) % 3;
-      (void)Cd;
-      if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
-      const double c3 = (P->dt / P->dx[Bd]) / 3.0;
-      const int sb = g.hstride(Bd);
-      const double* __restrict__ Fb = g.fn(B.scr, Bd);
-      double VL[5], VR[5], tL[5], tR[5], f[5];
-      const int oL = o - sa, oR = o;  // owner cells of the left and right states
+    march(kFace0 + A, B, M, [&](int i, int j, int k) {
+      const int x[3] = {i, j, k};
+      const int o = g.h(i, j, k);
+      double sL[5], sR[5], UL[5], UR[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        const double* Fm = Fb + m * g.hcomp;
-        VL[m] = UL[m] - c3 * (Fm[oL + sb] - Fm[oL]);
-        VR[m] = UR[m] - c3 * (Fm[oR + sb] - Fm[oR]);
+        sL[m] = ql[m * g.hcomp + o];
+        sR[m] = qr[m * g.hcomp + o];
       }
-      fb += to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
-      fb += to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
-      hllc(tL, tR, P->gamma, P->rgm1, f);
-      store_flux<A>(g.f1(B.scr, 2 * A + which), g.hcomp, o, f);
-    }
+      to_cons<A>(sL, P->rgm1, UL);
+      to_cons<A>(sR, P->rgm1, UR);
+#pragma unroll
+      for (int which = 0; which < 2; ++which) {
+        const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
+        if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
+        const double c3 = (P->dt / P->dx[Bd]) / 3.0;
+        const int sb = g.hstride(Bd);
+        const double* __restrict__ Fb = g.fn(B.scr, Bd);
+        double VL[5], VR[5], tL[5], tR[5], f[5];
+        const int oL = o - sa, oR = o;  // owner cells of the left and right states
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          const double* Fm = Fb + m * g.hcomp;
+          VL[m] = UL[m] - c3 * (Fm[oL + sb] - Fm[oL]);
+          VR[m] = UR[m] - c3 * (Fm[oR + sb] - Fm[oR]);
+        }
+        fb += to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+        fb += to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+        hllc(tL, tR, P->gamma, P->rgm1, f);
+        store_flux<A>(g.f1(B.scr, 2 * A + which), g.hcomp, o, f);
+      }
+    });
     count(&B.P->cnt[3], fb);
   });
 }
 
-// Stage 2: face states along A corrected by dt/(2 dx_B) dF^{B|C} and
-// dt/(2 dx_C) dF^{C|B} with (B, C) the cyclic successors of A; final HLLC.
+// Stage 2 at one face along A: the face states corrected by dt/(2 dx_B)
+// dF^{B|C} and then dt/(2 dx_C) dF^{C|B}, with (B, C) the cyclic successors of
+// A, then the final HLLC flux (global component order).  fb counts states that
+// fell back to the uncorrected ones.
 template <int A>
-__global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ boxes,
-                                                   const Chunk* __restrict__ chunks, int nchunks) {
+CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, double F[5], int& fb) {
   constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
   // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
   constexpr int pbc = 2 * Bd + (Cd == (Bd + 1) % 3 ? 0 : 1);
   constexpr int pcb = 2 * Cd + (Bd == (Cd + 1) % 3 ? 0 : 1);
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
-    int x[3];
-    if (!decode(kFin0 + A, B.n, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
+  const int sa = g.hstride(A), sb = g.hstride(Bd), sc = g.hstride(Cd);
+  const double* __restrict__ ql = g.ql(B.scr, A);
+  const double* __restrict__ qr = g.qr(B.scr, A);
+  const double* __restrict__ Fbc = g.f1(B.scr, pbc);
+  const double* __restrict__ Fcb = g.f1(B.scr, pcb);
+  const double c2b = 0.5 * (P->dt / P->dx[Bd]);
+  const double c2c = 0.5 * (P->dt / P->dx[Cd]);
+  double sL[5], sR[5], UL[5], UR[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    sL[m] = ql[m * g.hcomp + o];
+    sR[m] = qr[m * g.hcomp + o];
+  }
+  to_cons<A>(sL, P->rgm1, UL);
+  to_cons<A>(sR, P->rgm1, UR);
+  const int oL = o - sa, oR = o;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const double* F1 = Fbc + m * g.hcomp;
+    const double* F2 = Fcb + m * g.hcomp;
+    UL[m] = UL[m] - c2b * (F1[oL + sb] - F1[oL]);
+    UR[m] = UR[m] - c2b * (F1[oR + sb] - F1[oR]);
+    UL[m] = UL[m] - c2c * (F2[oL + sc] - F2[oL]);
+    UR[m] = UR[m] - c2c * (F2[oR + sc] - F2[oR]);
+  }
+  double tL[5], tR[5], f[5];
+  fb += to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+  fb += to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+  hllc(tL, tR, P->gamma, P->rgm1, f);
+  F[0] = f[0];
+  F[1 + A] = f[1];
+  F[1 + (A + 1) % 3] = f[2];
+  F[1 + (A + 2) % 3] = f[3];
+  F[4] = f[4];
+}
+
+// Stage 2 along A over faces 0..n (cells 0..n-1 across): final fluxes.
+template <int A>
+__global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ boxes,
+                                                   const March* __restrict__ units, int nunits) {
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n);
-    const int o = g.h(x[0], x[1], x[2]);
-    const int sa = g.hstride(A), sb = g.hstride(Bd), sc = g.hstride(Cd);
-    const double* __restrict__ ql = g.ql(B.scr, A);
-    const double* __restrict__ qr = g.qr(B.scr, A);
-    const double* __restrict__ Fbc = g.f1(B.scr, pbc);
-    const double* __restrict__ Fcb = g.f1(B.scr, pcb);
-    const double c2b = 0.5 * (P->dt / P->dx[Bd]);
-    const double c2c = 0.5 * (P->dt / P->dx[Cd]);
-    double sL[5], sR[5], UL[5], UR[5];
+    double* __restrict__ ff = g.ff(B.scr, A);
+    int fb = 0;
+    march(kFin0 + A, B, M, [&](int i, int j, int k) {
+      const int o = g.h(i, j, k);
+      double F[5];
+      final_flux<A>(B, g, P, o, F, fb);
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      sL[m] = ql[m * g.hcomp + o];
-      sR[m] = qr[m * g.hcomp + o];
-    }
-    to_cons<A>(sL, P->rgm1, UL);
-    to_cons<A>(sR, P->rgm1, UR);
-    const int oL = o - sa, oR = o;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const double* F1 = Fbc + m * g.hcomp;
-      const double* F2 = Fcb + m * g.hcomp;
-      UL[m] = UL[m] - c2b * (F1[oL + sb] - F1[oL]);
-      UR[m] = UR[m] - c2b * (F1[oR + sb] - F1[oR]);
-      UL[m] = UL[m] - c2c * (F2[oL + sc] - F2[oL]);
-      UR[m] = UR[m] - c2c * (F2[oR + sc] - F2[oR]);
-    }
-    double tL[5], tR[5], f[5];
-    unsigned long long fb = 0;
-    fb += to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
-    fb += to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
-    hllc(tL, tR, P->gamma, P->rgm1, f);
-    store_flux<A>(g.ff(B.scr, A), g.hcomp, o, f);
-    count(&B.P->cnt[3], fb);
+      for (int m = 0; m < 5; ++m) ff[m * g.hcomp + o] = F[m];
+    });
+    count(&B.P->cnt[3], (unsigned long long)fb);
   });
 }
 
-// ---------------------------------------------------------------- update
-
+// Conservative update U^{n+1} = U^n + sum_d dt/dx_d (F_lo - F_hi) in the order
+// x, y, z, the trapezoid gravity corrector on rho w then rho E, and the
+// failure check (rho < small_dens, p < small_pres or a non-finite value).
 __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ boxes,
-                                                   const Chunk* __restrict__ chunks, int nchunks) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BoxRec& B = boxes[ch.box];
-    int i, j, k;
-    if (!decode(kValid, B.n, ch.start + threadIdx.x, i, j, k)) return;
+                                                   const March* __restrict__ units, int nunits) {
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n);
     const double* __restrict__ U = B.U[P->cur];
@@ -517,34 +539,39 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
     const double* __restrict__ Fx = g.ff(B.scr, 0);
     const double* __restrict__ Fy = g.ff(B.scr, 1);
     const double* __restrict__ Fz = g.ff(B.scr, 2);
-    const int o = g.h(i, j, k), og = g.g(i, j, k);
     const double dtdx = P->dt / P->dx[0], dtdy = P->dt / P->dx[1], dtdz = P->dt / P->dx[2];
-    double un[5];
+    const bool grav = P->grav_z != 0.0;
+    const double hdtg = 0.5 * P->dt * P->grav_z;
+    unsigned long long nbad = 0;
+    march(kValid, B, M, [&](int i, int j, int k) {
+      const int o = g.h(i, j, k), og = g.g(i, j, k);
+      double un[5];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const int mo = m * g.hcomp + o;
-      double du = dtdx * (Fx[mo] - Fx[mo + 1]);
-      du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
-      du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
-      un[m] = U[m * g.gcomp + og] + du;
-    }
-    if (P->grav_z != 0.0) {
-      const double hdtg = 0.5 * P->dt * P->grav_z;
-      un[3] = un[3] + hdtg * (U[og] + un[0]);
-      un[4] = un[4] + hdtg * (U[3 * g.gcomp + og] + un[3]);
-    }
-    bool bad = false;
+      for (int m = 0; m < 5; ++m) {
+        const int mo = m * g.hcomp + o;
+        double du = dtdx * (Fx[mo] - Fx[mo + 1]);
+        du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
+        du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
+        un[m] = U[m * g.gcomp + og] + du;
+      }
+      if (grav) {
+        un[3] = un[3] + hdtg * (U[og] + un[0]);
+        un[4] = un[4] + hdtg * (U[3 * g.gcomp + og] + un[3]);
+      }
+      bool bad = false;
 #pragma unroll
-    for (int m = 0; m < 5; ++m) bad = bad || !isfinite(un[m]);
-    if (un[0] < P->small_dens) bad = true;
-    if (!bad) {
-      const double u = un[1] / un[0], v = un[2] / un[0], w = un[3] / un[0];
-      const double ke = 0.5 * un[0] * ((u * u + v * v) + w * w);
-      if (P->gm1 * (un[4] - ke) < P->small_pres) bad = true;
-    }
+      for (int m = 0; m < 5; ++m) bad = bad || !isfinite(un[m]);
+      if (un[0] < P->small_dens) bad = true;
+      if (!bad) {
+        const double uu = un[1] / un[0], vv = un[2] / un[0], ww = un[3] / un[0];
+        const double ke = 0.5 * un[0] * ((uu * uu + vv * vv) + ww * ww);
+        if (P->gm1 * (un[4] - ke) < P->small_pres) bad = true;
+      }
 #pragma unroll
-    for (int m = 0; m < 5; ++m) Un[m * g.gcomp + og] = un[m];
-    count(&B.P->cnt[4], bad ? 1ull : 0ull);
+      for (int m = 0; m < 5; ++m) Un[m * g.gcomp + og] = un[m];
+      nbad += bad ? 1ull : 0ull;
+    });
+    count(&B.P->cnt[4], nbad);
   });
 }
 
@@ -554,36 +581,41 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
 
 const char* stage_name(int s) {
   static const char* names[kNumStages] = {
-      "fill", "bc_x", "bc_y", "bc_z", "cfl", "dt", "cons2prim", "flatten",
+      "fill", "bc_x", "bc_y", "bc_z", "cons2prim_cfl", "cfl", "cons2prim", "dt", "flatten",
       "trace_x", "trace_y", "trace_z", "riemann_x", "riemann_y", "riemann_z",
       "trans1_x", "trans1_y", "trans1_z", "trans2_x", "trans2_y", "trans2_z", "update", "flip"};
   return (s >= 0 && s < kNumStages) ? names[s] : "?";
 }
 
 hipError_t launch_stage(int stage, const Launch& L) {
-  if (L.nchunks <= 0) return hipSuccess;
+  if (L.nwork <= 0) return hipSuccess;
   const dim3 grid(L.grid), block(kBlock);
+  const Chunk* ch = (const Chunk*)L.work;
+  const March* mu = (const March*)L.work;
+  const int n = L.nwork;
+  hipStream_t s = L.stream;
   switch (stage) {
-    case kStFill: k_fill<<<grid, block, 0, L.stream>>>(L.boxes, (const FillTag*)L.tags, L.chunks, L.nchunks); break;
-    case kStBcX: k_bc<0><<<grid, block, 0, L.stream>>>(L.boxes, (const BcTag*)L.tags, L.chunks, L.nchunks); break;
-    case kStBcY: k_bc<1><<<grid, block, 0, L.stream>>>(L.boxes, (const BcTag*)L.tags, L.chunks, L.nchunks); break;
-    case kStBcZ: k_bc<2><<<grid, block, 0, L.stream>>>(L.boxes, (const BcTag*)L.tags, L.chunks, L.nchunks); break;
-    case kStCfl: k_cfl<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStC2P: k_c2p<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStFlatten: k_flatten<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStTraceX: k_trace<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStTraceY: k_trace<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStTraceZ: k_trace<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStRiemX: k_riemann<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStRiemY: k_riemann<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStRiemZ: k_riemann<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStT1X: k_trans1<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStT1Y: k_trans1<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStT1Z: k_trans1<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStT2X: k_trans2<0><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStT2Y: k_trans2<1><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStT2Z: k_trans2<2><<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
-    case kStUpdate: k_update<<<grid, block, 0, L.stream>>>(L.boxes, L.chunks, L.nchunks); break;
+    case kStFill: k_fill<<<grid, block, 0, s>>>(L.boxes, (const FillTag*)L.tags, ch, n); break;
+    case kStBcX: k_bc<0><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n); break;
+    case kStBcY: k_bc<1><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n); break;
+    case kStBcZ: k_bc<2><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n); break;
+    case kStC2P: k_c2p<true, true><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStCfl: k_c2p<false, true><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStC2POnly: k_c2p<true, false><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStFlatten: k_flatten<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStTraceX: k_trace<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStTraceY: k_trace<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStTraceZ: k_trace<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStRiemX: k_riemann<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStRiemY: k_riemann<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStRiemZ: k_riemann<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStT1X: k_trans1<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStT1Y: k_trans1<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStT1Z: k_trans1<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStT2X: k_trans2<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStT2Y: k_trans2<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStT2Z: k_trans2<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStUpdate: k_update<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -73,64 +73,65 @@ CTU_DEV double avg_left(const Parab& p, double sig) {
 
 // Reference-state tracing of one cell to the half time level.  par[m] are the
 // parabolas of the permuted primitives (rho, u_n, u_t1, u_t2, p); rho, un, c
-// the cell-centre values.  up: left state at the upper face; dn: right state
-// at the lower face.
-CTU_DEV void trace_cell(const Parab par[5], double rho, double un, double c, double dtdx,
-                        double up[5], double dn[5]) {
+// the cell-centre values.  trace_up gives the left state at the cell's upper
+// face (families with positive speed arrive; the reference is the u+c
+// family's average), trace_dn the right state at its lower face (negative
+// speeds; reference from the u-c family).
+CTU_DEV void trace_up(const Parab par[5], double rho, double un, double c, double dtdx, double up[5]) {
   const double lm = un - c, l0 = un, lp = un + c;
   const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, sp = fabs(lp) * dtdx;
   const double csq = c * c;
-  {
-    // upper face: families with positive speed arrive; reference = u+c family
-    double Im[5], I0[5], ref[5];
+  double Im[5], I0[5], ref[5];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      Im[m] = lm > 0.0 ? avg_right(par[m], sm) : par[m].aR;
-      I0[m] = l0 > 0.0 ? avg_right(par[m], s0) : par[m].aR;
-      ref[m] = lp > 0.0 ? avg_right(par[m], sp) : par[m].aR;
-    }
-    const double bm = -(rho / (2.0 * c)) * (ref[1] - Im[1]) + (ref[4] - Im[4]) / (2.0 * csq);
-    const double b0 = (ref[0] - I0[0]) - (ref[4] - I0[4]) / csq;
-    const double bt1 = ref[2] - I0[2];
-    const double bt2 = ref[3] - I0[3];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) up[m] = ref[m];
-    if (lm > 0.0) {
-      up[0] = up[0] - bm;
-      up[1] = up[1] - bm * (-(c / rho));
-      up[4] = up[4] - bm * csq;
-    }
-    if (l0 > 0.0) {
-      up[0] = up[0] - b0;
-      up[2] = up[2] - bt1;
-      up[3] = up[3] - bt2;
-    }
+  for (int m = 0; m < 5; ++m) {
+    Im[m] = lm > 0.0 ? avg_right(par[m], sm) : par[m].aR;
+    I0[m] = l0 > 0.0 ? avg_right(par[m], s0) : par[m].aR;
+    ref[m] = lp > 0.0 ? avg_right(par[m], sp) : par[m].aR;
   }
-  {
-    // lower face: families with negative speed arrive; reference = u-c family
-    double Ip[5], I0[5], ref[5];
+  const double bm = -(rho / (2.0 * c)) * (ref[1] - Im[1]) + (ref[4] - Im[4]) / (2.0 * csq);
+  const double b0 = (ref[0] - I0[0]) - (ref[4] - I0[4]) / csq;
+  const double bt1 = ref[2] - I0[2];
+  const double bt2 = ref[3] - I0[3];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      ref[m] = lm < 0.0 ? avg_left(par[m], sm) : par[m].aL;
-      I0[m] = l0 < 0.0 ? avg_left(par[m], s0) : par[m].aL;
-      Ip[m] = lp < 0.0 ? avg_left(par[m], sp) : par[m].aL;
-    }
-    const double bp = (rho / (2.0 * c)) * (ref[1] - Ip[1]) + (ref[4] - Ip[4]) / (2.0 * csq);
-    const double b0 = (ref[0] - I0[0]) - (ref[4] - I0[4]) / csq;
-    const double bt1 = ref[2] - I0[2];
-    const double bt2 = ref[3] - I0[3];
+  for (int m = 0; m < 5; ++m) up[m] = ref[m];
+  if (lm > 0.0) {
+    up[0] = up[0] - bm;
+    up[1] = up[1] - bm * (-(c / rho));
+    up[4] = up[4] - bm * csq;
+  }
+  if (l0 > 0.0) {
+    up[0] = up[0] - b0;
+    up[2] = up[2] - bt1;
+    up[3] = up[3] - bt2;
+  }
+}
+
+CTU_DEV void trace_dn(const Parab par[5], double rho, double un, double c, double dtdx, double dn[5]) {
+  const double lm = un - c, l0 = un, lp = un + c;
+  const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, sp = fabs(lp) * dtdx;
+  const double csq = c * c;
+  double Ip[5], I0[5], ref[5];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) dn[m] = ref[m];
-    if (lp < 0.0) {
-      dn[0] = dn[0] - bp;
-      dn[1] = dn[1] - bp * (c / rho);
-      dn[4] = dn[4] - bp * csq;
-    }
-    if (l0 < 0.0) {
-      dn[0] = dn[0] - b0;
-      dn[2] = dn[2] - bt1;
-      dn[3] = dn[3] - bt2;
-    }
+  for (int m = 0; m < 5; ++m) {
+    ref[m] = lm < 0.0 ? avg_left(par[m], sm) : par[m].aL;
+    I0[m] = l0 < 0.0 ? avg_left(par[m], s0) : par[m].aL;
+    Ip[m] = lp < 0.0 ? avg_left(par[m], sp) : par[m].aL;
+  }
+  const double bp = (rho / (2.0 * c)) * (ref[1] - Ip[1]) + (ref[4] - Ip[4]) / (2.0 * csq);
+  const double b0 = (ref[0] - I0[0]) - (ref[4] - I0[4]) / csq;
+  const double bt1 = ref[2] - I0[2];
+  const double bt2 = ref[3] - I0[3];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) dn[m] = ref[m];
+  if (lp < 0.0) {
+    dn[0] = dn[0] - bp;
+    dn[1] = dn[1] - bp * (c / rho);
+    dn[4] = dn[4] - bp * csq;
+  }
+  if (l0 < 0.0) {
+    dn[0] = dn[0] - b0;
+    dn[2] = dn[2] - bt1;
+    dn[3] = dn[3] - bt2;
   }
 }
 

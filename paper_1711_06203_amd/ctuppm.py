@@ -72,7 +72,7 @@ def lib() -> ctypes.CDLL:
             "ctuppm_num_stages": [],
             "ctuppm_stage_name": [ctypes.c_int],
             "ctuppm_stage_bytes": [vp, ctypes.c_int, ctypes.c_int, dp],
-            "ctuppm_set_blocks_per_cu": [vp, ctypes.c_int],
+            "ctuppm_set_tuning": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int],
             "ctuppm_last_error": [vp],
         }
         for name, args in sig.items():
@@ -89,7 +89,7 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_problem_destroy", "ctuppm_fab_elems", "ctuppm_workspace_bytes", "ctuppm_bind_state",
             "ctuppm_bind_workspace", "ctuppm_set_fixed_dt", "ctuppm_step", "ctuppm_current_state",
             "ctuppm_get_dt", "ctuppm_status", "ctuppm_set_timing", "ctuppm_stage_times", "ctuppm_num_stages",
-            "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_blocks_per_cu"]
+            "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning"]
 
 
 class Context:
@@ -136,8 +136,8 @@ class Context:
         self.call("ctuppm_stage_times", ms, cnt, n)
         return {self._L.ctuppm_stage_name(s).decode(): (ms[s], cnt[s]) for s in range(n)}
 
-    def set_blocks_per_cu(self, bpc: int):
-        self.call("ctuppm_set_blocks_per_cu", int(bpc))
+    def set_tuning(self, blocks_per_cu: int = 0, zseg_batched: int = 1, zseg_per_box: int = 1):
+        self.call("ctuppm_set_tuning", int(blocks_per_cu), int(zseg_batched), int(zseg_per_box))
 
     def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1):
         """Advance several problems together (one batched launch set per step)."""
