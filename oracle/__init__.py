@@ -238,3 +238,186 @@ def sample_step(Ufull_grown_filled: np.ndarray, P: Params, dt: float,
         Gn, _ = advance_box(loc, P, dt)
         out[s] = Gn[:, NG, NG, NG]
     return out
+
+
+# ----------------------------------------------------------------------------
+# two levels: coarse whole domain + one fine rectangular patch (ratio 2)
+# ----------------------------------------------------------------------------
+#
+# The paper's integration on a grid hierarchy (section 3.2) advances the coarse
+# level, advances the fine level in two half steps to the same time, then
+# synchronises the levels.  The synchronisation follows Berger & Colella
+# (1989): the coarse fluxes at the coarse-fine faces are replaced by the time-
+# and area-averaged fine fluxes (a flux register added back to the neighbouring
+# uncovered coarse cells), and covered coarse cells take the average of their
+# eight fine children.  Fine ghost cells come from the coarse state,
+# interpolated linearly in time and with MC-limited slopes in space.
+
+
+def _mc_slope(am, a0, ap):
+    """Monotonised-central slope, elementwise, in the same operation order as
+    the box advance's (CW84 eq. 1.7-1.8)."""
+    dm = a0 - am
+    dp = ap - a0
+    dc = 0.5 * (ap - am)
+    lim = np.minimum(np.abs(dc), np.minimum(2.0 * np.abs(dm), 2.0 * np.abs(dp)))
+    return np.where(dm * dp > 0.0, np.copysign(lim, dc), 0.0)
+
+
+def cf_interp(Uc_region: np.ndarray, region_lo, fine_cells) -> np.ndarray:
+    """Conservative MC-linear interpolation of fine cells from a coarse region.
+
+    Uc_region[:, k, j, i] holds coarse cell region_lo + (i, j, k).  fine_cells is
+    an (N, 3) array of global fine indices (I, J, K); each takes its coarse
+    parent's value plus s_x d_x + s_y d_y + s_z d_z (summed in that order),
+    s = -1/4 for an even fine index, +1/4 for an odd one."""
+    fc = np.asarray(fine_cells, dtype=np.int64)
+    par = fc // 2
+    loc = par - np.asarray(region_lo, dtype=np.int64)
+    out = np.empty((5, len(fc)))
+    for m in range(5):
+        A = Uc_region[m]
+        c = A[loc[:, 2], loc[:, 1], loc[:, 0]]
+        val = c.copy()
+        for d in range(3):
+            e = np.zeros(3, dtype=np.int64)
+            e[d] = 1
+            lm = loc - e
+            lp = loc + e
+            sl = _mc_slope(A[lm[:, 2], lm[:, 1], lm[:, 0]], c, A[lp[:, 2], lp[:, 1], lp[:, 0]])
+            s = np.where(fc[:, d] % 2 == 0, -0.25, 0.25)
+            val = val + s * sl
+        out[m] = val
+    return out
+
+
+def fine_ghost_values(Rn: np.ndarray, Rn1: np.ndarray, theta: float, region_lo, fine_cells) -> np.ndarray:
+    """Fine ghost values at substep time t^n + theta dt_c: the coarse state
+    interpolated linearly in time, (1 - theta) U^n + theta U^{n+1}, then
+    conservatively in space (cf_interp)."""
+    Ut = (1.0 - theta) * Rn + theta * Rn1
+    return cf_interp(Ut, region_lo, fine_cells)
+
+
+def _face_sl(d, lo, hi, idx):
+    """Slice of halo-1 face array axis order [m, k, j, i] for faces `idx` along d
+    and cells [lo, hi] (inclusive, box-local) across."""
+    sl = [slice(None)] * 4
+    for e in range(3):
+        ax = 3 - e
+        if e == d:
+            sl[ax] = slice(idx + 1, idx + 2)
+        else:
+            sl[ax] = slice(lo[e] + 1, hi[e] + 2)
+    return tuple(sl)
+
+
+def two_level_step(Gc: np.ndarray, Gf: np.ndarray, clo, chi, Pc: Params, Pf: Params):
+    """One coarse step of the two-level method.
+
+    Gc: whole-domain coarse grown array; Gf: grown array of the fine patch,
+    which covers coarse cells clo..chi (inclusive), i.e. fine cells
+    2 clo .. 2 chi + 1.  The patch must lie at least 3 coarse cells inside the
+    domain.  Returns (Gc, Gf, dt_c, counters); the arrays are updated copies."""
+    clo = np.asarray(clo, dtype=np.int64)
+    chi = np.asarray(chi, dtype=np.int64)
+    flo = 2 * clo
+    nf = 2 * (chi - clo + 1)
+    Gc = np.array(Gc, dtype=np.float64, copy=True)
+    Gf = np.array(Gf, dtype=np.float64, copy=True)
+    fill_domain(Gc, Pc)
+    s_c = signal_speed(Gc, Pc)
+    s_f = signal_speed(Gf, Pf)
+    a = Pc.cfl / s_c
+    b = 2.0 * (Pc.cfl / s_f)
+    dt_c = a if a < b else b
+    dt_f = 0.5 * dt_c
+    cnt = np.zeros(NCNT, dtype=np.int64)
+    Uc_old = Gc.copy()
+    Gc_new, c1, st = advance_box(Gc, Pc, dt_c, stages=True)
+    cnt += c1
+    # flux register on the 6 patch faces: the coarse flux dt_c F_c now, the
+    # fine sum S = sum over substeps of the four sub-face fluxes dt_f F_f
+    # (summed as a pairwise tree), and R = dt_c F_c - S / 4 at reflux time
+    Fc = {}
+    S = {}
+    for d in range(3):
+        for side, face in ((0, int(clo[d])), (1, int(chi[d]) + 1)):
+            Fc[(d, side)] = dt_c * st[f"ff{d}"][_face_sl(d, clo, chi, face)]
+            S[(d, side)] = np.zeros_like(Fc[(d, side)])
+    # coarse region for interpolation: patch footprint grown by 3 coarse cells
+    rlo = clo - 3
+    rhi = chi + 3
+    def region(G):
+        return G[:, NG + rlo[2]:NG + rhi[2] + 1, NG + rlo[1]:NG + rhi[1] + 1, NG + rlo[0]:NG + rhi[0] + 1]
+    Rn, Rn1 = region(Uc_old), region(Gc_new)
+    # fine ghost cells (global fine indices), in grown-array order
+    gz, gy, gx = np.meshgrid(np.arange(-NG, nf[2] + NG), np.arange(-NG, nf[1] + NG), np.arange(-NG, nf[0] + NG),
+                             indexing="ij")
+    ghost = ~((gx >= 0) & (gx < nf[0]) & (gy >= 0) & (gy < nf[1]) & (gz >= 0) & (gz < nf[2]))
+    loc = np.stack([gx[ghost], gy[ghost], gz[ghost]], axis=1)
+    fine_idx = loc + flo
+    for sub, theta in enumerate((0.0, 0.5)):
+        vals = fine_ghost_values(Rn, Rn1, theta, rlo, fine_idx)
+        for m in range(5):
+            Gf[m][loc[:, 2] + NG, loc[:, 1] + NG, loc[:, 0] + NG] = vals[m]
+        Gf_new, c2, stf = advance_box(Gf, Pf, dt_f, stages=True)
+        cnt += c2
+        # register: add the four fine sub-faces of each coarse face as
+        # ((t00 + t10) + (t01 + t11)), t = dt_f F_f, first transverse index fastest
+        for d in range(3):
+            t1, t2 = [e for e in range(3) if e != d]
+            for side, face in ((0, 0), (1, int(nf[d]))):
+                sl = [slice(None)] * 4
+                for e in range(3):
+                    sl[3 - e] = slice(face + 1, face + 2) if e == d else slice(1, nf[e] + 1)
+                Fd = stf[f"ff{d}"][tuple(sl)]
+
+                def sub(q1, q2):
+                    sl2 = [slice(None)] * 4
+                    for e in range(3):
+                        if e != d:
+                            sl2[3 - e] = slice(q1 if e == t1 else q2, None, 2)
+                    return dt_f * Fd[tuple(sl2)]
+                S[(d, side)] = S[(d, side)] + ((sub(0, 0) + sub(1, 0)) + (sub(0, 1) + sub(1, 1)))
+        Gf = Gf_new
+    # average down onto covered coarse cells: 1/8 of the eight children summed
+    # as a pairwise tree ((000 + 100) + (010 + 110)) + ((001 + 101) + (011 + 111))
+    fv = Gf[:, NG:NG + nf[2], NG:NG + nf[1], NG:NG + nf[0]]
+    ch = lambda i, j, k: fv[:, k::2, j::2, i::2]
+    avg = 0.125 * (((ch(0, 0, 0) + ch(1, 0, 0)) + (ch(0, 1, 0) + ch(1, 1, 0)))
+                   + ((ch(0, 0, 1) + ch(1, 0, 1)) + (ch(0, 1, 1) + ch(1, 1, 1))))
+    Gc_new[:, NG + clo[2]:NG + chi[2] + 1, NG + clo[1]:NG + chi[1] + 1, NG + clo[0]:NG + chi[0] + 1] = avg
+    # reflux the uncovered neighbours of the patch faces, x then y then z
+    for d in range(3):
+        rdx = 1.0 / Pc.dx[d]
+        for side in (0, 1):
+            cell = int(clo[d]) - 1 if side == 0 else int(chi[d]) + 1
+            sl = [slice(None)] * 4
+            for e in range(3):
+                sl[3 - e] = slice(NG + cell, NG + cell + 1) if e == d else slice(NG + clo[e], NG + chi[e] + 1)
+            R = Fc[(d, side)] - 0.25 * S[(d, side)]
+            cur = Gc_new[tuple(sl)]
+            Gc_new[tuple(sl)] = cur + R * rdx if side == 0 else cur - R * rdx
+    return Gc_new, Gf, dt_c, cnt
+
+
+def run_two_level(prob, nsteps: int):
+    """Two-level run of a workloads.Problem with fine_boxes / U0_fine set; the
+    fine level must be one rectangle (the union of its boxes).  Returns
+    (coarse valid, fine valid, dts, counters)."""
+    Pc = params_of(prob)
+    Pf = params_of(prob, fine=True)
+    flo = np.array(prob.fine_lo)
+    nf = np.array(prob.U0_fine.shape[1:][::-1])
+    clo = flo // 2
+    chi = (flo + nf) // 2 - 1
+    Gc = grow(prob.U0)
+    Gf = grow(prob.U0_fine)
+    dts = []
+    cnt = np.zeros(NCNT, dtype=np.int64)
+    for _ in range(nsteps):
+        Gc, Gf, dt, c = two_level_step(Gc, Gf, clo, chi, Pc, Pf)
+        dts.append(dt)
+        cnt += c
+    return valid(Gc), valid(Gf), np.array(dts), cnt
