@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ctuppm.h"
@@ -51,15 +52,19 @@ struct Problem {
   Level lev[2];
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  ProbDev* dP = nullptr;  // device record (library-allocated)
-  int cur = 0;            // host mirror of the parity
+  ProbDev* dP = nullptr;   // device record of level 0 (library-allocated)
+  ProbDev* dPf = nullptr;  // device record of level 1 (two-level problems)
+  int cur = 0;             // host mirror of the level-0 parity
   long long steps = 0;
+  // two-level geometry: fine level = fine cells flo..fhi = coarse cells clo..chi
+  int flo[3] = {0, 0, 0}, fhi[3] = {0, 0, 0}, clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
 };
 
 // Work lists of one set of problems stepped together in one form.
 struct StepSet {
   std::vector<int> pids;
   int form = 0;
+  int level = 0;
   int nboxes = 0;
   BoxRec* boxes = nullptr;
   March* units[kNumRegions] = {};
@@ -85,6 +90,32 @@ struct StepSet {
   }
 };
 
+// Device tables of one two-level problem (batched forms).
+struct TwoLevel {
+  StepSet* cset = nullptr;  // level-0 work lists (owned by ctx->sets)
+  StepSet* fset = nullptr;  // level-1 work lists
+  TwoLevelArgs args{};
+  GatherTag* gtags = nullptr;
+  Chunk* gchunks = nullptr;
+  int ngch = 0;
+  CfTag* ctags = nullptr;
+  Chunk* cchunks = nullptr;
+  int ncch = 0;
+  RegFace* faces = nullptr;
+  int nfaces = 0;
+  AvgTag* atags = nullptr;
+  Chunk* achunks = nullptr;
+  int nach = 0;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  DevAlloc mem;
+  ~TwoLevel() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    mem.release();
+  }
+};
+
 struct TimedLaunch {
   int stage;
   hipEvent_t a, b;
@@ -98,7 +129,8 @@ struct ctuppm_ctx {
   std::string err;
   std::map<int, std::unique_ptr<Problem>> probs;
   int next_id = 1;
-  std::map<std::pair<std::vector<int>, int>, std::unique_ptr<StepSet>> sets;
+  std::map<std::tuple<std::vector<int>, int, int>, std::unique_ptr<StepSet>> sets;
+  std::map<int, std::unique_ptr<TwoLevel>> two;
   bool timing = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
@@ -220,9 +252,50 @@ int run_stage(ctuppm_ctx* c, hipStream_t s, int stage, const BoxRec* boxes, cons
   return CTUPPM_OK;
 }
 
-// Build the work lists for a set of single-level problems in one form.
-int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** out) {
-  auto key = std::make_pair(pids, form == CTUPPM_FORM_GRAPH ? CTUPPM_FORM_BATCHED : form);
+// Coarse region of a two-level problem: coarse cells clo-3..chi+3.
+long long region_cells(const Problem* P, int ext[3], int lo[3]) {
+  long long v = 1;
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = P->clo[d] - 3;
+    ext[d] = P->chi[d] - P->clo[d] + 7;
+    v *= ext[d];
+  }
+  return v;
+}
+
+long long register_faces(const Problem* P) {
+  long long n = 0;
+  for (int d = 0; d < 3; ++d) {
+    long long a = 1;
+    for (int e = 0; e < 3; ++e)
+      if (e != d) a *= P->chi[e] - P->clo[e] + 1;
+    n += 2 * a;
+  }
+  return n;
+}
+
+// Workspace after the stage scratch of both levels: the region at t^n and at
+// t^{n+1} (5 doubles per cell each), then 10 doubles per register face.
+size_t two_level_extra_bytes(const Problem* P) {
+  if (P->nlevels != 2) return 0;
+  int ext[3], lo[3];
+  const long long rc = region_cells(P, ext, lo);
+  return 2 * align256(size_t(rc) * 5 * sizeof(double)) + align256(size_t(register_faces(P)) * 10 * sizeof(double));
+}
+
+// Forget the cached work lists (and graphs) that involve problem pid.
+void drop_sets(ctuppm_ctx* c, int pid) {
+  c->two.erase(pid);
+  for (auto it = c->sets.begin(); it != c->sets.end();) {
+    const auto& v = std::get<0>(it->first);
+    if (std::find(v.begin(), v.end(), pid) != v.end()) it = c->sets.erase(it);
+    else ++it;
+  }
+}
+
+// Build the work lists of level `level` for a set of problems in one form.
+int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** out, int level = 0) {
+  auto key = std::make_tuple(pids, form == CTUPPM_FORM_GRAPH ? CTUPPM_FORM_BATCHED : form, level);
   auto it = c->sets.find(key);
   if (it != c->sets.end()) {
     *out = it->second.get();
@@ -230,7 +303,8 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   }
   std::unique_ptr<StepSet> S(new StepSet);
   S->pids = pids;
-  S->form = key.second;
+  S->form = std::get<1>(key);
+  S->level = level;
   std::vector<BoxRec> boxes;
   std::vector<March> ch[kNumRegions];
   std::vector<FillTag> ftags;
@@ -241,18 +315,21 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   for (int pid : pids) {
     Problem* P = get_problem(c, pid);
     if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
-    if (P->nlevels != 1) return fail(c, CTUPPM_EINVAL, "problem %d: multi-level stepping is not built", pid);
-    const Level& L = P->lev[0];
+    if (level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
+    const Level& L = P->lev[level];
     if (!L.bound || !P->ws) return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
     size_t need = 0;
     if (ctuppm_workspace_bytes(c, pid, S->form, &need) != CTUPPM_OK) return CTUPPM_EINVAL;
     if (P->ws_bytes < need)
       return fail(c, CTUPPM_ENOMEM, "problem %d: workspace %zu < %zu bytes", pid, P->ws_bytes, need);
-    probs.push_back(P->dP);
+    ProbDev* dPl = level == 0 ? P->dP : P->dPf;
+    probs.push_back(dPl);
     const int base = int(boxes.size());
     size_t off = 0;
+    if (level == 1)  // level-1 scratch follows all level-0 scratch
+      for (const auto& b : P->lev[0].boxes) off += box_scratch_bytes(b);
     int dlo[3], dhi[3];
-    level_domain(P->prm, 0, dlo, dhi);
+    level_domain(P->prm, level, dlo, dhi);
     for (size_t b = 0; b < L.boxes.size(); ++b) {
       const ctuppm_box& bx = L.boxes[b];
       BoxRec r{};
@@ -260,7 +337,8 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
       r.U[1] = L.Ub[b];
       r.scr = (double*)((char*)P->ws + (S->form == CTUPPM_FORM_PER_BOX ? 0 : off));
       off += box_scratch_bytes(bx);
-      r.P = P->dP;
+      r.P = dPl;
+      r.level = level;
       for (int d = 0; d < 3; ++d) {
         r.n[d] = box_n(bx, d);
         r.lo[d] = bx.lo[d];
@@ -470,6 +548,262 @@ int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
   return CTUPPM_OK;
 }
 
+int find_box(const std::vector<ctuppm_box>& boxes, const int x[3]) {
+  for (size_t b = 0; b < boxes.size(); ++b) {
+    const ctuppm_box& B = boxes[b];
+    if (x[0] >= B.lo[0] && x[0] <= B.hi[0] && x[1] >= B.lo[1] && x[1] <= B.hi[1] && x[2] >= B.lo[2] &&
+        x[2] <= B.hi[2])
+      return int(b);
+  }
+  return -1;
+}
+
+template <class T>
+int upload_vec(ctuppm_ctx* c, DevAlloc& mem, const std::vector<T>& v, T** out) {
+  void* p = nullptr;
+  HIPCHK(c, mem.upload(v.data(), v.size() * sizeof(T), &p));
+  *out = (T*)p;
+  return CTUPPM_OK;
+}
+
+// Device tables of a two-level problem (built once, batched forms).
+int build_two_level(ctuppm_ctx* c, int pid, TwoLevel** out) {
+  auto it = c->two.find(pid);
+  if (it != c->two.end()) {
+    *out = it->second.get();
+    return CTUPPM_OK;
+  }
+  Problem* P = get_problem(c, pid);
+  std::unique_ptr<TwoLevel> T(new TwoLevel);
+  const std::vector<int> v{pid};
+  int rc = build_set(c, v, CTUPPM_FORM_BATCHED, &T->cset, 0);
+  if (rc) return rc;
+  rc = build_set(c, v, CTUPPM_FORM_BATCHED, &T->fset, 1);
+  if (rc) return rc;
+  size_t off = 0;
+  for (int l = 0; l < 2; ++l)
+    for (const auto& b : P->lev[l].boxes) off += box_scratch_bytes(b);
+  int rext[3], rlo[3];
+  const long long rcells = region_cells(P, rext, rlo);
+  char* base = (char*)P->ws;
+  TwoLevelArgs& A = T->args;
+  A.ct0 = (double*)(base + off);
+  off += align256(size_t(rcells) * 5 * sizeof(double));
+  A.ct1 = (double*)(base + off);
+  off += align256(size_t(rcells) * 5 * sizeof(double));
+  A.reg = (double*)(base + off);
+  A.cboxes = T->cset->boxes;
+  A.fboxes = T->fset->boxes;
+  A.Pc = P->dP;
+  A.Pf = P->dPf;
+  for (int d = 0; d < 3; ++d) {
+    A.rlo[d] = rlo[d];
+    A.rext[d] = rext[d];
+  }
+  const auto& CB = P->lev[0].boxes;
+  const auto& FB = P->lev[1].boxes;
+  // gather: coarse valid cells inside the region
+  std::vector<GatherTag> gt;
+  std::vector<Chunk> gch;
+  int rhi[3];
+  for (int d = 0; d < 3; ++d) rhi[d] = rlo[d] + rext[d] - 1;
+  for (size_t b = 0; b < CB.size(); ++b) {
+    int lo[3], hi[3];
+    if (!intersect(CB[b].lo, CB[b].hi, rlo, rhi, lo, hi)) continue;
+    GatherTag t{};
+    t.box = int(b);
+    long long vol = 1;
+    for (int d = 0; d < 3; ++d) {
+      t.lo[d] = lo[d] - CB[b].lo[d];
+      t.ext[d] = hi[d] - lo[d] + 1;
+      t.roff[d] = lo[d] - rlo[d];
+      vol *= t.ext[d];
+    }
+    chunk_region(gch, int(gt.size()), vol);
+    gt.push_back(t);
+  }
+  // coarse-to-fine: the ghost cells of each fine box outside the fine rectangle
+  std::vector<CfTag> ct;
+  std::vector<Chunk> cch;
+  for (size_t b = 0; b < FB.size(); ++b) {
+    int seg[3][3][2];
+    for (int d = 0; d < 3; ++d) {
+      const int glo = FB[b].lo[d] - kNG, ghi = FB[b].hi[d] + kNG;
+      seg[d][0][0] = glo; seg[d][0][1] = std::min(ghi, P->flo[d] - 1);
+      seg[d][1][0] = std::max(glo, P->flo[d]); seg[d][1][1] = std::min(ghi, P->fhi[d]);
+      seg[d][2][0] = std::max(glo, P->fhi[d] + 1); seg[d][2][1] = ghi;
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int bb = 0; bb < 3; ++bb)
+        for (int cc = 0; cc < 3; ++cc) {
+          if (a == 1 && bb == 1 && cc == 1) continue;
+          const int q[3] = {a, bb, cc};
+          CfTag t{};
+          t.box = int(b);
+          long long vol = 1;
+          bool empty = false;
+          for (int d = 0; d < 3; ++d) {
+            const int lo = seg[d][q[d]][0], hi = seg[d][q[d]][1];
+            if (lo > hi) empty = true;
+            t.lo[d] = lo - FB[b].lo[d];
+            t.ext[d] = hi - lo + 1;
+            vol *= std::max(0, t.ext[d]);
+          }
+          if (empty) continue;
+          chunk_region(cch, int(ct.size()), vol);
+          ct.push_back(t);
+        }
+  }
+  // register faces on the six sides of the fine rectangle
+  std::vector<RegFace> rf;
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    for (int side = 0; side < 2; ++side) {
+      const int cf = side == 0 ? P->clo[d] : P->chi[d] + 1;
+      const int uc = side == 0 ? P->clo[d] - 1 : P->chi[d] + 1;
+      const int fcell = side == 0 ? P->flo[d] : P->fhi[d];
+      const int fface = side == 0 ? P->flo[d] : P->fhi[d] + 1;
+      for (int b2 = P->clo[t2]; b2 <= P->chi[t2]; ++b2)
+        for (int b1 = P->clo[t1]; b1 <= P->chi[t1]; ++b1) {
+          RegFace F{};
+          F.d = d;
+          F.side = side;
+          int u[3];
+          u[d] = uc; u[t1] = b1; u[t2] = b2;
+          F.cbox = find_box(CB, u);
+          int fc[3];
+          fc[d] = fcell; fc[t1] = 2 * b1; fc[t2] = 2 * b2;
+          F.fbox = find_box(FB, fc);
+          if (F.cbox < 0 || F.fbox < 0) return fail(c, CTUPPM_EINVAL, "coarse-fine face without boxes");
+          const ctuppm_box& C = CB[F.cbox];
+          const ctuppm_box& Fb = FB[F.fbox];
+          for (int e = 0; e < 3; ++e) {
+            F.ucell[e] = u[e] - C.lo[e];
+            F.cface[e] = (e == d ? cf : u[e]) - C.lo[e];
+            F.fface[e] = (e == d ? fface : fc[e]) - Fb.lo[e];
+          }
+          rf.push_back(F);
+        }
+    }
+  }
+  // average down: coarse cells covered by each fine box
+  std::vector<AvgTag> at;
+  std::vector<Chunk> ach;
+  for (size_t cb = 0; cb < CB.size(); ++cb)
+    for (size_t fb = 0; fb < FB.size(); ++fb) {
+      int flo[3], fhi[3], lo[3], hi[3];
+      for (int d = 0; d < 3; ++d) {
+        flo[d] = FB[fb].lo[d] / 2;
+        fhi[d] = (FB[fb].hi[d] + 1) / 2 - 1;
+      }
+      if (!intersect(CB[cb].lo, CB[cb].hi, flo, fhi, lo, hi)) continue;
+      AvgTag t{};
+      t.cbox = int(cb);
+      t.fbox = int(fb);
+      long long vol = 1;
+      for (int d = 0; d < 3; ++d) {
+        t.clo[d] = lo[d] - CB[cb].lo[d];
+        t.ext[d] = hi[d] - lo[d] + 1;
+        t.flo[d] = 2 * lo[d] - FB[fb].lo[d];
+        vol *= t.ext[d];
+      }
+      chunk_region(ach, int(at.size()), vol);
+      at.push_back(t);
+    }
+  if ((rc = upload_vec(c, T->mem, gt, &T->gtags)) || (rc = upload_vec(c, T->mem, gch, &T->gchunks)) ||
+      (rc = upload_vec(c, T->mem, ct, &T->ctags)) || (rc = upload_vec(c, T->mem, cch, &T->cchunks)) ||
+      (rc = upload_vec(c, T->mem, rf, &T->faces)) || (rc = upload_vec(c, T->mem, at, &T->atags)) ||
+      (rc = upload_vec(c, T->mem, ach, &T->achunks)))
+    return rc;
+  T->ngch = int(gch.size());
+  T->ncch = int(cch.size());
+  T->nfaces = int(rf.size());
+  T->nach = int(ach.size());
+  *out = T.get();
+  c->two[pid] = std::move(T);
+  return CTUPPM_OK;
+}
+
+#define TLCHK(expr)                                                                                \
+  do {                                                                                             \
+    hipError_t _e = (expr);                                                                        \
+    if (_e != hipSuccess) return fail(c, CTUPPM_EHIP, "two-level launch %s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+int level_fill(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
+  int rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks, S->nfch, true, timed);
+  for (int d = 0; d < 3 && !rc; ++d)
+    rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d], S->nbch[d], true, timed);
+  return rc;
+}
+
+// One coarse step of a two-level problem: coarse advance, two fine substeps
+// with coarse-to-fine ghost cells at theta = 0 and 1/2, average down, reflux.
+int enqueue_two_level(ctuppm_ctx* c, Problem* P, TwoLevel* T, hipStream_t s, bool timed) {
+  StepSet* C = T->cset;
+  StepSet* F = T->fset;
+  const TwoLevelArgs& A = T->args;
+  const int nst = int(sizeof(kCellStages) / sizeof(int));
+  int rc;
+  if ((rc = level_fill(c, C, s, timed))) return rc;
+  if ((rc = run_cells(c, C, s, kStC2P, -1, timed))) return rc;
+  if ((rc = run_cells(c, F, s, kStCfl, -1, timed))) return rc;
+  TLCHK(launch_dt2(P->dP, P->dPf, s));
+  TLCHK(launch_gather(A, T->gtags, T->gchunks, T->ngch, 0, s));
+  for (int q = 0; q < nst; ++q)
+    if ((rc = run_cells(c, C, s, kCellStages[q], -1, timed))) return rc;
+  TLCHK(launch_reg_coarse(A, T->faces, T->nfaces, s));
+  TLCHK(launch_gather(A, T->gtags, T->gchunks, T->ngch, 1, s));
+  for (int sub = 0; sub < 2; ++sub) {
+    if ((rc = level_fill(c, F, s, timed))) return rc;
+    TLCHK(launch_cfinterp(A, T->ctags, T->cchunks, T->ncch, sub == 0 ? 0.0 : 0.5, s));
+    if ((rc = run_cells(c, F, s, kStC2POnly, -1, timed))) return rc;
+    for (int q = 0; q < nst; ++q)
+      if ((rc = run_cells(c, F, s, kCellStages[q], -1, timed))) return rc;
+    TLCHK(launch_reg_fine(A, T->faces, T->nfaces, s));
+    TLCHK(launch_flip(F->probs, F->nprobs, s));
+  }
+  TLCHK(launch_avgdown(A, T->atags, T->achunks, T->nach, s));
+  TLCHK(launch_reflux(A, T->faces, T->nfaces, s));
+  TLCHK(launch_flip(C->probs, C->nprobs, s));
+  return CTUPPM_OK;
+}
+
+int step_two_level(ctuppm_ctx* c, int pid, int form) {
+  Problem* P = get_problem(c, pid);
+  if (form == CTUPPM_FORM_PER_BOX) return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched forms only");
+  if (!P->lev[0].bound || !P->lev[1].bound || !P->ws)
+    return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
+  size_t need = 0;
+  if (ctuppm_workspace_bytes(c, pid, CTUPPM_FORM_BATCHED, &need) != CTUPPM_OK) return CTUPPM_EINVAL;
+  if (P->ws_bytes < need) return fail(c, CTUPPM_ENOMEM, "problem %d: workspace %zu < %zu bytes", pid, P->ws_bytes, need);
+  TwoLevel* T = nullptr;
+  int rc = build_two_level(c, pid, &T);
+  if (rc) return rc;
+  if (form == CTUPPM_FORM_GRAPH) {
+    if (!T->exec) {
+      HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_two_level(c, P, T, c->capture, false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->capture, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "graph capture: %s", hipGetErrorString(e));
+      T->graph = g;
+      HIPCHK(c, hipGraphInstantiate(&T->exec, g, nullptr, nullptr, 0));
+    }
+    HIPCHK(c, hipGraphLaunch(T->exec, c->stream));
+  } else {
+    rc = enqueue_two_level(c, P, T, c->stream, c->timing);
+    if (rc) return rc;
+  }
+  P->cur ^= 1;
+  P->steps += 1;
+  return CTUPPM_OK;
+}
+
 }  // namespace
 
 // ======================================================================== ABI
@@ -494,9 +828,12 @@ int ctuppm_ctx_create(void* hip_stream, ctuppm_ctx** out) {
 int ctuppm_ctx_destroy(ctuppm_ctx* c) {
   if (!c) return CTUPPM_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  c->two.clear();
   c->sets.clear();
-  for (auto& kv : c->probs)
+  for (auto& kv : c->probs) {
     if (kv.second->dP) (void)hipFree(kv.second->dP);
+    if (kv.second->dPf) (void)hipFree(kv.second->dPf);
+  }
   c->probs.clear();
   for (auto& t : c->timed) {
     (void)hipEventDestroy(t.a);
@@ -559,6 +896,36 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
       P->lev[l].boxes.push_back(B);
     }
   }
+  if (nlevels == 2) {
+    // the fine level must be one rectangle of boxes aligned to coarse cells,
+    // at least 3 coarse cells inside the domain
+    const auto& fb = P->lev[1].boxes;
+    long long vol = 0;
+    for (int d = 0; d < 3; ++d) {
+      P->flo[d] = fb[0].lo[d];
+      P->fhi[d] = fb[0].hi[d];
+    }
+    for (const auto& b : fb) {
+      long long v = 1;
+      for (int d = 0; d < 3; ++d) {
+        if ((b.lo[d] & 1) || !(b.hi[d] & 1))
+          return fail(c, CTUPPM_EINVAL, "fine boxes must start at even and end at odd indices");
+        P->flo[d] = std::min(P->flo[d], b.lo[d]);
+        P->fhi[d] = std::max(P->fhi[d], b.hi[d]);
+        v *= box_n(b, d);
+      }
+      vol += v;
+    }
+    long long bb = 1;
+    for (int d = 0; d < 3; ++d) {
+      bb *= P->fhi[d] - P->flo[d] + 1;
+      P->clo[d] = P->flo[d] / 2;
+      P->chi[d] = (P->fhi[d] + 1) / 2 - 1;
+      if (P->clo[d] - 3 < prm->domain_lo[d] || P->chi[d] + 3 > prm->domain_hi[d])
+        return fail(c, CTUPPM_EINVAL, "fine level must lie at least 3 coarse cells inside the domain");
+    }
+    if (bb != vol) return fail(c, CTUPPM_EINVAL, "fine boxes must tile one rectangle");
+  }
   ProbDev h{};
   h.gamma = prm->gamma;
   h.gm1 = prm->gamma - 1.0;
@@ -574,6 +941,14 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   h.nlevels = nlevels;
   HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
   HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
+  if (nlevels == 2) {
+    for (int d = 0; d < 3; ++d) {
+      h.dx[d] = prm->dx[d] / 2.0;
+      h.rdx[d] = 1.0 / h.dx[d];
+    }
+    HIPCHK(c, hipMalloc((void**)&P->dPf, sizeof(ProbDev)));
+    HIPCHK(c, hipMemcpy(P->dPf, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
+  }
   P->id = c->next_id++;
   *pid_out = P->id;
   c->probs[P->id] = std::move(P);
@@ -585,12 +960,9 @@ int ctuppm_problem_destroy(ctuppm_ctx* c, int pid) {
   Problem* P = get_problem(c, pid);
   if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
   (void)hipStreamSynchronize(c->stream);
-  for (auto it = c->sets.begin(); it != c->sets.end();) {
-    const auto& v = it->first.first;
-    if (std::find(v.begin(), v.end(), pid) != v.end()) it = c->sets.erase(it);
-    else ++it;
-  }
+  drop_sets(c, pid);
   if (P->dP) (void)hipFree(P->dP);
+  if (P->dPf) (void)hipFree(P->dPf);
   c->probs.erase(pid);
   return CTUPPM_OK;
 }
@@ -606,9 +978,14 @@ int ctuppm_workspace_bytes(ctuppm_ctx* c, int pid, int form, size_t* bytes) {
       total += s;
       mx = std::max(mx, s);
     }
-  if (form == CTUPPM_FORM_PER_BOX) *bytes = mx;
-  else if (form == CTUPPM_FORM_BATCHED || form == CTUPPM_FORM_GRAPH) *bytes = total;
-  else return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
+  if (form == CTUPPM_FORM_PER_BOX) {
+    if (P->nlevels == 2) return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched forms only");
+    *bytes = mx;
+  } else if (form == CTUPPM_FORM_BATCHED || form == CTUPPM_FORM_GRAPH) {
+    *bytes = total + two_level_extra_bytes(P);
+  } else {
+    return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
+  }
   return CTUPPM_OK;
 }
 
@@ -625,14 +1002,11 @@ int ctuppm_bind_state(ctuppm_ctx* c, int pid, int level, double* const* Ua, doub
       return fail(c, CTUPPM_EINVAL, "box %zu: null or misaligned fab pointer", b);
   L.bound = true;
   P->cur = 0;
-  for (auto it = c->sets.begin(); it != c->sets.end();) {
-    const auto& v = it->first.first;
-    if (std::find(v.begin(), v.end(), pid) != v.end()) it = c->sets.erase(it);
-    else ++it;
-  }
+  drop_sets(c, pid);
   // parity back to A
   int zero = 0;
-  HIPCHK(c, hipMemcpyAsync(&P->dP->cur, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&(level == 0 ? P->dP : P->dPf)->cur, &zero, sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return CTUPPM_OK;
 }
@@ -644,11 +1018,7 @@ int ctuppm_bind_workspace(ctuppm_ctx* c, int pid, void* ws, size_t bytes) {
   if ((uintptr_t)ws & 255) return fail(c, CTUPPM_EINVAL, "workspace must be 256-byte aligned");
   P->ws = ws;
   P->ws_bytes = bytes;
-  for (auto it = c->sets.begin(); it != c->sets.end();) {
-    const auto& v = it->first.first;
-    if (std::find(v.begin(), v.end(), pid) != v.end()) it = c->sets.erase(it);
-    else ++it;
-  }
+  drop_sets(c, pid);
   return CTUPPM_OK;
 }
 
@@ -666,9 +1036,16 @@ int ctuppm_step(ctuppm_ctx* c, const int* pids, int npids, int form) {
   if (!c || !pids || npids < 1) return CTUPPM_EINVAL;
   if (form < CTUPPM_FORM_PER_BOX || form > CTUPPM_FORM_GRAPH) return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
   std::vector<int> v(pids, pids + npids);
-  for (size_t i = 0; i < v.size(); ++i)
+  for (size_t i = 0; i < v.size(); ++i) {
     for (size_t j = 0; j < i; ++j)
       if (v[i] == v[j]) return fail(c, CTUPPM_EINVAL, "problem %d listed twice", v[i]);
+    Problem* P = get_problem(c, v[i]);
+    if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", v[i]);
+    if (P->nlevels == 2) {
+      if (npids != 1) return fail(c, CTUPPM_EINVAL, "a two-level problem steps on its own");
+      return step_two_level(c, v[i], form);
+    }
+  }
   StepSet* S = nullptr;
   int rc = build_set(c, v, form, &S);
   if (rc) return rc;
@@ -725,6 +1102,10 @@ int ctuppm_status(ctuppm_ctx* c, int pid, long long counters[6]) {
   HIPCHK(c, hipMemcpy(&h, P->dP, sizeof(ProbDev), hipMemcpyDeviceToHost));
   for (int i = 0; i < 5; ++i) counters[i] = (long long)h.cnt[i];
   counters[5] = h.nsteps;
+  if (P->dPf) {
+    HIPCHK(c, hipMemcpy(&h, P->dPf, sizeof(ProbDev), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 5; ++i) counters[i] += (long long)h.cnt[i];
+  }
   return CTUPPM_OK;
 }
 
@@ -764,6 +1145,7 @@ int ctuppm_set_tuning(ctuppm_ctx* c, int bpc, int zb, int zp) {
   c->blocks_per_cu = bpc;
   c->zseg_batched = zb;
   c->zseg_per_box = zp;
+  c->two.clear();
   c->sets.clear();  // work lists and graphs depend on the tuning
   return CTUPPM_OK;
 }
@@ -774,7 +1156,10 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
   if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
   double tot = 0.0;
   const double W = 8.0;  // bytes per double
-  for (const auto& bx : P->lev[0].boxes) {
+  std::vector<ctuppm_box> all(P->lev[0].boxes);
+  if (P->nlevels == 2)  // the fine level runs two substeps per step
+    for (int r = 0; r < 2; ++r) all.insert(all.end(), P->lev[1].boxes.begin(), P->lev[1].boxes.end());
+  for (const auto& bx : all) {
     const double n0 = box_n(bx, 0), n1 = box_n(bx, 1), n2 = box_n(bx, 2);
     const double nn[3] = {n0, n1, n2};
     const double valid = n0 * n1 * n2;

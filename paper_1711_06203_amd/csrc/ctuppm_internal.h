@@ -72,6 +72,33 @@ struct FillTag { int dst, src; int lo[3]; int ext[3]; int off[3]; int pad; };
 // Physical boundary along dir on one side of the domain, over a box's grown cells.
 struct BcTag { int box; int dir; int side; int bc; int lo[3]; int ext[3]; int dom_lo, dom_hi; double inflow[5]; };
 
+// Two-level problems (ratio 2).  The fine level is one rectangle of fine
+// boxes covering coarse cells clo..chi; the coarse cells clo-3..chi+3 (the
+// "region") are gathered from the coarse boxes at t^n and t^{n+1} for the
+// coarse-to-fine ghost interpolation.
+struct GatherTag { int box; int lo[3]; int ext[3]; int roff[3]; };   // box-local valid cells -> region offset
+struct CfTag { int box; int lo[3]; int ext[3]; int pad; };           // fine box-local ghost cells to interpolate
+// A coarse face on the patch boundary: the coarse box holding the uncovered
+// neighbour cell, the face and that cell in its box-local index, the fine box
+// holding the four fine sub-faces and the first sub-face in its box-local
+// index; register slot = index of the face in the list.
+struct RegFace { int d, side, cbox, fbox; int cface[3]; int ucell[3]; int fface[3]; int pad; };
+// Coarse cells covered by one fine box: coarse box-local range and the fine
+// box-local index of the first child.
+struct AvgTag { int cbox, fbox; int clo[3]; int ext[3]; int flo[3]; int pad; };
+
+struct TwoLevelArgs {
+  const BoxRec* cboxes;
+  const BoxRec* fboxes;
+  ProbDev* Pc;
+  ProbDev* Pf;
+  double* ct0;      // region state at t^n
+  double* ct1;      // region state at t^{n+1}
+  double* reg;      // per face: dt_c F_c (5), fine sum S (5)
+  int rlo[3];       // region origin (coarse index)
+  int rext[3];      // region extent
+};
+
 // Scratch layout per box, in doubles: q (6 x grown), phi (1 x halo-1),
 // ql[3], qr[3], fn[3] (5 x halo-1 each), f1[6], ff[3] (5 x halo-1 each).
 __host__ __device__ inline long long grown_cells(const int n[3]) {
@@ -119,6 +146,19 @@ struct Launch {
 };
 
 hipError_t launch_stage(int stage, const Launch& L);
+// Two-level kernels: gather (which: 0 = state at t^n into ct0, 1 = new state
+// into ct1), coarse-to-fine interpolation at theta, register init from the
+// coarse fluxes, register accumulation of the fine fluxes, average down,
+// reflux, and the two-level dt.
+hipError_t launch_gather(const TwoLevelArgs& A, const GatherTag* tags, const Chunk* chunks, int n, int which,
+                         hipStream_t s);
+hipError_t launch_cfinterp(const TwoLevelArgs& A, const CfTag* tags, const Chunk* chunks, int n, double theta,
+                           hipStream_t s);
+hipError_t launch_reg_coarse(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s);
+hipError_t launch_reg_fine(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s);
+hipError_t launch_avgdown(const TwoLevelArgs& A, const AvgTag* tags, const Chunk* chunks, int n, hipStream_t s);
+hipError_t launch_reflux(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s);
+hipError_t launch_dt2(ProbDev* Pc, ProbDev* Pf, hipStream_t s);
 hipError_t launch_dt(ProbDev* const* probs, int nprobs, hipStream_t s);
 hipError_t launch_flip(ProbDev* const* probs, int nprobs, hipStream_t s);
 const char* stage_name(int stage);

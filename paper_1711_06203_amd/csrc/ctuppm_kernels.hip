@@ -575,6 +575,181 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
   });
 }
 
+// ------------------------------------------------------------- two levels
+//
+// Subcycled two-level advance (section 3.2: coarse advanced, fine advanced in
+// steps to the same time, levels then synchronised), synchronised as in
+// Berger & Colella (1989): a flux register replaces the coarse fluxes at the
+// coarse-fine faces by the fine ones, covered coarse cells take the average of
+// their eight children, and fine ghost cells come from the coarse state
+// interpolated linearly in time and MC-linearly in space.
+
+// Box-local item of a 3-D tag range.
+CTU_DEV bool tag_item(const int ext[3], int t, int& a, int& b, int& c) {
+  if (t >= ext[0] * ext[1] * ext[2]) return false;
+  a = t % ext[0];
+  const int r = t / ext[0];
+  b = r % ext[1];
+  c = r / ext[1];
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(TwoLevelArgs A, const GatherTag* __restrict__ tags,
+                                                   const Chunk* __restrict__ chunks, int n, int which) {
+  const int rplane = A.rext[0] * A.rext[1], rcomp = rplane * A.rext[2];
+  double* __restrict__ dst = which ? A.ct1 : A.ct0;
+  for_each_chunk(n, [&](int c) {
+    const Chunk ch = chunks[c];
+    const GatherTag T = tags[ch.box];
+    int a, b, cc;
+    if (!tag_item(T.ext, ch.start + threadIdx.x, a, b, cc)) return;
+    const BoxRec& B = A.cboxes[T.box];
+    const Geo g(B.n);
+    const double* __restrict__ U = B.U[which ? (B.P->cur ^ 1) : B.P->cur];
+    const int so = g.g(T.lo[0] + a, T.lo[1] + b, T.lo[2] + cc);
+    const int ro = (T.roff[2] + cc) * rplane + (T.roff[1] + b) * A.rext[0] + (T.roff[0] + a);
+#pragma unroll
+    for (int m = 0; m < kNV; ++m) dst[m * rcomp + ro] = U[m * g.gcomp + so];
+  });
+}
+
+__global__ __launch_bounds__(kBlock) void k_cfinterp(TwoLevelArgs A, const CfTag* __restrict__ tags,
+                                                     const Chunk* __restrict__ chunks, int n, double theta) {
+  const int rplane = A.rext[0] * A.rext[1], rcomp = rplane * A.rext[2];
+  const double w0 = 1.0 - theta;
+  for_each_chunk(n, [&](int c) {
+    const Chunk ch = chunks[c];
+    const CfTag T = tags[ch.box];
+    int x[3];
+    if (!tag_item(T.ext, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
+    const BoxRec& B = A.fboxes[T.box];
+    const Geo g(B.n);
+    double* __restrict__ U = B.U[B.P->cur];
+    int I[3], rp[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x[d] += T.lo[d];
+      I[d] = B.lo[d] + x[d];          // global fine index (>= 0: the patch is interior)
+      rp[d] = (I[d] >> 1) - A.rlo[d];  // parent's region index
+    }
+    const int po = (rp[2] * A.rext[1] + rp[1]) * A.rext[0] + rp[0];
+    const int st[3] = {1, A.rext[0], rplane};
+    const int go = g.g(x[0], x[1], x[2]);
+#pragma unroll
+    for (int m = 0; m < kNV; ++m) {
+      const double* __restrict__ a0 = A.ct0 + m * rcomp;
+      const double* __restrict__ a1 = A.ct1 + m * rcomp;
+      const double cpar = w0 * a0[po] + theta * a1[po];
+      double val = cpar;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double um = w0 * a0[po - st[d]] + theta * a1[po - st[d]];
+        const double up = w0 * a0[po + st[d]] + theta * a1[po + st[d]];
+        const double sl = mc_slope(um, cpar, up);
+        const double sgn = (I[d] & 1) ? 0.25 : -0.25;
+        val = val + sgn * sl;
+      }
+      U[m * g.gcomp + go] = val;
+    }
+  });
+}
+
+__global__ void k_reg_coarse(TwoLevelArgs A, const RegFace* __restrict__ faces, int n) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  const RegFace F = faces[f];
+  const BoxRec& B = A.cboxes[F.cbox];
+  const Geo g(B.n);
+  const double* __restrict__ Ff = g.ff(B.scr, F.d);
+  const int o = g.h(F.cface[0], F.cface[1], F.cface[2]);
+  const double dt = A.Pc->dt;
+  double* r = A.reg + 10 * f;
+#pragma unroll
+  for (int m = 0; m < kNV; ++m) {
+    r[m] = dt * Ff[m * g.hcomp + o];
+    r[5 + m] = 0.0;
+  }
+}
+
+__global__ void k_reg_fine(TwoLevelArgs A, const RegFace* __restrict__ faces, int n) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  const RegFace F = faces[f];
+  const BoxRec& B = A.fboxes[F.fbox];
+  const Geo g(B.n);
+  const double* __restrict__ Ff = g.ff(B.scr, F.d);
+  const int t1 = F.d == 0 ? 1 : 0, t2 = F.d == 2 ? 1 : 2;  // transverse directions, increasing
+  const int s1 = g.hstride(t1), s2 = g.hstride(t2);
+  const int o = g.h(F.fface[0], F.fface[1], F.fface[2]);
+  const double dt = A.Pf->dt;
+  double* r = A.reg + 10 * f;
+#pragma unroll
+  for (int m = 0; m < kNV; ++m) {
+    const double* Fm = Ff + m * g.hcomp;
+    const double t00 = dt * Fm[o], t10 = dt * Fm[o + s1], t01 = dt * Fm[o + s2], t11 = dt * Fm[o + s1 + s2];
+    r[5 + m] = r[5 + m] + ((t00 + t10) + (t01 + t11));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_avgdown(TwoLevelArgs A, const AvgTag* __restrict__ tags,
+                                                    const Chunk* __restrict__ chunks, int n) {
+  for_each_chunk(n, [&](int c) {
+    const Chunk ch = chunks[c];
+    const AvgTag T = tags[ch.box];
+    int a, b, cc;
+    if (!tag_item(T.ext, ch.start + threadIdx.x, a, b, cc)) return;
+    const BoxRec& C = A.cboxes[T.cbox];
+    const BoxRec& Fb = A.fboxes[T.fbox];
+    const Geo gc(C.n), gf(Fb.n);
+    double* __restrict__ Uc = C.U[C.P->cur ^ 1];
+    const double* __restrict__ Uf = Fb.U[Fb.P->cur];
+    const int co = gc.g(T.clo[0] + a, T.clo[1] + b, T.clo[2] + cc);
+    const int fo = gf.g(T.flo[0] + 2 * a, T.flo[1] + 2 * b, T.flo[2] + 2 * cc);
+    const int sx = 1, sy = gf.gx, sz = gf.gplane;
+#pragma unroll
+    for (int m = 0; m < kNV; ++m) {
+      const double* f = Uf + m * gf.gcomp + fo;
+      const double s0 = (f[0] + f[sx]) + (f[sy] + f[sx + sy]);
+      const double s1 = (f[sz] + f[sx + sz]) + (f[sy + sz] + f[sx + sy + sz]);
+      Uc[m * gc.gcomp + co] = 0.125 * (s0 + s1);
+    }
+  });
+}
+
+__global__ void k_reflux(TwoLevelArgs A, const RegFace* __restrict__ faces, int n) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  const RegFace F = faces[f];
+  const BoxRec& B = A.cboxes[F.cbox];
+  const Geo g(B.n);
+  double* __restrict__ U = B.U[B.P->cur ^ 1];
+  const int o = g.g(F.ucell[0], F.ucell[1], F.ucell[2]);
+  const double rdx = A.Pc->rdx[F.d];
+  const double* r = A.reg + 10 * f;
+#pragma unroll
+  for (int m = 0; m < kNV; ++m) {
+    const double R = r[m] - 0.25 * r[5 + m];
+    const double u = U[m * g.gcomp + o];
+    U[m * g.gcomp + o] = F.side == 0 ? u + R * rdx : u - R * rdx;
+  }
+}
+
+__global__ void k_dt2(ProbDev* Pc, ProbDev* Pf) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long bc = 0ull, bf = 0ull;
+  for (int q = 0; q < kSlots; ++q) {
+    bc = Pc->smax[q][0] > bc ? Pc->smax[q][0] : bc;
+    bf = Pf->smax[q][0] > bf ? Pf->smax[q][0] : bf;
+    Pc->smax[q][0] = 0ull;
+    Pf->smax[q][0] = 0ull;
+  }
+  const double a = Pc->cfl / __longlong_as_double((long long)bc);
+  const double b = 2.0 * (Pc->cfl / __longlong_as_double((long long)bf));
+  const double dt = Pc->fixed_dt > 0.0 ? Pc->fixed_dt : (a < b ? a : b);
+  Pc->dt = dt;
+  Pf->dt = 0.5 * dt;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -618,6 +793,49 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStUpdate: k_update<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const TwoLevelArgs& A, const GatherTag* tags, const Chunk* chunks, int n, int which,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_gather<<<(n + 7) / 8 * 8, kBlock, 0, s>>>(A, tags, chunks, n, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfinterp(const TwoLevelArgs& A, const CfTag* tags, const Chunk* chunks, int n, double theta,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_cfinterp<<<(n + 7) / 8 * 8, kBlock, 0, s>>>(A, tags, chunks, n, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_reg_coarse(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_reg_coarse<<<(n + 255) / 256, 256, 0, s>>>(A, faces, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reg_fine(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_reg_fine<<<(n + 255) / 256, 256, 0, s>>>(A, faces, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_avgdown(const TwoLevelArgs& A, const AvgTag* tags, const Chunk* chunks, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_avgdown<<<(n + 7) / 8 * 8, kBlock, 0, s>>>(A, tags, chunks, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reflux(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_reflux<<<(n + 255) / 256, 256, 0, s>>>(A, faces, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt2(ProbDev* Pc, ProbDev* Pf, hipStream_t s) {
+  k_dt2<<<1, 64, 0, s>>>(Pc, Pf);
   return hipGetLastError();
 }
 

@@ -168,62 +168,82 @@ def _params(prob: W.Problem) -> Params:
 
 
 class Solver:
-    """One single-level problem resident on the GPU: two fabs per box, one
-    workspace, all allocated with torch and handed to the library."""
+    """One problem resident on the GPU: two fabs per box (per level), one
+    workspace, all allocated with torch and handed to the library.  A problem
+    with ``fine_boxes`` has a second level (ratio 2) whose initial state is
+    ``U0_fine`` over the fine rectangle starting at ``fine_lo``."""
 
     def __init__(self, ctx: Context, prob: W.Problem, form="batched", fixed_dt: Optional[float] = None):
         torch = ctx.torch
         self.ctx, self.prob = ctx, prob
         self.form = FORMS[form] if isinstance(form, str) else int(form)
         L = lib()
-        boxes = (Box * len(prob.boxes))()
-        for b, (lo, hi) in enumerate(prob.boxes):
-            boxes[b].lo[:] = list(lo)
-            boxes[b].hi[:] = list(hi)
-        self._boxes = boxes
-        ptrs = (ctypes.POINTER(Box) * 1)(ctypes.cast(boxes, ctypes.POINTER(Box)))
-        nb = (ctypes.c_int * 1)(len(prob.boxes))
+        self.levels = [list(prob.boxes)] + ([list(prob.fine_boxes)] if prob.fine_boxes else [])
+        arrays = []
+        for boxes in self.levels:
+            arr = (Box * len(boxes))()
+            for b, (lo, hi) in enumerate(boxes):
+                arr[b].lo[:] = list(lo)
+                arr[b].hi[:] = list(hi)
+            arrays.append(arr)
+        self._boxes = arrays
+        nl = len(self.levels)
+        ptrs = (ctypes.POINTER(Box) * nl)(*[ctypes.cast(a, ctypes.POINTER(Box)) for a in arrays])
+        nb = (ctypes.c_int * nl)(*[len(b) for b in self.levels])
         pid = ctypes.c_int()
-        ctx.call("ctuppm_problem_create", ctypes.byref(_params(prob)), 1, ptrs, nb, ctypes.byref(pid))
+        ctx.call("ctuppm_problem_create", ctypes.byref(_params(prob)), nl, ptrs, nb, ctypes.byref(pid))
         self.pid = pid.value
-        # fab offsets in one tensor per parity, 256-byte aligned
-        self.offsets, self.shapes = [], []
-        off = 0
-        for lo, hi in prob.boxes:
-            n = [hi[d] - lo[d] + 1 for d in range(3)]
-            shape = (5, n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG)
-            self.offsets.append(off)
-            self.shapes.append(shape)
-            off += (int(np.prod(shape)) + 31) // 32 * 32
-        self.total = off
         dev = torch.device("cuda", torch.cuda.current_device())
-        self.UA = torch.full((self.total,), float("nan"), dtype=torch.float64, device=dev)
-        self.UB = torch.full((self.total,), float("nan"), dtype=torch.float64, device=dev)
+        self.lv = []
+        for boxes in self.levels:
+            offsets, shapes, off = [], [], 0
+            for lo, hi in boxes:
+                n = [hi[d] - lo[d] + 1 for d in range(3)]
+                shape = (5, n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG)
+                offsets.append(off)
+                shapes.append(shape)
+                off += (int(np.prod(shape)) + 31) // 32 * 32
+            A = torch.full((off,), float("nan"), dtype=torch.float64, device=dev)
+            B = torch.full((off,), float("nan"), dtype=torch.float64, device=dev)
+            self.lv.append({"boxes": boxes, "offsets": offsets, "shapes": shapes, "total": off, "A": A, "B": B})
         ws = ctypes.c_size_t()
         best = 0
-        for f in (FORM_PER_BOX, FORM_BATCHED):
-            L.ctuppm_workspace_bytes(ctx.h, self.pid, f, ctypes.byref(ws))
+        for f in ((FORM_BATCHED,) if nl == 2 else (FORM_PER_BOX, FORM_BATCHED)):
+            ctx.call("ctuppm_workspace_bytes", self.pid, f, ctypes.byref(ws))
             best = max(best, ws.value)
         self.ws = torch.empty((max(best, 256),), dtype=torch.uint8, device=dev)
-        self.upload(prob.U0)
+        self.upload(prob.U0, prob.U0_fine)
         ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel())
         if fixed_dt:
             ctx.call("ctuppm_set_fixed_dt", self.pid, float(fixed_dt))
 
-    def _bind(self):
-        nb = len(self.prob.boxes)
-        a = (ctypes.c_void_p * nb)(*[self.UA.data_ptr() + 8 * o for o in self.offsets])
-        b = (ctypes.c_void_p * nb)(*[self.UB.data_ptr() + 8 * o for o in self.offsets])
-        self.ctx.call("ctuppm_bind_state", self.pid, 0, a, b)
+    # backwards-compatible views of level 0
+    @property
+    def UA(self):
+        return self.lv[0]["A"]
 
-    def upload(self, Uvalid: np.ndarray):
-        """Copy a level state (5, nz, ny, nx) into the A fabs; ghosts NaN."""
-        host = np.full(self.total, np.nan)
-        for (box, off, shape) in zip(self.prob.boxes, self.offsets, self.shapes):
-            host[off:off + int(np.prod(shape))] = W.grown_fab(Uvalid, box).ravel()
-        self.UA.copy_(self.ctx.torch.from_numpy(host))
-        self.UB.fill_(float("nan"))
-        self._bind()
+    @property
+    def UB(self):
+        return self.lv[0]["B"]
+
+    def _bind(self, level: int):
+        L = self.lv[level]
+        nb = len(L["boxes"])
+        a = (ctypes.c_void_p * nb)(*[L["A"].data_ptr() + 8 * o for o in L["offsets"]])
+        b = (ctypes.c_void_p * nb)(*[L["B"].data_ptr() + 8 * o for o in L["offsets"]])
+        self.ctx.call("ctuppm_bind_state", self.pid, level, a, b)
+
+    def upload(self, Uvalid: np.ndarray, Ufine: Optional[np.ndarray] = None):
+        """Copy a level-0 state (5, nz, ny, nx) (and the fine rectangle's state)
+        into the A fabs; ghosts NaN."""
+        for level, (U, origin) in enumerate([(Uvalid, (0, 0, 0)), (Ufine, self.prob.fine_lo)][:len(self.lv)]):
+            L = self.lv[level]
+            host = np.full(L["total"], np.nan)
+            for box, off, shape in zip(L["boxes"], L["offsets"], L["shapes"]):
+                host[off:off + int(np.prod(shape))] = W.grown_fab(U, box, origin=origin).ravel()
+            L["A"].copy_(self.ctx.torch.from_numpy(host))
+            L["B"].fill_(float("nan"))
+            self._bind(level)
 
     def step(self, nsteps: int = 1, form=None):
         f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
@@ -234,13 +254,21 @@ class Solver:
         self.ctx.call("ctuppm_current_state", self.pid, ctypes.byref(w))
         return w.value
 
-    def fabs(self) -> List[np.ndarray]:
-        t = (self.UA if self.current() == 0 else self.UB).cpu().numpy()
-        return [t[o:o + int(np.prod(s))].reshape(s) for o, s in zip(self.offsets, self.shapes)]
+    def fabs(self, level: int = 0) -> List[np.ndarray]:
+        L = self.lv[level]
+        # the fine level takes two substeps per step and is back in its A fabs
+        which = self.current() if level == 0 else 0
+        t = (L["A"] if which == 0 else L["B"]).cpu().numpy()
+        return [t[o:o + int(np.prod(s))].reshape(s) for o, s in zip(L["offsets"], L["shapes"])]
 
     def state(self) -> np.ndarray:
-        """Valid cells of the current state, (5, nz, ny, nx)."""
-        return W.gather_valid(self.fabs(), self.prob.boxes, self.prob.n)
+        """Valid cells of the current level-0 state, (5, nz, ny, nx)."""
+        return W.gather_valid(self.fabs(0), self.prob.boxes, self.prob.n)
+
+    def state_fine(self) -> np.ndarray:
+        """Valid cells of the fine rectangle's current state."""
+        nf = self.prob.U0_fine.shape[1:][::-1]
+        return W.gather_valid(self.fabs(1), self.prob.fine_boxes, nf, origin=self.prob.fine_lo)
 
     def dt(self) -> float:
         v = ctypes.c_double()
