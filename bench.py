@@ -56,9 +56,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="kh256", choices=["kh256", "sod32", "rt384", "cloud256", "serving"],
+                    help="kh256: 256^3 KH in 64 boxes of 64^3 (default); sod32: 32^3 Sod, one box; rt384: "
+                         "384^3 RT in seeded uneven boxes; cloud256: two-level cloud in a Mach-2 wind; serving: "
+                         "Poisson stream of independent problems")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
+    ap.add_argument("--requests", type=int, default=200, help="serving: requests per arrival rate")
+    ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-forms", action="store_true", help="time only the requested form")
@@ -83,10 +89,32 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8}))
         return
-    prob = W.kelvin_helmholtz(n=args.n, box=args.box)
+    if args.workload == "serving":
+        return bench_serving(args)
+    if args.workload == "sod32":
+        prob = W.sod(n=32, steps=20)
+        args.form = "per_box" if args.form == "graph" and "--form" not in sys.argv else args.form
+        wname = "sod_32^3_single_box_outflow_x"
+    elif args.workload == "rt384":
+        prob = W.rayleigh_taylor(n=384)
+        wname = f"rayleigh_taylor_384^3_{len(prob.boxes)}_uneven_boxes_gz-1"
+    elif args.workload == "cloud256":
+        prob = W.cloud_wind(n=256, box=64, fine_box=32)
+        args.form = "batched" if args.form == "per_box" else args.form
+        wname = "cloud_wind_two_level_256^3_64x64^3_fine_256^3_512x32^3"
+    else:
+        prob = W.kelvin_helmholtz(n=args.n, box=args.box)
+        wname = f"kelvin_helmholtz_{args.n}^3_{(args.n // args.box) ** 3}x{args.box}^3_periodic"
     ctx = ctuppm.Context()
     solver = ctuppm.Solver(ctx, prob, form=args.form)
-    zones = prob.zones
+    two_level = prob.fine_boxes is not None
+    # zone-updates per step: the fine level takes two substeps per coarse step
+    zones = prob.zones + (2 * int(prob.U0_fine[0].size) if two_level else 0)
+    tuning = None
+    if args.tune:
+        from paper_1711_06203_amd import autotune
+        tuning = autotune.tune(ctx, [solver], steps=3, cache=None)
+        solver.upload(prob.U0, prob.U0_fine)
 
     def timed(form, steps, warm):
         solver.step(warm, form=form)
@@ -101,6 +129,8 @@ def main():
     value = zones * args.steps / el
     forms = {args.form: value}
     for f in ("per_box", "batched", "graph"):
+        if two_level and f == "per_box":
+            continue
         if f not in forms and not args.skip_forms:
             k = max(3, args.steps // 5)
             forms[f] = zones * k / timed(f, k, 1)
@@ -129,8 +159,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"kelvin_helmholtz_{args.n}^3_{(args.n // args.box) ** 3}x{args.box}^3_periodic",
-                   "form": args.form, "zones": zones, "gamma": prob.gamma, "cfl": prob.cfl},
+        "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
+                   "gamma": prob.gamma, "cfl": prob.cfl, "tuning": tuning and {k: tuning[k] for k in
+                                                                               ("blocks_per_cu", "zseg")}},
         "forms": {k: v for k, v in forms.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -142,8 +173,41 @@ def main():
     ctx.close()
     del solver
     torch.cuda.empty_cache()
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "kh256":
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Poisson streams of independent periodic problems (N in {32,...,128}, 50
+    steps each) at 0.5, 0.8 and 0.95 of the measured saturated capacity."""
+    import numpy as np
+    import torch
+    from paper_1711_06203_amd import ctuppm, serving
+    ctx = ctuppm.Context()
+    # capacity: all requests present at t = 0 (saturated continuous batching)
+    reqs = serving.poisson_requests(args.requests, rate=0.0, seed=11)
+    srv = serving.Server(ctx, hbm_budget=64e9)
+    t0 = time.perf_counter()
+    res = srv.run(reqs, realtime=True)
+    el = time.perf_counter() - t0
+    capacity = len(res) / el
+    lines = {"saturated": {"requests_per_s": capacity, "zone_updates_per_s": srv.zone_updates / el,
+                           "mean_batch": float(np.mean(srv.batch_sizes)), **serving.latency_stats(res)}}
+    for frac in (0.5, 0.8, 0.95):
+        reqs = serving.poisson_requests(args.requests, rate=frac * capacity, seed=12 + int(100 * frac))
+        srv = serving.Server(ctx, hbm_budget=64e9)
+        t0 = time.perf_counter()
+        res = srv.run(reqs, realtime=True)
+        el = time.perf_counter() - t0
+        lines[f"rate_{frac}"] = {"arrival_rate_per_s": frac * capacity, "zone_updates_per_s": srv.zone_updates / el,
+                                 "mean_batch": float(np.mean(srv.batch_sizes)), **serving.latency_stats(res)}
+        print(json.dumps({"serving": lines[f"rate_{frac}"], "frac": frac}), file=sys.stderr, flush=True)
+    out = {"metric": "p50/p99 solve latency of a served stream (FP64 CTU/PPM)", "value": lines["rate_0.8"]["p99_s"],
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "serving_periodic_N^3_N_in_32-128_50_steps",
+                                            "requests_per_rate": args.requests, "hbm_budget_bytes": 64e9},
+           "serving": lines}
     print(json.dumps(out), flush=True)
 
 

@@ -119,6 +119,18 @@ int ctuppm_set_fixed_dt(ctuppm_ctx* ctx, int pid, double dt);
  * reflux.  Asynchronous. */
 int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
 
+/* One step of a single-level problem with the retry criterion of the paper's
+ * retry mechanism (section 3.2, a step redone on criteria evaluated during the
+ * integration): after the step (synchronising), if any new cell failed
+ * (rho < small_dens, p < small_pres or non-finite, counter [4] of
+ * ctuppm_status), the step is rejected -- U^n is still intact in the other fab
+ * -- and redone as two steps of half the rejected dt.  *retried = 1 then. */
+int ctuppm_step_checked(ctuppm_ctx* ctx, int pid, int form, int* retried);
+/* Test hook: the update flags one failed cell at step index step_index
+ * (0-based count of accepted steps), -1 turns it off.  Forced from the host so
+ * every kernel still runs to completion. */
+int ctuppm_set_fail_hook(ctuppm_ctx* ctx, int pid, int step_index);
+
 /* Which fab (0 = A, 1 = B) holds the current state of problem pid. */
 int ctuppm_current_state(ctuppm_ctx* ctx, int pid, int* which);
 /* dt of the last step (synchronises the stream). */

@@ -939,6 +939,7 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
     h.rdx[d] = 1.0 / prm->dx[d];
   }
   h.nlevels = nlevels;
+  h.fail_step = -1;
   HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
   HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
   if (nlevels == 2) {
@@ -1073,6 +1074,46 @@ int ctuppm_step(ctuppm_ctx* c, const int* pids, int npids, int form) {
     P->cur ^= 1;
     P->steps += 1;
   }
+  return CTUPPM_OK;
+}
+
+int ctuppm_step_checked(ctuppm_ctx* c, int pid, int form, int* retried) {
+  if (!c || !retried) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (P->nlevels != 1) return fail(c, CTUPPM_EINVAL, "checked steps are for single-level problems");
+  *retried = 0;
+  long long before[6], after[6];
+  int rc = ctuppm_status(c, pid, before);
+  if (rc) return rc;
+  if ((rc = ctuppm_step(c, &pid, 1, form))) return rc;
+  if ((rc = ctuppm_status(c, pid, after))) return rc;
+  if (after[4] == before[4]) return CTUPPM_OK;
+  // rejected: U^n is intact in the other fab; undo the flip and the step count
+  ProbDev h;
+  HIPCHK(c, hipMemcpy(&h, P->dP, sizeof(ProbDev), hipMemcpyDeviceToHost));
+  const double dt = h.dt, keep_fixed = h.fixed_dt;
+  h.cur ^= 1;
+  h.nsteps -= 1;
+  h.fail_step = -1;
+  h.fixed_dt = 0.5 * dt;
+  HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
+  P->cur ^= 1;
+  P->steps -= 1;
+  for (int half = 0; half < 2; ++half)
+    if ((rc = ctuppm_step(c, &pid, 1, form))) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&P->dP->fixed_dt, &keep_fixed, sizeof(double), hipMemcpyHostToDevice));
+  *retried = 1;
+  return CTUPPM_OK;
+}
+
+int ctuppm_set_fail_hook(ctuppm_ctx* c, int pid, int step_index) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&P->dP->fail_step, &step_index, sizeof(int), hipMemcpyHostToDevice));
   return CTUPPM_OK;
 }
 

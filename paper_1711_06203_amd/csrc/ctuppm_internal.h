@@ -44,7 +44,7 @@ struct ProbDev {
   int cur;                         // which of U[0], U[1] holds the current state
   int nsteps;
   int nlevels;
-  int pad;
+  int fail_step;                   // test hook: the update flags a failure at this step (-1: off)
   // running max of the signal speed as bit patterns (>= 0), one 128-byte
   // line per slot so blocks of one launch do not contend on one address
   unsigned long long smax[kSlots][16];

@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
             "ctuppm_stage_name": [ctypes.c_int],
             "ctuppm_stage_bytes": [vp, ctypes.c_int, ctypes.c_int, dp],
             "ctuppm_set_tuning": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+            "ctuppm_step_checked": [vp, ctypes.c_int, ctypes.c_int, ip],
+            "ctuppm_set_fail_hook": [vp, ctypes.c_int, ctypes.c_int],
             "ctuppm_last_error": [vp],
         }
         for name, args in sig.items():
@@ -89,7 +91,8 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_problem_destroy", "ctuppm_fab_elems", "ctuppm_workspace_bytes", "ctuppm_bind_state",
             "ctuppm_bind_workspace", "ctuppm_set_fixed_dt", "ctuppm_step", "ctuppm_current_state",
             "ctuppm_get_dt", "ctuppm_status", "ctuppm_set_timing", "ctuppm_stage_times", "ctuppm_num_stages",
-            "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning"]
+            "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning", "ctuppm_step_checked",
+            "ctuppm_set_fail_hook"]
 
 
 class Context:
@@ -248,6 +251,16 @@ class Solver:
     def step(self, nsteps: int = 1, form=None):
         f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
         self.ctx.step([self], f, nsteps)
+
+    def step_checked(self, form=None) -> bool:
+        """One step with the retry criterion; True if it was redone as two half steps."""
+        f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
+        r = ctypes.c_int()
+        self.ctx.call("ctuppm_step_checked", self.pid, f, ctypes.byref(r))
+        return bool(r.value)
+
+    def set_fail_hook(self, step_index: int):
+        self.ctx.call("ctuppm_set_fail_hook", self.pid, int(step_index))
 
     def current(self) -> int:
         w = ctypes.c_int()

@@ -1,0 +1,59 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py times.
+
+The GPU takes one step of the whole 256^3 (64 boxes) and 384^3 (uneven
+boxes) workloads in the graph form; the oracle computes sampled cells one by
+one from their 9^3 neighbourhoods of the same initial state (ghosts filled by
+the oracle), with the dt it computes itself from the whole initial state."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_06203_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1711_06203_amd import ctuppm
+    c = ctuppm.Context()
+    yield c
+    c.close()
+
+
+def _sampled(ctx, prob, nsamp, seed):
+    from paper_1711_06203_amd import ctuppm
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(1)
+    got = s.state()
+    dt_gpu = s.dt()
+    s.close()
+    ctx.torch.cuda.empty_cache()
+    P = oracle.params_of(prob)
+    G = oracle.fill_domain(oracle.grow(prob.U0), P)
+    dt = P.cfl / oracle.signal_speed(G, P)
+    assert dt_gpu == dt
+    rng = np.random.default_rng(seed)
+    n = prob.n
+    cells = [tuple(int(rng.integers(n[d])) for d in range(3)) for _ in range(nsamp)]
+    # always include box corners and domain faces
+    for (lo, hi) in prob.boxes[:8]:
+        cells.append(tuple(lo))
+        cells.append(tuple(hi))
+    cells += [(0, 0, 0), (n[0] - 1, n[1] - 1, n[2] - 1), (0, n[1] - 1, 0)]
+    want = oracle.sample_step(G, P, dt, cells)
+    for c, w in zip(cells, want):
+        g = got[:, c[2], c[1], c[0]]
+        assert np.array_equal(g, w), (c, g, w)
+
+
+@pytest.mark.slow
+def test_kh256_one_step_sampled(ctx):
+    _sampled(ctx, W.kelvin_helmholtz(n=256, box=64), 400, 1)
+
+
+@pytest.mark.slow
+def test_rt384_uneven_one_step_sampled(ctx):
+    prob = W.rayleigh_taylor(n=384)
+    assert len(prob.boxes) > 500
+    _sampled(ctx, prob, 400, 2)

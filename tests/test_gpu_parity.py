@@ -118,3 +118,31 @@ def test_forms_bitwise_equal(ctx):
     prob = W.rayleigh_taylor(n=48, seed=5, boxes=W.uneven_boxes((48, 48, 48), 5, edges=(16, 32)))
     res = [_run_gpu(ctx, prob, 3, f)[0] for f in ("per_box", "batched", "graph")]
     assert np.array_equal(res[0], res[1]) and np.array_equal(res[1], res[2])
+
+
+def test_retry_equals_explicit_half_steps(ctx):
+    # a failure forced at step 2 (host hook) makes the checked step redo it as
+    # two half steps; the result must equal running those half steps directly
+    from paper_1711_06203_amd import ctuppm
+    prob = W.kelvin_helmholtz(n=24, box=12, seed=3)
+    a = ctuppm.Solver(ctx, prob, form="batched")
+    a.set_fail_hook(2)
+    flags = [a.step_checked() for _ in range(4)]
+    assert flags == [False, False, True, False]
+    got = a.state()
+    a.close()
+    b = ctuppm.Solver(ctx, prob, form="batched")
+    b.step(2)
+    dt2 = None
+    ref_state = b.state()
+    # dt of step 2 from the state after two steps, by the oracle's CFL rule
+    P = oracle.params_of(prob)
+    G = oracle.fill_domain(oracle.grow(ref_state), P)
+    dt2 = P.cfl / oracle.signal_speed(G, P)
+    ctx.call("ctuppm_set_fixed_dt", b.pid, 0.5 * dt2)
+    b.step(2)
+    ctx.call("ctuppm_set_fixed_dt", b.pid, 0.0)
+    b.step(1)
+    want = b.state()
+    b.close()
+    assert np.array_equal(got, want)
