@@ -26,6 +26,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources, to tell whether a stored counter summary was
+    taken on the kernels that run now."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1711_06203_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the plain-copy calibration),
+    or None when there is none for this workload or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(f"bytes_per_launch[{kernel}]")
+    return float(v) if v else None
+
+
 def cpu_baseline(prob, seconds: float = 12.0):
     """Oracle on one 64^3 box of the same initial state (ghosts from the
     filled whole-domain state), advanced repeatedly until ~`seconds` pass."""
@@ -68,9 +100,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-forms", action="store_true", help="time only the requested form")
+    ap.add_argument("--print-hash", action="store_true", help="print the kernel source hash and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 10 plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.print_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the box decomposition would shard across GPUs; see DESIGN.md)", file=sys.stderr)
@@ -135,16 +171,21 @@ def main():
             k = max(3, args.steps // 5)
             forms[f] = zones * k / timed(f, k, 1)
 
-    # dominant kernel: event-timed stage launches of the batched form
+    # dominant kernel: event-timed stage launches of the batched form (the same
+    # kernels and grids the graph replays), on the stream they run on
+    tsteps = max(3, args.steps // 5)
     ctx.set_timing(True)
-    solver.step(max(3, args.steps // 5), form="batched")
+    solver.step(tsteps, form="batched")
     ctx.set_timing(False)
     st = ctx.stage_times()
     sbytes = solver.stage_bytes()
     stage_avg = {k: (ms / n if n else 0.0) for k, (ms, n) in st.items()}
     dom = max(st, key=lambda k: st[k][0])
     avg_ms = stage_avg[dom]
-    achieved = sbytes[dom] / (avg_ms * 1e-3) / 1e9
+    launches_per_step = st[dom][1] / tsteps
+    # algorithmic bytes of the stage per step over its launch time per step
+    achieved = sbytes[dom] / (avg_ms * launches_per_step * 1e-3) / 1e9
+    traffic = measured_traffic(dom, args.workload)
     cnt = solver.counters()
     out = {
         "metric": "zone-updates/s FP64 (unsplit CTU/PPM advance)",
@@ -164,8 +205,8 @@ def main():
                                                                                ("blocks_per_cu", "zseg")}},
         "forms": {k: v for k, v in forms.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": sbytes[dom], "avg_launch_ms": avg_ms},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": sbytes[dom] / launches_per_step, "avg_launch_ms": avg_ms},
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items() if v},
         "counters": [int(c) for c in cnt],
     }
