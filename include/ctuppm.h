@@ -161,6 +161,10 @@ int ctuppm_stage_bytes(ctuppm_ctx* ctx, int pid, int stage, double* bytes);
  * do not depend on the tuning (each cell's arithmetic is the same); graphs are
  * re-captured and work lists rebuilt on the next step. */
 int ctuppm_set_tuning(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int zseg_per_box);
+/* As ctuppm_set_tuning, plus the rows per tile the work units of a plane are
+ * grouped into (0: the whole plane), which sets how far apart in the work list
+ * a unit and its z neighbour are. */
+int ctuppm_set_tuning2(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int zseg_per_box, int ytile);
 
 #ifdef __cplusplus
 }

@@ -1,8 +1,9 @@
 """Autotuner of the launch shapes of the batched form.
 
-Tunables (``ctuppm_set_tuning``): blocks per CU of the launches (0 = one
+Tunables (``ctuppm_set_tuning2``): blocks per CU of the launches (0 = one
 block per work unit, else a persistent grid of that many blocks per CU
-walking the units) and the z planes a work unit marches through.  Every
+walking the units), the z planes a work unit marches through, and the rows
+per tile the units of a plane are grouped into.  Every
 choice gives bitwise the same results (each cell's arithmetic is fixed), so
 the tuner only times: it runs a few event-timed eager steps per candidate on
 the caller's problems and keeps the fastest.  Choices are cached in a JSON
@@ -17,7 +18,9 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 
 from . import ctuppm
 
-DEFAULT_CANDIDATES: Tuple[Tuple[int, int], ...] = ((0, 1), (0, 2), (0, 4), (8, 1), (16, 1), (4, 2), (16, 4))
+# (blocks_per_cu, zseg, ytile)
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int], ...] = ((0, 1, 0), (0, 2, 0), (0, 1, 4), (0, 1, 8), (0, 2, 8),
+                                                        (0, 4, 8), (16, 1, 0), (16, 2, 8))
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 
@@ -41,9 +44,9 @@ def _time_steps(ctx: ctuppm.Context, solvers, steps: int) -> float:
     return sum(ms for ms, n in st.values()) / steps
 
 
-def tune(ctx: ctuppm.Context, solvers: Sequence[ctuppm.Solver], candidates: Iterable[Tuple[int, int]] = DEFAULT_CANDIDATES,
+def tune(ctx: ctuppm.Context, solvers: Sequence[ctuppm.Solver], candidates: Iterable[Tuple[int, ...]] = DEFAULT_CANDIDATES,
          steps: int = 3, cache: Optional[str] = CACHE, use_cache: bool = True) -> dict:
-    """Pick (blocks_per_cu, zseg) for these problems; applies and returns it.
+    """Pick (blocks_per_cu, zseg, ytile) for these problems; applies and returns it.
 
     The problems are advanced by the timing steps (1 + steps per candidate),
     so callers tune on a copy or before loading the real initial state."""
@@ -57,18 +60,21 @@ def tune(ctx: ctuppm.Context, solvers: Sequence[ctuppm.Solver], candidates: Iter
             db = {}
     if use_cache and key in db:
         best = db[key]
-        ctx.set_tuning(best["blocks_per_cu"], best["zseg"], 1)
+        ctx.set_tuning(best["blocks_per_cu"], best["zseg"], 1, best.get("ytile", 0))
         return dict(best, cached=True)
     trials: List[dict] = []
-    for bpc, zseg in candidates:
-        ctx.set_tuning(bpc, zseg, 1)
+    for cand in candidates:
+        bpc, zseg = cand[0], cand[1]
+        ytile = cand[2] if len(cand) > 2 else 0
+        ctx.set_tuning(bpc, zseg, 1, ytile)
         ms = _time_steps(ctx, solvers, steps)
-        trials.append({"blocks_per_cu": bpc, "zseg": zseg, "ms_per_step": ms})
+        trials.append({"blocks_per_cu": bpc, "zseg": zseg, "ytile": ytile, "ms_per_step": ms})
     best = min(trials, key=lambda t: t["ms_per_step"])
-    ctx.set_tuning(best["blocks_per_cu"], best["zseg"], 1)
+    ctx.set_tuning(best["blocks_per_cu"], best["zseg"], 1, best["ytile"])
     out = dict(best, trials=trials, signature=key, when=time.strftime("%Y-%m-%dT%H:%M:%S"))
     if cache:
-        db[key] = {"blocks_per_cu": best["blocks_per_cu"], "zseg": best["zseg"], "ms_per_step": best["ms_per_step"]}
+        db[key] = {"blocks_per_cu": best["blocks_per_cu"], "zseg": best["zseg"], "ytile": best["ytile"],
+                   "ms_per_step": best["ms_per_step"]}
         try:
             with open(cache, "w") as f:
                 json.dump(db, f, indent=1, sort_keys=True)

@@ -140,6 +140,7 @@ struct ctuppm_ctx {
   int blocks_per_cu = 0;  // 0: one block per work unit
   int zseg_batched = 1;   // planes per march unit, batched / graph forms
   int zseg_per_box = 1;   // planes per march unit, per-box form
+  int ytile = 0;          // rows per tile of the march units (0: whole plane)
 };
 
 namespace {
@@ -202,15 +203,20 @@ void chunk_region(std::vector<Chunk>& out, int box, long long items) {
   for (long long s = 0; s < items; s += kBlock) out.push_back(Chunk{box, int(s)});
 }
 
-// March units of one box region: z segments of `zseg` planes, each cut into
-// 256-item pieces of the (x, y) plane; ordered (segment, piece) so adjacent
-// units are y neighbours.
-void march_region(std::vector<March>& out, int box, const int org[3], const int ext[3], int zseg) {
-  const long long plane = (long long)ext[0] * ext[1];
-  for (int z0 = 0; z0 < ext[2]; z0 += zseg) {
-    const int z1 = std::min(ext[2], z0 + zseg);
-    for (long long s = 0; s < plane; s += kBlock)
-      out.push_back(March{box, int(s), org[2] + z0, org[2] + z1});
+// March units of one box region.  The (x, y) plane is cut into tiles of
+// `ytile` rows (0: the whole plane); the units of a tile run through z
+// segments of `zseg` planes, each segment cut into 256-item pieces.  Units are
+// ordered (tile, segment, piece), so a unit's y neighbour is the next unit and
+// its z neighbour a tile's worth of pieces later.
+void march_region(std::vector<March>& out, int box, const int org[3], const int ext[3], int zseg, int ytile) {
+  const int rows = ytile > 0 ? ytile : ext[1];
+  for (int y0 = 0; y0 < ext[1]; y0 += rows) {
+    const int y1 = std::min(ext[1], y0 + rows);
+    const int beg = y0 * ext[0], end = y1 * ext[0];
+    for (int z0 = 0; z0 < ext[2]; z0 += zseg) {
+      const int z1 = std::min(ext[2], z0 + zseg);
+      for (int s = beg; s < end; s += kBlock) out.push_back(March{box, s, end, org[2] + z0, org[2] + z1, 0});
+    }
   }
 }
 
@@ -444,7 +450,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
       int org[3], ext[3];
       region_of(k, boxes[b].n, org, ext);
       S->box_beg[k][b] = int(ch[k].size());
-      march_region(ch[k], b, org, ext, zseg);
+      march_region(ch[k], b, org, ext, zseg, c->ytile);
       S->box_cnt[k][b] = int(ch[k].size()) - S->box_beg[k][b];
     }
     S->nch[k] = int(ch[k].size());
@@ -1181,8 +1187,13 @@ int ctuppm_num_stages(void) { return kNumStages; }
 const char* ctuppm_stage_name(int s) { return stage_name(s); }
 
 int ctuppm_set_tuning(ctuppm_ctx* c, int bpc, int zb, int zp) {
-  if (!c || bpc < 0 || zb < 1 || zp < 1) return CTUPPM_EINVAL;
+  return ctuppm_set_tuning2(c, bpc, zb, zp, c ? c->ytile : 0);
+}
+
+int ctuppm_set_tuning2(ctuppm_ctx* c, int bpc, int zb, int zp, int ytile) {
+  if (!c || bpc < 0 || zb < 1 || zp < 1 || ytile < 0) return CTUPPM_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->ytile = ytile;
   c->blocks_per_cu = bpc;
   c->zseg_batched = zb;
   c->zseg_per_box = zp;

@@ -63,9 +63,10 @@ struct BoxRec {
 
 struct Chunk { int box; int start; };  // tag index, first item (ghost-fill work lists)
 
-// Column-march work unit: items [start, start+256) of the (x, y) plane of a
-// box region, for the box-local planes z in [z0, z1), visited in order.
-struct March { int box; int start; int z0; int z1; };
+// Column-march work unit: items [start, min(start+256, end)) of the (x, y)
+// plane of a box region (i fastest), for the box-local planes z in [z0, z1),
+// visited in order.
+struct March { int box; int start; int end; int z0; int z1; int pad; };
 
 // Same-level ghost copy: dst-local cells [lo, lo+ext) <- src-local (cell + off).
 struct FillTag { int dst, src; int lo[3]; int ext[3]; int off[3]; int pad; };

@@ -39,7 +39,7 @@ CTU_DEV void march(int kind, const BoxRec& B, const March& M, F&& f) {
   int org[3], ext[3];
   region_of(kind, B.n, org, ext);
   const int t = M.start + threadIdx.x;
-  if (t >= ext[0] * ext[1]) return;
+  if (t >= M.end) return;
   const int i = t % ext[0] + org[0];
   const int j = t / ext[0] + org[1];
   for (int k = M.z0; k < M.z1; ++k) f(i, j, k);

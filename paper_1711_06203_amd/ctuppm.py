@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "ctuppm_stage_name": [ctypes.c_int],
             "ctuppm_stage_bytes": [vp, ctypes.c_int, ctypes.c_int, dp],
             "ctuppm_set_tuning": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+            "ctuppm_set_tuning2": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
             "ctuppm_step_checked": [vp, ctypes.c_int, ctypes.c_int, ip],
             "ctuppm_set_fail_hook": [vp, ctypes.c_int, ctypes.c_int],
             "ctuppm_last_error": [vp],
@@ -92,7 +93,7 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_bind_workspace", "ctuppm_set_fixed_dt", "ctuppm_step", "ctuppm_current_state",
             "ctuppm_get_dt", "ctuppm_status", "ctuppm_set_timing", "ctuppm_stage_times", "ctuppm_num_stages",
             "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning", "ctuppm_step_checked",
-            "ctuppm_set_fail_hook"]
+            "ctuppm_set_fail_hook", "ctuppm_set_tuning2"]
 
 
 class Context:
@@ -139,8 +140,8 @@ class Context:
         self.call("ctuppm_stage_times", ms, cnt, n)
         return {self._L.ctuppm_stage_name(s).decode(): (ms[s], cnt[s]) for s in range(n)}
 
-    def set_tuning(self, blocks_per_cu: int = 0, zseg_batched: int = 1, zseg_per_box: int = 1):
-        self.call("ctuppm_set_tuning", int(blocks_per_cu), int(zseg_batched), int(zseg_per_box))
+    def set_tuning(self, blocks_per_cu: int = 0, zseg_batched: int = 1, zseg_per_box: int = 1, ytile: int = 0):
+        self.call("ctuppm_set_tuning2", int(blocks_per_cu), int(zseg_batched), int(zseg_per_box), int(ytile))
 
     def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1):
         """Advance several problems together (one batched launch set per step)."""

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     txt = open(os.path.join(ROOT, "include", "ctuppm.h")).read()
-    return sorted(set(re.findall(r"\b(ctuppm_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(ctuppm_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():

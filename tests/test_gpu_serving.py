@@ -76,8 +76,8 @@ def test_tuning_does_not_change_results(ctx):
     from paper_1711_06203_amd import autotune, ctuppm
     prob = W.rayleigh_taylor(n=48, seed=8, boxes=W.uneven_boxes((48, 48, 48), 8, edges=(16, 32)))
     outs = []
-    for bpc, zseg in ((0, 1), (16, 4), (4, 3)):
-        ctx.set_tuning(bpc, zseg, 2)
+    for bpc, zseg, ytile in ((0, 1, 0), (16, 4, 3), (4, 3, 8)):
+        ctx.set_tuning(bpc, zseg, 2, ytile)
         s = ctuppm.Solver(ctx, prob, form="graph")
         s.step(3)
         outs.append(s.state())
@@ -85,7 +85,7 @@ def test_tuning_does_not_change_results(ctx):
     ctx.set_tuning(0, 1, 1)
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
     s = ctuppm.Solver(ctx, prob, form="batched")
-    best = autotune.tune(ctx, [s], candidates=((0, 1), (8, 2)), steps=1, cache=None)
+    best = autotune.tune(ctx, [s], candidates=((0, 1, 0), (8, 2, 4)), steps=1, cache=None)
     assert best["blocks_per_cu"] in (0, 8) and best["ms_per_step"] > 0
     s.close()
     ctx.set_tuning(0, 1, 1)
