@@ -57,3 +57,61 @@ def test_rt384_uneven_one_step_sampled(ctx):
     prob = W.rayleigh_taylor(n=384)
     assert len(prob.boxes) > 500
     _sampled(ctx, prob, 400, 2)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [32, 48, 64, 96, 128])
+def test_serving_sizes_ten_steps(ctx, n):
+    from paper_1711_06203_amd import ctuppm
+    from gpu_helpers import max_rel, totals_rel
+    prob = W.serving_request(seed=40 + n, n=n, steps=10)
+    ref, _, _ = oracle.run_problem(prob, 10)
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(10)
+    got = s.state()
+    s.close()
+    print(f"serving N={n}: bitwise={np.array_equal(got, ref)}", flush=True)
+    assert max(max_rel(got, ref)) <= 1e-10 and max(totals_rel(got, ref)) <= 1e-13
+
+
+@pytest.mark.slow
+def test_kh256_ten_steps_full(ctx):
+    from paper_1711_06203_amd import ctuppm
+    from gpu_helpers import l1_rel, totals_rel
+    prob = W.kelvin_helmholtz(n=256, box=64)
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(10)
+    got = s.state()
+    s.close()
+    ctx.torch.cuda.empty_cache()
+    ref, _, cnt = oracle.run_problem(prob, 10)
+    print(f"kh256 10 steps: bitwise={np.array_equal(got, ref)}", flush=True)
+    assert max(l1_rel(got, ref)) <= 1e-8 and max(totals_rel(got, ref)) <= 1e-13
+    assert not cnt.any()
+
+
+@pytest.mark.slow
+def test_rt96_twenty_steps(ctx):
+    from paper_1711_06203_amd import ctuppm
+    from gpu_helpers import l1_rel
+    prob = W.rayleigh_taylor(n=96, seed=6)
+    ref, _, _ = oracle.run_problem(prob, 20)
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(20)
+    got = s.state()
+    s.close()
+    assert max(l1_rel(got, ref)) <= 1e-8
+
+
+@pytest.mark.slow
+def test_cloud_two_level_64_twenty_steps(ctx):
+    from paper_1711_06203_amd import ctuppm
+    from gpu_helpers import l1_rel
+    prob = W.cloud_wind(n=64, box=32, fine_box=32)
+    rc, rf, _, _ = oracle.run_two_level(prob, 20)
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(20)
+    gc, gf = s.state(), s.state_fine()
+    s.close()
+    print(f"cloud64 20 steps: bitwise coarse={np.array_equal(gc, rc)} fine={np.array_equal(gf, rf)}", flush=True)
+    assert max(l1_rel(gc, rc)) <= 1e-8 and max(l1_rel(gf, rf)) <= 1e-8
