@@ -40,12 +40,16 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+MAXSPEC = 16
+
+
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("small_dens", ctypes.c_double), ("small_pres", ctypes.c_double),
                 ("grav_z", ctypes.c_double), ("dx", ctypes.c_double * 3),
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3),
-                ("inflow", ctypes.c_double * 5)]
+                ("inflow", ctypes.c_double * 5), ("nspec", ctypes.c_int), ("pad", ctypes.c_int),
+                ("inflow_X", ctypes.c_double * MAXSPEC)]
 
 
 class Stages(ctypes.Structure):
@@ -102,8 +106,12 @@ def _ip(seq):
 
 
 def make_params(gamma, dx, cfl=0.5, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), grav_z=0.0,
-                inflow=(1.0, 0.0, 0.0, 0.0, 1.0), small_dens=1e-12, small_pres=1e-12) -> Params:
+                inflow=(1.0, 0.0, 0.0, 0.0, 1.0), small_dens=1e-12, small_pres=1e-12, nspec=0,
+                inflow_X=()) -> Params:
     P = Params()
+    P.nspec = int(nspec)
+    for s_, v in enumerate(inflow_X):
+        P.inflow_X[s_] = v
     P.gamma, P.cfl, P.small_dens, P.small_pres, P.grav_z = gamma, cfl, small_dens, small_pres, grav_z
     for d in range(3):
         P.dx[d] = dx[d]
@@ -119,13 +127,13 @@ def params_of(prob, fine: bool = False) -> Params:
     if fine:
         dx = tuple(v / 2.0 for v in dx)
     return make_params(prob.gamma, dx, prob.cfl, prob.bc_lo, prob.bc_hi, prob.grav_z, prob.inflow,
-                       prob.small_dens, prob.small_pres)
+                       prob.small_dens, prob.small_pres, getattr(prob, "nspec", 0), getattr(prob, "inflow_X", ()))
 
 
 def grow(Uvalid: np.ndarray, fill=np.nan) -> np.ndarray:
     """Whole-domain valid state (5, nz, ny, nx) -> grown array with ghost cells."""
     nz, ny, nx = Uvalid.shape[1:]
-    G = np.full((5, nz + 2 * NG, ny + 2 * NG, nx + 2 * NG), fill)
+    G = np.full((Uvalid.shape[0], nz + 2 * NG, ny + 2 * NG, nx + 2 * NG), fill)
     G[:, NG:NG + nz, NG:NG + ny, NG:NG + nx] = Uvalid
     return G
 
@@ -154,19 +162,22 @@ def advance_box(G: np.ndarray, P: Params, dt: float, stages: bool = False):
     cnt = (ctypes.c_longlong * NCNT)()
     st = None
     arrays: Dict[str, np.ndarray] = {}
+    nv = G.shape[0]
+    if nv != 5 + P.nspec:
+        raise ValueError("state components do not match nspec")
     if stages:
         hs = (nz + 2, ny + 2, nx + 2)
         st = Stages()
-        arrays["q"] = np.full((6,) + G.shape[1:], np.nan)
+        arrays["q"] = np.full((nv + 1,) + G.shape[1:], np.nan)
         arrays["phi"] = np.full((1,) + hs, np.nan)
         st.q = _dp(arrays["q"])
         st.phi = _dp(arrays["phi"])
         for d in range(3):
             for key in ("ql", "qr", "fn", "ff"):
-                arrays[f"{key}{d}"] = np.full((5,) + hs, np.nan)
+                arrays[f"{key}{d}"] = np.full((nv,) + hs, np.nan)
                 getattr(st, key)[d] = _dp(arrays[f"{key}{d}"])
         for p in range(6):
-            arrays[f"f1{p}"] = np.full((5,) + hs, np.nan)
+            arrays[f"f1{p}"] = np.full((nv,) + hs, np.nan)
             st.f1[p] = _dp(arrays[f"f1{p}"])
     rc = lib().orc_advance_box(_dp(G), _ip(n), ctypes.byref(P), float(dt), _dp(Gn), cnt,
                                ctypes.byref(st) if st is not None else None)
@@ -231,8 +242,8 @@ def sample_step(Ufull_grown_filled: np.ndarray, P: Params, dt: float,
                 cells: Sequence[Tuple[int, int, int]]) -> np.ndarray:
     """U^{n+1} at chosen cells (i, j, k), each computed on its own from the 9^3
     neighbourhood of a whole-domain grown array whose ghosts are filled."""
-    out = np.zeros((len(cells), 5))
     G = Ufull_grown_filled
+    out = np.zeros((len(cells), G.shape[0]))
     for s, (i, j, k) in enumerate(cells):
         loc = np.ascontiguousarray(G[:, k:k + 2 * NG + 1, j:j + 2 * NG + 1, i:i + 2 * NG + 1])
         Gn, _ = advance_box(loc, P, dt)
@@ -274,8 +285,8 @@ def cf_interp(Uc_region: np.ndarray, region_lo, fine_cells) -> np.ndarray:
     fc = np.asarray(fine_cells, dtype=np.int64)
     par = fc // 2
     loc = par - np.asarray(region_lo, dtype=np.int64)
-    out = np.empty((5, len(fc)))
-    for m in range(5):
+    out = np.empty((Uc_region.shape[0], len(fc)))
+    for m in range(Uc_region.shape[0]):
         A = Uc_region[m]
         c = A[loc[:, 2], loc[:, 1], loc[:, 0]]
         val = c.copy()
@@ -359,7 +370,7 @@ def two_level_step(Gc: np.ndarray, Gf: np.ndarray, clo, chi, Pc: Params, Pf: Par
     fine_idx = loc + flo
     for sub, theta in enumerate((0.0, 0.5)):
         vals = fine_ghost_values(Rn, Rn1, theta, rlo, fine_idx)
-        for m in range(5):
+        for m in range(Gf.shape[0]):
             Gf[m][loc[:, 2] + NG, loc[:, 1] + NG, loc[:, 0] + NG] = vals[m]
         Gf_new, c2, stf = advance_box(Gf, Pf, dt_f, stages=True)
         cnt += c2

@@ -25,8 +25,14 @@
  * stated formulas parenthesise them and are compiled without contraction
  * (-ffp-contract=off) and without fast-math.
  *
+ * Passive species (mass fractions X_s, conserved rho X_s after rho E) follow
+ * the flow: reconstructed like any primitive, traced with the contact family
+ * (like the transverse velocities), corrected and fluxed like the transverse
+ * momenta (HLLC star state scaled by the same factor), updated conservatively.
+ *
  * Layouts.  A box of n = (nx, ny, nz) valid cells is stored "grown" by 4 ghost
- * cells: U[c][k][j][i], c in 0..4 = (rho, rho u, rho v, rho w, rho E), i fastest,
+ * cells: U[c][k][j][i], c in 0..4 = (rho, rho u, rho v, rho w, rho E), then
+ * c = 5.. the species rho X_s, i fastest,
  * cell (i,j,k) of the box at offset ((c*(nz+8)+k+4)*(ny+8)+j+4)*(nx+8)+i+4.
  * Stage arrays use the "halo-1" geometry, indices -1..n in every direction,
  * offset ((c*(nz+2)+k+1)*(ny+2)+j+1)*(nx+2)+i+1.  A face array for direction d
@@ -37,8 +43,9 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NV 5
 #define NG 4
+#define MAXSPEC 16
+#define MAXV (5 + MAXSPEC)
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_INFLOW = 3 };
 
@@ -51,17 +58,22 @@ typedef struct {
     double dx[3];
     int bc_lo[3], bc_hi[3];
     double inflow[5]; /* rho, u, v, w, p */
+    int nspec;        /* passive species (0..16) */
+    int pad;
+    double inflow_X[MAXSPEC];
 } orc_params;
+
+static int nvar_of(const orc_params *P) { return 5 + P->nspec; }
 
 /* optional stage outputs (NULL entries are allocated internally) */
 typedef struct {
-    double *q;        /* 6 x grown: rho,u,v,w,p,c */
+    double *q;        /* (6 + nspec) x grown: rho,u,v,w,p,c,X_s */
     double *phi;      /* 1 x halo-1 */
-    double *ql[3];    /* 5 x halo-1, permuted primitives, left state of face */
-    double *qr[3];    /* 5 x halo-1, right state of face */
-    double *fn[3];    /* 5 x halo-1, normal fluxes (conserved order) */
-    double *f1[6];    /* 5 x halo-1, stage-1 fluxes, pair index 2a+(b==(a+1)%3?0:1) */
-    double *ff[3];    /* 5 x halo-1, final fluxes */
+    double *ql[3];    /* nvar x halo-1, permuted primitives (+ X_s), left state of face */
+    double *qr[3];    /* nvar x halo-1, right state of face */
+    double *fn[3];    /* nvar x halo-1, normal fluxes (conserved order) */
+    double *f1[6];    /* nvar x halo-1, stage-1 fluxes, pair index 2a+(b==(a+1)%3?0:1) */
+    double *ff[3];    /* nvar x halo-1, final fluxes */
 } orc_stages;
 
 static double omin(double a, double b) { return a < b ? a : b; }
@@ -95,7 +107,7 @@ static int t2of(int d) { return (d + 2) % 3; }
 
 /* Conserved -> primitive for a cell (rho,u,v,w,p,c), with the density and
  * pressure floors; the kinetic energy sums u^2+v^2 first, then w^2. */
-static void cons_to_prim_cell(const double U[5], const orc_params *P, double q[6], long long *cnt) {
+static void cons_to_prim_cell(const double *U, const orc_params *P, double *q, long long *cnt) {
     const double gm1 = P->gamma - 1.0;
     double rho = U[0];
     if (rho < P->small_dens) { rho = P->small_dens; cnt[0]++; }
@@ -105,11 +117,12 @@ static void cons_to_prim_cell(const double U[5], const orc_params *P, double q[6
     if (p < P->small_pres) { p = P->small_pres; cnt[1]++; }
     q[0] = rho; q[1] = u; q[2] = v; q[3] = w; q[4] = p;
     q[5] = sqrt(P->gamma * p / rho);
+    for (int sp = 0; sp < P->nspec; ++sp) q[6 + sp] = U[5 + sp] / rho;
 }
 
 /* Permuted primitive state of a sweep along d (rho, u_n, u_t1, u_t2, p) to the
  * conserved state in global component order. */
-static void perm_prim_to_cons(const double s[5], int d, const orc_params *P, double U[5]) {
+static void perm_prim_to_cons(const double *s, int d, const orc_params *P, double *U) {
     const double rgm1 = 1.0 / (P->gamma - 1.0);
     double rho = s[0];
     U[0] = rho;
@@ -117,26 +130,30 @@ static void perm_prim_to_cons(const double s[5], int d, const orc_params *P, dou
     U[1 + t1of(d)] = rho * s[2];
     U[1 + t2of(d)] = rho * s[3];
     U[4] = s[4] * rgm1 + 0.5 * rho * ((s[1] * s[1] + s[2] * s[2]) + s[3] * s[3]);
+    for (int sp = 0; sp < P->nspec; ++sp) U[5 + sp] = rho * s[5 + sp];
 }
 
 /* Conserved (global order) to the permuted primitive state of a sweep along d,
  * without floors (the caller decides what a non-physical result means). */
-static void cons_to_perm_prim(const double U[5], int d, const orc_params *P, double s[5]) {
+static void cons_to_perm_prim(const double *U, int d, const orc_params *P, double *s) {
     const double gm1 = P->gamma - 1.0;
     double rho = U[0];
     double un = U[1 + d] / rho, ut1 = U[1 + t1of(d)] / rho, ut2 = U[1 + t2of(d)] / rho;
     double ke = 0.5 * rho * ((un * un + ut1 * ut1) + ut2 * ut2);
     s[0] = rho; s[1] = un; s[2] = ut1; s[3] = ut2;
     s[4] = gm1 * (U[4] - ke);
+    for (int sp = 0; sp < P->nspec; ++sp) s[5 + sp] = U[5 + sp] / rho;
 }
 
 /* ------------------------------------------------------------ HLLC flux (O7) */
 
 /* HLLC flux (Toro, Spruce & Speares 1994) with Davis (1988) speed bounds
  * S_L = min(u_L-c_L, u_R-c_R), S_R = max(u_L+c_L, u_R+c_R).  L and R are
- * permuted primitives of a sweep along d; the flux is returned in global
- * conserved order. */
-void orc_hllc(const double L[5], const double R[5], int d, const orc_params *P, double Fg[5]) {
+ * permuted primitives of a sweep along d (species after p); the flux is
+ * returned in global conserved order.  Species X ride the contact: their star
+ * state is the same factor times X_K as the transverse momenta. */
+static void hllc_n(const double *L, const double *R, int d, const orc_params *P, double *Fg) {
+    const int ns = P->nspec;
     const double g = P->gamma, rgm1 = 1.0 / (g - 1.0);
     const double rL = L[0], uL = L[1], vL = L[2], wL = L[3], pL = L[4];
     const double rR = R[0], uR = R[1], vR = R[2], wR = R[3], pR = R[4];
@@ -145,21 +162,23 @@ void orc_hllc(const double L[5], const double R[5], int d, const orc_params *P, 
     const double SR = omax(uL + cL, uR + cR);
     const double EL = pL * rgm1 + 0.5 * rL * ((uL * uL + vL * vL) + wL * wL);
     const double ER = pR * rgm1 + 0.5 * rR * ((uR * uR + vR * vR) + wR * wR);
-    double F[5];
+    double F[MAXV];
     if (SL >= 0.0) {
         double m = rL * uL;
         F[0] = m; F[1] = m * uL + pL; F[2] = m * vL; F[3] = m * wL; F[4] = uL * (EL + pL);
+        for (int sp = 0; sp < ns; ++sp) F[5 + sp] = m * L[5 + sp];
     } else {
         const double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
                           (rL * (SL - uL) - rR * (SR - uR));
         if (Ss >= 0.0 || SR > 0.0) {
             /* one star region: K = L if S* >= 0, else K = R */
             const int left = (Ss >= 0.0);
+            const double *K = left ? L : R;
             const double rK = left ? rL : rR, uK = left ? uL : uR, vK = left ? vL : vR;
             const double wK = left ? wL : wR, pK = left ? pL : pR, EK = left ? EL : ER;
             const double SK = left ? SL : SR;
             const double m = rK * uK;
-            double FK[5], UK[5], Us[5];
+            double FK[MAXV], UK[MAXV], Us[MAXV];
             FK[0] = m; FK[1] = m * uK + pK; FK[2] = m * vK; FK[3] = m * wK; FK[4] = uK * (EK + pK);
             UK[0] = rK; UK[1] = m; UK[2] = rK * vK; UK[3] = rK * wK; UK[4] = EK;
             const double fac = rK * (SK - uK) / (SK - Ss);
@@ -168,10 +187,16 @@ void orc_hllc(const double L[5], const double R[5], int d, const orc_params *P, 
             Us[2] = fac * vK;
             Us[3] = fac * wK;
             Us[4] = fac * (EK / rK + (Ss - uK) * (Ss + pK / (rK * (SK - uK))));
-            for (int c = 0; c < 5; ++c) F[c] = FK[c] + SK * (Us[c] - UK[c]);
+            for (int sp = 0; sp < ns; ++sp) {
+                FK[5 + sp] = m * K[5 + sp];
+                UK[5 + sp] = rK * K[5 + sp];
+                Us[5 + sp] = fac * K[5 + sp];
+            }
+            for (int c = 0; c < 5 + ns; ++c) F[c] = FK[c] + SK * (Us[c] - UK[c]);
         } else {
             double m = rR * uR;
             F[0] = m; F[1] = m * uR + pR; F[2] = m * vR; F[3] = m * wR; F[4] = uR * (ER + pR);
+            for (int sp = 0; sp < ns; ++sp) F[5 + sp] = m * R[5 + sp];
         }
     }
     Fg[0] = F[0];
@@ -179,6 +204,14 @@ void orc_hllc(const double L[5], const double R[5], int d, const orc_params *P, 
     Fg[1 + t1of(d)] = F[2];
     Fg[1 + t2of(d)] = F[3];
     Fg[4] = F[4];
+    for (int sp = 0; sp < ns; ++sp) Fg[5 + sp] = F[5 + sp];
+}
+
+/* Five-component entry point (pins). */
+void orc_hllc(const double L[5], const double R[5], int d, const orc_params *P, double Fg[5]) {
+    orc_params Q = *P;
+    Q.nspec = 0;
+    hllc_n(L, R, d, &Q, Fg);
 }
 
 /* ------------------------------------------------------ PPM pieces (O5, O6) */
@@ -238,27 +271,27 @@ double orc_iminus(double aL, double da, double a6, double sig) {
 }
 
 /* Characteristic tracing of one cell to t + dt/2 (CW84 section 3, reference
- * state form; Colella 1990).  par[m] = (aL, aR, da, a6) of permuted component m,
- * rho, un, c are the cell's centre values.  Returns the left state of the
- * upper face (qL) and the right state of the lower face (qR), before floors. */
-void orc_trace_cell(const double par[5][4], double rho, double un, double c, double dtdx,
-                    double qL[5], double qR[5]) {
+ * state form; Colella 1990).  par[m] = (aL, aR, da, a6) of permuted component
+ * m (ncomp >= 5: species after p ride the contact family like the transverse
+ * velocities), rho, un, c are the cell's centre values.  Returns the left
+ * state of the upper face (qL) and the right state of the lower face (qR),
+ * before floors. */
+static void trace_cell_n(const double (*par)[4], int ncomp, double rho, double un, double c, double dtdx,
+                         double *qL, double *qR) {
     const double lam[3] = {un - c, un, un + c};
-    double I[3][5];
+    double I[3][MAXV];
     const double csq = c * c;
     /* upper face: waves with lam > 0 reach it */
     for (int nu = 0; nu < 3; ++nu) {
         double sig = fabs(lam[nu]) * dtdx;
-        for (int m = 0; m < 5; ++m)
+        for (int m = 0; m < ncomp; ++m)
             I[nu][m] = lam[nu] > 0.0 ? orc_iplus(par[m][1], par[m][2], par[m][3], sig) : par[m][1];
     }
     {
         const double *ref = I[2];
         double bm = -(rho / (2.0 * c)) * (ref[1] - I[0][1]) + (ref[4] - I[0][4]) / (2.0 * csq);
         double b0 = (ref[0] - I[1][0]) - (ref[4] - I[1][4]) / csq;
-        double bt1 = ref[2] - I[1][2];
-        double bt2 = ref[3] - I[1][3];
-        for (int m = 0; m < 5; ++m) qL[m] = ref[m];
+        for (int m = 0; m < ncomp; ++m) qL[m] = ref[m];
         if (lam[0] > 0.0) {
             qL[0] = qL[0] - bm;
             qL[1] = qL[1] - bm * (-(c / rho));
@@ -266,23 +299,24 @@ void orc_trace_cell(const double par[5][4], double rho, double un, double c, dou
         }
         if (lam[1] > 0.0) {
             qL[0] = qL[0] - b0;
-            qL[2] = qL[2] - bt1;
-            qL[3] = qL[3] - bt2;
+            for (int m = 2; m < ncomp; ++m) {
+                if (m == 4) continue;
+                double bt = ref[m] - I[1][m];
+                qL[m] = qL[m] - bt;
+            }
         }
     }
     /* lower face: waves with lam < 0 reach it */
     for (int nu = 0; nu < 3; ++nu) {
         double sig = fabs(lam[nu]) * dtdx;
-        for (int m = 0; m < 5; ++m)
+        for (int m = 0; m < ncomp; ++m)
             I[nu][m] = lam[nu] < 0.0 ? orc_iminus(par[m][0], par[m][2], par[m][3], sig) : par[m][0];
     }
     {
         const double *ref = I[0];
         double bp = (rho / (2.0 * c)) * (ref[1] - I[2][1]) + (ref[4] - I[2][4]) / (2.0 * csq);
         double b0 = (ref[0] - I[1][0]) - (ref[4] - I[1][4]) / csq;
-        double bt1 = ref[2] - I[1][2];
-        double bt2 = ref[3] - I[1][3];
-        for (int m = 0; m < 5; ++m) qR[m] = ref[m];
+        for (int m = 0; m < ncomp; ++m) qR[m] = ref[m];
         if (lam[2] < 0.0) {
             qR[0] = qR[0] - bp;
             qR[1] = qR[1] - bp * (c / rho);
@@ -290,10 +324,19 @@ void orc_trace_cell(const double par[5][4], double rho, double un, double c, dou
         }
         if (lam[1] < 0.0) {
             qR[0] = qR[0] - b0;
-            qR[2] = qR[2] - bt1;
-            qR[3] = qR[3] - bt2;
+            for (int m = 2; m < ncomp; ++m) {
+                if (m == 4) continue;
+                double bt = ref[m] - I[1][m];
+                qR[m] = qR[m] - bt;
+            }
         }
     }
+}
+
+/* Five-component entry point (pins). */
+void orc_trace_cell(const double par[5][4], double rho, double un, double c, double dtdx,
+                    double qL[5], double qR[5]) {
+    trace_cell_n(par, 5, rho, un, c, dtdx, qL, qR);
 }
 
 /* ------------------------------------------------------------ flattening (O4) */
@@ -354,10 +397,11 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
     do {                                         \
         if (!(ptr)) { ptr = xalloc(count); own[nown++] = ptr; } \
     } while (0)
-    NEED(S.q, 6 * gs);
+    const int nv = nvar_of(P), nq = 6 + P->nspec;
+    NEED(S.q, nq * gs);
     NEED(S.phi, hs);
-    for (int d = 0; d < 3; ++d) { NEED(S.ql[d], 5 * hs); NEED(S.qr[d], 5 * hs); NEED(S.fn[d], 5 * hs); NEED(S.ff[d], 5 * hs); }
-    for (int p = 0; p < 6; ++p) NEED(S.f1[p], 5 * hs);
+    for (int d = 0; d < 3; ++d) { NEED(S.ql[d], nv * hs); NEED(S.qr[d], nv * hs); NEED(S.fn[d], nv * hs); NEED(S.ff[d], nv * hs); }
+    for (int p = 0; p < 6; ++p) NEED(S.f1[p], nv * hs);
 #undef NEED
     for (int i = 0; i < nown; ++i) if (!own[i]) return -2;
 
@@ -372,12 +416,12 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
     for (int k = -NG; k < n[2] + NG; ++k)
         for (int j = -NG; j < n[1] + NG; ++j)
             for (int i = -NG; i < n[0] + NG; ++i) {
-                double Uc[5], q[6];
+                double Uc[MAXV], q[MAXV + 1];
                 long long lc[NCNT] = {0, 0, 0, 0, 0};
-                for (int c = 0; c < 5; ++c) Uc[c] = U[gidx(g, c, i, j, k)];
+                for (int c = 0; c < nv; ++c) Uc[c] = U[gidx(g, c, i, j, k)];
                 cons_to_prim_cell(Uc, P, q, lc);
                 c0 += lc[0]; c1 += lc[1];
-                for (int c = 0; c < 6; ++c) S.q[gidx(g, c, i, j, k)] = q[c];
+                for (int c = 0; c < nq; ++c) S.q[gidx(g, c, i, j, k)] = q[c];
             }
 
     /* (a4) flattening coefficient on cells -1..n */
@@ -392,7 +436,8 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
     /* (a5, a6) reconstruction and tracing along each direction, cells -1..n */
     for (int d = 0; d < 3; ++d) {
         const int t1 = t1of(d), t2 = t2of(d);
-        const int comp[5] = {0, 1 + d, 1 + t1, 1 + t2, 4};
+        int comp[MAXV] = {0, 1 + d, 1 + t1, 1 + t2, 4};
+        for (int sp = 0; sp < P->nspec; ++sp) comp[5 + sp] = 6 + sp;
         const int zpos = 1 + (2 - d + 3) % 3; /* permuted position of the z velocity */
 #pragma omp parallel for reduction(+ : c2cnt) schedule(static)
         for (int k = -1; k <= n[2]; ++k)
@@ -401,9 +446,9 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                     int c[3] = {i, j, k};
                     int e[3] = {0, 0, 0};
                     e[d] = 1;
-                    double par[5][4], a[5];
+                    double par[MAXV][4], a[5];
                     double phi = S.phi[hidx(g, 0, i, j, k)];
-                    for (int m = 0; m < 5; ++m) {
+                    for (int m = 0; m < nv; ++m) {
                         for (int s = -2; s <= 2; ++s)
                             a[s + 2] = S.q[gidx(g, comp[m], i + s * e[0], j + s * e[1], k + s * e[2])];
                         orc_ppm_cell(a, phi, par[m]);
@@ -411,8 +456,8 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                     double rho = S.q[gidx(g, 0, i, j, k)];
                     double un = S.q[gidx(g, 1 + d, i, j, k)];
                     double cs = S.q[gidx(g, 5, i, j, k)];
-                    double qL[5], qR[5];
-                    orc_trace_cell(par, rho, un, cs, dtdx[d], qL, qR);
+                    double qL[MAXV], qR[MAXV];
+                    trace_cell_n((const double (*)[4])par, nv, rho, un, cs, dtdx[d], qL, qR);
                     /* floors, gravity predictor; keep the left state of the
                      * upper face (faces 0..n) and the right state of the lower face */
                     double *both[2] = {qL, qR};
@@ -425,10 +470,10 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                         if (P->grav_z != 0.0) s[zpos] = s[zpos] + hdtg;
                     }
                     if (keep[0])
-                        for (int m = 0; m < 5; ++m)
+                        for (int m = 0; m < nv; ++m)
                             S.ql[d][hidx(g, m, i + e[0], j + e[1], k + e[2])] = qL[m];
                     if (keep[1])
-                        for (int m = 0; m < 5; ++m) S.qr[d][hidx(g, m, i, j, k)] = qR[m];
+                        for (int m = 0; m < nv; ++m) S.qr[d][hidx(g, m, i, j, k)] = qR[m];
                 }
     }
 
@@ -440,13 +485,13 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                 for (int i = -1; i <= n[0]; ++i) {
                     int c[3] = {i, j, k};
                     if (c[d] < 0) continue;
-                    double L[5], R[5], F[5];
-                    for (int m = 0; m < 5; ++m) {
+                    double L[MAXV], R[MAXV], F[MAXV];
+                    for (int m = 0; m < nv; ++m) {
                         L[m] = S.ql[d][hidx(g, m, i, j, k)];
                         R[m] = S.qr[d][hidx(g, m, i, j, k)];
                     }
-                    orc_hllc(L, R, d, P, F);
-                    for (int m = 0; m < 5; ++m) S.fn[d][hidx(g, m, i, j, k)] = F[m];
+                    hllc_n(L, R, d, P, F);
+                    for (int m = 0; m < nv; ++m) S.fn[d][hidx(g, m, i, j, k)] = F[m];
                 }
     }
 
@@ -468,27 +513,27 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                         (void)cdir;                          /* c cells -1..n */
                         int ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0};
                         ea[a] = 1; eb[b] = 1;
-                        double st2[2][5];
+                        double st2[2][MAXV];
                         for (int side = 0; side < 2; ++side) {
                             const double *src = side == 0 ? S.ql[a] : S.qr[a];
                             int o[3] = {i - (side == 0 ? ea[0] : 0), j - (side == 0 ? ea[1] : 0),
                                         k - (side == 0 ? ea[2] : 0)};
-                            double s0[5], Uc[5], s1[5];
-                            for (int m = 0; m < 5; ++m) s0[m] = src[hidx(g, m, i, j, k)];
+                            double s0[MAXV], Uc[MAXV], s1[MAXV];
+                            for (int m = 0; m < nv; ++m) s0[m] = src[hidx(g, m, i, j, k)];
                             perm_prim_to_cons(s0, a, P, Uc);
-                            for (int m = 0; m < 5; ++m)
+                            for (int m = 0; m < nv; ++m)
                                 Uc[m] = Uc[m] - c3[b] * (S.fn[b][hidx(g, m, o[0] + eb[0], o[1] + eb[1], o[2] + eb[2])] -
                                                          S.fn[b][hidx(g, m, o[0], o[1], o[2])]);
                             cons_to_perm_prim(Uc, a, P, s1);
                             if (s1[0] < P->small_dens || s1[4] < P->small_pres) {
-                                for (int m = 0; m < 5; ++m) s1[m] = s0[m];
+                                for (int m = 0; m < nv; ++m) s1[m] = s0[m];
                                 lfb++;
                             }
-                            for (int m = 0; m < 5; ++m) st2[side][m] = s1[m];
+                            for (int m = 0; m < nv; ++m) st2[side][m] = s1[m];
                         }
-                        double F[5];
-                        orc_hllc(st2[0], st2[1], a, P, F);
-                        for (int m = 0; m < 5; ++m) S.f1[pidx][hidx(g, m, i, j, k)] = F[m];
+                        double F[MAXV];
+                        hllc_n(st2[0], st2[1], a, P, F);
+                        for (int m = 0; m < nv; ++m) S.f1[pidx][hidx(g, m, i, j, k)] = F[m];
                     }
             c3cnt += lfb;
         }
@@ -508,30 +553,30 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                     if (c[b] >= n[b] || c[cdir] >= n[cdir]) continue; /* a faces 0..n, others 0..n-1 */
                     int ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0}, ec[3] = {0, 0, 0};
                     ea[a] = 1; eb[b] = 1; ec[cdir] = 1;
-                    double st2[2][5];
+                    double st2[2][MAXV];
                     for (int side = 0; side < 2; ++side) {
                         const double *src = side == 0 ? S.ql[a] : S.qr[a];
                         int o[3] = {i - (side == 0 ? ea[0] : 0), j - (side == 0 ? ea[1] : 0),
                                     k - (side == 0 ? ea[2] : 0)};
-                        double s0[5], Uc[5], s1[5];
-                        for (int m = 0; m < 5; ++m) s0[m] = src[hidx(g, m, i, j, k)];
+                        double s0[MAXV], Uc[MAXV], s1[MAXV];
+                        for (int m = 0; m < nv; ++m) s0[m] = src[hidx(g, m, i, j, k)];
                         perm_prim_to_cons(s0, a, P, Uc);
-                        for (int m = 0; m < 5; ++m)
+                        for (int m = 0; m < nv; ++m)
                             Uc[m] = Uc[m] - c2[b] * (S.f1[pbc][hidx(g, m, o[0] + eb[0], o[1] + eb[1], o[2] + eb[2])] -
                                                      S.f1[pbc][hidx(g, m, o[0], o[1], o[2])]);
-                        for (int m = 0; m < 5; ++m)
+                        for (int m = 0; m < nv; ++m)
                             Uc[m] = Uc[m] - c2[cdir] * (S.f1[pcb][hidx(g, m, o[0] + ec[0], o[1] + ec[1], o[2] + ec[2])] -
                                                         S.f1[pcb][hidx(g, m, o[0], o[1], o[2])]);
                         cons_to_perm_prim(Uc, a, P, s1);
                         if (s1[0] < P->small_dens || s1[4] < P->small_pres) {
-                            for (int m = 0; m < 5; ++m) s1[m] = s0[m];
+                            for (int m = 0; m < nv; ++m) s1[m] = s0[m];
                             lfb++;
                         }
-                        for (int m = 0; m < 5; ++m) st2[side][m] = s1[m];
+                        for (int m = 0; m < nv; ++m) st2[side][m] = s1[m];
                     }
-                    double F[5];
-                    orc_hllc(st2[0], st2[1], a, P, F);
-                    for (int m = 0; m < 5; ++m) S.ff[a][hidx(g, m, i, j, k)] = F[m];
+                    double F[MAXV];
+                    hllc_n(st2[0], st2[1], a, P, F);
+                    for (int m = 0; m < nv; ++m) S.ff[a][hidx(g, m, i, j, k)] = F[m];
                 }
         c3cnt += lfb;
     }
@@ -542,8 +587,8 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
     for (int k = 0; k < n[2]; ++k)
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) {
-                double Un[5];
-                for (int m = 0; m < 5; ++m) {
+                double Un[MAXV];
+                for (int m = 0; m < nv; ++m) {
                     double du = dtdx[0] * (S.ff[0][hidx(g, m, i, j, k)] - S.ff[0][hidx(g, m, i + 1, j, k)]);
                     du = du + dtdx[1] * (S.ff[1][hidx(g, m, i, j, k)] - S.ff[1][hidx(g, m, i, j + 1, k)]);
                     du = du + dtdx[2] * (S.ff[2][hidx(g, m, i, j, k)] - S.ff[2][hidx(g, m, i, j, k + 1)]);
@@ -554,7 +599,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                     Un[4] = Un[4] + hdtg * (U[gidx(g, 3, i, j, k)] + Un[3]);
                 }
                 int bad = 0;
-                for (int m = 0; m < 5; ++m) if (!isfinite(Un[m])) bad = 1;
+                for (int m = 0; m < nv; ++m) if (!isfinite(Un[m])) bad = 1;
                 if (Un[0] < P->small_dens) bad = 1;
                 if (!bad) {
                     double u = Un[1] / Un[0], v = Un[2] / Un[0], w = Un[3] / Un[0];
@@ -562,7 +607,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                     if (gm1 * (Un[4] - ke) < P->small_pres) bad = 1;
                 }
                 c4 += bad;
-                for (int m = 0; m < 5; ++m) Unew[gidx(g, m, i, j, k)] = Un[m];
+                for (int m = 0; m < nv; ++m) Unew[gidx(g, m, i, j, k)] = Un[m];
             }
 
     if (cnt) { cnt[0] += c0; cnt[1] += c1; cnt[2] += c2cnt; cnt[3] += c3cnt; cnt[4] += c4; }
@@ -573,7 +618,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
 /* ------------------------------------------------------- ghost fill (O11) */
 
 /* Conserved state of the inflow primitive (rho, u, v, w, p). */
-static void inflow_cons(const orc_params *P, double U[5]) {
+static void inflow_cons(const orc_params *P, double *U) {
     const double rgm1 = 1.0 / (P->gamma - 1.0);
     const double *s = P->inflow;
     U[0] = s[0];
@@ -581,6 +626,7 @@ static void inflow_cons(const orc_params *P, double U[5]) {
     U[2] = s[0] * s[2];
     U[3] = s[0] * s[3];
     U[4] = s[4] * rgm1 + 0.5 * s[0] * ((s[1] * s[1] + s[2] * s[2]) + s[3] * s[3]);
+    for (int sp = 0; sp < P->nspec; ++sp) U[5 + sp] = s[0] * P->inflow_X[sp];
 }
 
 /* Fill the ghost cells of a whole-domain grown array: first every ghost cell
@@ -590,6 +636,7 @@ static void inflow_cons(const orc_params *P, double U[5]) {
 void orc_fill_domain(double *U, const int n[3], const orc_params *P) {
     const geom G = mkgeom(n);
     const geom *g = &G;
+    const int nv = nvar_of(P);
 #pragma omp parallel for schedule(static)
     for (int k = -NG; k < n[2] + NG; ++k)
         for (int j = -NG; j < n[1] + NG; ++j)
@@ -603,13 +650,13 @@ void orc_fill_domain(double *U, const int n[3], const orc_params *P) {
                     else ok = 0;
                 }
                 if (valid || !ok) continue;
-                for (int m = 0; m < 5; ++m) U[gidx(g, m, i, j, k)] = U[gidx(g, m, s[0], s[1], s[2])];
+                for (int m = 0; m < nv; ++m) U[gidx(g, m, i, j, k)] = U[gidx(g, m, s[0], s[1], s[2])];
             }
     for (int d = 0; d < 3; ++d) {
         if (P->bc_lo[d] == BC_PERIODIC) continue;
         for (int side = 0; side < 2; ++side) {
             const int bc = side == 0 ? P->bc_lo[d] : P->bc_hi[d];
-            double Uin[5];
+            double Uin[MAXV];
             inflow_cons(P, Uin);
             for (int k = -NG; k < n[2] + NG; ++k)
                 for (int j = -NG; j < n[1] + NG; ++j)
@@ -619,7 +666,7 @@ void orc_fill_domain(double *U, const int n[3], const orc_params *P) {
                         int s[3] = {i, j, k};
                         if (bc == BC_OUTFLOW) s[d] = side == 0 ? 0 : n[d] - 1;
                         else if (bc == BC_REFLECT) s[d] = side == 0 ? -c[d] - 1 : 2 * n[d] - 1 - c[d];
-                        for (int m = 0; m < 5; ++m) {
+                        for (int m = 0; m < nv; ++m) {
                             double v;
                             if (bc == BC_INFLOW) v = Uin[m];
                             else {
@@ -646,9 +693,9 @@ double orc_signal_speed(const double *U, const int n[3], const orc_params *P) {
     for (int k = 0; k < n[2]; ++k)
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) {
-                double Uc[5], q[6];
+                double Uc[MAXV], q[MAXV + 1];
                 long long lc[NCNT] = {0, 0, 0, 0, 0};
-                for (int m = 0; m < 5; ++m) Uc[m] = U[gidx(g, m, i, j, k)];
+                for (int m = 0; m < nvar_of(P); ++m) Uc[m] = U[gidx(g, m, i, j, k)];
                 cons_to_prim_cell(Uc, P, q, lc);
                 for (int d = 0; d < 3; ++d) {
                     double s = (fabs(q[1 + d]) + q[5]) * rdx[d];
@@ -670,11 +717,12 @@ int orc_step(double *U, const int n[3], const orc_params *P, double dt_fixed, do
         double s = orc_signal_speed(U, n, P);
         dt = P->cfl / s;
     }
-    double *Un = xalloc(NV * gs);
+    const int nv = nvar_of(P);
+    double *Un = xalloc(nv * gs);
     if (!Un) return -2;
-    memcpy(Un, U, sizeof(double) * NV * gs);
+    memcpy(Un, U, sizeof(double) * nv * gs);
     int rc = orc_advance_box(U, n, P, dt, Un, cnt, NULL);
-    if (rc == 0) memcpy(U, Un, sizeof(double) * NV * gs);
+    if (rc == 0) memcpy(U, Un, sizeof(double) * nv * gs);
     free(Un);
     if (dt_used) *dt_used = dt;
     return rc;

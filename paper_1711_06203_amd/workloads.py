@@ -49,6 +49,8 @@ class Problem:
     steps: int = 10
     small_dens: float = 1e-12
     small_pres: float = 1e-12
+    nspec: int = 0                          # passive species (rho X_s after rho E)
+    inflow_X: Tuple[float, ...] = ()        # species mass fractions written by inflow
     # two-level problems only
     fine_boxes: Optional[List[Box]] = None   # fine-level index space
     U0_fine: Optional[np.ndarray] = None     # (5, nzf, nyf, nxf) over the fine bounding region
@@ -77,11 +79,14 @@ def cell_centres(n: Sequence[int], lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), offse
     return x, y, z
 
 
-def conserved(gamma, rho, u, v, w, p) -> np.ndarray:
-    """Ideal-gas conserved state (rho, rho u, rho v, rho w, rho E) of primitive fields."""
+def conserved(gamma, rho, u, v, w, p, X=None) -> np.ndarray:
+    """Ideal-gas conserved state (rho, rho u, rho v, rho w, rho E[, rho X_s]) of
+    primitive fields; X is an optional sequence of species mass fractions."""
     rho = np.asarray(rho, dtype=np.float64)
-    shape = np.broadcast_shapes(np.shape(rho), np.shape(u), np.shape(v), np.shape(w), np.shape(p))
-    U = np.empty((NVAR,) + shape, dtype=np.float64)
+    ns = 0 if X is None else len(X)
+    shape = np.broadcast_shapes(np.shape(rho), np.shape(u), np.shape(v), np.shape(w), np.shape(p),
+                                *[np.shape(x) for x in (X or [])])
+    U = np.empty((NVAR + ns,) + shape, dtype=np.float64)
     rho = np.broadcast_to(rho, shape)
     u = np.broadcast_to(np.asarray(u, np.float64), shape)
     v = np.broadcast_to(np.asarray(v, np.float64), shape)
@@ -92,6 +97,8 @@ def conserved(gamma, rho, u, v, w, p) -> np.ndarray:
     U[2] = rho * v
     U[3] = rho * w
     U[4] = p / (gamma - 1.0) + 0.5 * rho * ((u * u + v * v) + w * w)
+    for s_ in range(ns):
+        U[NVAR + s_] = rho * np.broadcast_to(np.asarray(X[s_], np.float64), shape)
     return U
 
 
@@ -166,9 +173,22 @@ def sod(n=32, axis=0, gamma=1.4, boxes_edge=None, steps=20, flip=False) -> Probl
                    cfl=0.5, steps=steps)
 
 
-def kelvin_helmholtz(n=256, box=64, seed=20260102, gamma=5.0 / 3.0, steps=100) -> Problem:
+def species_bands(y, nspec: int, width: float = 0.05):
+    """nspec smooth mass fractions summing to 1: normalised Gaussian bands centred
+    at (s + 1/2) / nspec across y (periodic images included)."""
+    raw = []
+    for s_ in range(nspec):
+        c = (s_ + 0.5) / nspec
+        b = sum(np.exp(-((y - c + sh) / width) ** 2) for sh in (-1.0, 0.0, 1.0))
+        raw.append(b + 1e-3)
+    tot = sum(raw)
+    return [r / tot for r in raw]
+
+
+def kelvin_helmholtz(n=256, box=64, seed=20260102, gamma=5.0 / 3.0, steps=100, nspec=0) -> Problem:
     """Periodic shear layer: rho=2, u_x=+0.5 in |y-0.5|<0.25; rho=1, u_x=-0.5 outside;
-    p=2.5; u_y = 0.01 (2r-1) with r ~ U[0,1) per cell."""
+    p=2.5; u_y = 0.01 (2r-1) with r ~ U[0,1) per cell; optionally nspec passive
+    species in smooth bands across y (mass fractions summing to 1)."""
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     x, y, z = cell_centres(nn)
     rng = np.random.default_rng(seed)
@@ -177,9 +197,9 @@ def kelvin_helmholtz(n=256, box=64, seed=20260102, gamma=5.0 / 3.0, steps=100) -
     rho = np.where(inside, 2.0, 1.0)
     u = np.where(inside, 0.5, -0.5)
     v = 0.01 * (2.0 * r - 1.0)
-    U = conserved(gamma, rho, u, v, 0.0, 2.5)
+    U = conserved(gamma, rho, u, v, 0.0, 2.5, species_bands(y, nspec) if nspec else None)
     be = (box, box, box) if np.isscalar(box) else tuple(box)
-    return Problem("kh", nn, gamma, U, regular_boxes(nn, be), cfl=0.5, steps=steps)
+    return Problem("kh", nn, gamma, U, regular_boxes(nn, be), cfl=0.5, steps=steps, nspec=nspec)
 
 
 def rayleigh_taylor(n=384, seed=20260103, box_seed=None, gamma=1.4, steps=200, boxes=None) -> Problem:
@@ -309,7 +329,7 @@ def grown_fab(U: np.ndarray, box: Box, origin=(0, 0, 0), fill=np.nan) -> np.ndar
     lo, hi = box
     nx, ny, nz = box_shape(box)
     g = NGHOST
-    out = np.full((NVAR, nz + 2 * g, ny + 2 * g, nx + 2 * g), fill, dtype=np.float64)
+    out = np.full((U.shape[0], nz + 2 * g, ny + 2 * g, nx + 2 * g), fill, dtype=np.float64)
     sl = (slice(None),
           slice(lo[2] - origin[2], hi[2] + 1 - origin[2]),
           slice(lo[1] - origin[1], hi[1] + 1 - origin[1]),
@@ -320,7 +340,7 @@ def grown_fab(U: np.ndarray, box: Box, origin=(0, 0, 0), fill=np.nan) -> np.ndar
 
 def gather_valid(fabs: Sequence[np.ndarray], boxes: Sequence[Box], n, origin=(0, 0, 0)) -> np.ndarray:
     """Inverse of grown_fab over a box list: assemble the level's valid cells."""
-    out = np.full((NVAR, n[2], n[1], n[0]), np.nan, dtype=np.float64)
+    out = np.full((np.asarray(fabs[0]).shape[0], n[2], n[1], n[0]), np.nan, dtype=np.float64)
     g = NGHOST
     for f, b in zip(fabs, boxes):
         lo, hi = b
