@@ -79,7 +79,8 @@ def cpu_baseline(prob, seconds: float = 12.0):
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     return {"value": n ** 3 * reps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} advances of one 64^3 box (72^3 grown) of the 256^3 KH initial state, "
+            "sample": f"{reps} advances of one 64^3 box (72^3 grown) of the 256^3 KH initial state "
+                      f"({prob.nspec} species), "
                       f"{el:.1f} s wall, OpenMP threads={threads}"}
 
 
@@ -92,6 +93,9 @@ def main():
                     help="kh256: 256^3 KH in 64 boxes of 64^3 (default); sod32: 32^3 Sod, one box; rt384: "
                          "384^3 RT in seeded uneven boxes; cloud256: two-level cloud in a Mach-2 wind; serving: "
                          "Poisson stream of independent problems")
+    ap.add_argument("--nspec", type=int, default=0,
+                    help="passive species advected with the flow (kh256, rt384, cloud256; the paper's GPU "
+                         "proxy advects 13)")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
@@ -132,15 +136,19 @@ def main():
         args.form = "per_box" if args.form == "graph" and "--form" not in sys.argv else args.form
         wname = "sod_32^3_single_box_outflow_x"
     elif args.workload == "rt384":
-        prob = W.rayleigh_taylor(n=384)
+        prob = W.rayleigh_taylor(n=384, nspec=args.nspec)
         wname = f"rayleigh_taylor_384^3_{len(prob.boxes)}_uneven_boxes_gz-1"
     elif args.workload == "cloud256":
-        prob = W.cloud_wind(n=256, box=64, fine_box=32)
+        prob = W.cloud_wind(n=256, box=64, fine_box=32, nspec=args.nspec)
         args.form = "batched" if args.form == "per_box" else args.form
         wname = "cloud_wind_two_level_256^3_64x64^3_fine_256^3_512x32^3"
     else:
-        prob = W.kelvin_helmholtz(n=args.n, box=args.box)
+        prob = W.kelvin_helmholtz(n=args.n, box=args.box, nspec=args.nspec)
         wname = f"kelvin_helmholtz_{args.n}^3_{(args.n // args.box) ** 3}x{args.box}^3_periodic"
+    if args.nspec and args.workload != "sod32":
+        wname += f"_{args.nspec}_species"
+    # key of the stored counter summary of this workload
+    tkey = args.workload + (f"s{args.nspec}" if args.nspec else "")
     ctx = ctuppm.Context()
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
@@ -185,7 +193,7 @@ def main():
     launches_per_step = st[dom][1] / tsteps
     # algorithmic bytes of the stage per step over its launch time per step
     achieved = sbytes[dom] / (avg_ms * launches_per_step * 1e-3) / 1e9
-    traffic = measured_traffic(dom, args.workload)
+    traffic = measured_traffic(dom, tkey)
     cnt = solver.counters()
     out = {
         "metric": "zone-updates/s FP64 (unsplit CTU/PPM advance)",
@@ -201,6 +209,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
+                   "species": prob.nspec,
                    "gamma": prob.gamma, "cfl": prob.cfl, "tuning": tuning and {k: tuning[k] for k in
                                                                                ("blocks_per_cu", "zseg", "ytile")}},
         "forms": {k: v for k, v in forms.items()},
@@ -214,7 +223,7 @@ def main():
     ctx.close()
     del solver
     torch.cuda.empty_cache()
-    if not args.no_cpu and args.workload == "kh256":
+    if not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -24,8 +24,9 @@
  *
  * State layout: one "fab" per box, FP64, [comp][k][j][i] over the box grown by
  * CTUPPM_NGHOST cells on every side, i fastest; components
- * (rho, rho u, rho v, rho w, rho E).  A box (nx, ny, nz) has
- * 5 (nx+8)(ny+8)(nz+8) doubles.  Each box has two fabs, A and B; steps
+ * (rho, rho u, rho v, rho w, rho E, rho X_1 .. rho X_nspec).  A box (nx, ny, nz)
+ * has (5 + nspec)(nx+8)(ny+8)(nz+8) doubles.  Passive species are advected
+ * with the flow (the paper's GPU proxy advects 13 species, section 4).  Each box has two fabs, A and B; steps
  * alternate between them and ctuppm_current_state() tells which holds the
  * current state.
  */
@@ -73,6 +74,9 @@ typedef struct {
   int bc_lo[3];        /* CTUPPM_BC_* per direction and side; periodic on both */
   int bc_hi[3];        /*   sides or neither */
   double inflow[5];    /* (rho, u, v, w, p) written by CTUPPM_BC_INFLOW */
+  int nspec;           /* passive species (mass fractions) after rho E, 0..16 */
+  int pad;
+  double inflow_X[16]; /* species mass fractions written by CTUPPM_BC_INFLOW */
 } ctuppm_params;
 
 typedef struct ctuppm_ctx ctuppm_ctx;
@@ -95,8 +99,9 @@ int ctuppm_problem_create(ctuppm_ctx* ctx, const ctuppm_params* params, int nlev
                           const ctuppm_box* const* boxes, const int* nboxes, int* pid_out);
 int ctuppm_problem_destroy(ctuppm_ctx* ctx, int pid);
 
-/* Doubles in one fab of a box: 5 (nx+8)(ny+8)(nz+8). */
-int ctuppm_fab_elems(const ctuppm_box* box, long long* elems);
+/* Doubles in one fab of a box with nspec species: (5 + nspec)(nx+8)(ny+8)(nz+8).
+ * CTUPPM_EINVAL for an empty box or nspec outside 0..16. */
+int ctuppm_fab_elems(const ctuppm_box* box, int nspec, long long* elems);
 
 /* Bytes of stage workspace a problem needs in a form (the batched and graph
  * forms need scratch for all boxes at once, the per-box form for the largest). */

@@ -165,9 +165,9 @@ int box_n(const ctuppm_box& b, int d) { return b.hi[d] - b.lo[d] + 1; }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-size_t box_scratch_bytes(const ctuppm_box& b) {
+size_t box_scratch_bytes(const ctuppm_box& b, int nspec) {
   const int n[3] = {box_n(b, 0), box_n(b, 1), box_n(b, 2)};
-  return align256(size_t(scratch_doubles(n)) * sizeof(double));
+  return align256(size_t(scratch_doubles(n, nspec)) * sizeof(double));
 }
 
 Problem* get_problem(ctuppm_ctx* c, int pid) {
@@ -281,12 +281,15 @@ long long register_faces(const Problem* P) {
 }
 
 // Workspace after the stage scratch of both levels: the region at t^n and at
-// t^{n+1} (5 doubles per cell each), then 10 doubles per register face.
+// t^{n+1} (nv = 5 + nspec doubles per cell each), then 2 nv doubles per
+// register face.
 size_t two_level_extra_bytes(const Problem* P) {
   if (P->nlevels != 2) return 0;
   int ext[3], lo[3];
   const long long rc = region_cells(P, ext, lo);
-  return 2 * align256(size_t(rc) * 5 * sizeof(double)) + align256(size_t(register_faces(P)) * 10 * sizeof(double));
+  const size_t nv = size_t(kNV + P->prm.nspec);
+  return 2 * align256(size_t(rc) * nv * sizeof(double)) +
+         align256(size_t(register_faces(P)) * 2 * nv * sizeof(double));
 }
 
 // Forget the cached work lists (and graphs) that involve problem pid.
@@ -333,7 +336,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     const int base = int(boxes.size());
     size_t off = 0;
     if (level == 1)  // level-1 scratch follows all level-0 scratch
-      for (const auto& b : P->lev[0].boxes) off += box_scratch_bytes(b);
+      for (const auto& b : P->lev[0].boxes) off += box_scratch_bytes(b, P->prm.nspec);
     int dlo[3], dhi[3];
     level_domain(P->prm, level, dlo, dhi);
     for (size_t b = 0; b < L.boxes.size(); ++b) {
@@ -342,9 +345,10 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
       r.U[0] = L.Ua[b];
       r.U[1] = L.Ub[b];
       r.scr = (double*)((char*)P->ws + (S->form == CTUPPM_FORM_PER_BOX ? 0 : off));
-      off += box_scratch_bytes(bx);
+      off += box_scratch_bytes(bx, P->prm.nspec);
       r.P = dPl;
       r.level = level;
+      r.ns = P->prm.nspec;
       for (int d = 0; d < 3; ++d) {
         r.n[d] = box_n(bx, d);
         r.lo[d] = bx.lo[d];
@@ -403,12 +407,13 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     // physical boundaries, one list per direction
     const double rgm1 = 1.0 / (P->prm.gamma - 1.0);
     const double* s = P->prm.inflow;
-    double inflow_cons[5];
+    double inflow_cons[kMaxV];
     inflow_cons[0] = s[0];
     inflow_cons[1] = s[0] * s[1];
     inflow_cons[2] = s[0] * s[2];
     inflow_cons[3] = s[0] * s[3];
     inflow_cons[4] = s[4] * rgm1 + 0.5 * s[0] * ((s[1] * s[1] + s[2] * s[2]) + s[3] * s[3]);
+    for (int sp = 0; sp < P->prm.nspec; ++sp) inflow_cons[kNV + sp] = s[0] * P->prm.inflow_X[sp];
     for (int d = 0; d < 3; ++d) {
       if (P->prm.bc_lo[d] == CTUPPM_BC_PERIODIC) continue;
       for (int b = 0; b < nb; ++b) {
@@ -421,7 +426,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
           t.bc = side == 0 ? P->prm.bc_lo[d] : P->prm.bc_hi[d];
           t.dom_lo = dlo[d];
           t.dom_hi = dhi[d];
-          for (int m = 0; m < 5; ++m) t.inflow[m] = inflow_cons[m];
+          for (int m = 0; m < kNV + P->prm.nspec; ++m) t.inflow[m] = inflow_cons[m];
           bool any = true;
           for (int e = 0; e < 3; ++e) {
             int lo = -kNG, hi = box_n(B, e) + kNG - 1;  // box-local grown range
@@ -588,15 +593,16 @@ int build_two_level(ctuppm_ctx* c, int pid, TwoLevel** out) {
   if (rc) return rc;
   size_t off = 0;
   for (int l = 0; l < 2; ++l)
-    for (const auto& b : P->lev[l].boxes) off += box_scratch_bytes(b);
+    for (const auto& b : P->lev[l].boxes) off += box_scratch_bytes(b, P->prm.nspec);
   int rext[3], rlo[3];
   const long long rcells = region_cells(P, rext, rlo);
   char* base = (char*)P->ws;
   TwoLevelArgs& A = T->args;
+  const size_t nv = size_t(kNV + P->prm.nspec);
   A.ct0 = (double*)(base + off);
-  off += align256(size_t(rcells) * 5 * sizeof(double));
+  off += align256(size_t(rcells) * nv * sizeof(double));
   A.ct1 = (double*)(base + off);
-  off += align256(size_t(rcells) * 5 * sizeof(double));
+  off += align256(size_t(rcells) * nv * sizeof(double));
   A.reg = (double*)(base + off);
   A.cboxes = T->cset->boxes;
   A.fboxes = T->fset->boxes;
@@ -853,9 +859,9 @@ int ctuppm_ctx_destroy(ctuppm_ctx* c) {
 
 const char* ctuppm_last_error(ctuppm_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int ctuppm_fab_elems(const ctuppm_box* b, long long* elems) {
-  if (!b || !elems) return CTUPPM_EINVAL;
-  long long v = kNV;
+int ctuppm_fab_elems(const ctuppm_box* b, int nspec, long long* elems) {
+  if (!b || !elems || nspec < 0 || nspec > kMaxSpec) return CTUPPM_EINVAL;
+  long long v = kNV + nspec;
   for (int d = 0; d < 3; ++d) {
     const int n = b->hi[d] - b->lo[d] + 1;
     if (n < 1) return CTUPPM_EINVAL;
@@ -870,6 +876,8 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   if (!c || !prm || !boxes || !nboxes || !pid_out) return CTUPPM_EINVAL;
   if (nlevels != 1 && nlevels != 2) return fail(c, CTUPPM_EINVAL, "nlevels must be 1 or 2");
   if (!(prm->gamma > 1.0)) return fail(c, CTUPPM_EINVAL, "gamma must be > 1");
+  if (prm->nspec < 0 || prm->nspec > kMaxSpec)
+    return fail(c, CTUPPM_EINVAL, "nspec must be in 0..%d", kMaxSpec);
   for (int d = 0; d < 3; ++d) {
     if (!(prm->dx[d] > 0.0)) return fail(c, CTUPPM_EINVAL, "dx must be > 0");
     if (prm->domain_hi[d] < prm->domain_lo[d]) return fail(c, CTUPPM_EINVAL, "empty domain");
@@ -945,6 +953,7 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
     h.rdx[d] = 1.0 / prm->dx[d];
   }
   h.nlevels = nlevels;
+  h.nspec = prm->nspec;
   h.fail_step = -1;
   HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
   HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
@@ -981,7 +990,7 @@ int ctuppm_workspace_bytes(ctuppm_ctx* c, int pid, int form, size_t* bytes) {
   size_t total = 0, mx = 0;
   for (int l = 0; l < P->nlevels; ++l)
     for (const auto& b : P->lev[l].boxes) {
-      const size_t s = box_scratch_bytes(b);
+      const size_t s = box_scratch_bytes(b, P->prm.nspec);
       total += s;
       mx = std::max(mx, s);
     }
@@ -1211,6 +1220,7 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
   std::vector<ctuppm_box> all(P->lev[0].boxes);
   if (P->nlevels == 2)  // the fine level runs two substeps per step
     for (int r = 0; r < 2; ++r) all.insert(all.end(), P->lev[1].boxes.begin(), P->lev[1].boxes.end());
+  const double nv = kNV + P->prm.nspec, nq = nv + 1;  // conserved / primitive components
   for (const auto& bx : all) {
     const double n0 = box_n(bx, 0), n1 = box_n(bx, 1), n2 = box_n(bx, 2);
     const double nn[3] = {n0, n1, n2};
@@ -1221,29 +1231,29 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
     auto fin = [&](int d) { return valid / nn[d] * (nn[d] + 1); };                    // faces 0..n x 0..n-1
     auto half = [&](int a, int b) { return face(a) / (nn[b] + 2) * nn[b]; };         // F^{a|b} region
     switch (stage) {
-      case kStFill: tot += 2 * 5 * W * (grown - valid); break;
-      case kStC2P: case kStC2POnly: tot += (5 + 6) * W * grown; break;
+      case kStFill: tot += 2 * nv * W * (grown - valid); break;
+      case kStC2P: case kStC2POnly: tot += (nv + nq) * W * grown; break;
       case kStCfl: tot += 5 * W * valid; break;
       case kStFlatten: tot += 4 * W * cells1 + W * cells1; break;
       case kStTraceX: case kStTraceY: case kStTraceZ: {
         const int d = stage - kStTraceX;
         // q over cells -3..n+2 along d (the 5-cell stencils of cells -1..n), phi,
         // then the left and right states of faces 0..n
-        tot += 6 * W * cells1 / (nn[d] + 2) * (nn[d] + 6) + W * cells1 + 2 * 5 * W * face(d);
+        tot += nq * W * cells1 / (nn[d] + 2) * (nn[d] + 6) + W * cells1 + 2 * nv * W * face(d);
         break;
       }
-      case kStRiemX: case kStRiemY: case kStRiemZ: tot += 3 * 5 * W * face(stage - kStRiemX); break;
+      case kStRiemX: case kStRiemY: case kStRiemZ: tot += 3 * nv * W * face(stage - kStRiemX); break;
       case kStT1X: case kStT1Y: case kStT1Z: {
         const int a = stage - kStT1X, b = (a + 1) % 3, cc = (a + 2) % 3;
-        tot += 2 * 5 * W * face(a) + 5 * W * face(b) + 5 * W * face(cc) + 5 * W * (half(a, b) + half(a, cc));
+        tot += 2 * nv * W * face(a) + nv * W * face(b) + nv * W * face(cc) + nv * W * (half(a, b) + half(a, cc));
         break;
       }
       case kStT2X: case kStT2Y: case kStT2Z: {
         const int a = stage - kStT2X, b = (a + 1) % 3, cc = (a + 2) % 3;
-        tot += 2 * 5 * W * fin(a) + 5 * W * half(b, cc) + 5 * W * half(cc, b) + 5 * W * fin(a);
+        tot += 2 * nv * W * fin(a) + nv * W * half(b, cc) + nv * W * half(cc, b) + nv * W * fin(a);
         break;
       }
-      case kStUpdate: tot += 2 * 5 * W * valid + 5 * W * (fin(0) + fin(1) + fin(2)); break;
+      case kStUpdate: tot += 2 * nv * W * valid + nv * W * (fin(0) + fin(1) + fin(2)); break;
       default: break;
     }
   }

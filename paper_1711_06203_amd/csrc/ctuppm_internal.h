@@ -7,7 +7,9 @@
 
 namespace ctu {
 
-constexpr int kNV = 5;     // rho, rho u, rho v, rho w, rho E
+constexpr int kNV = 5;     // rho, rho u, rho v, rho w, rho E (species rho X_s follow)
+constexpr int kMaxSpec = 16;
+constexpr int kMaxV = kNV + kMaxSpec;
 constexpr int kNG = 4;     // ghost layers
 constexpr int kBlock = 256;  // threads per block = items per chunk
 constexpr int kSlots = 64;   // signal-speed max accumulators per problem (spread atomics)
@@ -45,6 +47,8 @@ struct ProbDev {
   int nsteps;
   int nlevels;
   int fail_step;                   // test hook: the update flags a failure at this step (-1: off)
+  int nspec;                       // passive species after rho E
+  int pad2;
   // running max of the signal speed as bit patterns (>= 0), one 128-byte
   // line per slot so blocks of one launch do not contend on one address
   unsigned long long smax[kSlots][16];
@@ -52,13 +56,13 @@ struct ProbDev {
 
 // One box of a step set.
 struct BoxRec {
-  double* U[2];     // grown fabs [5][nz+8][ny+8][nx+8], caller-owned
+  double* U[2];     // grown fabs [5 + ns][nz+8][ny+8][nx+8], caller-owned
   double* scr;      // stage scratch of this box
   ProbDev* P;       // problem the box belongs to
   int n[3];         // valid cells
   int lo[3];        // level index of valid cell (0,0,0)
   int level;
-  int pad;
+  int ns;           // passive species of the problem
 };
 
 struct Chunk { int box; int start; };  // tag index, first item (ghost-fill work lists)
@@ -71,7 +75,7 @@ struct March { int box; int start; int end; int z0; int z1; int pad; };
 // Same-level ghost copy: dst-local cells [lo, lo+ext) <- src-local (cell + off).
 struct FillTag { int dst, src; int lo[3]; int ext[3]; int off[3]; int pad; };
 // Physical boundary along dir on one side of the domain, over a box's grown cells.
-struct BcTag { int box; int dir; int side; int bc; int lo[3]; int ext[3]; int dom_lo, dom_hi; double inflow[5]; };
+struct BcTag { int box; int dir; int side; int bc; int lo[3]; int ext[3]; int dom_lo, dom_hi; double inflow[kMaxV]; };
 
 // Two-level problems (ratio 2).  The fine level is one rectangle of fine
 // boxes covering coarse cells clo..chi; the coarse cells clo-3..chi+3 (the
@@ -95,21 +99,22 @@ struct TwoLevelArgs {
   ProbDev* Pf;
   double* ct0;      // region state at t^n
   double* ct1;      // region state at t^{n+1}
-  double* reg;      // per face: dt_c F_c (5), fine sum S (5)
+  double* reg;      // per face: dt_c F_c (nv), fine sum S (nv)
   int rlo[3];       // region origin (coarse index)
   int rext[3];      // region extent
 };
 
-// Scratch layout per box, in doubles: q (6 x grown), phi (1 x halo-1),
-// ql[3], qr[3], fn[3] (5 x halo-1 each), f1[6], ff[3] (5 x halo-1 each).
+// Scratch layout per box, in doubles, with nv = 5 + nspec components:
+// q ((6 + nspec) x grown: rho, u, v, w, p, c, X_s), phi (1 x halo-1),
+// ql[3], qr[3], fn[3], f1[6], ff[3] (nv x halo-1 each).
 __host__ __device__ inline long long grown_cells(const int n[3]) {
   return (long long)(n[0] + 2 * kNG) * (n[1] + 2 * kNG) * (n[2] + 2 * kNG);
 }
 __host__ __device__ inline long long h1_cells(const int n[3]) {
   return (long long)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
 }
-__host__ __device__ inline long long scratch_doubles(const int n[3]) {
-  return 6 * grown_cells(n) + 91 * h1_cells(n);
+__host__ __device__ inline long long scratch_doubles(const int n[3], int nspec) {
+  return (6 + nspec) * grown_cells(n) + (1 + 18 * (kNV + nspec)) * h1_cells(n);
 }
 
 // ---------------------------------------------------------------- launchers

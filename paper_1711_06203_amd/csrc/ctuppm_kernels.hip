@@ -45,11 +45,15 @@ CTU_DEV void march(int kind, const BoxRec& B, const March& M, F&& f) {
   for (int k = M.z0; k < M.z1; ++k) f(i, j, k);
 }
 
-// Geometry of one box: grown arrays (ghosts -4..n+3) and halo-1 arrays (-1..n).
+// Geometry of one box: grown arrays (ghosts -4..n+3) and halo-1 arrays (-1..n);
+// ns passive species follow the five hydro components of every array.
 struct Geo {
   int gx, gplane, gcomp;
   int hx, hplane, hcomp;
-  CTU_DEV explicit Geo(const int n[3]) {
+  int ns, nv;
+  CTU_DEV Geo(const int n[3], int nspec) {
+    ns = nspec;
+    nv = kNV + nspec;
     gx = n[0] + 2 * kNG;
     gplane = gx * (n[1] + 2 * kNG);
     gcomp = gplane * (n[2] + 2 * kNG);
@@ -61,14 +65,19 @@ struct Geo {
   CTU_DEV int h(int i, int j, int k) const { return (k + 1) * hplane + (j + 1) * hx + (i + 1); }
   CTU_DEV int gstride(int d) const { return d == 0 ? 1 : (d == 1 ? gx : gplane); }
   CTU_DEV int hstride(int d) const { return d == 0 ? 1 : (d == 1 ? hx : hplane); }
-  // scratch sub-arrays
+  // scratch sub-arrays: q, phi, then 18 arrays of nv components (ql[3], qr[3],
+  // fn[3], f1[6], ff[3]); offsets in 64 bits (a 256^3 box with 16 species
+  // spans more than 2^31 doubles)
+  CTU_DEV double* h1arr(double* s, int a) const {
+    return s + (long long)(kNV + 1 + ns) * gcomp + (1 + (long long)nv * a) * hcomp;
+  }
   CTU_DEV double* q(double* s) const { return s; }
-  CTU_DEV double* phi(double* s) const { return s + 6 * gcomp; }
-  CTU_DEV double* ql(double* s, int d) const { return s + 6 * gcomp + (1 + 5 * d) * hcomp; }
-  CTU_DEV double* qr(double* s, int d) const { return s + 6 * gcomp + (16 + 5 * d) * hcomp; }
-  CTU_DEV double* fn(double* s, int d) const { return s + 6 * gcomp + (31 + 5 * d) * hcomp; }
-  CTU_DEV double* f1(double* s, int p) const { return s + 6 * gcomp + (46 + 5 * p) * hcomp; }
-  CTU_DEV double* ff(double* s, int d) const { return s + 6 * gcomp + (76 + 5 * d) * hcomp; }
+  CTU_DEV double* phi(double* s) const { return s + (long long)(kNV + 1 + ns) * gcomp; }
+  CTU_DEV double* ql(double* s, int d) const { return h1arr(s, d); }
+  CTU_DEV double* qr(double* s, int d) const { return h1arr(s, 3 + d); }
+  CTU_DEV double* fn(double* s, int d) const { return h1arr(s, 6 + d); }
+  CTU_DEV double* f1(double* s, int p) const { return h1arr(s, 9 + p); }
+  CTU_DEV double* ff(double* s, int d) const { return h1arr(s, 15 + d); }
 };
 
 CTU_DEV void count(unsigned long long* c, unsigned long long v) {
@@ -92,13 +101,14 @@ __global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxe
     const BoxRec& D = boxes[T.dst];
     const BoxRec& S = boxes[T.src];
     const int cur = D.P->cur;
-    const Geo gd(D.n), gs(S.n);
+    const Geo gd(D.n, D.ns), gs(S.n, S.ns);
     const double* __restrict__ src = S.U[cur];
     double* __restrict__ dst = D.U[cur];
     const int si = gs.g(i + T.off[0], j + T.off[1], k + T.off[2]);
     const int di = gd.g(i, j, k);
 #pragma unroll
     for (int m = 0; m < kNV; ++m) dst[m * gd.gcomp + di] = src[m * gs.gcomp + si];
+    for (int m = kNV; m < gd.nv; ++m) dst[m * gd.gcomp + di] = src[m * gs.gcomp + si];
   });
 }
 
@@ -110,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
                                                const Chunk* __restrict__ chunks, int nchunks) {
   for_each_chunk(nchunks, [&](int c) {
     const Chunk ch = chunks[c];
-    const BcTag T = tags[ch.box];
+    const BcTag& T = tags[ch.box];  // by reference: the inflow state is indexed at run time
     const int t = ch.start + threadIdx.x;
     if (t >= T.ext[0] * T.ext[1] * T.ext[2]) return;
     int x[3];
@@ -119,12 +129,11 @@ __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
     x[1] = T.lo[1] + r % T.ext[1];
     x[2] = T.lo[2] + r / T.ext[1];
     const BoxRec& B = boxes[T.box];
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     double* __restrict__ U = B.U[B.P->cur];
     const int di = g.g(x[0], x[1], x[2]);
     if (T.bc == 3) {
-#pragma unroll
-      for (int m = 0; m < kNV; ++m) U[m * g.gcomp + di] = T.inflow[m];
+      for (int m = 0; m < g.nv; ++m) U[m * g.gcomp + di] = T.inflow[m];
       return;
     }
     const int X = B.lo[D] + x[D];  // level index of the ghost cell
@@ -140,6 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
       if (T.bc == 2 && m == 1 + D) v = -v;
       U[m * g.gcomp + di] = v;
     }
+    for (int m = kNV; m < g.nv; ++m) U[m * g.gcomp + di] = U[m * g.gcomp + si];
   });
 }
 
@@ -183,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes
       smax = 0.0;
       curP = P;
     }
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     const double* __restrict__ U = B.U[P->cur];
     double* __restrict__ q = g.q(B.scr);
     const double gamma = P->gamma, gm1 = P->gm1, sd = P->small_dens, sp = P->small_pres;
@@ -205,6 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes
         q[3 * g.gcomp + o] = w;
         q[4 * g.gcomp + o] = p;
         q[5 * g.gcomp + o] = cs;
+        for (int is = 0; is < g.ns; ++is) q[(6 + is) * g.gcomp + o] = U[(kNV + is) * g.gcomp + o] / rho;
       }
       if (CFL && i >= 0 && i < B.n[0] && j >= 0 && j < B.n[1] && k >= 0 && k < B.n[2]) {
         const double sx = (fabs(u) + cs) * rdx;
@@ -259,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_flatten(const BoxRec* __restrict__ b
   for_each_chunk(nunits, [&](int u) {
     const March M = units[u];
     const BoxRec& B = boxes[M.box];
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     const double* __restrict__ q = g.q(B.scr);
     const double* __restrict__ p = q + 4 * g.gcomp;
     double* __restrict__ phiout = g.phi(B.scr);
@@ -304,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
     const March M = units[u];
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     const double* __restrict__ q = g.q(B.scr);
     const double* __restrict__ phiv = g.phi(B.scr);
     double* __restrict__ ql = g.ql(B.scr, D);
@@ -336,6 +347,16 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
 #pragma unroll
         for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
       }
+      if (g.ns > 0) {
+        const double lm = un - cs, l0 = un, lp = un + cs;
+        const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, spp = fabs(lp) * dtdx;
+        for (int is = 0; is < g.ns; ++is) {
+          const double* a = q + (6 + is) * g.gcomp + o;
+          const Parab px = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+          if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
+          if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
+        }
+      }
       if (x[D] >= 0) {
         double dn[5];
         trace_dn(par, rho, un, cs, dtdx, dn);
@@ -358,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ b
     const March M = units[u];
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     const double* __restrict__ ql = g.ql(B.scr, D);
     const double* __restrict__ qr = g.qr(B.scr, D);
     double* __restrict__ fn = g.fn(B.scr, D);
@@ -370,8 +391,13 @@ __global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ b
         L[m] = ql[m * g.hcomp + o];
         R[m] = qr[m * g.hcomp + o];
       }
-      hllc(L, R, P->gamma, P->rgm1, f);
+      Wave W;
+      hllc(L, R, P->gamma, P->rgm1, f, W);
       store_flux<D>(fn, g.hcomp, o, f);
+      for (int is = 0; is < g.ns; ++is) {
+        const int mo = (kNV + is) * g.hcomp + o;
+        fn[mo] = species_flux(W, ql[mo], qr[mo]);
+      }
     });
   });
 }
@@ -415,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
     const March M = units[u];
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     const int sa = g.hstride(A);
     const double* __restrict__ ql = g.ql(B.scr, A);
     const double* __restrict__ qr = g.qr(B.scr, A);
@@ -446,10 +472,23 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
           VL[m] = UL[m] - c3 * (Fm[oL + sb] - Fm[oL]);
           VR[m] = UR[m] - c3 * (Fm[oR + sb] - Fm[oR]);
         }
-        fb += to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
-        fb += to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
-        hllc(tL, tR, P->gamma, P->rgm1, f);
-        store_flux<A>(g.f1(B.scr, 2 * A + which), g.hcomp, o, f);
+        const int kL = to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+        const int kR = to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+        fb += kL + kR;
+        Wave W;
+        hllc(tL, tR, P->gamma, P->rgm1, f, W);
+        double* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
+        store_flux<A>(F1, g.hcomp, o, f);
+        // species: rho X corrected by the same flux difference, back to X with
+        // the corrected density (or the traced X where the state fell back)
+        for (int is = 0; is < g.ns; ++is) {
+          const int c = (kNV + is) * g.hcomp;
+          const double* Fm = Fb + c;
+          const double xL = ql[c + o], xR = qr[c + o];
+          const double wL = sL[0] * xL - c3 * (Fm[oL + sb] - Fm[oL]);
+          const double wR = sR[0] * xR - c3 * (Fm[oR + sb] - Fm[oR]);
+          F1[c + o] = species_flux(W, kL ? xL : wL / VL[0], kR ? xR : wR / VR[0]);
+        }
       }
     });
     count(&B.P->cnt[3], fb);
@@ -461,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
 // A, then the final HLLC flux (global component order).  fb counts states that
 // fell back to the uncorrected ones.
 template <int A>
-CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, double F[5], int& fb) {
+CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, double* __restrict__ ff, int& fb) {
   constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
   // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
   constexpr int pbc = 2 * Bd + (Cd == (Bd + 1) % 3 ? 0 : 1);
@@ -492,14 +531,24 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
     UR[m] = UR[m] - c2c * (F2[oR + sc] - F2[oR]);
   }
   double tL[5], tR[5], f[5];
-  fb += to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
-  fb += to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
-  hllc(tL, tR, P->gamma, P->rgm1, f);
-  F[0] = f[0];
-  F[1 + A] = f[1];
-  F[1 + (A + 1) % 3] = f[2];
-  F[1 + (A + 2) % 3] = f[3];
-  F[4] = f[4];
+  const int kL = to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+  const int kR = to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+  fb += kL + kR;
+  Wave W;
+  hllc(tL, tR, P->gamma, P->rgm1, f, W);
+  store_flux<A>(ff, g.hcomp, o, f);
+  for (int is = 0; is < g.ns; ++is) {
+    const int c = (kNV + is) * g.hcomp;
+    const double* F1 = Fbc + c;
+    const double* F2 = Fcb + c;
+    const double xL = ql[c + o], xR = qr[c + o];
+    double wL = sL[0] * xL, wR = sR[0] * xR;
+    wL = wL - c2b * (F1[oL + sb] - F1[oL]);
+    wR = wR - c2b * (F1[oR + sb] - F1[oR]);
+    wL = wL - c2c * (F2[oL + sc] - F2[oL]);
+    wR = wR - c2c * (F2[oR + sc] - F2[oR]);
+    ff[c + o] = species_flux(W, kL ? xL : wL / UL[0], kR ? xR : wR / UR[0]);
+  }
 }
 
 // Stage 2 along A over faces 0..n (cells 0..n-1 across): final fluxes.
@@ -510,15 +559,11 @@ __global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ bo
     const March M = units[u];
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     double* __restrict__ ff = g.ff(B.scr, A);
     int fb = 0;
     march(kFin0 + A, B, M, [&](int i, int j, int k) {
-      const int o = g.h(i, j, k);
-      double F[5];
-      final_flux<A>(B, g, P, o, F, fb);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) ff[m * g.hcomp + o] = F[m];
+      final_flux<A>(B, g, P, g.h(i, j, k), ff, fb);
     });
     count(&B.P->cnt[3], (unsigned long long)fb);
   });
@@ -533,7 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
     const March M = units[u];
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     const double* __restrict__ U = B.U[P->cur];
     double* __restrict__ Un = B.U[P->cur ^ 1];
     const double* __restrict__ Fx = g.ff(B.scr, 0);
@@ -571,6 +616,15 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
       if (forced && i == 0 && j == 0 && k == 0) bad = true;  // host-set test hook
 #pragma unroll
       for (int m = 0; m < 5; ++m) Un[m * g.gcomp + og] = un[m];
+      for (int m = kNV; m < g.nv; ++m) {
+        const int mo = m * g.hcomp + o;
+        double du = dtdx * (Fx[mo] - Fx[mo + 1]);
+        du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
+        du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
+        const double v = U[m * g.gcomp + og] + du;
+        bad = bad || !isfinite(v);
+        Un[m * g.gcomp + og] = v;
+      }
       nbad += bad ? 1ull : 0ull;
     });
     count(&B.P->cnt[4], nbad);
@@ -606,12 +660,11 @@ __global__ __launch_bounds__(kBlock) void k_gather(TwoLevelArgs A, const GatherT
     int a, b, cc;
     if (!tag_item(T.ext, ch.start + threadIdx.x, a, b, cc)) return;
     const BoxRec& B = A.cboxes[T.box];
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     const double* __restrict__ U = B.U[which ? (B.P->cur ^ 1) : B.P->cur];
     const int so = g.g(T.lo[0] + a, T.lo[1] + b, T.lo[2] + cc);
     const int ro = (T.roff[2] + cc) * rplane + (T.roff[1] + b) * A.rext[0] + (T.roff[0] + a);
-#pragma unroll
-    for (int m = 0; m < kNV; ++m) dst[m * rcomp + ro] = U[m * g.gcomp + so];
+    for (int m = 0; m < g.nv; ++m) dst[m * rcomp + ro] = U[m * g.gcomp + so];
   });
 }
 
@@ -625,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_cfinterp(TwoLevelArgs A, const CfTag
     int x[3];
     if (!tag_item(T.ext, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
     const BoxRec& B = A.fboxes[T.box];
-    const Geo g(B.n);
+    const Geo g(B.n, B.ns);
     double* __restrict__ U = B.U[B.P->cur];
     int I[3], rp[3];
 #pragma unroll
@@ -637,8 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_cfinterp(TwoLevelArgs A, const CfTag
     const int po = (rp[2] * A.rext[1] + rp[1]) * A.rext[0] + rp[0];
     const int st[3] = {1, A.rext[0], rplane};
     const int go = g.g(x[0], x[1], x[2]);
-#pragma unroll
-    for (int m = 0; m < kNV; ++m) {
+    for (int m = 0; m < g.nv; ++m) {
       const double* __restrict__ a0 = A.ct0 + m * rcomp;
       const double* __restrict__ a1 = A.ct1 + m * rcomp;
       const double cpar = w0 * a0[po] + theta * a1[po];
@@ -661,15 +713,14 @@ __global__ void k_reg_coarse(TwoLevelArgs A, const RegFace* __restrict__ faces, 
   if (f >= n) return;
   const RegFace F = faces[f];
   const BoxRec& B = A.cboxes[F.cbox];
-  const Geo g(B.n);
+  const Geo g(B.n, B.ns);
   const double* __restrict__ Ff = g.ff(B.scr, F.d);
   const int o = g.h(F.cface[0], F.cface[1], F.cface[2]);
   const double dt = A.Pc->dt;
-  double* r = A.reg + 10 * f;
-#pragma unroll
-  for (int m = 0; m < kNV; ++m) {
+  double* r = A.reg + 2 * g.nv * f;
+  for (int m = 0; m < g.nv; ++m) {
     r[m] = dt * Ff[m * g.hcomp + o];
-    r[5 + m] = 0.0;
+    r[g.nv + m] = 0.0;
   }
 }
 
@@ -678,18 +729,17 @@ __global__ void k_reg_fine(TwoLevelArgs A, const RegFace* __restrict__ faces, in
   if (f >= n) return;
   const RegFace F = faces[f];
   const BoxRec& B = A.fboxes[F.fbox];
-  const Geo g(B.n);
+  const Geo g(B.n, B.ns);
   const double* __restrict__ Ff = g.ff(B.scr, F.d);
   const int t1 = F.d == 0 ? 1 : 0, t2 = F.d == 2 ? 1 : 2;  // transverse directions, increasing
   const int s1 = g.hstride(t1), s2 = g.hstride(t2);
   const int o = g.h(F.fface[0], F.fface[1], F.fface[2]);
   const double dt = A.Pf->dt;
-  double* r = A.reg + 10 * f;
-#pragma unroll
-  for (int m = 0; m < kNV; ++m) {
+  double* r = A.reg + 2 * g.nv * f;
+  for (int m = 0; m < g.nv; ++m) {
     const double* Fm = Ff + m * g.hcomp;
     const double t00 = dt * Fm[o], t10 = dt * Fm[o + s1], t01 = dt * Fm[o + s2], t11 = dt * Fm[o + s1 + s2];
-    r[5 + m] = r[5 + m] + ((t00 + t10) + (t01 + t11));
+    r[g.nv + m] = r[g.nv + m] + ((t00 + t10) + (t01 + t11));
   }
 }
 
@@ -702,14 +752,13 @@ __global__ __launch_bounds__(kBlock) void k_avgdown(TwoLevelArgs A, const AvgTag
     if (!tag_item(T.ext, ch.start + threadIdx.x, a, b, cc)) return;
     const BoxRec& C = A.cboxes[T.cbox];
     const BoxRec& Fb = A.fboxes[T.fbox];
-    const Geo gc(C.n), gf(Fb.n);
+    const Geo gc(C.n, C.ns), gf(Fb.n, Fb.ns);
     double* __restrict__ Uc = C.U[C.P->cur ^ 1];
     const double* __restrict__ Uf = Fb.U[Fb.P->cur];
     const int co = gc.g(T.clo[0] + a, T.clo[1] + b, T.clo[2] + cc);
     const int fo = gf.g(T.flo[0] + 2 * a, T.flo[1] + 2 * b, T.flo[2] + 2 * cc);
     const int sx = 1, sy = gf.gx, sz = gf.gplane;
-#pragma unroll
-    for (int m = 0; m < kNV; ++m) {
+    for (int m = 0; m < gc.nv; ++m) {
       const double* f = Uf + m * gf.gcomp + fo;
       const double s0 = (f[0] + f[sx]) + (f[sy] + f[sx + sy]);
       const double s1 = (f[sz] + f[sx + sz]) + (f[sy + sz] + f[sx + sy + sz]);
@@ -723,14 +772,13 @@ __global__ void k_reflux(TwoLevelArgs A, const RegFace* __restrict__ faces, int 
   if (f >= n) return;
   const RegFace F = faces[f];
   const BoxRec& B = A.cboxes[F.cbox];
-  const Geo g(B.n);
+  const Geo g(B.n, B.ns);
   double* __restrict__ U = B.U[B.P->cur ^ 1];
   const int o = g.g(F.ucell[0], F.ucell[1], F.ucell[2]);
   const double rdx = A.Pc->rdx[F.d];
-  const double* r = A.reg + 10 * f;
-#pragma unroll
-  for (int m = 0; m < kNV; ++m) {
-    const double R = r[m] - 0.25 * r[5 + m];
+  const double* r = A.reg + 2 * g.nv * f;
+  for (int m = 0; m < g.nv; ++m) {
+    const double R = r[m] - 0.25 * r[g.nv + m];
     const double u = U[m * g.gcomp + o];
     U[m * g.gcomp + o] = F.side == 0 ? u + R * rdx : u - R * rdx;
   }

@@ -135,9 +135,15 @@ CTU_DEV void trace_dn(const Parab par[5], double rho, double un, double c, doubl
   }
 }
 
+// Which HLLC state a face flux comes from and the numbers a passive species
+// needs to take the same state: kind 0 the left state, 1 the left star state,
+// 2 the right star state, 3 the right state; m the mass flux of that state,
+// SK its wave speed, fac the star-density factor, rK its density.
+struct Wave { double m, SK, fac, rK; int kind; };
+
 // HLLC flux between permuted primitive states L and R; F in permuted
 // conserved order (mass, normal momentum, t1 momentum, t2 momentum, energy).
-CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, double F[5]) {
+CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, double F[5], Wave& W) {
   const double rL = L[0], uL = L[1], vL = L[2], wL = L[3], pL = L[4];
   const double rR = R[0], uR = R[1], vR = R[2], wR = R[3], pR = R[4];
   const double cL = sqrt(g * pL / rL);
@@ -146,9 +152,12 @@ CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, d
   const double SR = dmax(uL + cL, uR + cR);
   const double EL = pL * rgm1 + 0.5 * rL * ((uL * uL + vL * vL) + wL * wL);
   const double ER = pR * rgm1 + 0.5 * rR * ((uR * uR + vR * vR) + wR * wR);
+  W.SK = 0.0;
+  W.fac = 0.0;
   if (SL >= 0.0) {
     const double m = rL * uL;
     F[0] = m; F[1] = m * uL + pL; F[2] = m * vL; F[3] = m * wL; F[4] = uL * (EL + pL);
+    W.m = m; W.rK = rL; W.kind = 0;
     return;
   }
   const double Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
@@ -156,6 +165,7 @@ CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, d
   if (Ss < 0.0 && !(SR > 0.0)) {
     const double m = rR * uR;
     F[0] = m; F[1] = m * uR + pR; F[2] = m * vR; F[3] = m * wR; F[4] = uR * (ER + pR);
+    W.m = m; W.rK = rR; W.kind = 3;
     return;
   }
   const bool left = Ss >= 0.0;
@@ -170,6 +180,42 @@ CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, d
   F[2] = m * vK + SK * (fac * vK - rK * vK);
   F[3] = m * wK + SK * (fac * wK - rK * wK);
   F[4] = uK * (EK + pK) + SK * (us4 - EK);
+  W.m = m; W.SK = SK; W.fac = fac; W.rK = rK; W.kind = left ? 1 : 2;
+}
+
+CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, double F[5]) {
+  Wave W;
+  hllc(L, R, g, rgm1, F, W);
+}
+
+// Flux of a passive mass fraction (X_L, X_R at the face) for the HLLC state
+// W chose: X rides the contact like a transverse velocity, so its star value
+// is fac X_K.
+CTU_DEV double species_flux(const Wave& W, double XL, double XR) {
+  if (W.kind == 0) return W.m * XL;
+  if (W.kind == 3) return W.m * XR;
+  const double XK = W.kind == 1 ? XL : XR;
+  return W.m * XK + W.SK * (W.fac * XK - W.rK * XK);
+}
+
+// Tracing of a passive mass fraction with parabola p: only the contact
+// family (speed un) carries it, so like a transverse velocity it takes the
+// reference average and subtracts the reference's excess over the contact
+// family's average when that family reaches the face.  sp, s0, sm are the
+// |speed| dt/dx of the u+c, u and u-c families.
+CTU_DEV double species_up(const Parab& p, double lp, double l0, double sp, double s0) {
+  const double ref = lp > 0.0 ? avg_right(p, sp) : p.aR;
+  const double I0 = l0 > 0.0 ? avg_right(p, s0) : p.aR;
+  double v = ref;
+  if (l0 > 0.0) v = v - (ref - I0);
+  return v;
+}
+CTU_DEV double species_dn(const Parab& p, double lm, double l0, double sm, double s0) {
+  const double ref = lm < 0.0 ? avg_left(p, sm) : p.aL;
+  const double I0 = l0 < 0.0 ? avg_left(p, s0) : p.aL;
+  double v = ref;
+  if (l0 < 0.0) v = v - (ref - I0);
+  return v;
 }
 
 }  // namespace ctu

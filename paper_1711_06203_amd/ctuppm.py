@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("small_dens", ctypes.c_double),
                 ("small_pres", ctypes.c_double), ("grav_z", ctypes.c_double), ("dx", ctypes.c_double * 3),
                 ("domain_lo", ctypes.c_int * 3), ("domain_hi", ctypes.c_int * 3),
-                ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3), ("inflow", ctypes.c_double * 5)]
+                ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3), ("inflow", ctypes.c_double * 5),
+                ("nspec", ctypes.c_int), ("pad", ctypes.c_int), ("inflow_X", ctypes.c_double * 16)]
 
 
 _lib = None
@@ -58,7 +59,7 @@ def lib() -> ctypes.CDLL:
             "ctuppm_problem_create": [vp, ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(ctypes.POINTER(Box)),
                                       ip, ip],
             "ctuppm_problem_destroy": [vp, ctypes.c_int],
-            "ctuppm_fab_elems": [ctypes.POINTER(Box), llp],
+            "ctuppm_fab_elems": [ctypes.POINTER(Box), ctypes.c_int, llp],
             "ctuppm_workspace_bytes": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)],
             "ctuppm_bind_state": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp)],
             "ctuppm_bind_workspace": [vp, ctypes.c_int, vp, sz],
@@ -168,6 +169,9 @@ def _params(prob: W.Problem) -> Params:
         P.bc_hi[d] = prob.bc_hi[d]
     for m in range(5):
         P.inflow[m] = prob.inflow[m]
+    P.nspec = int(prob.nspec)
+    for s, x in enumerate(prob.inflow_X):
+        P.inflow_X[s] = x
     return P
 
 
@@ -198,12 +202,13 @@ class Solver:
         ctx.call("ctuppm_problem_create", ctypes.byref(_params(prob)), nl, ptrs, nb, ctypes.byref(pid))
         self.pid = pid.value
         dev = torch.device("cuda", torch.cuda.current_device())
+        self.nv = 5 + int(prob.nspec)
         self.lv = []
         for boxes in self.levels:
             offsets, shapes, off = [], [], 0
             for lo, hi in boxes:
                 n = [hi[d] - lo[d] + 1 for d in range(3)]
-                shape = (5, n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG)
+                shape = (self.nv, n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG)
                 offsets.append(off)
                 shapes.append(shape)
                 off += (int(np.prod(shape)) + 31) // 32 * 32
@@ -238,9 +243,11 @@ class Solver:
         self.ctx.call("ctuppm_bind_state", self.pid, level, a, b)
 
     def upload(self, Uvalid: np.ndarray, Ufine: Optional[np.ndarray] = None):
-        """Copy a level-0 state (5, nz, ny, nx) (and the fine rectangle's state)
-        into the A fabs; ghosts NaN."""
+        """Copy a level-0 state (5 + nspec, nz, ny, nx) (and the fine
+        rectangle's state) into the A fabs; ghosts NaN."""
         for level, (U, origin) in enumerate([(Uvalid, (0, 0, 0)), (Ufine, self.prob.fine_lo)][:len(self.lv)]):
+            if U.shape[0] != self.nv:
+                raise ValueError(f"state has {U.shape[0]} components, the problem {self.nv}")
             L = self.lv[level]
             host = np.full(L["total"], np.nan)
             for box, off, shape in zip(L["boxes"], L["offsets"], L["shapes"]):
@@ -276,7 +283,7 @@ class Solver:
         return [t[o:o + int(np.prod(s))].reshape(s) for o, s in zip(L["offsets"], L["shapes"])]
 
     def state(self) -> np.ndarray:
-        """Valid cells of the current level-0 state, (5, nz, ny, nx)."""
+        """Valid cells of the current level-0 state, (5 + nspec, nz, ny, nx)."""
         return W.gather_valid(self.fabs(0), self.prob.boxes, self.prob.n)
 
     def state_fine(self) -> np.ndarray:

@@ -28,13 +28,15 @@ NG = 4
 
 def footprint_bytes(prob: W.Problem) -> int:
     """Device bytes a resident problem needs: two fabs per box plus the
-    batched-form stage workspace (q on the grown box, 91 halo-1 arrays)."""
+    batched-form stage workspace (q with 6 + nspec components on the grown box,
+    phi and 18 halo-1 arrays of 5 + nspec components)."""
     total = 0
+    nv = 5 + int(prob.nspec)
     for lo, hi in prob.boxes:
         n = [hi[d] - lo[d] + 1 for d in range(3)]
         grown = (n[0] + 2 * NG) * (n[1] + 2 * NG) * (n[2] + 2 * NG)
         h1 = (n[0] + 2) * (n[1] + 2) * (n[2] + 2)
-        total += 2 * 5 * grown * 8 + ((6 * grown + 91 * h1) * 8 + 255) // 256 * 256
+        total += 2 * nv * grown * 8 + (((nv + 1) * grown + (1 + 18 * nv) * h1) * 8 + 255) // 256 * 256
     return total
 
 

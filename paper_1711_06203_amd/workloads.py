@@ -202,10 +202,27 @@ def kelvin_helmholtz(n=256, box=64, seed=20260102, gamma=5.0 / 3.0, steps=100, n
     return Problem("kh", nn, gamma, U, regular_boxes(nn, be), cfl=0.5, steps=steps, nspec=nspec)
 
 
-def rayleigh_taylor(n=384, seed=20260103, box_seed=None, gamma=1.4, steps=200, boxes=None) -> Problem:
+def material_species(mask, y, nspec: int):
+    """nspec mass fractions for a two-material problem: species 0 marks the
+    material where ``mask`` holds, species 1 the other one (sharp interfaces,
+    carried by the contact), any further species smooth bands across y; they
+    sum to 1."""
+    if nspec <= 0:
+        return None
+    m = np.asarray(mask, dtype=np.float64)
+    if nspec == 1:
+        return [m]
+    if nspec == 2:
+        return [m, 1.0 - m]
+    bands = species_bands(y, nspec - 2)
+    return [0.8 * m, 0.8 * (1.0 - m)] + [0.2 * b for b in bands]
+
+
+def rayleigh_taylor(n=384, seed=20260103, box_seed=None, gamma=1.4, steps=200, boxes=None, nspec=0) -> Problem:
     """Heavy over light in g_z = -1: rho=2 for z>0.5 else 1, p = 2.5 - rho (z-0.5),
     u_z = 0.01 (2r-1) (1+cos(4 pi (z-0.5)))/2 for |z-0.5| < 0.25; periodic x, y,
-    reflecting z; boxes from seeded hierarchical compositions."""
+    reflecting z; boxes from seeded hierarchical compositions; optionally
+    nspec passive species marking the two fluids (material_species)."""
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     x, y, z = cell_centres(nn)
     rng = np.random.default_rng(seed)
@@ -214,11 +231,11 @@ def rayleigh_taylor(n=384, seed=20260103, box_seed=None, gamma=1.4, steps=200, b
     p = 2.5 - rho * (z - 0.5)
     window = np.abs(z - 0.5) < 0.25
     w = np.where(window, 0.01 * (2.0 * r - 1.0) * 0.5 * (1.0 + np.cos(4.0 * np.pi * (z - 0.5))), 0.0)
-    U = conserved(gamma, rho, 0.0, 0.0, w, p)
+    U = conserved(gamma, rho, 0.0, 0.0, w, p, material_species(z > 0.5, y, nspec))
     if boxes is None:
         boxes = uneven_boxes(nn, seed if box_seed is None else box_seed)
     return Problem("rt", nn, gamma, U, boxes, (BC_PERIODIC, BC_PERIODIC, BC_REFLECT),
-                   (BC_PERIODIC, BC_PERIODIC, BC_REFLECT), cfl=0.5, grav_z=-1.0, steps=steps)
+                   (BC_PERIODIC, BC_PERIODIC, BC_REFLECT), cfl=0.5, grav_z=-1.0, steps=steps, nspec=nspec)
 
 
 def _fourier_field(rng: np.random.Generator, x, y, z, modes=8):
@@ -236,9 +253,10 @@ def _fourier_field(rng: np.random.Generator, x, y, z, modes=8):
 SERVING_SIZES = (32, 48, 64, 96, 128)
 
 
-def serving_request(seed: int, n: Optional[int] = None, gamma=1.4, steps=50) -> Problem:
+def serving_request(seed: int, n: Optional[int] = None, gamma=1.4, steps=50, nspec=0) -> Problem:
     """One serving request: a periodic N^3 box with a smooth random state
-    (rho = 1 + 0.1 f, p = 1 + 0.1 f, u_d = 0.3 sqrt(gamma) f; 8 Fourier modes each)."""
+    (rho = 1 + 0.1 f, p = 1 + 0.1 f, u_d = 0.3 sqrt(gamma) f; 8 Fourier modes
+    each), optionally with nspec smooth species bands across y."""
     rng = np.random.default_rng(seed)
     if n is None:
         n = SERVING_SIZES[int(rng.integers(len(SERVING_SIZES)))]
@@ -250,8 +268,9 @@ def serving_request(seed: int, n: Optional[int] = None, gamma=1.4, steps=50) -> 
     u = a * _fourier_field(rng, x, y, z)
     v = a * _fourier_field(rng, x, y, z)
     w = a * _fourier_field(rng, x, y, z)
-    U = conserved(gamma, rho, u, v, w, p)
-    return Problem(f"serve{n}", nn, gamma, U, [((0, 0, 0), (n - 1, n - 1, n - 1))], cfl=0.5, steps=steps)
+    U = conserved(gamma, rho, u, v, w, p, species_bands(y, nspec) if nspec else None)
+    return Problem(f"serve{n}", nn, gamma, U, [((0, 0, 0), (n - 1, n - 1, n - 1))], cfl=0.5, steps=steps,
+                   nspec=nspec)
 
 
 def smooth_wave(n=32, gamma=1.4, box=None, amp=0.2) -> Problem:
@@ -276,11 +295,13 @@ def uniform(n=16, gamma=1.4, rho=1.3, vel=(0.3, -0.2, 0.1), p=0.9, box=None, bc=
     return Problem("uniform", nn, gamma, U, regular_boxes(nn, be), (bc,) * 3, (bc,) * 3, grav_z=grav_z)
 
 
-def cloud_wind(n=256, box=64, fine_box=32, fine_region=None, gamma=5.0 / 3.0, steps=100) -> Problem:
+def cloud_wind(n=256, box=64, fine_box=32, fine_region=None, gamma=5.0 / 3.0, steps=100, nspec=0) -> Problem:
     """Dense cloud (rho 10, radius 0.1, at rest, pressure-matched p=1) in a Mach-2
     wind (rho 1, p 1, u_x = 2 sqrt(gamma)); inflow x-lo, outflow x-hi, periodic y, z.
     Two levels: the fine level (ratio 2) covers coarse cells ``fine_region``
-    (default: the central half of the domain)."""
+    (default: the central half of the domain).  Optionally nspec passive
+    species mark cloud and wind material (material_species); the inflow
+    carries the wind's mass fractions."""
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     wind = 2.0 * math.sqrt(gamma)
 
@@ -289,7 +310,7 @@ def cloud_wind(n=256, box=64, fine_box=32, fine_region=None, gamma=5.0 / 3.0, st
         inc = r2 < 0.01
         rho = np.where(inc, 10.0, 1.0)
         u = np.where(inc, 0.0, wind)
-        return conserved(gamma, rho, u, 0.0, 0.0, 1.0)
+        return conserved(gamma, rho, u, 0.0, 0.0, 1.0, material_species(inc, y, nspec))
 
     x, y, z = cell_centres(nn)
     U = state(x, y, z)
@@ -307,7 +328,11 @@ def cloud_wind(n=256, box=64, fine_box=32, fine_region=None, gamma=5.0 / 3.0, st
     fbe = (fine_box,) * 3 if np.isscalar(fine_box) else tuple(fine_box)
     prob = Problem("cloud", nn, gamma, U, regular_boxes(nn, be),
                    (BC_INFLOW, BC_PERIODIC, BC_PERIODIC), (BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC),
-                   cfl=0.5, inflow=(1.0, wind, 0.0, 0.0, 1.0), steps=steps)
+                   cfl=0.5, inflow=(1.0, wind, 0.0, 0.0, 1.0), steps=steps, nspec=nspec)
+    if nspec:
+        # the wind's fractions at the inflow face (y = 0.5 for the bands)
+        prob.inflow_X = tuple(float(np.asarray(a).ravel()[0])
+                              for a in material_species(np.zeros(1, bool), np.full(1, 0.5), nspec))
     prob.fine_boxes = regular_boxes(fn, fbe, origin=flo)
     prob.U0_fine = Uf
     prob.fine_lo = flo

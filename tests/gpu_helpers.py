@@ -11,13 +11,13 @@ def field_scale(ref, m):
 
 def max_rel(got, ref):
     """Per-field max|g - o| / max|o|."""
-    return [float(np.abs(got[m] - ref[m]).max() / field_scale(ref, m)) for m in range(5)]
+    return [float(np.abs(got[m] - ref[m]).max() / field_scale(ref, m)) for m in range(ref.shape[0])]
 
 
 def l1_rel(got, ref):
     """Per-field sum|g - o| / sum|o|."""
     out = []
-    for m in range(5):
+    for m in range(ref.shape[0]):
         s = np.abs(ref[m]).sum()
         if s == 0.0:
             s = np.abs(ref[0]).sum()
@@ -27,7 +27,7 @@ def l1_rel(got, ref):
 
 def totals_rel(got, ref):
     out = []
-    for m in range(5):
+    for m in range(ref.shape[0]):
         tg = math.fsum(got[m].ravel())
         to = math.fsum(ref[m].ravel())
         s = math.fsum(np.abs(ref[m]).ravel()) or math.fsum(np.abs(ref[0]).ravel())

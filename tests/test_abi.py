@@ -35,10 +35,13 @@ def test_host_only_calls_without_gpu():
     b.lo[:] = [0, 0, 0]
     b.hi[:] = [63, 31, 15]
     e = ctypes.c_longlong()
-    assert L.ctuppm_fab_elems(ctypes.byref(b), ctypes.byref(e)) == 0
+    assert L.ctuppm_fab_elems(ctypes.byref(b), 0, ctypes.byref(e)) == 0
     assert e.value == 5 * 72 * 40 * 24
+    assert L.ctuppm_fab_elems(ctypes.byref(b), 13, ctypes.byref(e)) == 0
+    assert e.value == 18 * 72 * 40 * 24
+    assert L.ctuppm_fab_elems(ctypes.byref(b), 17, ctypes.byref(e)) == ctuppm.EINVAL
     b.hi[:] = [-1, 3, 3]
-    assert L.ctuppm_fab_elems(ctypes.byref(b), ctypes.byref(e)) == ctuppm.EINVAL
+    assert L.ctuppm_fab_elems(ctypes.byref(b), 0, ctypes.byref(e)) == ctuppm.EINVAL
     assert L.ctuppm_num_stages() == len(ctuppm.stage_names())
 
 

@@ -115,3 +115,10 @@ def test_cloud_two_level_64_twenty_steps(ctx):
     s.close()
     print(f"cloud64 20 steps: bitwise coarse={np.array_equal(gc, rc)} fine={np.array_equal(gf, rf)}", flush=True)
     assert max(l1_rel(gc, rc)) <= 1e-8 and max(l1_rel(gf, rf)) <= 1e-8
+
+
+@pytest.mark.slow
+def test_kh256_13species_one_step_sampled(ctx):
+    prob = W.kelvin_helmholtz(n=256, box=64, nspec=13)
+    assert prob.U0.shape[0] == 18
+    _sampled(ctx, prob, 200, 3)
