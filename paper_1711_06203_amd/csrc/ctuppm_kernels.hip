@@ -21,6 +21,14 @@ namespace ctu {
 
 namespace {
 
+// Device arrays are accessed through global-address-space pointers, so loads
+// and stores compile to global (not flat) memory instructions: their
+// completion is tracked by the vector-memory counter alone and a uniform base
+// goes in scalar registers.
+using gdbl = __attribute__((address_space(1))) double;
+CTU_DEV gdbl* gp(double* p) { return (gdbl*)p; }
+CTU_DEV const gdbl* gp(const double* p) { return (const gdbl*)p; }
+
 template <class F>
 CTU_DEV void for_each_chunk(int nchunks, F&& f) {
   const int per = gridDim.x >> 3;
@@ -68,16 +76,16 @@ struct Geo {
   // scratch sub-arrays: q, phi, then 18 arrays of nv components (ql[3], qr[3],
   // fn[3], f1[6], ff[3]); offsets in 64 bits (a 256^3 box with 16 species
   // spans more than 2^31 doubles)
-  CTU_DEV double* h1arr(double* s, int a) const {
-    return s + (long long)(kNV + 1 + ns) * gcomp + (1 + (long long)nv * a) * hcomp;
+  CTU_DEV gdbl* h1arr(double* s, int a) const {
+    return gp(s) + (long long)(kNV + 1 + ns) * gcomp + (1 + (long long)nv * a) * hcomp;
   }
-  CTU_DEV double* q(double* s) const { return s; }
-  CTU_DEV double* phi(double* s) const { return s + (long long)(kNV + 1 + ns) * gcomp; }
-  CTU_DEV double* ql(double* s, int d) const { return h1arr(s, d); }
-  CTU_DEV double* qr(double* s, int d) const { return h1arr(s, 3 + d); }
-  CTU_DEV double* fn(double* s, int d) const { return h1arr(s, 6 + d); }
-  CTU_DEV double* f1(double* s, int p) const { return h1arr(s, 9 + p); }
-  CTU_DEV double* ff(double* s, int d) const { return h1arr(s, 15 + d); }
+  CTU_DEV gdbl* q(double* s) const { return gp(s); }
+  CTU_DEV gdbl* phi(double* s) const { return gp(s) + (long long)(kNV + 1 + ns) * gcomp; }
+  CTU_DEV gdbl* ql(double* s, int d) const { return h1arr(s, d); }
+  CTU_DEV gdbl* qr(double* s, int d) const { return h1arr(s, 3 + d); }
+  CTU_DEV gdbl* fn(double* s, int d) const { return h1arr(s, 6 + d); }
+  CTU_DEV gdbl* f1(double* s, int p) const { return h1arr(s, 9 + p); }
+  CTU_DEV gdbl* ff(double* s, int d) const { return h1arr(s, 15 + d); }
 };
 
 CTU_DEV void count(unsigned long long* c, unsigned long long v) {
@@ -102,8 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxe
     const BoxRec& S = boxes[T.src];
     const int cur = D.P->cur;
     const Geo gd(D.n, D.ns), gs(S.n, S.ns);
-    const double* __restrict__ src = S.U[cur];
-    double* __restrict__ dst = D.U[cur];
+    const gdbl* __restrict__ src = gp(S.U[cur]);
+    gdbl* __restrict__ dst = gp(D.U[cur]);
     const int si = gs.g(i + T.off[0], j + T.off[1], k + T.off[2]);
     const int di = gd.g(i, j, k);
 #pragma unroll
@@ -130,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
     x[2] = T.lo[2] + r / T.ext[1];
     const BoxRec& B = boxes[T.box];
     const Geo g(B.n, B.ns);
-    double* __restrict__ U = B.U[B.P->cur];
+    gdbl* __restrict__ U = gp(B.U[B.P->cur]);
     const int di = g.g(x[0], x[1], x[2]);
     if (T.bc == 3) {
       for (int m = 0; m < g.nv; ++m) U[m * g.gcomp + di] = T.inflow[m];
@@ -194,8 +202,8 @@ __global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes
       curP = P;
     }
     const Geo g(B.n, B.ns);
-    const double* __restrict__ U = B.U[P->cur];
-    double* __restrict__ q = g.q(B.scr);
+    const gdbl* __restrict__ U = gp(B.U[P->cur]);
+    gdbl* __restrict__ q = g.q(B.scr);
     const double gamma = P->gamma, gm1 = P->gm1, sd = P->small_dens, sp = P->small_pres;
     const double rdx = P->rdx[0], rdy = P->rdx[1], rdz = P->rdx[2];
     unsigned long long hd = 0, hp = 0;
@@ -256,7 +264,7 @@ __global__ void k_flip(ProbDev* const* probs, int nprobs) {
 // ---------------------------------------------------------------- flattening
 
 // CW84 shock indicator of the cell at offset o along stride st (direction d).
-CTU_DEV double shock_ind(const double* __restrict__ p, const double* __restrict__ un, int o, int st) {
+CTU_DEV double shock_ind(const gdbl* __restrict__ p, const gdbl* __restrict__ un, int o, int st) {
   const double dp1 = p[o + st] - p[o - st];
   const double dp2 = p[o + 2 * st] - p[o - 2 * st];
   double f = 0.0;
@@ -271,16 +279,16 @@ __global__ __launch_bounds__(kBlock) void k_flatten(const BoxRec* __restrict__ b
     const March M = units[u];
     const BoxRec& B = boxes[M.box];
     const Geo g(B.n, B.ns);
-    const double* __restrict__ q = g.q(B.scr);
-    const double* __restrict__ p = q + 4 * g.gcomp;
-    double* __restrict__ phiout = g.phi(B.scr);
+    const gdbl* __restrict__ q = g.q(B.scr);
+    const gdbl* __restrict__ p = q + 4 * g.gcomp;
+    gdbl* __restrict__ phiout = g.phi(B.scr);
     march(kCells1, B, M, [&](int i, int j, int k) {
       const int o = g.g(i, j, k);
       double phi = 1.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int st = g.gstride(d);
-        const double* __restrict__ un = q + (1 + d) * g.gcomp;
+        const gdbl* __restrict__ un = q + (1 + d) * g.gcomp;
         const int s = (p[o + st] - p[o - st]) > 0.0 ? 1 : -1;
         const double fd = dmax(shock_ind(p, un, o, st), shock_ind(p, un, o - s * st, st));
         const double v = 1.0 - fd;
@@ -294,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_flatten(const BoxRec* __restrict__ b
 // ------------------------------------------------------ PPM + tracing along D
 
 template <int D>
-CTU_DEV void store_flux(double* __restrict__ F, int hcomp, int o, const double f[5]) {
+CTU_DEV void store_flux(gdbl* __restrict__ F, int hcomp, int o, const double f[5]) {
   F[o] = f[0];
   F[(1 + D) * hcomp + o] = f[1];
   F[(1 + (D + 1) % 3) * hcomp + o] = f[2];
@@ -316,10 +324,10 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
-    const double* __restrict__ q = g.q(B.scr);
-    const double* __restrict__ phiv = g.phi(B.scr);
-    double* __restrict__ ql = g.ql(B.scr, D);
-    double* __restrict__ qr = g.qr(B.scr, D);
+    const gdbl* __restrict__ q = g.q(B.scr);
+    const gdbl* __restrict__ phiv = g.phi(B.scr);
+    gdbl* __restrict__ ql = g.ql(B.scr, D);
+    gdbl* __restrict__ qr = g.qr(B.scr, D);
     const int st = g.gstride(D), sth = g.hstride(D);
     const double dtdx = P->dt / P->dx[D];
     const double hdtg = 0.5 * P->dt * P->grav_z;
@@ -334,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
       Parab par[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        const double* a = q + comp[m] * g.gcomp + o;
+        const gdbl* a = q + comp[m] * g.gcomp + o;
         par[m] = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
       }
       const double rho = q[o], un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
@@ -351,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
         const double lm = un - cs, l0 = un, lp = un + cs;
         const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, spp = fabs(lp) * dtdx;
         for (int is = 0; is < g.ns; ++is) {
-          const double* a = q + (6 + is) * g.gcomp + o;
+          const gdbl* a = q + (6 + is) * g.gcomp + o;
           const Parab px = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
           if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
           if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
@@ -380,9 +388,9 @@ __global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ b
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
-    const double* __restrict__ ql = g.ql(B.scr, D);
-    const double* __restrict__ qr = g.qr(B.scr, D);
-    double* __restrict__ fn = g.fn(B.scr, D);
+    const gdbl* __restrict__ ql = g.ql(B.scr, D);
+    const gdbl* __restrict__ qr = g.qr(B.scr, D);
+    gdbl* __restrict__ fn = g.fn(B.scr, D);
     march(kFace0 + D, B, M, [&](int i, int j, int k) {
       const int o = g.h(i, j, k);
       double L[5], R[5], f[5];
@@ -443,8 +451,8 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     const int sa = g.hstride(A);
-    const double* __restrict__ ql = g.ql(B.scr, A);
-    const double* __restrict__ qr = g.qr(B.scr, A);
+    const gdbl* __restrict__ ql = g.ql(B.scr, A);
+    const gdbl* __restrict__ qr = g.qr(B.scr, A);
     unsigned long long fb = 0;
     march(kFace0 + A, B, M, [&](int i, int j, int k) {
       const int x[3] = {i, j, k};
@@ -463,12 +471,12 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
         if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
         const double c3 = (P->dt / P->dx[Bd]) / 3.0;
         const int sb = g.hstride(Bd);
-        const double* __restrict__ Fb = g.fn(B.scr, Bd);
+        const gdbl* __restrict__ Fb = g.fn(B.scr, Bd);
         double VL[5], VR[5], tL[5], tR[5], f[5];
         const int oL = o - sa, oR = o;  // owner cells of the left and right states
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
-          const double* Fm = Fb + m * g.hcomp;
+          const gdbl* Fm = Fb + m * g.hcomp;
           VL[m] = UL[m] - c3 * (Fm[oL + sb] - Fm[oL]);
           VR[m] = UR[m] - c3 * (Fm[oR + sb] - Fm[oR]);
         }
@@ -477,13 +485,13 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
         fb += kL + kR;
         Wave W;
         hllc(tL, tR, P->gamma, P->rgm1, f, W);
-        double* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
+        gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
         store_flux<A>(F1, g.hcomp, o, f);
         // species: rho X corrected by the same flux difference, back to X with
         // the corrected density (or the traced X where the state fell back)
         for (int is = 0; is < g.ns; ++is) {
           const int c = (kNV + is) * g.hcomp;
-          const double* Fm = Fb + c;
+          const gdbl* Fm = Fb + c;
           const double xL = ql[c + o], xR = qr[c + o];
           const double wL = sL[0] * xL - c3 * (Fm[oL + sb] - Fm[oL]);
           const double wR = sR[0] * xR - c3 * (Fm[oR + sb] - Fm[oR]);
@@ -500,16 +508,16 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
 // A, then the final HLLC flux (global component order).  fb counts states that
 // fell back to the uncorrected ones.
 template <int A>
-CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, double* __restrict__ ff, int& fb) {
+CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, gdbl* __restrict__ ff, int& fb) {
   constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
   // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
   constexpr int pbc = 2 * Bd + (Cd == (Bd + 1) % 3 ? 0 : 1);
   constexpr int pcb = 2 * Cd + (Bd == (Cd + 1) % 3 ? 0 : 1);
   const int sa = g.hstride(A), sb = g.hstride(Bd), sc = g.hstride(Cd);
-  const double* __restrict__ ql = g.ql(B.scr, A);
-  const double* __restrict__ qr = g.qr(B.scr, A);
-  const double* __restrict__ Fbc = g.f1(B.scr, pbc);
-  const double* __restrict__ Fcb = g.f1(B.scr, pcb);
+  const gdbl* __restrict__ ql = g.ql(B.scr, A);
+  const gdbl* __restrict__ qr = g.qr(B.scr, A);
+  const gdbl* __restrict__ Fbc = g.f1(B.scr, pbc);
+  const gdbl* __restrict__ Fcb = g.f1(B.scr, pcb);
   const double c2b = 0.5 * (P->dt / P->dx[Bd]);
   const double c2c = 0.5 * (P->dt / P->dx[Cd]);
   double sL[5], sR[5], UL[5], UR[5];
@@ -523,8 +531,8 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
   const int oL = o - sa, oR = o;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    const double* F1 = Fbc + m * g.hcomp;
-    const double* F2 = Fcb + m * g.hcomp;
+    const gdbl* F1 = Fbc + m * g.hcomp;
+    const gdbl* F2 = Fcb + m * g.hcomp;
     UL[m] = UL[m] - c2b * (F1[oL + sb] - F1[oL]);
     UR[m] = UR[m] - c2b * (F1[oR + sb] - F1[oR]);
     UL[m] = UL[m] - c2c * (F2[oL + sc] - F2[oL]);
@@ -539,8 +547,8 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
   store_flux<A>(ff, g.hcomp, o, f);
   for (int is = 0; is < g.ns; ++is) {
     const int c = (kNV + is) * g.hcomp;
-    const double* F1 = Fbc + c;
-    const double* F2 = Fcb + c;
+    const gdbl* F1 = Fbc + c;
+    const gdbl* F2 = Fcb + c;
     const double xL = ql[c + o], xR = qr[c + o];
     double wL = sL[0] * xL, wR = sR[0] * xR;
     wL = wL - c2b * (F1[oL + sb] - F1[oL]);
@@ -560,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ bo
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
-    double* __restrict__ ff = g.ff(B.scr, A);
+    gdbl* __restrict__ ff = g.ff(B.scr, A);
     int fb = 0;
     march(kFin0 + A, B, M, [&](int i, int j, int k) {
       final_flux<A>(B, g, P, g.h(i, j, k), ff, fb);
@@ -579,11 +587,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
     const BoxRec& B = boxes[M.box];
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
-    const double* __restrict__ U = B.U[P->cur];
-    double* __restrict__ Un = B.U[P->cur ^ 1];
-    const double* __restrict__ Fx = g.ff(B.scr, 0);
-    const double* __restrict__ Fy = g.ff(B.scr, 1);
-    const double* __restrict__ Fz = g.ff(B.scr, 2);
+    const gdbl* __restrict__ U = gp(B.U[P->cur]);
+    gdbl* __restrict__ Un = gp(B.U[P->cur ^ 1]);
+    const gdbl* __restrict__ Fx = g.ff(B.scr, 0);
+    const gdbl* __restrict__ Fy = g.ff(B.scr, 1);
+    const gdbl* __restrict__ Fz = g.ff(B.scr, 2);
     const double dtdx = P->dt / P->dx[0], dtdy = P->dt / P->dx[1], dtdz = P->dt / P->dx[2];
     const bool grav = P->grav_z != 0.0;
     const double hdtg = 0.5 * P->dt * P->grav_z;
@@ -653,7 +661,7 @@ CTU_DEV bool tag_item(const int ext[3], int t, int& a, int& b, int& c) {
 __global__ __launch_bounds__(kBlock) void k_gather(TwoLevelArgs A, const GatherTag* __restrict__ tags,
                                                    const Chunk* __restrict__ chunks, int n, int which) {
   const int rplane = A.rext[0] * A.rext[1], rcomp = rplane * A.rext[2];
-  double* __restrict__ dst = which ? A.ct1 : A.ct0;
+  gdbl* __restrict__ dst = gp(which ? A.ct1 : A.ct0);
   for_each_chunk(n, [&](int c) {
     const Chunk ch = chunks[c];
     const GatherTag T = tags[ch.box];
@@ -661,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(TwoLevelArgs A, const GatherT
     if (!tag_item(T.ext, ch.start + threadIdx.x, a, b, cc)) return;
     const BoxRec& B = A.cboxes[T.box];
     const Geo g(B.n, B.ns);
-    const double* __restrict__ U = B.U[which ? (B.P->cur ^ 1) : B.P->cur];
+    const gdbl* __restrict__ U = gp(B.U[which ? (B.P->cur ^ 1) : B.P->cur]);
     const int so = g.g(T.lo[0] + a, T.lo[1] + b, T.lo[2] + cc);
     const int ro = (T.roff[2] + cc) * rplane + (T.roff[1] + b) * A.rext[0] + (T.roff[0] + a);
     for (int m = 0; m < g.nv; ++m) dst[m * rcomp + ro] = U[m * g.gcomp + so];
@@ -679,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_cfinterp(TwoLevelArgs A, const CfTag
     if (!tag_item(T.ext, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
     const BoxRec& B = A.fboxes[T.box];
     const Geo g(B.n, B.ns);
-    double* __restrict__ U = B.U[B.P->cur];
+    gdbl* __restrict__ U = gp(B.U[B.P->cur]);
     int I[3], rp[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -691,8 +699,8 @@ __global__ __launch_bounds__(kBlock) void k_cfinterp(TwoLevelArgs A, const CfTag
     const int st[3] = {1, A.rext[0], rplane};
     const int go = g.g(x[0], x[1], x[2]);
     for (int m = 0; m < g.nv; ++m) {
-      const double* __restrict__ a0 = A.ct0 + m * rcomp;
-      const double* __restrict__ a1 = A.ct1 + m * rcomp;
+      const gdbl* __restrict__ a0 = gp(A.ct0) + m * rcomp;
+      const gdbl* __restrict__ a1 = gp(A.ct1) + m * rcomp;
       const double cpar = w0 * a0[po] + theta * a1[po];
       double val = cpar;
 #pragma unroll
@@ -714,10 +722,10 @@ __global__ void k_reg_coarse(TwoLevelArgs A, const RegFace* __restrict__ faces, 
   const RegFace F = faces[f];
   const BoxRec& B = A.cboxes[F.cbox];
   const Geo g(B.n, B.ns);
-  const double* __restrict__ Ff = g.ff(B.scr, F.d);
+  const gdbl* __restrict__ Ff = g.ff(B.scr, F.d);
   const int o = g.h(F.cface[0], F.cface[1], F.cface[2]);
   const double dt = A.Pc->dt;
-  double* r = A.reg + 2 * g.nv * f;
+  gdbl* r = gp(A.reg) + 2 * g.nv * f;
   for (int m = 0; m < g.nv; ++m) {
     r[m] = dt * Ff[m * g.hcomp + o];
     r[g.nv + m] = 0.0;
@@ -730,14 +738,14 @@ __global__ void k_reg_fine(TwoLevelArgs A, const RegFace* __restrict__ faces, in
   const RegFace F = faces[f];
   const BoxRec& B = A.fboxes[F.fbox];
   const Geo g(B.n, B.ns);
-  const double* __restrict__ Ff = g.ff(B.scr, F.d);
+  const gdbl* __restrict__ Ff = g.ff(B.scr, F.d);
   const int t1 = F.d == 0 ? 1 : 0, t2 = F.d == 2 ? 1 : 2;  // transverse directions, increasing
   const int s1 = g.hstride(t1), s2 = g.hstride(t2);
   const int o = g.h(F.fface[0], F.fface[1], F.fface[2]);
   const double dt = A.Pf->dt;
-  double* r = A.reg + 2 * g.nv * f;
+  gdbl* r = gp(A.reg) + 2 * g.nv * f;
   for (int m = 0; m < g.nv; ++m) {
-    const double* Fm = Ff + m * g.hcomp;
+    const gdbl* Fm = Ff + m * g.hcomp;
     const double t00 = dt * Fm[o], t10 = dt * Fm[o + s1], t01 = dt * Fm[o + s2], t11 = dt * Fm[o + s1 + s2];
     r[g.nv + m] = r[g.nv + m] + ((t00 + t10) + (t01 + t11));
   }
@@ -753,13 +761,13 @@ __global__ __launch_bounds__(kBlock) void k_avgdown(TwoLevelArgs A, const AvgTag
     const BoxRec& C = A.cboxes[T.cbox];
     const BoxRec& Fb = A.fboxes[T.fbox];
     const Geo gc(C.n, C.ns), gf(Fb.n, Fb.ns);
-    double* __restrict__ Uc = C.U[C.P->cur ^ 1];
-    const double* __restrict__ Uf = Fb.U[Fb.P->cur];
+    gdbl* __restrict__ Uc = gp(C.U[C.P->cur ^ 1]);
+    const gdbl* __restrict__ Uf = gp(Fb.U[Fb.P->cur]);
     const int co = gc.g(T.clo[0] + a, T.clo[1] + b, T.clo[2] + cc);
     const int fo = gf.g(T.flo[0] + 2 * a, T.flo[1] + 2 * b, T.flo[2] + 2 * cc);
     const int sx = 1, sy = gf.gx, sz = gf.gplane;
     for (int m = 0; m < gc.nv; ++m) {
-      const double* f = Uf + m * gf.gcomp + fo;
+      const gdbl* f = Uf + m * gf.gcomp + fo;
       const double s0 = (f[0] + f[sx]) + (f[sy] + f[sx + sy]);
       const double s1 = (f[sz] + f[sx + sz]) + (f[sy + sz] + f[sx + sy + sz]);
       Uc[m * gc.gcomp + co] = 0.125 * (s0 + s1);
@@ -773,10 +781,10 @@ __global__ void k_reflux(TwoLevelArgs A, const RegFace* __restrict__ faces, int 
   const RegFace F = faces[f];
   const BoxRec& B = A.cboxes[F.cbox];
   const Geo g(B.n, B.ns);
-  double* __restrict__ U = B.U[B.P->cur ^ 1];
+  gdbl* __restrict__ U = gp(B.U[B.P->cur ^ 1]);
   const int o = g.g(F.ucell[0], F.ucell[1], F.ucell[2]);
   const double rdx = A.Pc->rdx[F.d];
-  const double* r = A.reg + 2 * g.nv * f;
+  const gdbl* r = gp(A.reg) + 2 * g.nv * f;
   for (int m = 0; m < g.nv; ++m) {
     const double R = r[m] - 0.25 * r[g.nv + m];
     const double u = U[m * g.gcomp + o];
