@@ -49,7 +49,9 @@ class Params(ctypes.Structure):
                 ("grav_z", ctypes.c_double), ("dx", ctypes.c_double * 3),
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3),
                 ("inflow", ctypes.c_double * 5), ("nspec", ctypes.c_int), ("pad", ctypes.c_int),
-                ("inflow_X", ctypes.c_double * MAXSPEC)]
+                ("inflow_X", ctypes.c_double * MAXSPEC), ("scheme", ctypes.c_int), ("pad2", ctypes.c_int)]
+
+SCHEMES = {"ctu": 0, "mol2": 1, "mol3": 2}
 
 
 class Stages(ctypes.Structure):
@@ -92,6 +94,8 @@ def lib():
         L.orc_trace_cell.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, dp, dp]
         L.orc_trace_cell.restype = None
+        L.orc_mol_stage.argtypes = [dp, dp, ip, pp, ctypes.c_double, ctypes.c_double, dp, lp]
+        L.orc_mol_stage.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -107,8 +111,9 @@ def _ip(seq):
 
 def make_params(gamma, dx, cfl=0.5, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), grav_z=0.0,
                 inflow=(1.0, 0.0, 0.0, 0.0, 1.0), small_dens=1e-12, small_pres=1e-12, nspec=0,
-                inflow_X=()) -> Params:
+                inflow_X=(), scheme=0) -> Params:
     P = Params()
+    P.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     P.nspec = int(nspec)
     for s_, v in enumerate(inflow_X):
         P.inflow_X[s_] = v
@@ -127,7 +132,8 @@ def params_of(prob, fine: bool = False) -> Params:
     if fine:
         dx = tuple(v / 2.0 for v in dx)
     return make_params(prob.gamma, dx, prob.cfl, prob.bc_lo, prob.bc_hi, prob.grav_z, prob.inflow,
-                       prob.small_dens, prob.small_pres, getattr(prob, "nspec", 0), getattr(prob, "inflow_X", ()))
+                       prob.small_dens, prob.small_pres, getattr(prob, "nspec", 0), getattr(prob, "inflow_X", ()),
+                       getattr(prob, "scheme", 0))
 
 
 def grow(Uvalid: np.ndarray, fill=np.nan) -> np.ndarray:
@@ -243,11 +249,52 @@ def sample_step(Ufull_grown_filled: np.ndarray, P: Params, dt: float,
     """U^{n+1} at chosen cells (i, j, k), each computed on its own from the 9^3
     neighbourhood of a whole-domain grown array whose ghosts are filled."""
     G = Ufull_grown_filled
+    if P.scheme != 0:
+        raise ValueError("MOL schemes: use sample_step_mol on a periodic domain")
     out = np.zeros((len(cells), G.shape[0]))
     for s, (i, j, k) in enumerate(cells):
         loc = np.ascontiguousarray(G[:, k:k + 2 * NG + 1, j:j + 2 * NG + 1, i:i + 2 * NG + 1])
         Gn, _ = advance_box(loc, P, dt)
         out[s] = Gn[:, NG, NG, NG]
+    return out
+
+
+def mol_stage(Gs: np.ndarray, P: Params, dt: float, G0: Optional[np.ndarray] = None,
+              c: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:
+    """One MOL Runge-Kutta stage on a grown array with filled ghosts: valid cells
+    of the result are T = Us + dt L(Us), or U0 + c (T - U0) when G0 is given;
+    ghosts are copied from Gs.  Returns (result, counters)."""
+    Gs = np.ascontiguousarray(Gs, dtype=np.float64)
+    n = _ip([Gs.shape[3] - 2 * NG, Gs.shape[2] - 2 * NG, Gs.shape[1] - 2 * NG])
+    out = Gs.copy()
+    cnt = np.zeros(NCNT, dtype=np.int64)
+    g0 = None if G0 is None else np.ascontiguousarray(G0, dtype=np.float64)
+    rc = lib().orc_mol_stage(_dp(Gs), _dp(g0) if g0 is not None else None, n, ctypes.byref(P), float(dt),
+                             float(c), _dp(out), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+    if rc:
+        raise RuntimeError(f"orc_mol_stage failed ({rc})")
+    return out, cnt
+
+
+def sample_step_mol(Uvalid: np.ndarray, P: Params, dt: float, cells: Sequence[Tuple[int, int, int]]) -> np.ndarray:
+    """U^{n+1} of the MOL-RK2 step at chosen cells of a periodic domain, each on
+    its own: stage 1 over the 9^3 cells around the sample (from their 17^3
+    periodic neighbourhood), then stage 2 on the sample cell from the 9^3
+    neighbourhood of the stage-1 state."""
+    if P.scheme != 1:
+        raise ValueError("sampled MOL steps are written for SSP-RK2")
+    R = 2 * NG
+    nz, ny, nx = Uvalid.shape[1:]
+    out = np.zeros((len(cells), Uvalid.shape[0]))
+    for s, (i, j, k) in enumerate(cells):
+        iz = np.arange(k - R, k + R + 1) % nz
+        iy = np.arange(j - R, j + R + 1) % ny
+        ix = np.arange(i - R, i + R + 1) % nx
+        loc = np.ascontiguousarray(Uvalid[:, iz][:, :, iy][:, :, :, ix])
+        W1, _ = mol_stage(loc, P, dt)
+        core = (slice(None), slice(NG, NG + 2 * NG + 1), slice(NG, NG + 2 * NG + 1), slice(NG, NG + 2 * NG + 1))
+        Un, _ = mol_stage(np.ascontiguousarray(W1[core]), P, dt, np.ascontiguousarray(loc[core]), 0.5)
+        out[s] = Un[:, NG, NG, NG]
     return out
 
 

@@ -25,6 +25,16 @@
  * stated formulas parenthesise them and are compiled without contraction
  * (-ffp-contract=off) and without fast-math.
  *
+ * Method-of-lines variant (the formulation of the paper's GPU proxy, section
+ * 4, which names it and nothing more): the spatial operator reconstructs the
+ * same PPM parabolas (with flattening) and takes their edge values as the face
+ * states, with no characteristic tracing and no transverse corrections, then
+ * the HLLC flux and the flux divergence; gravity enters as a source term.
+ * Time integration is the strong-stability-preserving Runge-Kutta method of
+ * Shu & Osher 1988 (JCP 77:439) of order 2 or 3, ghost cells refilled before
+ * every stage, dt from the CFL condition on the sum over directions of the
+ * signal speeds (an unsplit multi-stage scheme sees all three at once).
+ *
  * Passive species (mass fractions X_s, conserved rho X_s after rho E) follow
  * the flow: reconstructed like any primitive, traced with the contact family
  * (like the transverse velocities), corrected and fluxed like the transverse
@@ -61,6 +71,8 @@ typedef struct {
     int nspec;        /* passive species (0..16) */
     int pad;
     double inflow_X[MAXSPEC];
+    int scheme;       /* 0 unsplit CTU/PPM, 1 MOL with SSP-RK2, 2 MOL with SSP-RK3 */
+    int pad2;
 } orc_params;
 
 static int nvar_of(const orc_params *P) { return 5 + P->nspec; }
@@ -615,6 +627,146 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
     return 0;
 }
 
+/* ------------------------------------------------ method of lines (f2) */
+
+/* One Runge-Kutta stage of the MOL variant on a grown box whose ghost cells
+ * are filled: with T = Us + dt L(Us), where
+ *   dt L(Us) = sum over x, y, z of dt/dx_d (F_lo - F_hi), then the gravity
+ *   source dt g (0, 0, 0, rho, rho w) of Us added to rho w and rho E,
+ * the valid cells of Uout receive T when U0 is NULL, else the convex
+ * combination (1 - c) U0 + c T, evaluated as U0 + c (T - U0) so that a
+ * constant state stays exactly constant.
+ * The fluxes are HLLC fluxes between the PPM edge values of the two cells of
+ * each face (left: the upper edge of the lower cell, right: the lower edge of
+ * the upper cell), floored like the CTU face states.  Failures (density or
+ * pressure below the floors, non-finite values) of the result are counted. */
+int orc_mol_stage(const double *Us, const double *U0, const int n[3], const orc_params *P, double dt,
+                  double c, double *Uout, long long *cnt) {
+    const geom G = mkgeom(n);
+    const geom *g = &G;
+    const long gs = gsize(g), hs = hsize(g);
+    const int nv = nvar_of(P), nq = 6 + P->nspec;
+    double *q = xalloc(nq * gs), *phi = xalloc(hs);
+    double *ql[3], *qr[3], *fn[3];
+    for (int d = 0; d < 3; ++d) { ql[d] = xalloc(nv * hs); qr[d] = xalloc(nv * hs); fn[d] = xalloc(nv * hs); }
+    int bad_alloc = !q || !phi;
+    for (int d = 0; d < 3; ++d) bad_alloc |= !ql[d] || !qr[d] || !fn[d];
+    if (bad_alloc) return -2;
+    long long c0n = 0, c1n = 0, c2n = 0, c4n = 0;
+
+    /* primitive state on every grown cell, flattening on cells -1..n */
+#pragma omp parallel for reduction(+ : c0n, c1n) schedule(static)
+    for (int k = -NG; k < n[2] + NG; ++k)
+        for (int j = -NG; j < n[1] + NG; ++j)
+            for (int i = -NG; i < n[0] + NG; ++i) {
+                double Uc[MAXV], qc[MAXV + 1];
+                long long lc[NCNT] = {0, 0, 0, 0, 0};
+                for (int c = 0; c < nv; ++c) Uc[c] = Us[gidx(g, c, i, j, k)];
+                cons_to_prim_cell(Uc, P, qc, lc);
+                c0n += lc[0]; c1n += lc[1];
+                for (int c = 0; c < nq; ++c) q[gidx(g, c, i, j, k)] = qc[c];
+            }
+#pragma omp parallel for schedule(static)
+    for (int k = -1; k <= n[2]; ++k)
+        for (int j = -1; j <= n[1]; ++j)
+            for (int i = -1; i <= n[0]; ++i) {
+                int c[3] = {i, j, k};
+                phi[hidx(g, 0, i, j, k)] = flatten_cell(q, g, c);
+            }
+
+    /* edge values of the parabolas as face states, cells -1..n */
+    for (int d = 0; d < 3; ++d) {
+        int comp[MAXV] = {0, 1 + d, 1 + t1of(d), 1 + t2of(d), 4};
+        for (int sp = 0; sp < P->nspec; ++sp) comp[5 + sp] = 6 + sp;
+#pragma omp parallel for reduction(+ : c2n) schedule(static)
+        for (int k = -1; k <= n[2]; ++k)
+            for (int j = -1; j <= n[1]; ++j)
+                for (int i = -1; i <= n[0]; ++i) {
+                    int c[3] = {i, j, k}, e[3] = {0, 0, 0};
+                    e[d] = 1;
+                    double up[MAXV], dn[MAXV], par[4], a[5];
+                    const double ph = phi[hidx(g, 0, i, j, k)];
+                    for (int m = 0; m < nv; ++m) {
+                        for (int s = -2; s <= 2; ++s)
+                            a[s + 2] = q[gidx(g, comp[m], i + s * e[0], j + s * e[1], k + s * e[2])];
+                        orc_ppm_cell(a, ph, par);
+                        up[m] = par[1]; /* upper edge: left state of face c+1 */
+                        dn[m] = par[0]; /* lower edge: right state of face c */
+                    }
+                    if (c[d] <= n[d] - 1) {
+                        if (up[0] < P->small_dens) { up[0] = P->small_dens; c2n++; }
+                        if (up[4] < P->small_pres) { up[4] = P->small_pres; c2n++; }
+                        for (int m = 0; m < nv; ++m) ql[d][hidx(g, m, i + e[0], j + e[1], k + e[2])] = up[m];
+                    }
+                    if (c[d] >= 0) {
+                        if (dn[0] < P->small_dens) { dn[0] = P->small_dens; c2n++; }
+                        if (dn[4] < P->small_pres) { dn[4] = P->small_pres; c2n++; }
+                        for (int m = 0; m < nv; ++m) qr[d][hidx(g, m, i, j, k)] = dn[m];
+                    }
+                }
+    }
+
+    /* HLLC fluxes on faces 0..n along d, valid cells across */
+    for (int d = 0; d < 3; ++d) {
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k <= n[2]; ++k)
+            for (int j = 0; j <= n[1]; ++j)
+                for (int i = 0; i <= n[0]; ++i) {
+                    int c[3] = {i, j, k};
+                    int skip = 0;
+                    for (int e = 0; e < 3; ++e) if (e != d && c[e] >= n[e]) skip = 1;
+                    if (skip) continue;
+                    double L[MAXV], R[MAXV], F[MAXV];
+                    for (int m = 0; m < nv; ++m) {
+                        L[m] = ql[d][hidx(g, m, i, j, k)];
+                        R[m] = qr[d][hidx(g, m, i, j, k)];
+                    }
+                    hllc_n(L, R, d, P, F);
+                    for (int m = 0; m < nv; ++m) fn[d][hidx(g, m, i, j, k)] = F[m];
+                }
+    }
+
+    /* T = Us + dt L(Us), then the stage combination, failure check */
+    const double dtdx[3] = {dt / P->dx[0], dt / P->dx[1], dt / P->dx[2]};
+    const double dtg = dt * P->grav_z;
+    const double gm1 = P->gamma - 1.0;
+#pragma omp parallel for reduction(+ : c4n) schedule(static)
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                double T[MAXV];
+                for (int m = 0; m < nv; ++m) {
+                    double du = dtdx[0] * (fn[0][hidx(g, m, i, j, k)] - fn[0][hidx(g, m, i + 1, j, k)]);
+                    du = du + dtdx[1] * (fn[1][hidx(g, m, i, j, k)] - fn[1][hidx(g, m, i, j + 1, k)]);
+                    du = du + dtdx[2] * (fn[2][hidx(g, m, i, j, k)] - fn[2][hidx(g, m, i, j, k + 1)]);
+                    T[m] = Us[gidx(g, m, i, j, k)] + du;
+                }
+                if (P->grav_z != 0.0) {
+                    T[3] = T[3] + dtg * Us[gidx(g, 0, i, j, k)];
+                    T[4] = T[4] + dtg * Us[gidx(g, 3, i, j, k)];
+                }
+                if (U0)
+                    for (int m = 0; m < nv; ++m) {
+                        const double a = U0[gidx(g, m, i, j, k)];
+                        T[m] = a + c * (T[m] - a);
+                    }
+                int bad = 0;
+                for (int m = 0; m < nv; ++m) if (!isfinite(T[m])) bad = 1;
+                if (T[0] < P->small_dens) bad = 1;
+                if (!bad) {
+                    double u = T[1] / T[0], v = T[2] / T[0], w = T[3] / T[0];
+                    double ke = 0.5 * T[0] * ((u * u + v * v) + w * w);
+                    if (gm1 * (T[4] - ke) < P->small_pres) bad = 1;
+                }
+                c4n += bad;
+                for (int m = 0; m < nv; ++m) Uout[gidx(g, m, i, j, k)] = T[m];
+            }
+    if (cnt) { cnt[0] += c0n; cnt[1] += c1n; cnt[2] += c2n; cnt[4] += c4n; }
+    free(q); free(phi);
+    for (int d = 0; d < 3; ++d) { free(ql[d]); free(qr[d]); free(fn[d]); }
+    return 0;
+}
+
 /* ------------------------------------------------------- ghost fill (O11) */
 
 /* Conserved state of the inflow primitive (rho, u, v, w, p). */
@@ -683,7 +835,8 @@ void orc_fill_domain(double *U, const int n[3], const orc_params *P) {
 /* --------------------------------------------------------------- dt (O2) */
 
 /* Largest signal speed over valid cells: max over cells and directions of
- * (|u_d| + c) / dx_d, using the floored primitive state. */
+ * (|u_d| + c) / dx_d, using the floored primitive state; for the MOL schemes
+ * the max over cells of the sum over directions (x + y) + z. */
 double orc_signal_speed(const double *U, const int n[3], const orc_params *P) {
     const geom G = mkgeom(n);
     const geom *g = &G;
@@ -697,8 +850,13 @@ double orc_signal_speed(const double *U, const int n[3], const orc_params *P) {
                 long long lc[NCNT] = {0, 0, 0, 0, 0};
                 for (int m = 0; m < nvar_of(P); ++m) Uc[m] = U[gidx(g, m, i, j, k)];
                 cons_to_prim_cell(Uc, P, q, lc);
-                for (int d = 0; d < 3; ++d) {
-                    double s = (fabs(q[1 + d]) + q[5]) * rdx[d];
+                double sd[3];
+                for (int d = 0; d < 3; ++d) sd[d] = (fabs(q[1 + d]) + q[5]) * rdx[d];
+                if (P->scheme == 0) {
+                    for (int d = 0; d < 3; ++d)
+                        if (sd[d] > smax) smax = sd[d];
+                } else {
+                    double s = (sd[0] + sd[1]) + sd[2];
                     if (s > smax) smax = s;
                 }
             }
@@ -721,7 +879,29 @@ int orc_step(double *U, const int n[3], const orc_params *P, double dt_fixed, do
     double *Un = xalloc(nv * gs);
     if (!Un) return -2;
     memcpy(Un, U, sizeof(double) * nv * gs);
-    int rc = orc_advance_box(U, n, P, dt, Un, cnt, NULL);
+    int rc;
+    if (P->scheme == 0) {
+        rc = orc_advance_box(U, n, P, dt, Un, cnt, NULL);
+    } else {
+        /* SSP-RK2: W = U + dt L(U); U' = 1/2 U + 1/2 (W + dt L(W)).
+         * SSP-RK3: W1 = U + dt L(U); W2 = 3/4 U + 1/4 (W1 + dt L(W1));
+         *          U' = 1/3 U + 2/3 (W2 + dt L(W2)). */
+        double *W1 = xalloc(nv * gs), *W2 = xalloc(nv * gs);
+        if (!W1 || !W2) return -2;
+        memcpy(W1, U, sizeof(double) * nv * gs);
+        rc = orc_mol_stage(U, NULL, n, P, dt, 0.0, W1, cnt);
+        if (rc == 0) orc_fill_domain(W1, n, P);
+        if (P->scheme == 1) {
+            if (rc == 0) rc = orc_mol_stage(W1, U, n, P, dt, 0.5, Un, cnt);
+        } else {
+            memcpy(W2, U, sizeof(double) * nv * gs);
+            if (rc == 0) rc = orc_mol_stage(W1, U, n, P, dt, 0.25, W2, cnt);
+            if (rc == 0) orc_fill_domain(W2, n, P);
+            if (rc == 0) rc = orc_mol_stage(W2, U, n, P, dt, 2.0 / 3.0, Un, cnt);
+        }
+        free(W1);
+        free(W2);
+    }
     if (rc == 0) memcpy(U, Un, sizeof(double) * nv * gs);
     free(Un);
     if (dt_used) *dt_used = dt;
