@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--nspec", type=int, default=0,
                     help="passive species advected with the flow (kh256, rt384, cloud256; the paper's GPU "
                          "proxy advects 13)")
+    ap.add_argument("--scheme", default="ctu", choices=["ctu", "mol2", "mol3"],
+                    help="ctu: unsplit CTU/PPM (default); mol2 / mol3: the method-of-lines formulation of the "
+                         "paper's GPU proxy with SSP-RK2 / RK3 (single-level workloads)")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
@@ -147,8 +150,14 @@ def main():
         wname = f"kelvin_helmholtz_{args.n}^3_{(args.n // args.box) ** 3}x{args.box}^3_periodic"
     if args.nspec and args.workload != "sod32":
         wname += f"_{args.nspec}_species"
+    if args.scheme != "ctu":
+        if prob.fine_boxes is not None:
+            print("the method-of-lines schemes are single-level", file=sys.stderr)
+            sys.exit(2)
+        prob.scheme = ctuppm.SCHEMES[args.scheme]
+        wname += f"_{args.scheme}"
     # key of the stored counter summary of this workload
-    tkey = args.workload + (f"s{args.nspec}" if args.nspec else "")
+    tkey = args.workload + (f"s{args.nspec}" if args.nspec else "") + ("" if args.scheme == "ctu" else args.scheme)
     ctx = ctuppm.Context()
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
@@ -196,7 +205,8 @@ def main():
     traffic = measured_traffic(dom, tkey)
     cnt = solver.counters()
     out = {
-        "metric": "zone-updates/s FP64 (unsplit CTU/PPM advance)",
+        "metric": "zone-updates/s FP64 (unsplit CTU/PPM advance)" if args.scheme == "ctu" else
+                  "zone-updates/s FP64 (method-of-lines PPM advance)",
         "value": value,
         "unit": "zone-updates/s",
         "n_gpus": 1,
@@ -209,7 +219,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
-                   "species": prob.nspec,
+                   "species": prob.nspec, "scheme": args.scheme,
                    "gamma": prob.gamma, "cfl": prob.cfl, "tuning": tuning and {k: tuning[k] for k in
                                                                                ("blocks_per_cu", "zseg", "ytile")}},
         "forms": {k: v for k, v in forms.items()},
@@ -223,7 +233,8 @@ def main():
     ctx.close()
     del solver
     torch.cuda.empty_cache()
-    if not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64:
+    if (not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64
+            and args.scheme == "ctu"):
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

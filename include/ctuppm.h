@@ -26,9 +26,17 @@
  * CTUPPM_NGHOST cells on every side, i fastest; components
  * (rho, rho u, rho v, rho w, rho E, rho X_1 .. rho X_nspec).  A box (nx, ny, nz)
  * has (5 + nspec)(nx+8)(ny+8)(nz+8) doubles.  Passive species are advected
- * with the flow (the paper's GPU proxy advects 13 species, section 4).  Each box has two fabs, A and B; steps
- * alternate between them and ctuppm_current_state() tells which holds the
- * current state.
+ * with the flow (the paper's GPU proxy advects 13 species, section 4).  Each
+ * box has two fabs, A and B; steps alternate between them and
+ * ctuppm_current_state() tells which holds the current state.
+ *
+ * Schemes: the unsplit CTU/PPM advance (section 3.2), or the method-of-lines
+ * formulation of the paper's GPU proxy (section 4): the same PPM parabolas
+ * give the face states directly (edge values, no characteristic tracing, no
+ * transverse corrections), HLLC fluxes give the flux divergence, and a
+ * strong-stability-preserving Runge-Kutta method of order 2 or 3 advances the
+ * state with a ghost fill before each stage.  Its dt uses the sum over
+ * directions of the signal speeds.
  */
 #ifndef CTUPPM_H
 #define CTUPPM_H
@@ -51,6 +59,8 @@ enum { CTUPPM_BC_PERIODIC = 0, CTUPPM_BC_OUTFLOW = 1, CTUPPM_BC_REFLECT = 2, CTU
  * over the boxes of every problem stepped; the batched launches replayed from
  * a captured hipGraph. */
 enum { CTUPPM_FORM_PER_BOX = 0, CTUPPM_FORM_BATCHED = 1, CTUPPM_FORM_GRAPH = 2 };
+/* Schemes: unsplit CTU/PPM; method of lines with SSP-RK2; with SSP-RK3. */
+enum { CTUPPM_SCHEME_CTU = 0, CTUPPM_SCHEME_MOL_RK2 = 1, CTUPPM_SCHEME_MOL_RK3 = 2 };
 
 #define CTUPPM_NVAR 5
 #define CTUPPM_NGHOST 4
@@ -64,7 +74,8 @@ typedef struct {
 /* Problem parameters (level 0).  Level l has cell size dx / 2^l. */
 typedef struct {
   double gamma;        /* ideal-gas ratio of specific heats, > 1 */
-  double cfl;          /* Courant number for dt = cfl / max_cells max_d (|u_d|+c)/dx_d */
+  double cfl;          /* Courant number: dt = cfl / max_cells max_d (|u_d|+c)/dx_d for CTU,
+                          cfl / max_cells sum_d (|u_d|+c)/dx_d for the MOL schemes */
   double small_dens;   /* density floor */
   double small_pres;   /* pressure floor */
   double grav_z;       /* constant gravitational acceleration along z (0: none) */
@@ -77,6 +88,8 @@ typedef struct {
   int nspec;           /* passive species (mass fractions) after rho E, 0..16 */
   int pad;
   double inflow_X[16]; /* species mass fractions written by CTUPPM_BC_INFLOW */
+  int scheme;          /* CTUPPM_SCHEME_*; the MOL schemes are single-level */
+  int pad2;
 } ctuppm_params;
 
 typedef struct ctuppm_ctx ctuppm_ctx;
@@ -94,7 +107,9 @@ const char* ctuppm_last_error(ctuppm_ctx* ctx);
  * the level's domain, have edges of at most 256 cells, and periodic domain
  * extents must be >= CTUPPM_NGHOST.
  * A fine level must lie at least 3 coarse cells inside the domain (section 3.2,
- * subcycled levels synchronised by refluxing).  *pid_out receives the id. */
+ * subcycled levels synchronised by refluxing).  nspec must be 0..16, scheme a
+ * CTUPPM_SCHEME_* value, and a two-level problem uses CTUPPM_SCHEME_CTU
+ * (CTUPPM_EINVAL otherwise).  *pid_out receives the id. */
 int ctuppm_problem_create(ctuppm_ctx* ctx, const ctuppm_params* params, int nlevels,
                           const ctuppm_box* const* boxes, const int* nboxes, int* pid_out);
 int ctuppm_problem_destroy(ctuppm_ctx* ctx, int pid);
@@ -121,7 +136,9 @@ int ctuppm_set_fixed_dt(ctuppm_ctx* ctx, int pid, double dt);
  * fill, dt from the CFL condition, cons->prim, flattening, PPM + tracing,
  * normal HLLC fluxes, the two transverse (CTU) stages, conservative update.
  * Two-level problems subcycle the fine level twice, then average down and
- * reflux.  Asynchronous. */
+ * reflux.  MOL problems take their Runge-Kutta stages instead.  Problems
+ * listed together must share one scheme (CTUPPM_EINVAL otherwise); a
+ * two-level problem steps on its own.  Asynchronous. */
 int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
 
 /* One step of a single-level problem with the retry criterion of the paper's
@@ -157,7 +174,10 @@ int ctuppm_num_stages(void);
 const char* ctuppm_stage_name(int stage);
 
 /* Algorithmic HBM bytes of one stage for one step of problem pid (each input
- * read once, each output written once, over that stage's regions). */
+ * read once, each output written once, over that stage's regions), counting
+ * every launch of the stage in a step of the batched form (the MOL schemes
+ * run the fill, cons->prim, flattening, face-state, flux and update stages
+ * once per Runge-Kutta stage). */
 int ctuppm_stage_bytes(ctuppm_ctx* ctx, int pid, int stage, double* bytes);
 
 /* Tuning of the launches: blocks per CU of the persistent batched launches

@@ -65,6 +65,7 @@ struct StepSet {
   std::vector<int> pids;
   int form = 0;
   int level = 0;
+  int scheme = 0;  // shared by every problem of the set
   int nboxes = 0;
   BoxRec* boxes = nullptr;
   March* units[kNumRegions] = {};
@@ -170,6 +171,22 @@ size_t box_scratch_bytes(const ctuppm_box& b, int nspec) {
   return align256(size_t(scratch_doubles(n, nspec)) * sizeof(double));
 }
 
+// Runge-Kutta stage fabs per box of a MOL problem (at the start of its workspace).
+int stage_fabs(const ctuppm_params& p) { return p.scheme == 1 ? 1 : (p.scheme == 2 ? 2 : 0); }
+
+size_t box_fab_bytes(const ctuppm_box& b, int nspec) {
+  size_t v = size_t(kNV + nspec);
+  for (int d = 0; d < 3; ++d) v *= size_t(box_n(b, d) + 2 * kNG);
+  return align256(v * sizeof(double));
+}
+
+// Bytes of the stage fabs of all level-0 boxes (zero for CTU problems).
+size_t stage_fab_bytes(const std::vector<ctuppm_box>& boxes, const ctuppm_params& p) {
+  size_t t = 0;
+  for (const auto& b : boxes) t += box_fab_bytes(b, p.nspec);
+  return t * size_t(stage_fabs(p));
+}
+
 Problem* get_problem(ctuppm_ctx* c, int pid) {
   auto it = c->probs.find(pid);
   return it == c->probs.end() ? nullptr : it->second.get();
@@ -237,11 +254,26 @@ hipEvent_t take_event(ctuppm_ctx* c) {
   return e;
 }
 
+// Per-launch arguments of the stages that take them (array selection and the
+// Runge-Kutta combination of the MOL update).
+struct StageArgs {
+  int arr = kArrCur;
+  int out = kArrNext;
+  int comb = 0;
+  double c = 0.0;
+  int last = 1;
+};
+
 // Launch one stage over a work range (march units, or fill/bc tag chunks) with optional timing.
 int run_stage(ctuppm_ctx* c, hipStream_t s, int stage, const BoxRec* boxes, const void* tags,
-              const void* work, int nwork, bool persistent, bool timed) {
+              const void* work, int nwork, bool persistent, bool timed, const StageArgs& A = StageArgs()) {
   if (nwork <= 0) return CTUPPM_OK;
   Launch L{boxes, tags, work, nwork, grid_for(c, nwork, persistent), s};
+  L.arr = A.arr;
+  L.out = A.out;
+  L.comb = A.comb;
+  L.c = A.c;
+  L.last = A.last;
   hipEvent_t a = nullptr, b = nullptr;
   if (timed) {
     a = take_event(c);
@@ -321,9 +353,13 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   std::vector<BcTag> btags[3];
   std::vector<Chunk> bch[3];
   std::vector<ProbDev*> probs;
-  for (int pid : pids) {
+  for (size_t ip = 0; ip < pids.size(); ++ip) {
+    const int pid = pids[ip];
     Problem* P = get_problem(c, pid);
     if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+    if (ip == 0) S->scheme = P->prm.scheme;
+    if (P->prm.scheme != S->scheme)
+      return fail(c, CTUPPM_EINVAL, "problems stepped together must use the same scheme");
     if (level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
     const Level& L = P->lev[level];
     if (!L.bound || !P->ws) return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
@@ -334,7 +370,10 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     ProbDev* dPl = level == 0 ? P->dP : P->dPf;
     probs.push_back(dPl);
     const int base = int(boxes.size());
-    size_t off = 0;
+    // stage fabs of a MOL problem first, then the stage scratch
+    const size_t wbytes = stage_fab_bytes(L.boxes, P->prm);
+    size_t woff = 0;
+    size_t off = wbytes;
     if (level == 1)  // level-1 scratch follows all level-0 scratch
       for (const auto& b : P->lev[0].boxes) off += box_scratch_bytes(b, P->prm.nspec);
     int dlo[3], dhi[3];
@@ -344,11 +383,14 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
       BoxRec r{};
       r.U[0] = L.Ua[b];
       r.U[1] = L.Ub[b];
-      r.scr = (double*)((char*)P->ws + (S->form == CTUPPM_FORM_PER_BOX ? 0 : off));
+      r.scr = (double*)((char*)P->ws + (S->form == CTUPPM_FORM_PER_BOX ? wbytes : off));
       off += box_scratch_bytes(bx, P->prm.nspec);
       r.P = dPl;
       r.level = level;
       r.ns = P->prm.nspec;
+      for (int w = 0; w < stage_fabs(P->prm); ++w)
+        r.W[w] = (double*)((char*)P->ws + woff + size_t(w) * (wbytes / size_t(stage_fabs(P->prm))));
+      woff += box_fab_bytes(bx, P->prm.nspec);
       for (int d = 0; d < 3; ++d) {
         r.n[d] = box_n(bx, d);
         r.lo[d] = bx.lo[d];
@@ -511,15 +553,86 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
 const int kCellStages[] = {kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
                            kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate};
 
-int run_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int box, bool timed) {
+int run_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int box, bool timed,
+              const StageArgs& A = StageArgs()) {
   const int k = stage_region(stage);
-  if (box < 0) return run_stage(c, s, stage, S->boxes, nullptr, S->units[k], S->nch[k], true, timed);
+  if (box < 0) return run_stage(c, s, stage, S->boxes, nullptr, S->units[k], S->nch[k], true, timed, A);
   return run_stage(c, s, stage, S->boxes, nullptr, S->units[k] + S->box_beg[k][box], S->box_cnt[k][box], false,
-                   timed);
+                   timed, A);
+}
+
+// Ghost fill of the state array `arr` of every box of a set: same-level
+// copies, then the physical boundaries x, y, z.
+int fill_arr(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed, int arr) {
+  StageArgs A;
+  A.arr = arr;
+  int rc;
+  if (S->form == CTUPPM_FORM_PER_BOX) {
+    for (int b = 0; b < S->nboxes; ++b)
+      if ((rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks + S->fbox_beg[b], S->fbox_cnt[b], false,
+                          timed, A)))
+        return rc;
+    for (int d = 0; d < 3; ++d)
+      for (int b = 0; b < S->nboxes; ++b)
+        if ((rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d] + S->bbox_beg[d][b],
+                            S->bbox_cnt[d][b], false, timed, A)))
+          return rc;
+    return CTUPPM_OK;
+  }
+  if ((rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks, S->nfch, true, timed, A))) return rc;
+  for (int d = 0; d < 3; ++d)
+    if ((rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d], S->nbch[d], true, timed, A)))
+      return rc;
+  return CTUPPM_OK;
+}
+
+// One method-of-lines step (SSP-RK2 or RK3): per stage a ghost fill of the
+// stage's input, cons->prim (with the CFL reduction and dt in the first
+// stage), flattening, edge-value face states and normal fluxes along x, y, z,
+// and the stage update; the last stage writes the other fab.
+int enqueue_mol(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
+  const bool per_box = S->form == CTUPPM_FORM_PER_BOX;
+  const int nst = S->scheme == 1 ? 2 : 3;
+  const int cells[] = {kStFlatten, kStReconX, kStReconY, kStReconZ, kStRiemX, kStRiemY, kStRiemZ};
+  int rc;
+  for (int r = 0; r < nst; ++r) {
+    const int arr = r == 0 ? kArrCur : (r == 1 ? kArrW0 : kArrW1);
+    if ((rc = fill_arr(c, S, s, timed, arr))) return rc;
+    StageArgs A;
+    A.arr = arr;
+    if (r == 0) {
+      if (per_box) {
+        for (int b = 0; b < S->nboxes; ++b)
+          if ((rc = run_cells(c, S, s, kStCfl, b, timed, A))) return rc;
+      } else if ((rc = run_cells(c, S, s, kStC2P, -1, timed, A))) {
+        return rc;
+      }
+      hipError_t e = launch_dt(S->probs, S->nprobs, s);
+      if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "dt launch: %s", hipGetErrorString(e));
+    }
+    StageArgs U;
+    U.arr = arr;
+    U.out = r == nst - 1 ? kArrNext : (r == 0 ? kArrW0 : kArrW1);
+    U.comb = r > 0;
+    U.c = nst == 2 ? 0.5 : (r == 1 ? 0.25 : 2.0 / 3.0);
+    U.last = r == nst - 1;
+    const int nb = per_box ? S->nboxes : 1;
+    for (int b = 0; b < nb; ++b) {
+      const int box = per_box ? b : -1;
+      if ((per_box || r > 0) && (rc = run_cells(c, S, s, kStC2POnly, box, timed, A))) return rc;
+      for (int st : cells)
+        if ((rc = run_cells(c, S, s, st, box, timed))) return rc;
+      if ((rc = run_cells(c, S, s, kStMolUpdate, box, timed, U))) return rc;
+    }
+  }
+  hipError_t e = launch_flip(S->probs, S->nprobs, s);
+  if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "flip launch: %s", hipGetErrorString(e));
+  return CTUPPM_OK;
 }
 
 // Enqueue one step of a set on stream s.
 int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
+  if (S->scheme != 0) return enqueue_mol(c, S, s, timed);
   const bool per_box = S->form == CTUPPM_FORM_PER_BOX;
   int rc;
   if (per_box) {
@@ -878,6 +991,10 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   if (!(prm->gamma > 1.0)) return fail(c, CTUPPM_EINVAL, "gamma must be > 1");
   if (prm->nspec < 0 || prm->nspec > kMaxSpec)
     return fail(c, CTUPPM_EINVAL, "nspec must be in 0..%d", kMaxSpec);
+  if (prm->scheme < CTUPPM_SCHEME_CTU || prm->scheme > CTUPPM_SCHEME_MOL_RK3)
+    return fail(c, CTUPPM_EINVAL, "unknown scheme %d", prm->scheme);
+  if (prm->scheme != CTUPPM_SCHEME_CTU && nlevels != 1)
+    return fail(c, CTUPPM_EINVAL, "the method-of-lines schemes are single-level");
   for (int d = 0; d < 3; ++d) {
     if (!(prm->dx[d] > 0.0)) return fail(c, CTUPPM_EINVAL, "dx must be > 0");
     if (prm->domain_hi[d] < prm->domain_lo[d]) return fail(c, CTUPPM_EINVAL, "empty domain");
@@ -954,6 +1071,7 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   }
   h.nlevels = nlevels;
   h.nspec = prm->nspec;
+  h.scheme = prm->scheme;
   h.fail_step = -1;
   HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
   HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
@@ -994,11 +1112,12 @@ int ctuppm_workspace_bytes(ctuppm_ctx* c, int pid, int form, size_t* bytes) {
       total += s;
       mx = std::max(mx, s);
     }
+  const size_t wb = stage_fab_bytes(P->lev[0].boxes, P->prm);
   if (form == CTUPPM_FORM_PER_BOX) {
     if (P->nlevels == 2) return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched forms only");
-    *bytes = mx;
+    *bytes = wb + mx;
   } else if (form == CTUPPM_FORM_BATCHED || form == CTUPPM_FORM_GRAPH) {
-    *bytes = total + two_level_extra_bytes(P);
+    *bytes = wb + total + two_level_extra_bytes(P);
   } else {
     return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
   }
@@ -1221,6 +1340,9 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
   if (P->nlevels == 2)  // the fine level runs two substeps per step
     for (int r = 0; r < 2; ++r) all.insert(all.end(), P->lev[1].boxes.begin(), P->lev[1].boxes.end());
   const double nv = kNV + P->prm.nspec, nq = nv + 1;  // conserved / primitive components
+  // launches per step of a stage run once per Runge-Kutta stage (MOL)
+  const int scheme = P->prm.scheme;
+  const double nst = scheme == 1 ? 2.0 : (scheme == 2 ? 3.0 : 1.0);
   for (const auto& bx : all) {
     const double n0 = box_n(bx, 0), n1 = box_n(bx, 1), n2 = box_n(bx, 2);
     const double nn[3] = {n0, n1, n2};
@@ -1231,10 +1353,22 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
     auto fin = [&](int d) { return valid / nn[d] * (nn[d] + 1); };                    // faces 0..n x 0..n-1
     auto half = [&](int a, int b) { return face(a) / (nn[b] + 2) * nn[b]; };         // F^{a|b} region
     switch (stage) {
-      case kStFill: tot += 2 * nv * W * (grown - valid); break;
-      case kStC2P: case kStC2POnly: tot += (nv + nq) * W * grown; break;
+      case kStFill: tot += nst * 2 * nv * W * (grown - valid); break;
+      case kStC2P: tot += (nv + nq) * W * grown; break;
+      case kStC2POnly: tot += (scheme ? nst - 1 : 1.0) * (nv + nq) * W * grown; break;
       case kStCfl: tot += 5 * W * valid; break;
-      case kStFlatten: tot += 4 * W * cells1 + W * cells1; break;
+      case kStFlatten: tot += nst * (4 * W * cells1 + W * cells1); break;
+      case kStReconX: case kStReconY: case kStReconZ: {
+        const int d = stage - kStReconX;
+        // q without the sound speed over the stencils of cells -1..n, phi, the face states
+        tot += nst * ((nq - 1) * W * cells1 / (nn[d] + 2) * (nn[d] + 6) + W * cells1 + 2 * nv * W * face(d));
+        break;
+      }
+      case kStMolUpdate:
+        // per stage: the stage input, three flux arrays and the output; the
+        // combination stages also read the current state
+        tot += nst * (2 * nv * W * valid + nv * W * (fin(0) + fin(1) + fin(2))) + (nst - 1) * nv * W * valid;
+        break;
       case kStTraceX: case kStTraceY: case kStTraceZ: {
         const int d = stage - kStTraceX;
         // q over cells -3..n+2 along d (the 5-cell stencils of cells -1..n), phi,
@@ -1242,7 +1376,7 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
         tot += nq * W * cells1 / (nn[d] + 2) * (nn[d] + 6) + W * cells1 + 2 * nv * W * face(d);
         break;
       }
-      case kStRiemX: case kStRiemY: case kStRiemZ: tot += 3 * nv * W * face(stage - kStRiemX); break;
+      case kStRiemX: case kStRiemY: case kStRiemZ: tot += nst * 3 * nv * W * face(stage - kStRiemX); break;
       case kStT1X: case kStT1Y: case kStT1Z: {
         const int a = stage - kStT1X, b = (a + 1) % 3, cc = (a + 2) % 3;
         tot += 2 * nv * W * face(a) + nv * W * face(b) + nv * W * face(cc) + nv * W * (half(a, b) + half(a, cc));

@@ -48,7 +48,7 @@ struct ProbDev {
   int nlevels;
   int fail_step;                   // test hook: the update flags a failure at this step (-1: off)
   int nspec;                       // passive species after rho E
-  int pad2;
+  int scheme;                      // 0 CTU, 1 MOL + SSP-RK2, 2 MOL + SSP-RK3
   // running max of the signal speed as bit patterns (>= 0), one 128-byte
   // line per slot so blocks of one launch do not contend on one address
   unsigned long long smax[kSlots][16];
@@ -57,6 +57,7 @@ struct ProbDev {
 // One box of a step set.
 struct BoxRec {
   double* U[2];     // grown fabs [5 + ns][nz+8][ny+8][nx+8], caller-owned
+  double* W[2];     // Runge-Kutta stage fabs (same layout, in the workspace; MOL only)
   double* scr;      // stage scratch of this box
   ProbDev* P;       // problem the box belongs to
   int n[3];         // valid cells
@@ -121,8 +122,14 @@ __host__ __device__ inline long long scratch_doubles(const int n[3], int nspec) 
 enum Stage : int {
   kStFill = 0, kStBcX, kStBcY, kStBcZ, kStC2P, kStCfl, kStC2POnly, kStDt, kStFlatten,
   kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ, kStT1X, kStT1Y, kStT1Z,
-  kStT2X, kStT2Y, kStT2Z, kStUpdate, kStFlip, kNumStages
+  kStT2X, kStT2Y, kStT2Z, kStUpdate, kStFlip,
+  kStReconX, kStReconY, kStReconZ, kStMolUpdate, kNumStages
 };
+
+// State array a stage reads (fill, boundaries, cons->prim, MOL stages) or
+// the MOL update writes: the current fab, a Runge-Kutta stage fab, or the
+// other fab (which receives the new state).
+enum Arr : int { kArrCur = 0, kArrW0 = 1, kArrW1 = 2, kArrNext = 3 };
 
 // Region each march stage runs over.
 __host__ __device__ inline int stage_region(int stage) {
@@ -131,6 +138,8 @@ __host__ __device__ inline int stage_region(int stage) {
     case kStCfl: return kValid;
     case kStFlatten: return kCells1;
     case kStTraceX: case kStTraceY: case kStTraceZ: return kCells1;
+    case kStReconX: case kStReconY: case kStReconZ: return kCells1;
+    case kStMolUpdate: return kValid;
     case kStRiemX: case kStT1X: return kFace0;
     case kStRiemY: case kStT1Y: return kFace1;
     case kStRiemZ: case kStT1Z: return kFace2;
@@ -149,6 +158,11 @@ struct Launch {
   int nwork;
   int grid;            // blocks (multiple of 8)
   hipStream_t stream;
+  int arr = kArrCur;   // array read by fill / boundaries / cons->prim / MOL update
+  int out = kArrNext;  // array the MOL update writes
+  int comb = 0;        // MOL update: combine with the current fab (U0 + c (T - U0))
+  double c = 0.0;      // its weight
+  int last = 1;        // MOL update: the step's last stage (test hook applies)
 };
 
 hipError_t launch_stage(int stage, const Launch& L);

@@ -92,11 +92,23 @@ CTU_DEV void count(unsigned long long* c, unsigned long long v) {
   if (v) atomicAdd(c, v);
 }
 
+// The state array `arr` of a box (current fab, Runge-Kutta stage fab, or the
+// fab that receives the new state).
+CTU_DEV double* state_arr(const BoxRec& B, int arr) {
+  const int cur = B.P->cur;
+  switch (arr) {
+    case kArrW0: return B.W[0];
+    case kArrW1: return B.W[1];
+    case kArrNext: return B.U[cur ^ 1];
+    default: return B.U[cur];
+  }
+}
+
 // ---------------------------------------------------------------- ghost fill
 
 __global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxes,
                                                  const FillTag* __restrict__ tags,
-                                                 const Chunk* __restrict__ chunks, int nchunks) {
+                                                 const Chunk* __restrict__ chunks, int nchunks, int arr) {
   for_each_chunk(nchunks, [&](int c) {
     const Chunk ch = chunks[c];
     const FillTag T = tags[ch.box];
@@ -108,10 +120,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxe
     const int k = T.lo[2] + r / T.ext[1];
     const BoxRec& D = boxes[T.dst];
     const BoxRec& S = boxes[T.src];
-    const int cur = D.P->cur;
     const Geo gd(D.n, D.ns), gs(S.n, S.ns);
-    const gdbl* __restrict__ src = gp(S.U[cur]);
-    gdbl* __restrict__ dst = gp(D.U[cur]);
+    const gdbl* __restrict__ src = gp(state_arr(S, arr));
+    gdbl* __restrict__ dst = gp(state_arr(D, arr));
     const int si = gs.g(i + T.off[0], j + T.off[1], k + T.off[2]);
     const int di = gd.g(i, j, k);
 #pragma unroll
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxe
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
                                                const BcTag* __restrict__ tags,
-                                               const Chunk* __restrict__ chunks, int nchunks) {
+                                               const Chunk* __restrict__ chunks, int nchunks, int arr) {
   for_each_chunk(nchunks, [&](int c) {
     const Chunk ch = chunks[c];
     const BcTag& T = tags[ch.box];  // by reference: the inflow state is indexed at run time
@@ -138,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
     x[2] = T.lo[2] + r / T.ext[1];
     const BoxRec& B = boxes[T.box];
     const Geo g(B.n, B.ns);
-    gdbl* __restrict__ U = gp(B.U[B.P->cur]);
+    gdbl* __restrict__ U = gp(state_arr(B, arr));
     const int di = g.g(x[0], x[1], x[2]);
     if (T.bc == 3) {
       for (int m = 0; m < g.nv; ++m) U[m * g.gcomp + di] = T.inflow[m];
@@ -188,7 +199,7 @@ CTU_DEV void flush_max(ProbDev* P, double m, double* lds) {
 // and stores q box by box after dt is known.
 template <bool WQ, bool CFL>
 __global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
-                                                int nunits) {
+                                                int nunits, int arr) {
   __shared__ double lds[kBlock / 64];
   double smax = 0.0;
   ProbDev* curP = nullptr;
@@ -202,8 +213,9 @@ __global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes
       curP = P;
     }
     const Geo g(B.n, B.ns);
-    const gdbl* __restrict__ U = gp(B.U[P->cur]);
+    const gdbl* __restrict__ U = gp(state_arr(B, arr));
     gdbl* __restrict__ q = g.q(B.scr);
+    const bool summed = P->scheme != 0;
     const double gamma = P->gamma, gm1 = P->gm1, sd = P->small_dens, sp = P->small_pres;
     const double rdx = P->rdx[0], rdy = P->rdx[1], rdz = P->rdx[2];
     unsigned long long hd = 0, hp = 0;
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes
         const double sx = (fabs(u) + cs) * rdx;
         const double sy = (fabs(v) + cs) * rdy;
         const double sz = (fabs(w) + cs) * rdz;
-        smax = dmax(smax, dmax(sx, dmax(sy, sz)));
+        smax = dmax(smax, summed ? (sx + sy) + sz : dmax(sx, dmax(sy, sz)));
       }
     });
     if (WQ) {
@@ -639,6 +651,147 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
   });
 }
 
+// ------------------------------------------------------- method of lines
+//
+// The method-of-lines variant (the formulation of the paper's GPU proxy,
+// section 4): the face states are the edge values of the same PPM parabolas,
+// with no characteristic tracing and no transverse corrections; the normal
+// HLLC fluxes (k_riemann) give the flux divergence, and a strong-stability-
+// preserving Runge-Kutta method (Shu & Osher 1988) of order 2 or 3 advances
+// the state, with a ghost fill before every stage.
+
+// Face states along D from cells -1..n: the upper edge value of each cell's
+// parabola is the left state of its upper face, the lower edge value the
+// right state of its lower face (both floored like the traced states).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_recon(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
+                                                  int nunits) {
+  constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
+    const ProbDev* P = B.P;
+    const Geo g(B.n, B.ns);
+    const gdbl* __restrict__ q = g.q(B.scr);
+    const gdbl* __restrict__ phiv = g.phi(B.scr);
+    gdbl* __restrict__ ql = g.ql(B.scr, D);
+    gdbl* __restrict__ qr = g.qr(B.scr, D);
+    const int st = g.gstride(D), sth = g.hstride(D);
+    const double sd = P->small_dens, sp = P->small_pres;
+    const int nD = B.n[D];
+    unsigned long long floors = 0;
+    march(kCells1, B, M, [&](int i, int j, int k) {
+      const int x[3] = {i, j, k};
+      const int o = g.g(i, j, k), oh = g.h(i, j, k);
+      const double phi = phiv[oh];
+      double up[5], dn[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const gdbl* a = q + comp[m] * g.gcomp + o;
+        const Parab par = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+        up[m] = par.aR;
+        dn[m] = par.aL;
+      }
+      if (x[D] <= nD - 1) {
+        if (up[0] < sd) { up[0] = sd; ++floors; }
+        if (up[4] < sp) { up[4] = sp; ++floors; }
+#pragma unroll
+        for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
+      }
+      if (x[D] >= 0) {
+        if (dn[0] < sd) { dn[0] = sd; ++floors; }
+        if (dn[4] < sp) { dn[4] = sp; ++floors; }
+#pragma unroll
+        for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
+      }
+      for (int is = 0; is < g.ns; ++is) {
+        const gdbl* a = q + (6 + is) * g.gcomp + o;
+        const Parab par = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+        if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = par.aR;
+        if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = par.aL;
+      }
+    });
+    count(&B.P->cnt[2], floors);
+  });
+}
+
+// One Runge-Kutta stage: T = Us + dt L(Us), L(Us) the flux divergence of the
+// normal fluxes (x, then y, then z) plus the gravity source g (0, 0, 0, rho,
+// rho w) of Us; written as T, or as U0 + c (T - U0) with U0 the current fab
+// (the convex combinations of the SSP methods, in a form that keeps a
+// constant state exactly constant).  Failures are counted as in k_update.
+__global__ __launch_bounds__(kBlock) void k_mol_update(const BoxRec* __restrict__ boxes,
+                                                       const March* __restrict__ units, int nunits, int arr,
+                                                       int out, int comb, double c, int last) {
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
+    const ProbDev* P = B.P;
+    const Geo g(B.n, B.ns);
+    const gdbl* __restrict__ Us = gp(state_arr(B, arr));
+    const gdbl* __restrict__ U0 = gp(B.U[P->cur]);
+    gdbl* __restrict__ Un = gp(state_arr(B, out));
+    const gdbl* __restrict__ Fx = g.fn(B.scr, 0);
+    const gdbl* __restrict__ Fy = g.fn(B.scr, 1);
+    const gdbl* __restrict__ Fz = g.fn(B.scr, 2);
+    const double dtdx = P->dt / P->dx[0], dtdy = P->dt / P->dx[1], dtdz = P->dt / P->dx[2];
+    const bool grav = P->grav_z != 0.0;
+    const double dtg = P->dt * P->grav_z;
+    const bool forced = last && P->fail_step == P->nsteps;
+    unsigned long long nbad = 0;
+    march(kValid, B, M, [&](int i, int j, int k) {
+      const int o = g.h(i, j, k), og = g.g(i, j, k);
+      double t[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const int mo = m * g.hcomp + o;
+        double du = dtdx * (Fx[mo] - Fx[mo + 1]);
+        du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
+        du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
+        t[m] = Us[m * g.gcomp + og] + du;
+      }
+      if (grav) {
+        t[3] = t[3] + dtg * Us[og];
+        t[4] = t[4] + dtg * Us[3 * g.gcomp + og];
+      }
+      if (comb) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          const double a = U0[m * g.gcomp + og];
+          t[m] = a + c * (t[m] - a);
+        }
+      }
+      bool bad = false;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) bad = bad || !isfinite(t[m]);
+      if (t[0] < P->small_dens) bad = true;
+      if (!bad) {
+        const double uu = t[1] / t[0], vv = t[2] / t[0], ww = t[3] / t[0];
+        const double ke = 0.5 * t[0] * ((uu * uu + vv * vv) + ww * ww);
+        if (P->gm1 * (t[4] - ke) < P->small_pres) bad = true;
+      }
+      if (forced && i == 0 && j == 0 && k == 0) bad = true;  // host-set test hook
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Un[m * g.gcomp + og] = t[m];
+      for (int m = kNV; m < g.nv; ++m) {
+        const int mo = m * g.hcomp + o;
+        double du = dtdx * (Fx[mo] - Fx[mo + 1]);
+        du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
+        du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
+        double v = Us[m * g.gcomp + og] + du;
+        if (comb) {
+          const double a = U0[m * g.gcomp + og];
+          v = a + c * (v - a);
+        }
+        bad = bad || !isfinite(v);
+        Un[m * g.gcomp + og] = v;
+      }
+      nbad += bad ? 1ull : 0ull;
+    });
+    count(&B.P->cnt[4], nbad);
+  });
+}
+
 // ------------------------------------------------------------- two levels
 //
 // Subcycled two-level advance (section 3.2: coarse advanced, fine advanced in
@@ -816,7 +969,8 @@ const char* stage_name(int s) {
   static const char* names[kNumStages] = {
       "fill", "bc_x", "bc_y", "bc_z", "cons2prim_cfl", "cfl", "cons2prim", "dt", "flatten",
       "trace_x", "trace_y", "trace_z", "riemann_x", "riemann_y", "riemann_z",
-      "trans1_x", "trans1_y", "trans1_z", "trans2_x", "trans2_y", "trans2_z", "update", "flip"};
+      "trans1_x", "trans1_y", "trans1_z", "trans2_x", "trans2_y", "trans2_z", "update", "flip",
+      "recon_x", "recon_y", "recon_z", "mol_update"};
   return (s >= 0 && s < kNumStages) ? names[s] : "?";
 }
 
@@ -828,13 +982,19 @@ hipError_t launch_stage(int stage, const Launch& L) {
   const int n = L.nwork;
   hipStream_t s = L.stream;
   switch (stage) {
-    case kStFill: k_fill<<<grid, block, 0, s>>>(L.boxes, (const FillTag*)L.tags, ch, n); break;
-    case kStBcX: k_bc<0><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n); break;
-    case kStBcY: k_bc<1><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n); break;
-    case kStBcZ: k_bc<2><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n); break;
-    case kStC2P: k_c2p<true, true><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStCfl: k_c2p<false, true><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStC2POnly: k_c2p<true, false><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStFill: k_fill<<<grid, block, 0, s>>>(L.boxes, (const FillTag*)L.tags, ch, n, L.arr); break;
+    case kStBcX: k_bc<0><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;
+    case kStBcY: k_bc<1><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;
+    case kStBcZ: k_bc<2><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;
+    case kStC2P: k_c2p<true, true><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
+    case kStCfl: k_c2p<false, true><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
+    case kStC2POnly: k_c2p<true, false><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
+    case kStReconX: k_recon<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStReconY: k_recon<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStReconZ: k_recon<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStMolUpdate:
+      k_mol_update<<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr, L.out, L.comb, L.c, L.last);
+      break;
     case kStFlatten: k_flatten<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     case kStTraceX: k_trace<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     case kStTraceY: k_trace<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libctuppm.so")
 OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
 FORM_PER_BOX, FORM_BATCHED, FORM_GRAPH = 0, 1, 2
 FORMS = {"per_box": FORM_PER_BOX, "batched": FORM_BATCHED, "graph": FORM_GRAPH}
+SCHEME_CTU, SCHEME_MOL_RK2, SCHEME_MOL_RK3 = 0, 1, 2
+SCHEMES = {"ctu": SCHEME_CTU, "mol2": SCHEME_MOL_RK2, "mol3": SCHEME_MOL_RK3}
 NG = 4
 
 
@@ -37,7 +39,8 @@ class Params(ctypes.Structure):
                 ("small_pres", ctypes.c_double), ("grav_z", ctypes.c_double), ("dx", ctypes.c_double * 3),
                 ("domain_lo", ctypes.c_int * 3), ("domain_hi", ctypes.c_int * 3),
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3), ("inflow", ctypes.c_double * 5),
-                ("nspec", ctypes.c_int), ("pad", ctypes.c_int), ("inflow_X", ctypes.c_double * 16)]
+                ("nspec", ctypes.c_int), ("pad", ctypes.c_int), ("inflow_X", ctypes.c_double * 16),
+                ("scheme", ctypes.c_int), ("pad2", ctypes.c_int)]
 
 
 _lib = None
@@ -145,11 +148,20 @@ class Context:
         self.call("ctuppm_set_tuning2", int(blocks_per_cu), int(zseg_batched), int(zseg_per_box), int(ytile))
 
     def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1):
-        """Advance several problems together (one batched launch set per step)."""
+        """Advance several problems together: one batched launch set per step
+        for the problems of each scheme."""
         f = FORMS[form] if isinstance(form, str) else int(form)
-        pids = (ctypes.c_int * len(solvers))(*[s.pid for s in solvers])
+        groups: Dict[int, List[int]] = {}
+        for s in solvers:
+            groups.setdefault(scheme_id(s.prob), []).append(s.pid)
+        sets = [(ctypes.c_int * len(v))(*v) for _, v in sorted(groups.items())]
         for _ in range(nsteps):
-            self.call("ctuppm_step", pids, len(solvers), f)
+            for pids in sets:
+                self.call("ctuppm_step", pids, len(pids), f)
+
+
+def scheme_id(prob: W.Problem) -> int:
+    return SCHEMES[prob.scheme] if isinstance(prob.scheme, str) else int(prob.scheme)
 
 
 def stage_names() -> List[str]:
@@ -170,6 +182,7 @@ def _params(prob: W.Problem) -> Params:
     for m in range(5):
         P.inflow[m] = prob.inflow[m]
     P.nspec = int(prob.nspec)
+    P.scheme = scheme_id(prob)
     for s, x in enumerate(prob.inflow_X):
         P.inflow_X[s] = x
     return P

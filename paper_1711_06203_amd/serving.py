@@ -29,14 +29,17 @@ NG = 4
 def footprint_bytes(prob: W.Problem) -> int:
     """Device bytes a resident problem needs: two fabs per box plus the
     batched-form stage workspace (q with 6 + nspec components on the grown box,
-    phi and 18 halo-1 arrays of 5 + nspec components)."""
+    phi and 18 halo-1 arrays of 5 + nspec components, plus the Runge-Kutta
+    stage fabs of the method-of-lines schemes)."""
     total = 0
     nv = 5 + int(prob.nspec)
+    stage_fabs = {0: 0, 1: 1, 2: 2}[ctuppm.scheme_id(prob)]  # Runge-Kutta stage fabs (MOL)
     for lo, hi in prob.boxes:
         n = [hi[d] - lo[d] + 1 for d in range(3)]
         grown = (n[0] + 2 * NG) * (n[1] + 2 * NG) * (n[2] + 2 * NG)
         h1 = (n[0] + 2) * (n[1] + 2) * (n[2] + 2)
         total += 2 * nv * grown * 8 + (((nv + 1) * grown + (1 + 18 * nv) * h1) * 8 + 255) // 256 * 256
+        total += stage_fabs * ((nv * grown * 8 + 255) // 256 * 256)
     return total
 
 

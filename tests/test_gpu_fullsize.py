@@ -122,3 +122,30 @@ def test_kh256_13species_one_step_sampled(ctx):
     prob = W.kelvin_helmholtz(n=256, box=64, nspec=13)
     assert prob.U0.shape[0] == 18
     _sampled(ctx, prob, 200, 3)
+
+
+@pytest.mark.slow
+def test_kh256_mol_rk2_one_step_sampled(ctx):
+    """The method-of-lines (SSP-RK2) step of the full 256^3 KH workload in the
+    graph form, sampled cells against the oracle's two stages computed from
+    each sample's periodic neighbourhood."""
+    from paper_1711_06203_amd import ctuppm
+    prob = W.kelvin_helmholtz(n=256, box=64)
+    prob.scheme = 1
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(1)
+    got = s.state()
+    dt_gpu = s.dt()
+    s.close()
+    ctx.torch.cuda.empty_cache()
+    P = oracle.params_of(prob)
+    G = oracle.fill_domain(oracle.grow(prob.U0), P)
+    dt = P.cfl / oracle.signal_speed(G, P)
+    assert dt_gpu == dt
+    rng = np.random.default_rng(4)
+    cells = [tuple(int(rng.integers(256)) for _ in range(3)) for _ in range(150)]
+    cells += [(0, 0, 0), (255, 255, 255), (63, 64, 0), (64, 63, 255)]
+    want = oracle.sample_step_mol(prob.U0, P, dt, cells)
+    for c, w in zip(cells, want):
+        g = got[:, c[2], c[1], c[0]]
+        assert np.array_equal(g, w), (c, g, w)
