@@ -49,7 +49,7 @@ class Params(ctypes.Structure):
                 ("grav_z", ctypes.c_double), ("dx", ctypes.c_double * 3),
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3),
                 ("inflow", ctypes.c_double * 5), ("nspec", ctypes.c_int), ("pad", ctypes.c_int),
-                ("inflow_X", ctypes.c_double * MAXSPEC), ("scheme", ctypes.c_int), ("pad2", ctypes.c_int)]
+                ("inflow_X", ctypes.c_double * MAXSPEC), ("scheme", ctypes.c_int), ("riemann", ctypes.c_int)]
 
 SCHEMES = {"ctu": 0, "mol2": 1, "mol3": 2}
 
@@ -96,6 +96,8 @@ def lib():
         L.orc_trace_cell.restype = None
         L.orc_mol_stage.argtypes = [dp, dp, ip, pp, ctypes.c_double, ctypes.c_double, dp, lp]
         L.orc_mol_stage.restype = ctypes.c_int
+        L.orc_twoshock.argtypes = [dp, dp, ctypes.c_int, pp, dp]
+        L.orc_twoshock.restype = None
         _lib = L
     return _lib
 
@@ -111,8 +113,9 @@ def _ip(seq):
 
 def make_params(gamma, dx, cfl=0.5, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), grav_z=0.0,
                 inflow=(1.0, 0.0, 0.0, 0.0, 1.0), small_dens=1e-12, small_pres=1e-12, nspec=0,
-                inflow_X=(), scheme=0) -> Params:
+                inflow_X=(), scheme=0, riemann=0) -> Params:
     P = Params()
+    P.riemann = int(riemann)
     P.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     P.nspec = int(nspec)
     for s_, v in enumerate(inflow_X):
@@ -133,7 +136,7 @@ def params_of(prob, fine: bool = False) -> Params:
         dx = tuple(v / 2.0 for v in dx)
     return make_params(prob.gamma, dx, prob.cfl, prob.bc_lo, prob.bc_hi, prob.grav_z, prob.inflow,
                        prob.small_dens, prob.small_pres, getattr(prob, "nspec", 0), getattr(prob, "inflow_X", ()),
-                       getattr(prob, "scheme", 0))
+                       getattr(prob, "scheme", 0), getattr(prob, "riemann", 0))
 
 
 def grow(Uvalid: np.ndarray, fill=np.nan) -> np.ndarray:
@@ -209,6 +212,18 @@ def run(Uvalid: np.ndarray, P: Params, nsteps: int, dt_fixed: Optional[float] = 
 
 def run_problem(prob, nsteps: Optional[int] = None, dt_fixed: Optional[float] = None):
     return run(prob.U0, params_of(prob), prob.steps if nsteps is None else nsteps, dt_fixed)
+
+
+def twoshock(L: Sequence[float], R: Sequence[float], d: int, gamma: float, small_dens: float = 1e-12,
+             small_pres: float = 1e-12) -> np.ndarray:
+    """Two-shock Riemann flux of permuted primitive states (rho, u_n, u_t1, u_t2, p),
+    returned in global conserved order for a sweep along d."""
+    P = make_params(gamma, (1.0, 1.0, 1.0), small_dens=small_dens, small_pres=small_pres)
+    l = np.ascontiguousarray(L, dtype=np.float64)
+    r = np.ascontiguousarray(R, dtype=np.float64)
+    F = np.zeros(5)
+    lib().orc_twoshock(_dp(l), _dp(r), int(d), ctypes.byref(P), _dp(F))
+    return F
 
 
 def hllc(L: Sequence[float], R: Sequence[float], d: int, gamma: float) -> np.ndarray:

@@ -19,6 +19,10 @@
  *     2002, JCP 183:26;
  *   - HLLC Riemann flux with Davis wave-speed bounds: Toro, Spruce & Speares
  *     1994, Shock Waves 4:25; Davis 1988, SIAM J. Sci. Stat. Comput. 9:445;
+ *   - or the two-shock approximate Riemann solver of the PPM lineage (both
+ *     waves on their shock curves, Newton iteration for the star pressure):
+ *     Colella 1982, SIAM J. Sci. Stat. Comput. 3:76; Colella & Glaz 1985,
+ *     JCP 59:264;
  *   - two-level refluxing: Berger & Colella 1989, JCP 82:64.
  * Steps are coded in the order the method takes them, on whole arrays, one
  * stage after another.  Floating-point expressions are written exactly as the
@@ -29,7 +33,7 @@
  * 4, which names it and nothing more): the spatial operator reconstructs the
  * same PPM parabolas (with flattening) and takes their edge values as the face
  * states, with no characteristic tracing and no transverse corrections, then
- * the HLLC flux and the flux divergence; gravity enters as a source term.
+ * the interface flux and the flux divergence; gravity enters as a source term.
  * Time integration is the strong-stability-preserving Runge-Kutta method of
  * Shu & Osher 1988 (JCP 77:439) of order 2 or 3, ghost cells refilled before
  * every stage, dt from the CFL condition on the sum over directions of the
@@ -72,7 +76,7 @@ typedef struct {
     int pad;
     double inflow_X[MAXSPEC];
     int scheme;       /* 0 unsplit CTU/PPM, 1 MOL with SSP-RK2, 2 MOL with SSP-RK3 */
-    int pad2;
+    int riemann;      /* 0 HLLC, 1 two-shock approximate solver */
 } orc_params;
 
 static int nvar_of(const orc_params *P) { return 5 + P->nspec; }
@@ -224,6 +228,98 @@ void orc_hllc(const double L[5], const double R[5], int d, const orc_params *P, 
     orc_params Q = *P;
     Q.nspec = 0;
     hllc_n(L, R, d, &Q, Fg);
+}
+
+/* ------------------------------------------- two-shock Riemann solver (f3) */
+
+#define TWOSHOCK_ITERS 6
+
+/* Godunov flux of the two-shock approximate Riemann solution between the
+ * permuted primitive states L and R (species after p).  Both nonlinear waves
+ * are put on their shock curves: with Lagrangian sound speeds C_K =
+ * sqrt(gamma p_K rho_K) and shock speeds W_K(p) = C_K sqrt(1 + (gamma+1)/(2
+ * gamma) (p/p_K - 1)), the star pressure solves u*_L(p) = u*_R(p), u*_L =
+ * u_L - (p - p_L)/W_L, u*_R = u_R + (p - p_R)/W_R, by Newton steps with the
+ * curve slopes Z_K = 2 W_K^3 / (W_K^2 + C_K^2), from the acoustic estimate,
+ * a fixed number of times, floored at small_pres.  The contact velocity is
+ * u* = (W_L u_L + W_R u_R + p_L - p_R) / (W_L + W_R).  The state at x/t = 0
+ * is taken on the upwind side of the contact (K = L if u* >= 0): the
+ * unperturbed state K beyond the K wave, the star state (rho* from the shock
+ * relation 1/rho* = 1/rho_K - (p* - p_K)/W_K^2) behind it, and for a
+ * rarefaction whose fan straddles x/t = 0 the linear blend of the two between
+ * the head u_K -+ c_K and the tail u* -+ c*.  Transverse velocities and
+ * species come from K.  The flux is the Euler flux of that state. */
+static void twoshock_n(const double *L, const double *R, int d, const orc_params *P, double *Fg) {
+    const int ns = P->nspec;
+    const double g = P->gamma, rgm1 = 1.0 / (g - 1.0), gp = (g + 1.0) / (2.0 * g);
+    const double rL = L[0], uL = L[1], pL = L[4];
+    const double rR = R[0], uR = R[1], pR = R[4];
+    const double CL = sqrt(g * pL * rL), CR = sqrt(g * pR * rR);
+    double ps = ((CR * pL + CL * pR) + CL * CR * (uL - uR)) / (CL + CR);
+    ps = omax(ps, P->small_pres);
+    double WL = CL, WR = CR;
+    for (int it = 0; it < TWOSHOCK_ITERS; ++it) {
+        WL = CL * sqrt(1.0 + gp * (ps / pL - 1.0));
+        WR = CR * sqrt(1.0 + gp * (ps / pR - 1.0));
+        const double ZL = 2.0 * (WL * WL * WL) / (WL * WL + CL * CL);
+        const double ZR = 2.0 * (WR * WR * WR) / (WR * WR + CR * CR);
+        const double usL = uL - (ps - pL) / WL;
+        const double usR = uR + (ps - pR) / WR;
+        ps = ps - (ZL * ZR) * (usR - usL) / (ZL + ZR);
+        ps = omax(ps, P->small_pres);
+    }
+    WL = CL * sqrt(1.0 + gp * (ps / pL - 1.0));
+    WR = CR * sqrt(1.0 + gp * (ps / pR - 1.0));
+    const double us = ((WL * uL + WR * uR) + (pL - pR)) / (WL + WR);
+    const int left = us >= 0.0;
+    const double *K = left ? L : R;
+    const double WK = left ? WL : WR;
+    const double rK = K[0], uK = K[1], pK = K[4];
+    const double sgn = left ? -1.0 : 1.0;
+    double rs = 1.0 / (1.0 / rK - (ps - pK) / (WK * WK));
+    rs = omax(rs, P->small_dens);
+    const double cK = sqrt(g * pK / rK), cs = sqrt(g * ps / rs);
+    double head, tail;
+    if (ps > pK) {
+        head = uK + sgn * (WK / rK);
+        tail = head;
+    } else {
+        head = uK + sgn * cK;
+        tail = us + sgn * cs;
+    }
+    double ri, ui, pi;
+    if (left ? head >= 0.0 : head <= 0.0) {
+        ri = rK; ui = uK; pi = pK;
+    } else if (left ? tail <= 0.0 : tail >= 0.0) {
+        ri = rs; ui = us; pi = ps;
+    } else {
+        const double f = (0.0 - tail) / (head - tail);
+        ri = rs + f * (rK - rs);
+        ui = us + f * (uK - us);
+        pi = ps + f * (pK - ps);
+    }
+    const double vK = K[2], wK = K[3];
+    const double m = ri * ui;
+    const double Ei = pi * rgm1 + 0.5 * ri * ((ui * ui + vK * vK) + wK * wK);
+    Fg[0] = m;
+    Fg[1 + d] = m * ui + pi;
+    Fg[1 + t1of(d)] = m * vK;
+    Fg[1 + t2of(d)] = m * wK;
+    Fg[4] = ui * (Ei + pi);
+    for (int sp = 0; sp < ns; ++sp) Fg[5 + sp] = m * K[5 + sp];
+}
+
+/* The interface flux of the chosen Riemann solver. */
+static void riemann_n(const double *L, const double *R, int d, const orc_params *P, double *Fg) {
+    if (P->riemann == 1) twoshock_n(L, R, d, P, Fg);
+    else hllc_n(L, R, d, P, Fg);
+}
+
+/* Five-component entry point of the two-shock flux (pins). */
+void orc_twoshock(const double L[5], const double R[5], int d, const orc_params *P, double Fg[5]) {
+    orc_params Q = *P;
+    Q.nspec = 0;
+    twoshock_n(L, R, d, &Q, Fg);
 }
 
 /* ------------------------------------------------------ PPM pieces (O5, O6) */
@@ -502,7 +598,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                         L[m] = S.ql[d][hidx(g, m, i, j, k)];
                         R[m] = S.qr[d][hidx(g, m, i, j, k)];
                     }
-                    hllc_n(L, R, d, P, F);
+                    riemann_n(L, R, d, P, F);
                     for (int m = 0; m < nv; ++m) S.fn[d][hidx(g, m, i, j, k)] = F[m];
                 }
     }
@@ -544,7 +640,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                             for (int m = 0; m < nv; ++m) st2[side][m] = s1[m];
                         }
                         double F[MAXV];
-                        hllc_n(st2[0], st2[1], a, P, F);
+                        riemann_n(st2[0], st2[1], a, P, F);
                         for (int m = 0; m < nv; ++m) S.f1[pidx][hidx(g, m, i, j, k)] = F[m];
                     }
             c3cnt += lfb;
@@ -587,7 +683,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                         for (int m = 0; m < nv; ++m) st2[side][m] = s1[m];
                     }
                     double F[MAXV];
-                    hllc_n(st2[0], st2[1], a, P, F);
+                    riemann_n(st2[0], st2[1], a, P, F);
                     for (int m = 0; m < nv; ++m) S.ff[a][hidx(g, m, i, j, k)] = F[m];
                 }
         c3cnt += lfb;
@@ -721,7 +817,7 @@ int orc_mol_stage(const double *Us, const double *U0, const int n[3], const orc_
                         L[m] = ql[d][hidx(g, m, i, j, k)];
                         R[m] = qr[d][hidx(g, m, i, j, k)];
                     }
-                    hllc_n(L, R, d, P, F);
+                    riemann_n(L, R, d, P, F);
                     for (int m = 0; m < nv; ++m) fn[d][hidx(g, m, i, j, k)] = F[m];
                 }
     }
