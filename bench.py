@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--scheme", default="ctu", choices=["ctu", "mol2", "mol3"],
                     help="ctu: unsplit CTU/PPM (default); mol2 / mol3: the method-of-lines formulation of the "
                          "paper's GPU proxy with SSP-RK2 / RK3 (single-level workloads)")
+    ap.add_argument("--riemann", default="hllc", choices=["hllc", "twoshock"],
+                    help="interface flux: HLLC (default) or the two-shock approximate Riemann solver")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
@@ -156,8 +158,12 @@ def main():
             sys.exit(2)
         prob.scheme = ctuppm.SCHEMES[args.scheme]
         wname += f"_{args.scheme}"
+    if args.riemann != "hllc":
+        prob.riemann = ctuppm.RIEMANN[args.riemann]
+        wname += f"_{args.riemann}"
     # key of the stored counter summary of this workload
-    tkey = args.workload + (f"s{args.nspec}" if args.nspec else "") + ("" if args.scheme == "ctu" else args.scheme)
+    tkey = args.workload + (f"s{args.nspec}" if args.nspec else "") + ("" if args.scheme == "ctu" else args.scheme) + (
+        "" if args.riemann == "hllc" else args.riemann)
     ctx = ctuppm.Context()
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
@@ -219,7 +225,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
-                   "species": prob.nspec, "scheme": args.scheme,
+                   "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann,
                    "gamma": prob.gamma, "cfl": prob.cfl, "tuning": tuning and {k: tuning[k] for k in
                                                                                ("blocks_per_cu", "zseg", "ytile")}},
         "forms": {k: v for k, v in forms.items()},
@@ -234,7 +240,7 @@ def main():
     del solver
     torch.cuda.empty_cache()
     if (not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64
-            and args.scheme == "ctu"):
+            and args.scheme == "ctu" and args.riemann == "hllc"):
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

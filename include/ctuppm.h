@@ -61,6 +61,11 @@ enum { CTUPPM_BC_PERIODIC = 0, CTUPPM_BC_OUTFLOW = 1, CTUPPM_BC_REFLECT = 2, CTU
 enum { CTUPPM_FORM_PER_BOX = 0, CTUPPM_FORM_BATCHED = 1, CTUPPM_FORM_GRAPH = 2 };
 /* Schemes: unsplit CTU/PPM; method of lines with SSP-RK2; with SSP-RK3. */
 enum { CTUPPM_SCHEME_CTU = 0, CTUPPM_SCHEME_MOL_RK2 = 1, CTUPPM_SCHEME_MOL_RK3 = 2 };
+/* Riemann solvers: HLLC (Toro, Spruce & Speares 1994, Davis speeds); the
+ * two-shock approximate solver of the PPM lineage (Colella 1982; Colella &
+ * Glaz 1985: both waves on shock curves, six Newton steps for the star
+ * pressure, upwind sampling with a linear blend inside a straddling fan). */
+enum { CTUPPM_RIEMANN_HLLC = 0, CTUPPM_RIEMANN_TWO_SHOCK = 1 };
 
 #define CTUPPM_NVAR 5
 #define CTUPPM_NGHOST 4
@@ -89,7 +94,7 @@ typedef struct {
   int pad;
   double inflow_X[16]; /* species mass fractions written by CTUPPM_BC_INFLOW */
   int scheme;          /* CTUPPM_SCHEME_*; the MOL schemes are single-level */
-  int pad2;
+  int riemann;         /* CTUPPM_RIEMANN_* */
 } ctuppm_params;
 
 typedef struct ctuppm_ctx ctuppm_ctx;
@@ -108,8 +113,9 @@ const char* ctuppm_last_error(ctuppm_ctx* ctx);
  * extents must be >= CTUPPM_NGHOST.
  * A fine level must lie at least 3 coarse cells inside the domain (section 3.2,
  * subcycled levels synchronised by refluxing).  nspec must be 0..16, scheme a
- * CTUPPM_SCHEME_* value, and a two-level problem uses CTUPPM_SCHEME_CTU
- * (CTUPPM_EINVAL otherwise).  *pid_out receives the id. */
+ * CTUPPM_SCHEME_* value, riemann a CTUPPM_RIEMANN_* value, and a two-level
+ * problem uses CTUPPM_SCHEME_CTU (CTUPPM_EINVAL otherwise).  *pid_out
+ * receives the id. */
 int ctuppm_problem_create(ctuppm_ctx* ctx, const ctuppm_params* params, int nlevels,
                           const ctuppm_box* const* boxes, const int* nboxes, int* pid_out);
 int ctuppm_problem_destroy(ctuppm_ctx* ctx, int pid);
@@ -137,8 +143,8 @@ int ctuppm_set_fixed_dt(ctuppm_ctx* ctx, int pid, double dt);
  * normal HLLC fluxes, the two transverse (CTU) stages, conservative update.
  * Two-level problems subcycle the fine level twice, then average down and
  * reflux.  MOL problems take their Runge-Kutta stages instead.  Problems
- * listed together must share one scheme (CTUPPM_EINVAL otherwise); a
- * two-level problem steps on its own.  Asynchronous. */
+ * listed together must share one scheme and one Riemann solver (CTUPPM_EINVAL
+ * otherwise); a two-level problem steps on its own.  Asynchronous. */
 int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
 
 /* One step of a single-level problem with the retry criterion of the paper's

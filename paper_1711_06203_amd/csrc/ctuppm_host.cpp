@@ -65,7 +65,8 @@ struct StepSet {
   std::vector<int> pids;
   int form = 0;
   int level = 0;
-  int scheme = 0;  // shared by every problem of the set
+  int scheme = 0;   // shared by every problem of the set
+  int riemann = 0;  // likewise
   int nboxes = 0;
   BoxRec* boxes = nullptr;
   March* units[kNumRegions] = {};
@@ -262,6 +263,7 @@ struct StageArgs {
   int comb = 0;
   double c = 0.0;
   int last = 1;
+  int rs = 0;
 };
 
 // Launch one stage over a work range (march units, or fill/bc tag chunks) with optional timing.
@@ -274,6 +276,7 @@ int run_stage(ctuppm_ctx* c, hipStream_t s, int stage, const BoxRec* boxes, cons
   L.comb = A.comb;
   L.c = A.c;
   L.last = A.last;
+  L.rs = A.rs;
   hipEvent_t a = nullptr, b = nullptr;
   if (timed) {
     a = take_event(c);
@@ -357,9 +360,12 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     const int pid = pids[ip];
     Problem* P = get_problem(c, pid);
     if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
-    if (ip == 0) S->scheme = P->prm.scheme;
-    if (P->prm.scheme != S->scheme)
-      return fail(c, CTUPPM_EINVAL, "problems stepped together must use the same scheme");
+    if (ip == 0) {
+      S->scheme = P->prm.scheme;
+      S->riemann = P->prm.riemann;
+    }
+    if (P->prm.scheme != S->scheme || P->prm.riemann != S->riemann)
+      return fail(c, CTUPPM_EINVAL, "problems stepped together must use the same scheme and Riemann solver");
     if (level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
     const Level& L = P->lev[level];
     if (!L.bound || !P->ws) return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
@@ -554,7 +560,9 @@ const int kCellStages[] = {kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX
                            kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate};
 
 int run_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int box, bool timed,
-              const StageArgs& A = StageArgs()) {
+              const StageArgs& A0 = StageArgs()) {
+  StageArgs A = A0;
+  A.rs = S->riemann;
   const int k = stage_region(stage);
   if (box < 0) return run_stage(c, s, stage, S->boxes, nullptr, S->units[k], S->nch[k], true, timed, A);
   return run_stage(c, s, stage, S->boxes, nullptr, S->units[k] + S->box_beg[k][box], S->box_cnt[k][box], false,
@@ -993,6 +1001,8 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
     return fail(c, CTUPPM_EINVAL, "nspec must be in 0..%d", kMaxSpec);
   if (prm->scheme < CTUPPM_SCHEME_CTU || prm->scheme > CTUPPM_SCHEME_MOL_RK3)
     return fail(c, CTUPPM_EINVAL, "unknown scheme %d", prm->scheme);
+  if (prm->riemann != CTUPPM_RIEMANN_HLLC && prm->riemann != CTUPPM_RIEMANN_TWO_SHOCK)
+    return fail(c, CTUPPM_EINVAL, "unknown Riemann solver %d", prm->riemann);
   if (prm->scheme != CTUPPM_SCHEME_CTU && nlevels != 1)
     return fail(c, CTUPPM_EINVAL, "the method-of-lines schemes are single-level");
   for (int d = 0; d < 3; ++d) {
@@ -1072,6 +1082,7 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   h.nlevels = nlevels;
   h.nspec = prm->nspec;
   h.scheme = prm->scheme;
+  h.riemann = prm->riemann;
   h.fail_step = -1;
   HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
   HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));

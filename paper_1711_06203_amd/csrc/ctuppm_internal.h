@@ -49,6 +49,8 @@ struct ProbDev {
   int fail_step;                   // test hook: the update flags a failure at this step (-1: off)
   int nspec;                       // passive species after rho E
   int scheme;                      // 0 CTU, 1 MOL + SSP-RK2, 2 MOL + SSP-RK3
+  int riemann;                     // 0 HLLC, 1 two-shock
+  int pad3;
   // running max of the signal speed as bit patterns (>= 0), one 128-byte
   // line per slot so blocks of one launch do not contend on one address
   unsigned long long smax[kSlots][16];
@@ -163,6 +165,7 @@ struct Launch {
   int comb = 0;        // MOL update: combine with the current fab (U0 + c (T - U0))
   double c = 0.0;      // its weight
   int last = 1;        // MOL update: the step's last stage (test hook applies)
+  int rs = 0;          // Riemann solver of the flux stages: 0 HLLC, 1 two-shock
 };
 
 hipError_t launch_stage(int stage, const Launch& L);

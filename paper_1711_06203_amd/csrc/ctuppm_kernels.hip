@@ -92,6 +92,13 @@ CTU_DEV void count(unsigned long long* c, unsigned long long v) {
   if (v) atomicAdd(c, v);
 }
 
+// Interface flux of the Riemann solver RS (0 HLLC, 1 two-shock), permuted order.
+template <int RS>
+CTU_DEV void rflux(const double L[5], const double R[5], const ProbDev* P, double F[5], Wave& W) {
+  if (RS == 1) twoshock(L, R, P->gamma, P->rgm1, P->small_dens, P->small_pres, F, W);
+  else hllc(L, R, P->gamma, P->rgm1, F, W);
+}
+
 // The state array `arr` of a box (current fab, Runge-Kutta stage fab, or the
 // fab that receives the new state).
 CTU_DEV double* state_arr(const BoxRec& B, int arr) {
@@ -391,8 +398,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
   });
 }
 
-// Normal HLLC flux of every face 0..n along D (cells -1..n across).
-template <int D>
+// Normal flux of every face 0..n along D (cells -1..n across).
+template <int D, int RS>
 __global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ boxes,
                                                     const March* __restrict__ units, int nunits) {
   for_each_chunk(nunits, [&](int u) {
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ b
         R[m] = qr[m * g.hcomp + o];
       }
       Wave W;
-      hllc(L, R, P->gamma, P->rgm1, f, W);
+      rflux<RS>(L, R, P, f, W);
       store_flux<D>(fn, g.hcomp, o, f);
       for (int is = 0; is < g.ns; ++is) {
         const int mo = (kNV + is) * g.hcomp + o;
@@ -453,8 +460,8 @@ CTU_DEV int to_prim_or_keep(const double U[5], const double s0[5], double gm1, d
 
 // Stage 1: face states along A corrected by dt/(3 dx_B) times the normal
 // B-flux difference across their owner cell, for B = the two other
-// directions, then HLLC -> F^{A|B}.
-template <int A>
+// directions, then the Riemann flux -> F^{A|B}.
+template <int A, int RS>
 __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ boxes,
                                                    const March* __restrict__ units, int nunits) {
   for_each_chunk(nunits, [&](int u) {
@@ -496,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
         const int kR = to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
         fb += kL + kR;
         Wave W;
-        hllc(tL, tR, P->gamma, P->rgm1, f, W);
+        rflux<RS>(tL, tR, P, f, W);
         gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
         store_flux<A>(F1, g.hcomp, o, f);
         // species: rho X corrected by the same flux difference, back to X with
@@ -519,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
 // dF^{B|C} and then dt/(2 dx_C) dF^{C|B}, with (B, C) the cyclic successors of
 // A, then the final HLLC flux (global component order).  fb counts states that
 // fell back to the uncorrected ones.
-template <int A>
+template <int A, int RS>
 CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, gdbl* __restrict__ ff, int& fb) {
   constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
   // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
@@ -555,7 +562,7 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
   const int kR = to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
   fb += kL + kR;
   Wave W;
-  hllc(tL, tR, P->gamma, P->rgm1, f, W);
+  rflux<RS>(tL, tR, P, f, W);
   store_flux<A>(ff, g.hcomp, o, f);
   for (int is = 0; is < g.ns; ++is) {
     const int c = (kNV + is) * g.hcomp;
@@ -572,7 +579,7 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
 }
 
 // Stage 2 along A over faces 0..n (cells 0..n-1 across): final fluxes.
-template <int A>
+template <int A, int RS>
 __global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ boxes,
                                                    const March* __restrict__ units, int nunits) {
   for_each_chunk(nunits, [&](int u) {
@@ -583,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ bo
     gdbl* __restrict__ ff = g.ff(B.scr, A);
     int fb = 0;
     march(kFin0 + A, B, M, [&](int i, int j, int k) {
-      final_flux<A>(B, g, P, g.h(i, j, k), ff, fb);
+      final_flux<A, RS>(B, g, P, g.h(i, j, k), ff, fb);
     });
     count(&B.P->cnt[3], (unsigned long long)fb);
   });
@@ -999,15 +1006,18 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStTraceX: k_trace<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     case kStTraceY: k_trace<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     case kStTraceZ: k_trace<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStRiemX: k_riemann<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStRiemY: k_riemann<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStRiemZ: k_riemann<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStT1X: k_trans1<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStT1Y: k_trans1<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStT1Z: k_trans1<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStT2X: k_trans2<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStT2Y: k_trans2<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStT2Z: k_trans2<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+#define CTU_RS(K, D) \
+  (L.rs ? K<D, 1><<<grid, block, 0, s>>>(L.boxes, mu, n) : K<D, 0><<<grid, block, 0, s>>>(L.boxes, mu, n))
+    case kStRiemX: CTU_RS(k_riemann, 0); break;
+    case kStRiemY: CTU_RS(k_riemann, 1); break;
+    case kStRiemZ: CTU_RS(k_riemann, 2); break;
+    case kStT1X: CTU_RS(k_trans1, 0); break;
+    case kStT1Y: CTU_RS(k_trans1, 1); break;
+    case kStT1Z: CTU_RS(k_trans1, 2); break;
+    case kStT2X: CTU_RS(k_trans2, 0); break;
+    case kStT2Y: CTU_RS(k_trans2, 1); break;
+    case kStT2Z: CTU_RS(k_trans2, 2); break;
+#undef CTU_RS
     case kStUpdate: k_update<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     default: return hipErrorInvalidValue;
   }

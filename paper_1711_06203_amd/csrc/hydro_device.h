@@ -5,7 +5,9 @@
 // PPM reconstruction, limiter and flattening of Colella & Woodward (1984),
 // reference-state characteristic tracing and corner-transport-upwind
 // coupling of Colella (1990), Saltzman (1994) and Miller & Colella (2002), and
-// the HLLC flux of Toro, Spruce & Speares (1994) with Davis (1988) wave speeds.
+// the HLLC flux of Toro, Spruce & Speares (1994) with Davis (1988) wave speeds,
+// or the two-shock approximate Riemann solver of the PPM lineage (Colella
+// 1982; Colella & Glaz 1985).
 // Every expression keeps the parenthesisation of the stated formulas and the
 // library is compiled without floating-point contraction, so each operation
 // rounds once, in IEEE order.
@@ -186,6 +188,81 @@ CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, d
 CTU_DEV void hllc(const double L[5], const double R[5], double g, double rgm1, double F[5]) {
   Wave W;
   hllc(L, R, g, rgm1, F, W);
+}
+
+// Godunov flux of the two-shock approximate Riemann solution between permuted
+// primitive states L and R (F in permuted conserved order).  Both waves on
+// their shock curves: Lagrangian sound speeds C = sqrt(gamma p rho), shock
+// speeds W(p) = C sqrt(1 + (gamma+1)/(2 gamma) (p/p_K - 1)); the star
+// pressure from the acoustic estimate by a fixed number of Newton steps on
+// u*_L(p) = u*_R(p) with curve slopes Z = 2 W^3 / (W^2 + C^2), floored; the
+// contact speed from the last W.  The state at x/t = 0 is on the contact's
+// upwind side K: K beyond the K wave, the star state (density from the shock
+// relation) behind it, a linear blend inside a rarefaction fan that straddles
+// x/t = 0; transverse velocities (and species, through W) from K.
+constexpr int kTwoShockIters = 6;
+
+CTU_DEV void twoshock(const double L[5], const double R[5], double g, double rgm1, double sd, double sp,
+                      double F[5], Wave& W) {
+  const double gp = (g + 1.0) / (2.0 * g);
+  const double rL = L[0], uL = L[1], pL = L[4];
+  const double rR = R[0], uR = R[1], pR = R[4];
+  const double CL = sqrt(g * pL * rL), CR = sqrt(g * pR * rR);
+  double ps = ((CR * pL + CL * pR) + CL * CR * (uL - uR)) / (CL + CR);
+  ps = dmax(ps, sp);
+  double WL = CL, WR = CR;
+  for (int it = 0; it < kTwoShockIters; ++it) {
+    WL = CL * sqrt(1.0 + gp * (ps / pL - 1.0));
+    WR = CR * sqrt(1.0 + gp * (ps / pR - 1.0));
+    const double ZL = 2.0 * (WL * WL * WL) / (WL * WL + CL * CL);
+    const double ZR = 2.0 * (WR * WR * WR) / (WR * WR + CR * CR);
+    const double usL = uL - (ps - pL) / WL;
+    const double usR = uR + (ps - pR) / WR;
+    ps = ps - (ZL * ZR) * (usR - usL) / (ZL + ZR);
+    ps = dmax(ps, sp);
+  }
+  WL = CL * sqrt(1.0 + gp * (ps / pL - 1.0));
+  WR = CR * sqrt(1.0 + gp * (ps / pR - 1.0));
+  const double us = ((WL * uL + WR * uR) + (pL - pR)) / (WL + WR);
+  const bool left = us >= 0.0;
+  const double WK = left ? WL : WR;
+  const double rK = left ? rL : rR, uK = left ? uL : uR, pK = left ? pL : pR;
+  const double vK = left ? L[2] : R[2], wK = left ? L[3] : R[3];
+  const double sgn = left ? -1.0 : 1.0;
+  double rs = 1.0 / (1.0 / rK - (ps - pK) / (WK * WK));
+  rs = dmax(rs, sd);
+  const double cK = sqrt(g * pK / rK), cs = sqrt(g * ps / rs);
+  double head, tail;
+  if (ps > pK) {
+    head = uK + sgn * (WK / rK);
+    tail = head;
+  } else {
+    head = uK + sgn * cK;
+    tail = us + sgn * cs;
+  }
+  double ri, ui, pi;
+  if (left ? head >= 0.0 : head <= 0.0) {
+    ri = rK; ui = uK; pi = pK;
+  } else if (left ? tail <= 0.0 : tail >= 0.0) {
+    ri = rs; ui = us; pi = ps;
+  } else {
+    const double f = (0.0 - tail) / (head - tail);
+    ri = rs + f * (rK - rs);
+    ui = us + f * (uK - us);
+    pi = ps + f * (pK - ps);
+  }
+  const double m = ri * ui;
+  const double Ei = pi * rgm1 + 0.5 * ri * ((ui * ui + vK * vK) + wK * wK);
+  F[0] = m;
+  F[1] = m * ui + pi;
+  F[2] = m * vK;
+  F[3] = m * wK;
+  F[4] = ui * (Ei + pi);
+  W.m = m;
+  W.rK = ri;
+  W.SK = 0.0;
+  W.fac = 0.0;
+  W.kind = left ? 0 : 3;
 }
 
 // Flux of a passive mass fraction (X_L, X_R at the face) for the HLLC state

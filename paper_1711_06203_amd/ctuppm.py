@@ -23,6 +23,8 @@ FORM_PER_BOX, FORM_BATCHED, FORM_GRAPH = 0, 1, 2
 FORMS = {"per_box": FORM_PER_BOX, "batched": FORM_BATCHED, "graph": FORM_GRAPH}
 SCHEME_CTU, SCHEME_MOL_RK2, SCHEME_MOL_RK3 = 0, 1, 2
 SCHEMES = {"ctu": SCHEME_CTU, "mol2": SCHEME_MOL_RK2, "mol3": SCHEME_MOL_RK3}
+RIEMANN_HLLC, RIEMANN_TWO_SHOCK = 0, 1
+RIEMANN = {"hllc": RIEMANN_HLLC, "twoshock": RIEMANN_TWO_SHOCK}
 NG = 4
 
 
@@ -40,7 +42,7 @@ class Params(ctypes.Structure):
                 ("domain_lo", ctypes.c_int * 3), ("domain_hi", ctypes.c_int * 3),
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3), ("inflow", ctypes.c_double * 5),
                 ("nspec", ctypes.c_int), ("pad", ctypes.c_int), ("inflow_X", ctypes.c_double * 16),
-                ("scheme", ctypes.c_int), ("pad2", ctypes.c_int)]
+                ("scheme", ctypes.c_int), ("riemann", ctypes.c_int)]
 
 
 _lib = None
@@ -149,11 +151,11 @@ class Context:
 
     def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1):
         """Advance several problems together: one batched launch set per step
-        for the problems of each scheme."""
+        for the problems of each (scheme, Riemann solver)."""
         f = FORMS[form] if isinstance(form, str) else int(form)
-        groups: Dict[int, List[int]] = {}
+        groups: Dict[tuple, List[int]] = {}
         for s in solvers:
-            groups.setdefault(scheme_id(s.prob), []).append(s.pid)
+            groups.setdefault((scheme_id(s.prob), riemann_id(s.prob)), []).append(s.pid)
         sets = [(ctypes.c_int * len(v))(*v) for _, v in sorted(groups.items())]
         for _ in range(nsteps):
             for pids in sets:
@@ -162,6 +164,10 @@ class Context:
 
 def scheme_id(prob: W.Problem) -> int:
     return SCHEMES[prob.scheme] if isinstance(prob.scheme, str) else int(prob.scheme)
+
+
+def riemann_id(prob: W.Problem) -> int:
+    return RIEMANN[prob.riemann] if isinstance(prob.riemann, str) else int(prob.riemann)
 
 
 def stage_names() -> List[str]:
@@ -183,6 +189,7 @@ def _params(prob: W.Problem) -> Params:
         P.inflow[m] = prob.inflow[m]
     P.nspec = int(prob.nspec)
     P.scheme = scheme_id(prob)
+    P.riemann = riemann_id(prob)
     for s, x in enumerate(prob.inflow_X):
         P.inflow_X[s] = x
     return P

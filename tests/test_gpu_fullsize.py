@@ -149,3 +149,10 @@ def test_kh256_mol_rk2_one_step_sampled(ctx):
     for c, w in zip(cells, want):
         g = got[:, c[2], c[1], c[0]]
         assert np.array_equal(g, w), (c, g, w)
+
+
+@pytest.mark.slow
+def test_kh256_twoshock_one_step_sampled(ctx):
+    prob = W.kelvin_helmholtz(n=256, box=64)
+    prob.riemann = 1
+    _sampled(ctx, prob, 150, 5)
