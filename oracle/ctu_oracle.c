@@ -13,7 +13,9 @@
  * paper gives no further detail, so every step below follows the published
  * method it names, in this reading:
  *   - PPM reconstruction, limiter and flattening: Colella & Woodward 1984
- *     (CW84), JCP 54:174, section 1 and appendix;
+ *     (CW84), JCP 54:174, section 1 and appendix; optionally the
+ *     extremum-preserving limiter of Colella & Sekora 2008 (CS08), JCP
+ *     227:7069;
  *   - corner-transport-upwind (unsplit) coupling and characteristic tracing:
  *     Colella 1990, JCP 87:171; Saltzman 1994, JCP 115:153; Miller & Colella
  *     2002, JCP 183:26;
@@ -77,6 +79,8 @@ typedef struct {
     double inflow_X[MAXSPEC];
     int scheme;       /* 0 unsplit CTU/PPM, 1 MOL with SSP-RK2, 2 MOL with SSP-RK3 */
     int riemann;      /* 0 HLLC, 1 two-shock approximate solver */
+    int limiter;      /* 0 CW84, 1 Colella & Sekora 2008 extremum-preserving */
+    int pad3;
 } orc_params;
 
 static int nvar_of(const orc_params *P) { return 5 + P->nspec; }
@@ -367,6 +371,83 @@ void orc_ppm_cell(const double a[5], double phi, double out[4]) {
     out[3] = 6.0 * (ai - 0.5 * (aL + aR));
 }
 
+/* ------------------------------------- extremum-preserving limiter (f3) */
+
+#define CS_C 1.25
+
+/* Sign test of CS08: v if a, b, c (and d) share v's sign, else 0, with the
+ * magnitude min(C|b|, C|c|, (C|d|,) |a|). */
+static double cs_lim3(double a, double b, double c) {
+    if ((a > 0.0 && b > 0.0 && c > 0.0) || (a < 0.0 && b < 0.0 && c < 0.0))
+        return copysign(omin(omin(CS_C * fabs(b), CS_C * fabs(c)), fabs(a)), a);
+    return 0.0;
+}
+static double cs_lim4(double a, double b, double c, double d) {
+    if ((a > 0.0 && b > 0.0 && c > 0.0 && d > 0.0) || (a < 0.0 && b < 0.0 && c < 0.0 && d < 0.0))
+        return copysign(omin(omin(CS_C * fabs(b), CS_C * fabs(c)), omin(CS_C * fabs(d), fabs(a))), a);
+    return 0.0;
+}
+
+/* CS08 interface value between cells with averages a0, a1 (neighbours am1,
+ * a2): the fourth-order value 7/12 (a0 + a1) - 1/12 (am1 + a2); where it is
+ * not between a0 and a1, the second difference 3 (a0 - 2 f + a1) is limited
+ * against those of the two cells and f = (a0 + a1)/2 - lim/6. */
+static double cs_face(double am1, double a0, double a1, double a2) {
+    double f = (7.0 / 12.0) * (a0 + a1) - (1.0 / 12.0) * (am1 + a2);
+    if ((f - a0) * (a1 - f) < 0.0) {
+        const double d2 = 3.0 * ((a0 - 2.0 * f) + a1);
+        const double d2L = (am1 - 2.0 * a0) + a1;
+        const double d2R = (a0 - 2.0 * a1) + a2;
+        f = 0.5 * (a0 + a1) - cs_lim3(d2, d2L, d2R) / 6.0;
+    }
+    return f;
+}
+
+/* PPM parabola of one cell with the CS08 limiter: limited interface values,
+ * flattening towards the average, then at a local extremum (of the parabola
+ * or of the cell averages) the parabola's second difference -2 (6 a - 3 (aL +
+ * aR)) limited against the three neighbouring second differences of the
+ * averages (scaling both edges' offsets from the average by lim / d2, flat if
+ * d2 = 0); elsewhere the overshoot correction (an edge farther than twice the
+ * other from the average is moved to twice, the right edge first). */
+static void ppm_cell_cs(const double a[5], double phi, double out[4]) {
+    const double ai = a[2];
+    double aL = cs_face(a[0], a[1], a[2], a[3]);
+    double aR = cs_face(a[1], a[2], a[3], a[4]);
+    aL = phi * aL + (1.0 - phi) * ai;
+    aR = phi * aR + (1.0 - phi) * ai;
+    if ((aR - ai) * (ai - aL) <= 0.0 || (a[1] - ai) * (ai - a[3]) <= 0.0) {
+        const double d2 = -2.0 * (6.0 * ai - 3.0 * (aL + aR));
+        const double d2C = (a[1] - 2.0 * ai) + a[3];
+        const double d2L = (a[0] - 2.0 * a[1]) + ai;
+        const double d2R = (ai - 2.0 * a[3]) + a[4];
+        if (d2 != 0.0) {
+            const double r = cs_lim4(d2, d2L, d2R, d2C) / d2;
+            aL = ai + (aL - ai) * r;
+            aR = ai + (aR - ai) * r;
+        } else {
+            aL = ai;
+            aR = ai;
+        }
+    } else {
+        if (fabs(aR - ai) >= 2.0 * fabs(aL - ai)) aR = ai - 2.0 * (aL - ai);
+        if (fabs(aL - ai) >= 2.0 * fabs(aR - ai)) aL = ai - 2.0 * (aR - ai);
+    }
+    out[0] = aL;
+    out[1] = aR;
+    out[2] = aR - aL;
+    out[3] = 6.0 * (ai - 0.5 * (aL + aR));
+}
+
+/* The parabola of the chosen limiter. */
+static void ppm_cell(const double a[5], double phi, int limiter, double out[4]) {
+    if (limiter == 1) ppm_cell_cs(a, phi, out);
+    else orc_ppm_cell(a, phi, out);
+}
+
+/* Entry point of the CS08 parabola (pins). */
+void orc_ppm_cell_cs(const double a[5], double phi, double out[4]) { ppm_cell_cs(a, phi, out); }
+
 /* Average of the parabola over the domain of dependence of the right edge
  * (I+) and of the left edge (I-) for a wave travelling sigma cells per dt. */
 double orc_iplus(double aR, double da, double a6, double sig) {
@@ -559,7 +640,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                     for (int m = 0; m < nv; ++m) {
                         for (int s = -2; s <= 2; ++s)
                             a[s + 2] = S.q[gidx(g, comp[m], i + s * e[0], j + s * e[1], k + s * e[2])];
-                        orc_ppm_cell(a, phi, par[m]);
+                        ppm_cell(a, phi, P->limiter, par[m]);
                     }
                     double rho = S.q[gidx(g, 0, i, j, k)];
                     double un = S.q[gidx(g, 1 + d, i, j, k)];
@@ -785,7 +866,7 @@ int orc_mol_stage(const double *Us, const double *U0, const int n[3], const orc_
                     for (int m = 0; m < nv; ++m) {
                         for (int s = -2; s <= 2; ++s)
                             a[s + 2] = q[gidx(g, comp[m], i + s * e[0], j + s * e[1], k + s * e[2])];
-                        orc_ppm_cell(a, ph, par);
+                        ppm_cell(a, ph, P->limiter, par);
                         up[m] = par[1]; /* upper edge: left state of face c+1 */
                         dn[m] = par[0]; /* lower edge: right state of face c */
                     }
