@@ -101,6 +101,8 @@ def main():
                          "paper's GPU proxy with SSP-RK2 / RK3 (single-level workloads)")
     ap.add_argument("--riemann", default="hllc", choices=["hllc", "twoshock"],
                     help="interface flux: HLLC (default) or the two-shock approximate Riemann solver")
+    ap.add_argument("--limiter", default="cw84", choices=["cw84", "cs"],
+                    help="PPM limiter: Colella & Woodward 1984 (default) or Colella & Sekora 2008")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
@@ -161,9 +163,12 @@ def main():
     if args.riemann != "hllc":
         prob.riemann = ctuppm.RIEMANN[args.riemann]
         wname += f"_{args.riemann}"
+    if args.limiter != "cw84":
+        prob.limiter = ctuppm.LIMITERS[args.limiter]
+        wname += f"_{args.limiter}"
     # key of the stored counter summary of this workload
     tkey = args.workload + (f"s{args.nspec}" if args.nspec else "") + ("" if args.scheme == "ctu" else args.scheme) + (
-        "" if args.riemann == "hllc" else args.riemann)
+        "" if args.riemann == "hllc" else args.riemann) + ("" if args.limiter == "cw84" else args.limiter)
     ctx = ctuppm.Context()
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
@@ -225,7 +230,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
-                   "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann,
+                   "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann, "limiter": args.limiter,
                    "gamma": prob.gamma, "cfl": prob.cfl, "tuning": tuning and {k: tuning[k] for k in
                                                                                ("blocks_per_cu", "zseg", "ytile")}},
         "forms": {k: v for k, v in forms.items()},
@@ -240,7 +245,7 @@ def main():
     del solver
     torch.cuda.empty_cache()
     if (not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64
-            and args.scheme == "ctu" and args.riemann == "hllc"):
+            and args.scheme == "ctu" and args.riemann == "hllc" and args.limiter == "cw84"):
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -66,6 +66,9 @@ enum { CTUPPM_SCHEME_CTU = 0, CTUPPM_SCHEME_MOL_RK2 = 1, CTUPPM_SCHEME_MOL_RK3 =
  * Glaz 1985: both waves on shock curves, six Newton steps for the star
  * pressure, upwind sampling with a linear blend inside a straddling fan). */
 enum { CTUPPM_RIEMANN_HLLC = 0, CTUPPM_RIEMANN_TWO_SHOCK = 1 };
+/* PPM limiters: Colella & Woodward 1984 (eq. 1.10); the extremum-preserving
+ * limiter of Colella & Sekora 2008 (smooth extrema keep their parabola). */
+enum { CTUPPM_LIMITER_CW84 = 0, CTUPPM_LIMITER_CS = 1 };
 
 #define CTUPPM_NVAR 5
 #define CTUPPM_NGHOST 4
@@ -95,6 +98,8 @@ typedef struct {
   double inflow_X[16]; /* species mass fractions written by CTUPPM_BC_INFLOW */
   int scheme;          /* CTUPPM_SCHEME_*; the MOL schemes are single-level */
   int riemann;         /* CTUPPM_RIEMANN_* */
+  int limiter;         /* CTUPPM_LIMITER_* */
+  int pad3;
 } ctuppm_params;
 
 typedef struct ctuppm_ctx ctuppm_ctx;
@@ -113,7 +118,8 @@ const char* ctuppm_last_error(ctuppm_ctx* ctx);
  * extents must be >= CTUPPM_NGHOST.
  * A fine level must lie at least 3 coarse cells inside the domain (section 3.2,
  * subcycled levels synchronised by refluxing).  nspec must be 0..16, scheme a
- * CTUPPM_SCHEME_* value, riemann a CTUPPM_RIEMANN_* value, and a two-level
+ * CTUPPM_SCHEME_* value, riemann a CTUPPM_RIEMANN_* value, limiter a
+ * CTUPPM_LIMITER_* value, and a two-level
  * problem uses CTUPPM_SCHEME_CTU (CTUPPM_EINVAL otherwise).  *pid_out
  * receives the id. */
 int ctuppm_problem_create(ctuppm_ctx* ctx, const ctuppm_params* params, int nlevels,
@@ -143,7 +149,7 @@ int ctuppm_set_fixed_dt(ctuppm_ctx* ctx, int pid, double dt);
  * normal HLLC fluxes, the two transverse (CTU) stages, conservative update.
  * Two-level problems subcycle the fine level twice, then average down and
  * reflux.  MOL problems take their Runge-Kutta stages instead.  Problems
- * listed together must share one scheme and one Riemann solver (CTUPPM_EINVAL
+ * listed together must share one scheme, Riemann solver and limiter (CTUPPM_EINVAL
  * otherwise); a two-level problem steps on its own.  Asynchronous. */
 int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
 

@@ -67,6 +67,7 @@ struct StepSet {
   int level = 0;
   int scheme = 0;   // shared by every problem of the set
   int riemann = 0;  // likewise
+  int limiter = 0;  // likewise
   int nboxes = 0;
   BoxRec* boxes = nullptr;
   March* units[kNumRegions] = {};
@@ -264,6 +265,7 @@ struct StageArgs {
   double c = 0.0;
   int last = 1;
   int rs = 0;
+  int lim = 0;
 };
 
 // Launch one stage over a work range (march units, or fill/bc tag chunks) with optional timing.
@@ -277,6 +279,7 @@ int run_stage(ctuppm_ctx* c, hipStream_t s, int stage, const BoxRec* boxes, cons
   L.c = A.c;
   L.last = A.last;
   L.rs = A.rs;
+  L.lim = A.lim;
   hipEvent_t a = nullptr, b = nullptr;
   if (timed) {
     a = take_event(c);
@@ -363,9 +366,11 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     if (ip == 0) {
       S->scheme = P->prm.scheme;
       S->riemann = P->prm.riemann;
+      S->limiter = P->prm.limiter;
     }
-    if (P->prm.scheme != S->scheme || P->prm.riemann != S->riemann)
-      return fail(c, CTUPPM_EINVAL, "problems stepped together must use the same scheme and Riemann solver");
+    if (P->prm.scheme != S->scheme || P->prm.riemann != S->riemann || P->prm.limiter != S->limiter)
+      return fail(c, CTUPPM_EINVAL,
+                  "problems stepped together must use the same scheme, Riemann solver and limiter");
     if (level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
     const Level& L = P->lev[level];
     if (!L.bound || !P->ws) return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
@@ -563,6 +568,7 @@ int run_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int box, bool
               const StageArgs& A0 = StageArgs()) {
   StageArgs A = A0;
   A.rs = S->riemann;
+  A.lim = S->limiter;
   const int k = stage_region(stage);
   if (box < 0) return run_stage(c, s, stage, S->boxes, nullptr, S->units[k], S->nch[k], true, timed, A);
   return run_stage(c, s, stage, S->boxes, nullptr, S->units[k] + S->box_beg[k][box], S->box_cnt[k][box], false,
@@ -1003,6 +1009,8 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
     return fail(c, CTUPPM_EINVAL, "unknown scheme %d", prm->scheme);
   if (prm->riemann != CTUPPM_RIEMANN_HLLC && prm->riemann != CTUPPM_RIEMANN_TWO_SHOCK)
     return fail(c, CTUPPM_EINVAL, "unknown Riemann solver %d", prm->riemann);
+  if (prm->limiter != CTUPPM_LIMITER_CW84 && prm->limiter != CTUPPM_LIMITER_CS)
+    return fail(c, CTUPPM_EINVAL, "unknown limiter %d", prm->limiter);
   if (prm->scheme != CTUPPM_SCHEME_CTU && nlevels != 1)
     return fail(c, CTUPPM_EINVAL, "the method-of-lines schemes are single-level");
   for (int d = 0; d < 3; ++d) {
@@ -1083,6 +1091,7 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   h.nspec = prm->nspec;
   h.scheme = prm->scheme;
   h.riemann = prm->riemann;
+  h.limiter = prm->limiter;
   h.fail_step = -1;
   HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
   HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));

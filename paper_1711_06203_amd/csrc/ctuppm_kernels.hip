@@ -333,7 +333,7 @@ CTU_DEV void store_flux(gdbl* __restrict__ F, int hcomp, int o, const double f[5
 // tracing to both faces along D, floors and the gravity predictor; the left
 // state of the upper face and the right state of the lower face are stored
 // for faces 0..n.
-template <int D>
+template <int D, int LIM>
 __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
                                                   int nunits) {
   constexpr int zpos = 1 + (2 - D + 3) % 3;  // permuted slot of the z velocity
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const gdbl* a = q + comp[m] * g.gcomp + o;
-        par[m] = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+        par[m] = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
       }
       const double rho = q[o], un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
       if (x[D] <= nD - 1) {
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
         const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, spp = fabs(lp) * dtdx;
         for (int is = 0; is < g.ns; ++is) {
           const gdbl* a = q + (6 + is) * g.gcomp + o;
-          const Parab px = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+          const Parab px = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
           if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
           if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
         }
@@ -670,7 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
 // Face states along D from cells -1..n: the upper edge value of each cell's
 // parabola is the left state of its upper face, the lower edge value the
 // right state of its lower face (both floored like the traced states).
-template <int D>
+template <int D, int LIM>
 __global__ __launch_bounds__(kBlock) void k_recon(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
                                                   int nunits) {
   constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_recon(const BoxRec* __restrict__ box
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const gdbl* a = q + comp[m] * g.gcomp + o;
-        const Parab par = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+        const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
         up[m] = par.aR;
         dn[m] = par.aL;
       }
@@ -713,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_recon(const BoxRec* __restrict__ box
       }
       for (int is = 0; is < g.ns; ++is) {
         const gdbl* a = q + (6 + is) * g.gcomp + o;
-        const Parab par = ppm(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+        const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
         if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = par.aR;
         if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = par.aL;
       }
@@ -988,6 +988,8 @@ hipError_t launch_stage(int stage, const Launch& L) {
   const March* mu = (const March*)L.work;
   const int n = L.nwork;
   hipStream_t s = L.stream;
+#define CTU_LIM(K, D) \
+  (L.lim ? K<D, 1><<<grid, block, 0, s>>>(L.boxes, mu, n) : K<D, 0><<<grid, block, 0, s>>>(L.boxes, mu, n))
   switch (stage) {
     case kStFill: k_fill<<<grid, block, 0, s>>>(L.boxes, (const FillTag*)L.tags, ch, n, L.arr); break;
     case kStBcX: k_bc<0><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;
@@ -996,16 +998,16 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStC2P: k_c2p<true, true><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
     case kStCfl: k_c2p<false, true><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
     case kStC2POnly: k_c2p<true, false><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
-    case kStReconX: k_recon<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStReconY: k_recon<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStReconZ: k_recon<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStReconX: CTU_LIM(k_recon, 0); break;
+    case kStReconY: CTU_LIM(k_recon, 1); break;
+    case kStReconZ: CTU_LIM(k_recon, 2); break;
     case kStMolUpdate:
       k_mol_update<<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr, L.out, L.comb, L.c, L.last);
       break;
     case kStFlatten: k_flatten<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStTraceX: k_trace<0><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStTraceY: k_trace<1><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
-    case kStTraceZ: k_trace<2><<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStTraceX: CTU_LIM(k_trace, 0); break;
+    case kStTraceY: CTU_LIM(k_trace, 1); break;
+    case kStTraceZ: CTU_LIM(k_trace, 2); break;
 #define CTU_RS(K, D) \
   (L.rs ? K<D, 1><<<grid, block, 0, s>>>(L.boxes, mu, n) : K<D, 0><<<grid, block, 0, s>>>(L.boxes, mu, n))
     case kStRiemX: CTU_RS(k_riemann, 0); break;
@@ -1021,6 +1023,7 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStUpdate: k_update<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
     default: return hipErrorInvalidValue;
   }
+#undef CTU_LIM
   return hipGetLastError();
 }
 

@@ -62,6 +62,73 @@ CTU_DEV Parab ppm(double s0, double s1, double s2, double s3, double s4, double 
   return p;
 }
 
+// Extremum-preserving variant (Colella & Sekora 2008): fourth-order interface
+// values 7/12 (a0 + a1) - 1/12 (am1 + a2), limited where not between their two
+// cells through second differences (C = 1.25); flattening towards the
+// average; at a local extremum of the parabola or of the averages the
+// parabola's second difference -2 (6 a - 3 (aL + aR)) is limited against the
+// neighbouring ones and both edge offsets scale by lim / d2 (flat if d2 = 0);
+// elsewhere an edge farther than twice the other from the average moves to
+// twice (right edge first).
+CTU_DEV double cs_lim3(double a, double b, double c) {
+  const double C = 1.25;
+  if ((a > 0.0 && b > 0.0 && c > 0.0) || (a < 0.0 && b < 0.0 && c < 0.0))
+    return copysign(dmin(dmin(C * fabs(b), C * fabs(c)), fabs(a)), a);
+  return 0.0;
+}
+CTU_DEV double cs_lim4(double a, double b, double c, double d) {
+  const double C = 1.25;
+  if ((a > 0.0 && b > 0.0 && c > 0.0 && d > 0.0) || (a < 0.0 && b < 0.0 && c < 0.0 && d < 0.0))
+    return copysign(dmin(dmin(C * fabs(b), C * fabs(c)), dmin(C * fabs(d), fabs(a))), a);
+  return 0.0;
+}
+CTU_DEV double cs_face(double am1, double a0, double a1, double a2) {
+  double f = (7.0 / 12.0) * (a0 + a1) - (1.0 / 12.0) * (am1 + a2);
+  if ((f - a0) * (a1 - f) < 0.0) {
+    const double d2 = 3.0 * ((a0 - 2.0 * f) + a1);
+    const double d2L = (am1 - 2.0 * a0) + a1;
+    const double d2R = (a0 - 2.0 * a1) + a2;
+    f = 0.5 * (a0 + a1) - cs_lim3(d2, d2L, d2R) / 6.0;
+  }
+  return f;
+}
+CTU_DEV Parab ppm_cs(double s0, double s1, double s2, double s3, double s4, double phi) {
+  double aL = cs_face(s0, s1, s2, s3);
+  double aR = cs_face(s1, s2, s3, s4);
+  aL = phi * aL + (1.0 - phi) * s2;
+  aR = phi * aR + (1.0 - phi) * s2;
+  if ((aR - s2) * (s2 - aL) <= 0.0 || (s1 - s2) * (s2 - s3) <= 0.0) {
+    const double d2 = -2.0 * (6.0 * s2 - 3.0 * (aL + aR));
+    const double d2C = (s1 - 2.0 * s2) + s3;
+    const double d2L = (s0 - 2.0 * s1) + s2;
+    const double d2R = (s2 - 2.0 * s3) + s4;
+    if (d2 != 0.0) {
+      const double r = cs_lim4(d2, d2L, d2R, d2C) / d2;
+      aL = s2 + (aL - s2) * r;
+      aR = s2 + (aR - s2) * r;
+    } else {
+      aL = s2;
+      aR = s2;
+    }
+  } else {
+    if (fabs(aR - s2) >= 2.0 * fabs(aL - s2)) aR = s2 - 2.0 * (aL - s2);
+    if (fabs(aL - s2) >= 2.0 * fabs(aR - s2)) aL = s2 - 2.0 * (aR - s2);
+  }
+  Parab p;
+  p.aL = aL;
+  p.aR = aR;
+  p.da = aR - aL;
+  p.a6 = 6.0 * (s2 - 0.5 * (aL + aR));
+  return p;
+}
+
+// The parabola of limiter LIM (0 CW84, 1 Colella & Sekora).
+template <int LIM>
+CTU_DEV Parab ppm_l(double s0, double s1, double s2, double s3, double s4, double phi) {
+  if (LIM == 1) return ppm_cs(s0, s1, s2, s3, s4, phi);
+  return ppm(s0, s1, s2, s3, s4, phi);
+}
+
 // Averages of the parabola over the last sig of the cell (towards its right
 // edge) and over the first sig (towards its left edge).
 CTU_DEV double avg_right(const Parab& p, double sig) {

@@ -25,6 +25,8 @@ SCHEME_CTU, SCHEME_MOL_RK2, SCHEME_MOL_RK3 = 0, 1, 2
 SCHEMES = {"ctu": SCHEME_CTU, "mol2": SCHEME_MOL_RK2, "mol3": SCHEME_MOL_RK3}
 RIEMANN_HLLC, RIEMANN_TWO_SHOCK = 0, 1
 RIEMANN = {"hllc": RIEMANN_HLLC, "twoshock": RIEMANN_TWO_SHOCK}
+LIMITER_CW84, LIMITER_CS = 0, 1
+LIMITERS = {"cw84": LIMITER_CW84, "cs": LIMITER_CS}
 NG = 4
 
 
@@ -42,7 +44,8 @@ class Params(ctypes.Structure):
                 ("domain_lo", ctypes.c_int * 3), ("domain_hi", ctypes.c_int * 3),
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3), ("inflow", ctypes.c_double * 5),
                 ("nspec", ctypes.c_int), ("pad", ctypes.c_int), ("inflow_X", ctypes.c_double * 16),
-                ("scheme", ctypes.c_int), ("riemann", ctypes.c_int)]
+                ("scheme", ctypes.c_int), ("riemann", ctypes.c_int),
+                ("limiter", ctypes.c_int), ("pad3", ctypes.c_int)]
 
 
 _lib = None
@@ -151,11 +154,12 @@ class Context:
 
     def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1):
         """Advance several problems together: one batched launch set per step
-        for the problems of each (scheme, Riemann solver)."""
+        for the problems of each (scheme, Riemann solver, limiter)."""
         f = FORMS[form] if isinstance(form, str) else int(form)
         groups: Dict[tuple, List[int]] = {}
         for s in solvers:
-            groups.setdefault((scheme_id(s.prob), riemann_id(s.prob)), []).append(s.pid)
+            key = (scheme_id(s.prob), riemann_id(s.prob), limiter_id(s.prob))
+            groups.setdefault(key, []).append(s.pid)
         sets = [(ctypes.c_int * len(v))(*v) for _, v in sorted(groups.items())]
         for _ in range(nsteps):
             for pids in sets:
@@ -168,6 +172,10 @@ def scheme_id(prob: W.Problem) -> int:
 
 def riemann_id(prob: W.Problem) -> int:
     return RIEMANN[prob.riemann] if isinstance(prob.riemann, str) else int(prob.riemann)
+
+
+def limiter_id(prob: W.Problem) -> int:
+    return LIMITERS[prob.limiter] if isinstance(prob.limiter, str) else int(prob.limiter)
 
 
 def stage_names() -> List[str]:
@@ -190,6 +198,7 @@ def _params(prob: W.Problem) -> Params:
     P.nspec = int(prob.nspec)
     P.scheme = scheme_id(prob)
     P.riemann = riemann_id(prob)
+    P.limiter = limiter_id(prob)
     for s, x in enumerate(prob.inflow_X):
         P.inflow_X[s] = x
     return P

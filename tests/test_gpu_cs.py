@@ -1,0 +1,113 @@
+"""Parity of the HIP path with the oracle for the extremum-preserving PPM
+limiter (Colella & Sekora 2008), alone and with the two-shock solver, in the
+CTU and MOL schemes and on two levels.  Tolerances as elsewhere; the build
+aims at bitwise equality and the tests report it."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import l1_rel, max_rel, totals_rel
+from paper_1711_06203_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1711_06203_amd import ctuppm
+    c = ctuppm.Context()
+    yield c
+    c.close()
+
+
+def _run_gpu(ctx, prob, nsteps, form="batched"):
+    from paper_1711_06203_amd import ctuppm
+    s = ctuppm.Solver(ctx, prob, form=form)
+    s.step(nsteps)
+    out = s.state()
+    cnt = s.counters()
+    s.close()
+    return out, cnt
+
+
+def _report(name, got, ref):
+    d = np.abs(got - ref)
+    print(f"{name}: bitwise={np.array_equal(got, ref)} max_abs={d.max():.3e} "
+          f"max_rel={max(max_rel(got, ref)):.3e} l1={max(l1_rel(got, ref)):.3e}", flush=True)
+
+
+def _check(got, ref):
+    assert got.shape == ref.shape
+    assert max(l1_rel(got, ref)) <= 1e-8
+    assert max(totals_rel(got, ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("form", ["per_box", "batched", "graph"])
+def test_cs_sod(ctx, form):
+    prob = W.sod(n=32, steps=20)
+    prob.limiter = 1
+    ref, _, _ = oracle.run_problem(prob)
+    got, cnt = _run_gpu(ctx, prob, 20, form)
+    _report(f"cs sod32 {form}", got, ref)
+    _check(got, ref)
+    assert not cnt[:5].any()
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_cs_kh_species_ragged(ctx, scheme):
+    prob = W.kelvin_helmholtz(n=(40, 36, 20), box=(16, 16, 20), nspec=2)
+    prob.limiter = 1
+    prob.scheme = scheme
+    ref, _, _ = oracle.run_problem(prob, 10)
+    got, cnt = _run_gpu(ctx, prob, 10, "graph")
+    _report(f"cs kh scheme{scheme}", got, ref)
+    _check(got, ref)
+    assert not cnt[:5].any()
+
+
+def test_cs_with_two_shock_rt_uneven(ctx):
+    prob = W.rayleigh_taylor(n=48, seed=9, boxes=W.uneven_boxes((48, 48, 48), 9, edges=(16, 32)), nspec=1)
+    prob.limiter = 1
+    prob.riemann = 1
+    ref, _, _ = oracle.run_problem(prob, 10)
+    got, _ = _run_gpu(ctx, prob, 10)
+    _report("cs+twoshock rt48", got, ref)
+    _check(got, ref)
+
+
+def test_cs_smooth_state(ctx):
+    prob = W.serving_request(seed=66, n=24)
+    prob.limiter = 1
+    ref, _, _ = oracle.run_problem(prob, 10)
+    got, _ = _run_gpu(ctx, prob, 10)
+    _report("cs serving24", got, ref)
+    assert max(max_rel(got, ref)) <= 1e-10
+
+
+def test_cs_two_level_cloud(ctx):
+    from paper_1711_06203_amd import ctuppm
+    prob = W.cloud_wind(n=32, box=16, fine_box=16)
+    prob.limiter = 1
+    rc, rf, _, _ = oracle.run_two_level(prob, 6)
+    s = ctuppm.Solver(ctx, prob)
+    s.step(6)
+    gc, gf = s.state(), s.state_fine()
+    s.close()
+    _report("cs cloud coarse", gc, rc)
+    _report("cs cloud fine", gf, rf)
+    _check(gc, rc)
+    _check(gf, rf)
+
+
+def test_mixed_limiters_step_together_equal_alone(ctx):
+    from paper_1711_06203_amd import ctuppm
+    probs = [W.serving_request(seed=600 + r, n=16) for r in range(3)]
+    probs[1].limiter = 1
+    probs[2].limiter = 1
+    probs[2].riemann = 1
+    alone = [_run_gpu(ctx, p, 4)[0] for p in probs]
+    solvers = [ctuppm.Solver(ctx, p) for p in probs]
+    ctx.step(solvers, "graph", 4)
+    for s, a in zip(solvers, alone):
+        assert np.array_equal(s.state(), a)
+        s.close()

@@ -156,3 +156,10 @@ def test_kh256_twoshock_one_step_sampled(ctx):
     prob = W.kelvin_helmholtz(n=256, box=64)
     prob.riemann = 1
     _sampled(ctx, prob, 150, 5)
+
+
+@pytest.mark.slow
+def test_kh256_cs_limiter_one_step_sampled(ctx):
+    prob = W.kelvin_helmholtz(n=256, box=64)
+    prob.limiter = 1
+    _sampled(ctx, prob, 150, 6)
