@@ -103,6 +103,9 @@ def main():
                     help="interface flux: HLLC (default) or the two-shock approximate Riemann solver")
     ap.add_argument("--limiter", default="cw84", choices=["cw84", "cs"],
                     help="PPM limiter: Colella & Woodward 1984 (default) or Colella & Sekora 2008")
+    ap.add_argument("--regrid", type=float, default=0.0, metavar="THRESHOLD",
+                    help="cloud256: after timing, tag (density jump > THRESHOLD), cluster and regrid once, and "
+                         "report the time of each part")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
@@ -215,6 +218,26 @@ def main():
     achieved = sbytes[dom] / (avg_ms * launches_per_step * 1e-3) / 1e9
     traffic = measured_traffic(dom, tkey)
     cnt = solver.counters()
+    regrid_info = None
+    if args.regrid > 0.0 and two_level:
+        from paper_1711_06203_amd import regrid
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tags = solver.tag(args.regrid)
+        t1 = time.perf_counter()
+        patch = regrid.patch_from_tags(tags, buffer=2)
+        t2 = time.perf_counter()
+        boxes = regrid.fine_boxes(patch, 32) if patch else None
+        if boxes:
+            solver.regrid(boxes)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        solver.step(1)
+        torch.cuda.synchronize()
+        regrid_info = {"threshold": args.regrid, "tagged_cells": int(tags.sum()), "patch": patch,
+                       "fine_boxes": len(boxes) if boxes else 0, "tag_ms": (t1 - t0) * 1e3,
+                       "cluster_ms": (t2 - t1) * 1e3, "regrid_ms": (t3 - t2) * 1e3,
+                       "counters_after_step": [int(c) for c in solver.counters()]}
     out = {
         "metric": "zone-updates/s FP64 (unsplit CTU/PPM advance)" if args.scheme == "ctu" else
                   "zone-updates/s FP64 (method-of-lines PPM advance)",
@@ -240,6 +263,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items() if v},
         "counters": [int(c) for c in cnt],
     }
+    if regrid_info:
+        out["regrid"] = regrid_info
     solver.close()
     ctx.close()
     del solver

@@ -192,6 +192,44 @@ const char* ctuppm_stage_name(int stage);
  * once per Runge-Kutta stage). */
 int ctuppm_stage_bytes(ctuppm_ctx* ctx, int pid, int stage, double* bytes);
 
+/* ---------------------------------------------------------------- regridding
+ * The paper's grids adapt: cells are tagged for refinement and boxes are built
+ * around the tags (sections 2 and 3).  These calls tag, cluster and move the
+ * fine level of a two-level problem. */
+
+/* Tag the level-0 cells of problem pid whose density jumps across a cell in
+ * some direction by more than `threshold` relative to the two neighbours:
+ * |rho(i+e_d) - rho(i-e_d)| > threshold (rho(i+e_d) + rho(i-e_d)).  Fills the
+ * current state's ghost cells first (valid cells are unchanged).  tags is a
+ * caller-owned device array of nx*ny*nz bytes over the level-0 domain
+ * (i fastest, 1 = tagged).  Asynchronous. */
+int ctuppm_tag(ctuppm_ctx* ctx, int pid, double threshold, unsigned char* tags);
+
+/* Berger & Rigoutsos (1991) clustering on the host: tags (host, nx*ny*nz
+ * bytes, i fastest) are coarsened by `blocking` (a block is tagged if any of
+ * its cells is), the blocks are clustered until each cluster's fraction of
+ * tagged blocks reaches `efficiency` (0 < e <= 1) and no edge exceeds
+ * `max_edge` cells (cuts at signature holes, then at the strongest inflection
+ * of a signature, then across the middle of the longest edge), and the
+ * clusters are refined back: boxes aligned to `blocking`, disjoint, covering
+ * every tagged cell, clipped to the domain.  Writes at most `capacity` boxes;
+ * *nboxes receives the count (CTUPPM_ENOMEM if it exceeds capacity).  Needs no
+ * GPU. */
+int ctuppm_cluster(const unsigned char* tags, const int n[3], int blocking, double efficiency, int max_edge,
+                   ctuppm_box* boxes, int capacity, int* nboxes);
+
+/* Replace the fine level of two-level problem pid by new boxes (one rectangle
+ * tiled by boxes, the same rules as in ctuppm_problem_create) with new
+ * caller-owned fabs Ua[b], Ub[b].  The new fine state goes to Ua: cells inside
+ * the old fine rectangle are copied from the old fine state, the others are
+ * interpolated conservatively from the current coarse state (MC-limited
+ * linear, the coarse-fine ghost interpolation at the start of a step).  Call
+ * between steps; the old fabs may be freed after the next synchronisation.
+ * The workspace must then be re-bound with ctuppm_workspace_bytes() bytes
+ * before the next step (CTUPPM_ENOMEM otherwise).  Asynchronous. */
+int ctuppm_regrid(ctuppm_ctx* ctx, int pid, const ctuppm_box* fine_boxes, int nfine, double* const* Ua,
+                  double* const* Ub);
+
 /* Tuning of the launches: blocks per CU of the persistent batched launches
  * (0 = one block per work unit), and the z planes one work unit marches
  * through in the batched/graph forms and in the per-box form (>= 1).  Results

@@ -480,6 +480,54 @@ def two_level_step(Gc: np.ndarray, Gf: np.ndarray, clo, chi, Pc: Params, Pf: Par
     return Gc_new, Gf, dt_c, cnt
 
 
+def tag_cells(Uvalid: np.ndarray, P: Params, threshold: float) -> np.ndarray:
+    """Refinement tags (nz, ny, nx): a cell is tagged when, along some
+    direction, |rho(+1) - rho(-1)| > threshold (rho(+1) + rho(-1)), with the
+    domain's ghost cells filled."""
+    G = fill_domain(grow(np.asarray(Uvalid, dtype=np.float64)), P)
+    rho = G[0]
+    nz, ny, nx = Uvalid.shape[1:]
+    core = (slice(NG, NG + nz), slice(NG, NG + ny), slice(NG, NG + nx))
+    tags = np.zeros((nz, ny, nx), dtype=bool)
+    for axis in range(3):  # array axes z, y, x
+        hi = list(core)
+        lo = list(core)
+        hi[axis] = slice(core[axis].start + 1, core[axis].stop + 1)
+        lo[axis] = slice(core[axis].start - 1, core[axis].stop - 1)
+        rp, rm = rho[tuple(hi)], rho[tuple(lo)]
+        tags |= np.abs(rp - rm) > threshold * (rp + rm)
+    return tags
+
+
+def regrid_fine(Uc: np.ndarray, Uf_old: np.ndarray, old_lo, new_lo, new_n) -> np.ndarray:
+    """New fine-level state (valid cells of the new rectangle, fine index
+    new_lo, extent new_n = (nx, ny, nz)): cells inside the old fine rectangle
+    (fine index old_lo, array Uf_old) keep their old values, the others are
+    interpolated from the coarse valid state Uc (cf_interp; the patch lies at
+    least 3 coarse cells inside the domain)."""
+    new_lo = np.asarray(new_lo)
+    nx, ny, nz = new_n
+    gz, gy, gx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    fidx = np.stack([gx.ravel() + new_lo[0], gy.ravel() + new_lo[1], gz.ravel() + new_lo[2]], axis=1)
+    vals = cf_interp(Uc, (0, 0, 0), fidx).reshape((Uc.shape[0], nz, ny, nx))
+    olo = np.asarray(old_lo)
+    on = np.asarray(Uf_old.shape[1:][::-1])
+    lo = np.maximum(olo, new_lo)
+    hi = np.minimum(olo + on, new_lo + np.asarray(new_n))
+    if np.all(hi > lo):
+        dst = (slice(None),) + tuple(slice(lo[d] - new_lo[d], hi[d] - new_lo[d]) for d in (2, 1, 0))
+        src = (slice(None),) + tuple(slice(lo[d] - olo[d], hi[d] - olo[d]) for d in (2, 1, 0))
+        vals[dst] = Uf_old[src]
+    return vals
+
+
+def run_two_level_from(prob, Uc: np.ndarray, Uf: np.ndarray, fine_lo, nsteps: int):
+    """run_two_level from given coarse and fine states (fine rectangle at fine_lo)."""
+    import dataclasses
+    p2 = dataclasses.replace(prob, U0=Uc, U0_fine=Uf, fine_lo=tuple(int(v) for v in fine_lo))
+    return run_two_level(p2, nsteps)
+
+
 def run_two_level(prob, nsteps: int):
     """Two-level run of a workloads.Problem with fine_boxes / U0_fine set; the
     fine level must be one rectangle (the union of its boxes).  Returns

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctuppm.so")
-SOURCES = ["ctuppm_kernels.hip", "ctuppm_host.cpp"]
+SOURCES = ["ctuppm_kernels.hip", "ctuppm_host.cpp", "ctuppm_cluster.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -296,6 +296,79 @@ int run_stage(ctuppm_ctx* c, hipStream_t s, int stage, const BoxRec* boxes, cons
   return CTUPPM_OK;
 }
 
+// Boxes of level l: inside the level's domain, non-empty, edges <= 256, disjoint.
+int check_level(ctuppm_ctx* c, const ctuppm_params& prm, int l, const ctuppm_box* boxes, int n) {
+  int dlo[3], dhi[3];
+  level_domain(prm, l, dlo, dhi);
+  for (int b = 0; b < n; ++b) {
+    const ctuppm_box& B = boxes[b];
+    for (int d = 0; d < 3; ++d) {
+      if (B.lo[d] > B.hi[d] || B.lo[d] < dlo[d] || B.hi[d] > dhi[d])
+        return fail(c, CTUPPM_EINVAL, "level %d box %d outside the domain or empty", l, b);
+      if (B.hi[d] - B.lo[d] + 1 > 256)
+        return fail(c, CTUPPM_EINVAL, "level %d box %d: edges above 256 cells are not supported", l, b);
+    }
+    for (int o = 0; o < b; ++o)
+      if (overlap(B, boxes[o])) return fail(c, CTUPPM_EINVAL, "level %d boxes %d and %d overlap", l, o, b);
+  }
+  return CTUPPM_OK;
+}
+
+// The fine level must be one rectangle of boxes aligned to coarse cells, at
+// least 3 coarse cells inside the domain; gives its fine range flo..fhi and
+// the coarse cells clo..chi it covers.
+int fine_geometry(ctuppm_ctx* c, const ctuppm_params& prm, const std::vector<ctuppm_box>& fb, int flo[3],
+                  int fhi[3], int clo[3], int chi[3]) {
+  long long vol = 0;
+  for (int d = 0; d < 3; ++d) {
+    flo[d] = fb[0].lo[d];
+    fhi[d] = fb[0].hi[d];
+  }
+  for (const auto& b : fb) {
+    long long v = 1;
+    for (int d = 0; d < 3; ++d) {
+      if ((b.lo[d] & 1) || !(b.hi[d] & 1))
+        return fail(c, CTUPPM_EINVAL, "fine boxes must start at even and end at odd indices");
+      flo[d] = std::min(flo[d], b.lo[d]);
+      fhi[d] = std::max(fhi[d], b.hi[d]);
+      v *= box_n(b, d);
+    }
+    vol += v;
+  }
+  long long bb = 1;
+  for (int d = 0; d < 3; ++d) {
+    bb *= fhi[d] - flo[d] + 1;
+    clo[d] = flo[d] / 2;
+    chi[d] = (fhi[d] + 1) / 2 - 1;
+    if (clo[d] - 3 < prm.domain_lo[d] || chi[d] + 3 > prm.domain_hi[d])
+      return fail(c, CTUPPM_EINVAL, "fine level must lie at least 3 coarse cells inside the domain");
+  }
+  if (bb != vol) return fail(c, CTUPPM_EINVAL, "fine boxes must tile one rectangle");
+  return CTUPPM_OK;
+}
+
+// Gather tags of the coarse boxes' valid cells inside region rlo..rlo+rext-1.
+void gather_tags(const std::vector<ctuppm_box>& CB, const int rlo[3], const int rext[3], std::vector<GatherTag>& gt,
+                 std::vector<Chunk>& gch) {
+  int rhi[3];
+  for (int d = 0; d < 3; ++d) rhi[d] = rlo[d] + rext[d] - 1;
+  for (size_t b = 0; b < CB.size(); ++b) {
+    int lo[3], hi[3];
+    if (!intersect(CB[b].lo, CB[b].hi, rlo, rhi, lo, hi)) continue;
+    GatherTag t{};
+    t.box = int(b);
+    long long vol = 1;
+    for (int d = 0; d < 3; ++d) {
+      t.lo[d] = lo[d] - CB[b].lo[d];
+      t.ext[d] = hi[d] - lo[d] + 1;
+      t.roff[d] = lo[d] - rlo[d];
+      vol *= t.ext[d];
+    }
+    chunk_region(gch, int(gt.size()), vol);
+    gt.push_back(t);
+  }
+}
+
 // Coarse region of a two-level problem: coarse cells clo-3..chi+3.
 long long region_cells(const Problem* P, int ext[3], int lo[3]) {
   long long v = 1;
@@ -744,23 +817,7 @@ int build_two_level(ctuppm_ctx* c, int pid, TwoLevel** out) {
   // gather: coarse valid cells inside the region
   std::vector<GatherTag> gt;
   std::vector<Chunk> gch;
-  int rhi[3];
-  for (int d = 0; d < 3; ++d) rhi[d] = rlo[d] + rext[d] - 1;
-  for (size_t b = 0; b < CB.size(); ++b) {
-    int lo[3], hi[3];
-    if (!intersect(CB[b].lo, CB[b].hi, rlo, rhi, lo, hi)) continue;
-    GatherTag t{};
-    t.box = int(b);
-    long long vol = 1;
-    for (int d = 0; d < 3; ++d) {
-      t.lo[d] = lo[d] - CB[b].lo[d];
-      t.ext[d] = hi[d] - lo[d] + 1;
-      t.roff[d] = lo[d] - rlo[d];
-      vol *= t.ext[d];
-    }
-    chunk_region(gch, int(gt.size()), vol);
-    gt.push_back(t);
-  }
+  gather_tags(CB, rlo, rext, gt, gch);
   // coarse-to-fine: the ghost cells of each fine box outside the fine rectangle
   std::vector<CfTag> ct;
   std::vector<Chunk> cch;
@@ -1030,50 +1087,13 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   P->nlevels = nlevels;
   for (int l = 0; l < nlevels; ++l) {
     if (nboxes[l] < 1 || !boxes[l]) return fail(c, CTUPPM_EINVAL, "level %d has no boxes", l);
-    int dlo[3], dhi[3];
-    level_domain(*prm, l, dlo, dhi);
-    for (int b = 0; b < nboxes[l]; ++b) {
-      const ctuppm_box& B = boxes[l][b];
-      for (int d = 0; d < 3; ++d) {
-        if (B.lo[d] > B.hi[d] || B.lo[d] < dlo[d] || B.hi[d] > dhi[d])
-          return fail(c, CTUPPM_EINVAL, "level %d box %d outside the domain or empty", l, b);
-        if (B.hi[d] - B.lo[d] + 1 > 256)
-          return fail(c, CTUPPM_EINVAL, "level %d box %d: edges above 256 cells are not supported", l, b);
-      }
-      for (int o = 0; o < b; ++o)
-        if (overlap(B, boxes[l][o])) return fail(c, CTUPPM_EINVAL, "level %d boxes %d and %d overlap", l, o, b);
-      P->lev[l].boxes.push_back(B);
-    }
+    const int rc = check_level(c, *prm, l, boxes[l], nboxes[l]);
+    if (rc) return rc;
+    P->lev[l].boxes.assign(boxes[l], boxes[l] + nboxes[l]);
   }
   if (nlevels == 2) {
-    // the fine level must be one rectangle of boxes aligned to coarse cells,
-    // at least 3 coarse cells inside the domain
-    const auto& fb = P->lev[1].boxes;
-    long long vol = 0;
-    for (int d = 0; d < 3; ++d) {
-      P->flo[d] = fb[0].lo[d];
-      P->fhi[d] = fb[0].hi[d];
-    }
-    for (const auto& b : fb) {
-      long long v = 1;
-      for (int d = 0; d < 3; ++d) {
-        if ((b.lo[d] & 1) || !(b.hi[d] & 1))
-          return fail(c, CTUPPM_EINVAL, "fine boxes must start at even and end at odd indices");
-        P->flo[d] = std::min(P->flo[d], b.lo[d]);
-        P->fhi[d] = std::max(P->fhi[d], b.hi[d]);
-        v *= box_n(b, d);
-      }
-      vol += v;
-    }
-    long long bb = 1;
-    for (int d = 0; d < 3; ++d) {
-      bb *= P->fhi[d] - P->flo[d] + 1;
-      P->clo[d] = P->flo[d] / 2;
-      P->chi[d] = (P->fhi[d] + 1) / 2 - 1;
-      if (P->clo[d] - 3 < prm->domain_lo[d] || P->chi[d] + 3 > prm->domain_hi[d])
-        return fail(c, CTUPPM_EINVAL, "fine level must lie at least 3 coarse cells inside the domain");
-    }
-    if (bb != vol) return fail(c, CTUPPM_EINVAL, "fine boxes must tile one rectangle");
+    const int rc = fine_geometry(c, *prm, P->lev[1].boxes, P->flo, P->fhi, P->clo, P->chi);
+    if (rc) return rc;
   }
   ProbDev h{};
   h.gamma = prm->gamma;
@@ -1333,6 +1353,166 @@ int ctuppm_stage_times(ctuppm_ctx* c, double* ms, long long* launches, int n) {
 
 int ctuppm_num_stages(void) { return kNumStages; }
 const char* ctuppm_stage_name(int s) { return stage_name(s); }
+
+int ctuppm_tag(ctuppm_ctx* c, int pid, double threshold, unsigned char* tags) {
+  if (!c || !tags || !(threshold >= 0.0)) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  StepSet* S = nullptr;
+  const std::vector<int> v{pid};
+  int rc = build_set(c, v, CTUPPM_FORM_BATCHED, &S, 0);
+  if (rc) return rc;
+  if ((rc = fill_arr(c, S, c->stream, false, kArrCur))) return rc;
+  int dn[3];
+  for (int d = 0; d < 3; ++d) dn[d] = P->prm.domain_hi[d] - P->prm.domain_lo[d] + 1;
+  hipError_t e =
+      launch_tag(S->boxes, S->units[kValid], S->nch[kValid], threshold, tags, dn, P->prm.domain_lo, c->stream);
+  if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "tag launch: %s", hipGetErrorString(e));
+  return CTUPPM_OK;
+}
+
+int ctuppm_regrid(ctuppm_ctx* c, int pid, const ctuppm_box* fine_boxes, int nfine, double* const* Ua,
+                  double* const* Ub) {
+  if (!c || !fine_boxes || nfine < 1 || !Ua || !Ub) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (P->nlevels != 2) return fail(c, CTUPPM_EINVAL, "problem %d has no fine level", pid);
+  if (!P->lev[0].bound || !P->lev[1].bound) return fail(c, CTUPPM_ESTATE, "problem %d: state not bound", pid);
+  for (int b = 0; b < nfine; ++b)
+    if (!Ua[b] || !Ub[b]) return fail(c, CTUPPM_EINVAL, "null fab for fine box %d", b);
+  int rc = check_level(c, P->prm, 1, fine_boxes, nfine);
+  if (rc) return rc;
+  const std::vector<ctuppm_box> NB(fine_boxes, fine_boxes + nfine);
+  int flo[3], fhi[3], clo[3], chi[3];
+  if ((rc = fine_geometry(c, P->prm, NB, flo, fhi, clo, chi))) return rc;
+  // the coarse cells the interpolation reads: parents and their neighbours
+  StepSet* S0 = nullptr;
+  StepSet* S1 = nullptr;
+  const std::vector<int> v{pid};
+  if ((rc = build_set(c, v, CTUPPM_FORM_BATCHED, &S0, 0)) || (rc = build_set(c, v, CTUPPM_FORM_BATCHED, &S1, 1)))
+    return rc;
+  TwoLevelArgs A{};
+  int rlo[3], rext[3];
+  long long rcells = 1;
+  for (int d = 0; d < 3; ++d) {
+    rlo[d] = clo[d] - 1;
+    rext[d] = chi[d] - clo[d] + 3;
+    rcells *= rext[d];
+    A.rlo[d] = rlo[d];
+    A.rext[d] = rext[d];
+  }
+  std::vector<GatherTag> gt;
+  std::vector<Chunk> gch;
+  gather_tags(P->lev[0].boxes, rlo, rext, gt, gch);
+  // new fine box records (fabs A/B of the caller), and the copy / interpolate tags
+  const int ns = P->prm.nspec;
+  std::vector<BoxRec> nrec(nfine);
+  for (int b = 0; b < nfine; ++b) {
+    BoxRec& r = nrec[b];
+    r = BoxRec{};
+    r.U[0] = Ua[b];
+    r.U[1] = Ub[b];
+    r.P = P->dPf;
+    r.level = 1;
+    r.ns = ns;
+    for (int d = 0; d < 3; ++d) {
+      r.n[d] = box_n(NB[b], d);
+      r.lo[d] = NB[b].lo[d];
+    }
+  }
+  const auto& OB = P->lev[1].boxes;
+  std::vector<ProlongTag> pt;
+  std::vector<Chunk> pch;
+  auto add = [&](int box, int src, const int lo[3], const int hi[3]) {
+    ProlongTag t{};
+    t.box = box;
+    t.src = src;
+    long long vol = 1;
+    for (int d = 0; d < 3; ++d) {
+      t.lo[d] = lo[d] - NB[box].lo[d];
+      t.ext[d] = hi[d] - lo[d] + 1;
+      vol *= t.ext[d];
+    }
+    chunk_region(pch, int(pt.size()), vol);
+    pt.push_back(t);
+  };
+  for (int b = 0; b < nfine; ++b) {
+    // pieces of the box below, inside and above the old fine rectangle, per direction
+    int seg[3][3][2];
+    for (int d = 0; d < 3; ++d) {
+      const int lo = NB[b].lo[d], hi = NB[b].hi[d];
+      seg[d][0][0] = lo; seg[d][0][1] = std::min(hi, P->flo[d] - 1);
+      seg[d][1][0] = std::max(lo, P->flo[d]); seg[d][1][1] = std::min(hi, P->fhi[d]);
+      seg[d][2][0] = std::max(lo, P->fhi[d] + 1); seg[d][2][1] = hi;
+    }
+    for (int qa = 0; qa < 3; ++qa)
+      for (int qb = 0; qb < 3; ++qb)
+        for (int qc = 0; qc < 3; ++qc) {
+          const int q[3] = {qa, qb, qc};
+          int lo[3], hi[3];
+          bool empty = false;
+          for (int d = 0; d < 3; ++d) {
+            lo[d] = seg[d][q[d]][0];
+            hi[d] = seg[d][q[d]][1];
+            empty = empty || lo[d] > hi[d];
+          }
+          if (empty) continue;
+          if (qa == 1 && qb == 1 && qc == 1) {  // inside the old rectangle: copy, box by box
+            for (size_t o = 0; o < OB.size(); ++o) {
+              int ilo[3], ihi[3];
+              if (intersect(lo, hi, OB[o].lo, OB[o].hi, ilo, ihi)) add(b, int(o), ilo, ihi);
+            }
+          } else {
+            add(b, -1, lo, hi);
+          }
+        }
+  }
+  DevAlloc tmp;
+  double* region = nullptr;
+  const size_t rbytes = size_t(rcells) * size_t(kNV + ns) * sizeof(double);
+  HIPCHK(c, hipMalloc((void**)&region, rbytes));
+  tmp.ptrs.push_back(region);
+  GatherTag* dgt = nullptr;
+  Chunk* dgch = nullptr;
+  ProlongTag* dpt = nullptr;
+  Chunk* dpch = nullptr;
+  BoxRec* dnrec = nullptr;
+  if ((rc = upload_vec(c, tmp, gt, &dgt)) || (rc = upload_vec(c, tmp, gch, &dgch)) ||
+      (rc = upload_vec(c, tmp, pt, &dpt)) || (rc = upload_vec(c, tmp, pch, &dpch)) ||
+      (rc = upload_vec(c, tmp, nrec, &dnrec))) {
+    (void)hipStreamSynchronize(c->stream);
+    tmp.release();
+    return rc;
+  }
+  A.cboxes = S0->boxes;
+  A.fboxes = S1->boxes;
+  A.Pc = P->dP;
+  A.Pf = P->dPf;
+  A.ct0 = region;
+  hipError_t e = launch_gather(A, dgt, dgch, int(gch.size()), 0, c->stream);
+  if (e == hipSuccess) e = launch_prolong(A, dnrec, S1->boxes, dpt, dpch, int(pch.size()), c->stream);
+  hipError_t e2 = hipStreamSynchronize(c->stream);
+  tmp.release();
+  if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "regrid launch: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(c, CTUPPM_EHIP, "regrid: %s", hipGetErrorString(e2));
+  // the fine level's parity: the new state is in the A fabs
+  ProbDev h;
+  HIPCHK(c, hipMemcpy(&h, P->dPf, sizeof(ProbDev), hipMemcpyDeviceToHost));
+  h.cur = 0;
+  HIPCHK(c, hipMemcpy(P->dPf, &h, sizeof(ProbDev), hipMemcpyHostToDevice));
+  drop_sets(c, pid);
+  P->lev[1].boxes = NB;
+  P->lev[1].Ua.assign(Ua, Ua + nfine);
+  P->lev[1].Ub.assign(Ub, Ub + nfine);
+  P->lev[1].bound = true;
+  for (int d = 0; d < 3; ++d) {
+    P->flo[d] = flo[d];
+    P->fhi[d] = fhi[d];
+    P->clo[d] = clo[d];
+    P->chi[d] = chi[d];
+  }
+  return CTUPPM_OK;
+}
 
 int ctuppm_set_tuning(ctuppm_ctx* c, int bpc, int zb, int zp) {
   return ctuppm_set_tuning2(c, bpc, zb, zp, c ? c->ytile : 0);

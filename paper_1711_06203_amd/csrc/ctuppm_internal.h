@@ -95,6 +95,11 @@ struct RegFace { int d, side, cbox, fbox; int cface[3]; int ucell[3]; int fface[
 // box-local index of the first child.
 struct AvgTag { int cbox, fbox; int clo[3]; int ext[3]; int flo[3]; int pad; };
 
+// Regrid of a fine level: cells [lo, lo+ext) of new fine box `box` (box-local)
+// are copied from old fine box `src` (>= 0) or interpolated from the gathered
+// coarse region (src = -1).
+struct ProlongTag { int box, src; int lo[3]; int ext[3]; };
+
 struct TwoLevelArgs {
   const BoxRec* cboxes;
   const BoxRec* fboxes;
@@ -183,6 +188,13 @@ hipError_t launch_reg_fine(const TwoLevelArgs& A, const RegFace* faces, int n, h
 hipError_t launch_avgdown(const TwoLevelArgs& A, const AvgTag* tags, const Chunk* chunks, int n, hipStream_t s);
 hipError_t launch_reflux(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s);
 hipError_t launch_dt2(ProbDev* Pc, ProbDev* Pf, hipStream_t s);
+// Regridding: density-jump tags of level-0 valid cells into a dense domain
+// array (dn = domain extent, dlo = its first index), and the new fine state
+// of a regrid.
+hipError_t launch_tag(const BoxRec* boxes, const March* units, int nunits, double threshold, unsigned char* tags,
+                      const int dn[3], const int dlo[3], hipStream_t s);
+hipError_t launch_prolong(const TwoLevelArgs& A, const BoxRec* newf, const BoxRec* oldf, const ProlongTag* tags,
+                          const Chunk* chunks, int n, hipStream_t s);
 hipError_t launch_dt(ProbDev* const* probs, int nprobs, hipStream_t s);
 hipError_t launch_flip(ProbDev* const* probs, int nprobs, hipStream_t s);
 const char* stage_name(int stage);

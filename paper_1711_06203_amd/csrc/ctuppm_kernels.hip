@@ -27,7 +27,6 @@ namespace {
 // goes in scalar registers.
 using gdbl = __attribute__((address_space(1))) double;
 CTU_DEV gdbl* gp(double* p) { return (gdbl*)p; }
-CTU_DEV const gdbl* gp(const double* p) { return (const gdbl*)p; }
 
 template <class F>
 CTU_DEV void for_each_chunk(int nchunks, F&& f) {
@@ -952,6 +951,83 @@ __global__ void k_reflux(TwoLevelArgs A, const RegFace* __restrict__ faces, int 
   }
 }
 
+// ------------------------------------------------------------- regridding
+
+// Tag a level-0 valid cell when its density jumps across it along some
+// direction by more than `thr` relative to the two neighbours (ghosts filled).
+__global__ __launch_bounds__(kBlock) void k_tag(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
+                                                int nunits, double thr, unsigned char* __restrict__ tags, int dnx,
+                                                int dny, int dlx, int dly, int dlz) {
+  for_each_chunk(nunits, [&](int u) {
+    const March M = units[u];
+    const BoxRec& B = boxes[M.box];
+    const Geo g(B.n, B.ns);
+    const gdbl* __restrict__ U = gp(B.U[B.P->cur]);
+    march(kValid, B, M, [&](int i, int j, int k) {
+      const int o = g.g(i, j, k);
+      bool t = false;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int st = g.gstride(d);
+        const double rp = U[o + st], rm = U[o - st];
+        if (fabs(rp - rm) > thr * (rp + rm)) t = true;
+      }
+      const long long I = B.lo[0] + i - dlx, J = B.lo[1] + j - dly, K = B.lo[2] + k - dlz;
+      tags[(K * dny + J) * dnx + I] = t ? 1 : 0;
+    });
+  });
+}
+
+// New fine state of a regrid: copy from the old fine level, or MC-linear
+// interpolation from the gathered coarse region (the coarse-fine rule).
+__global__ __launch_bounds__(kBlock) void k_prolong(TwoLevelArgs A, const BoxRec* __restrict__ newf,
+                                                    const BoxRec* __restrict__ oldf,
+                                                    const ProlongTag* __restrict__ tags,
+                                                    const Chunk* __restrict__ chunks, int n) {
+  const int rplane = A.rext[0] * A.rext[1], rcomp = rplane * A.rext[2];
+  for_each_chunk(n, [&](int c) {
+    const Chunk ch = chunks[c];
+    const ProlongTag T = tags[ch.box];
+    int x[3];
+    if (!tag_item(T.ext, ch.start + threadIdx.x, x[0], x[1], x[2])) return;
+    const BoxRec& B = newf[T.box];
+    const Geo g(B.n, B.ns);
+    gdbl* __restrict__ U = gp(B.U[0]);
+    int I[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x[d] += T.lo[d];
+      I[d] = B.lo[d] + x[d];
+    }
+    const int go = g.g(x[0], x[1], x[2]);
+    if (T.src >= 0) {
+      const BoxRec& S = oldf[T.src];
+      const Geo gs(S.n, S.ns);
+      const gdbl* __restrict__ V = gp(S.U[S.P->cur]);
+      const int so = gs.g(I[0] - S.lo[0], I[1] - S.lo[1], I[2] - S.lo[2]);
+      for (int m = 0; m < g.nv; ++m) U[m * g.gcomp + go] = V[m * gs.gcomp + so];
+      return;
+    }
+    int rp[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rp[d] = (I[d] >> 1) - A.rlo[d];
+    const int po = (rp[2] * A.rext[1] + rp[1]) * A.rext[0] + rp[0];
+    const int st[3] = {1, A.rext[0], rplane};
+    for (int m = 0; m < g.nv; ++m) {
+      const gdbl* __restrict__ a0 = gp(A.ct0) + m * rcomp;
+      const double cpar = a0[po];
+      double val = cpar;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double sl = mc_slope(a0[po - st[d]], cpar, a0[po + st[d]]);
+        const double sgn = (I[d] & 1) ? 0.25 : -0.25;
+        val = val + sgn * sl;
+      }
+      U[m * g.gcomp + go] = val;
+    }
+  });
+}
+
 __global__ void k_dt2(ProbDev* Pc, ProbDev* Pf) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   unsigned long long bc = 0ull, bf = 0ull;
@@ -1062,6 +1138,21 @@ hipError_t launch_avgdown(const TwoLevelArgs& A, const AvgTag* tags, const Chunk
 hipError_t launch_reflux(const TwoLevelArgs& A, const RegFace* faces, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   k_reflux<<<(n + 255) / 256, 256, 0, s>>>(A, faces, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_tag(const BoxRec* boxes, const March* units, int nunits, double threshold, unsigned char* tags,
+                      const int dn[3], const int dlo[3], hipStream_t s) {
+  if (nunits <= 0) return hipSuccess;
+  k_tag<<<(nunits + 7) / 8 * 8, kBlock, 0, s>>>(boxes, units, nunits, threshold, tags, dn[0], dn[1], dlo[0], dlo[1],
+                                                dlo[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const TwoLevelArgs& A, const BoxRec* newf, const BoxRec* oldf, const ProlongTag* tags,
+                          const Chunk* chunks, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_prolong<<<(n + 7) / 8 * 8, kBlock, 0, s>>>(A, newf, oldf, tags, chunks, n);
   return hipGetLastError();
 }
 

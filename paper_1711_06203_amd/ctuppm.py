@@ -86,6 +86,11 @@ def lib() -> ctypes.CDLL:
             "ctuppm_step_checked": [vp, ctypes.c_int, ctypes.c_int, ip],
             "ctuppm_set_fail_hook": [vp, ctypes.c_int, ctypes.c_int],
             "ctuppm_last_error": [vp],
+            "ctuppm_tag": [vp, ctypes.c_int, ctypes.c_double, vp],
+            "ctuppm_cluster": [vp, ip, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Box), ctypes.c_int,
+                               ip],
+            "ctuppm_regrid": [vp, ctypes.c_int, ctypes.POINTER(Box), ctypes.c_int, ctypes.POINTER(vp),
+                              ctypes.POINTER(vp)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -102,7 +107,7 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_bind_workspace", "ctuppm_set_fixed_dt", "ctuppm_step", "ctuppm_current_state",
             "ctuppm_get_dt", "ctuppm_status", "ctuppm_set_timing", "ctuppm_stage_times", "ctuppm_num_stages",
             "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning", "ctuppm_step_checked",
-            "ctuppm_set_fail_hook", "ctuppm_set_tuning2"]
+            "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid"]
 
 
 class Context:
@@ -164,6 +169,22 @@ class Context:
         for _ in range(nsteps):
             for pids in sets:
                 self.call("ctuppm_step", pids, len(pids), f)
+
+
+def cluster(tags: np.ndarray, blocking: int = 4, efficiency: float = 0.7, max_edge: int = 64) -> List[W.Box]:
+    """Berger-Rigoutsos boxes around the tagged cells of a (nz, ny, nx) array
+    (host code of the library; needs no GPU)."""
+    t = np.ascontiguousarray(tags, dtype=np.uint8)
+    nz, ny, nx = t.shape
+    n = (ctypes.c_int * 3)(nx, ny, nz)
+    cap = max(16, t.size // max(1, blocking ** 3) + 1)
+    out = (Box * cap)()
+    nb = ctypes.c_int()
+    rc = lib().ctuppm_cluster(t.ctypes.data_as(ctypes.c_void_p), n, int(blocking), float(efficiency), int(max_edge),
+                              out, cap, ctypes.byref(nb))
+    if rc != OK:
+        raise CtuError(f"ctuppm_cluster failed ({rc})")
+    return [(tuple(out[q].lo), tuple(out[q].hi)) for q in range(nb.value)]
 
 
 def scheme_id(prob: W.Problem) -> int:
@@ -232,28 +253,37 @@ class Solver:
         self.pid = pid.value
         dev = torch.device("cuda", torch.cuda.current_device())
         self.nv = 5 + int(prob.nspec)
-        self.lv = []
-        for boxes in self.levels:
-            offsets, shapes, off = [], [], 0
-            for lo, hi in boxes:
-                n = [hi[d] - lo[d] + 1 for d in range(3)]
-                shape = (self.nv, n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG)
-                offsets.append(off)
-                shapes.append(shape)
-                off += (int(np.prod(shape)) + 31) // 32 * 32
-            A = torch.full((off,), float("nan"), dtype=torch.float64, device=dev)
-            B = torch.full((off,), float("nan"), dtype=torch.float64, device=dev)
-            self.lv.append({"boxes": boxes, "offsets": offsets, "shapes": shapes, "total": off, "A": A, "B": B})
-        ws = ctypes.c_size_t()
-        best = 0
-        for f in ((FORM_BATCHED,) if nl == 2 else (FORM_PER_BOX, FORM_BATCHED)):
-            ctx.call("ctuppm_workspace_bytes", self.pid, f, ctypes.byref(ws))
-            best = max(best, ws.value)
-        self.ws = torch.empty((max(best, 256),), dtype=torch.uint8, device=dev)
+        self.dev = dev
+        self.lv = [self._alloc_level(boxes) for boxes in self.levels]
+        if nl == 2:  # the fine rectangle: first fine index and extent
+            self.fine_lo = tuple(prob.fine_lo)
+            self.fine_n = tuple(prob.U0_fine.shape[1:][::-1])
+        self._bind_workspace()
         self.upload(prob.U0, prob.U0_fine)
-        ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel())
         if fixed_dt:
             ctx.call("ctuppm_set_fixed_dt", self.pid, float(fixed_dt))
+
+    def _alloc_level(self, boxes):
+        torch = self.ctx.torch
+        offsets, shapes, off = [], [], 0
+        for lo, hi in boxes:
+            n = [hi[d] - lo[d] + 1 for d in range(3)]
+            shape = (self.nv, n[2] + 2 * NG, n[1] + 2 * NG, n[0] + 2 * NG)
+            offsets.append(off)
+            shapes.append(shape)
+            off += (int(np.prod(shape)) + 31) // 32 * 32
+        A = torch.full((off,), float("nan"), dtype=torch.float64, device=self.dev)
+        B = torch.full((off,), float("nan"), dtype=torch.float64, device=self.dev)
+        return {"boxes": boxes, "offsets": offsets, "shapes": shapes, "total": off, "A": A, "B": B}
+
+    def _bind_workspace(self):
+        ws = ctypes.c_size_t()
+        best = 0
+        for f in ((FORM_BATCHED,) if len(self.levels) == 2 else (FORM_PER_BOX, FORM_BATCHED)):
+            self.ctx.call("ctuppm_workspace_bytes", self.pid, f, ctypes.byref(ws))
+            best = max(best, ws.value)
+        self.ws = self.ctx.torch.empty((max(best, 256),), dtype=self.ctx.torch.uint8, device=self.dev)
+        self.ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel())
 
     # backwards-compatible views of level 0
     @property
@@ -274,7 +304,7 @@ class Solver:
     def upload(self, Uvalid: np.ndarray, Ufine: Optional[np.ndarray] = None):
         """Copy a level-0 state (5 + nspec, nz, ny, nx) (and the fine
         rectangle's state) into the A fabs; ghosts NaN."""
-        for level, (U, origin) in enumerate([(Uvalid, (0, 0, 0)), (Ufine, self.prob.fine_lo)][:len(self.lv)]):
+        for level, (U, origin) in enumerate([(Uvalid, (0, 0, 0)), (Ufine, getattr(self, "fine_lo", None))][:len(self.lv)]):
             if U.shape[0] != self.nv:
                 raise ValueError(f"state has {U.shape[0]} components, the problem {self.nv}")
             L = self.lv[level]
@@ -317,8 +347,39 @@ class Solver:
 
     def state_fine(self) -> np.ndarray:
         """Valid cells of the fine rectangle's current state."""
-        nf = self.prob.U0_fine.shape[1:][::-1]
-        return W.gather_valid(self.fabs(1), self.prob.fine_boxes, nf, origin=self.prob.fine_lo)
+        return W.gather_valid(self.fabs(1), self.levels[1], self.fine_n, origin=self.fine_lo)
+
+    def tag(self, threshold: float) -> np.ndarray:
+        """Level-0 refinement tags (nz, ny, nx) from the density-jump criterion."""
+        torch = self.ctx.torch
+        nx, ny, nz = self.prob.n
+        t = torch.zeros((nx * ny * nz,), dtype=torch.uint8, device=self.dev)
+        self.ctx.call("ctuppm_tag", self.pid, float(threshold), ctypes.c_void_p(t.data_ptr()))
+        return t.cpu().numpy().reshape(nz, ny, nx).astype(bool)
+
+    def regrid(self, fine_boxes: Sequence[W.Box]):
+        """Move the fine level onto new boxes (one rectangle): new fabs, the new
+        fine state computed on the device, the workspace re-bound."""
+        boxes = [tuple(map(tuple, b)) for b in fine_boxes]
+        arr = (Box * len(boxes))()
+        for b, (lo, hi) in enumerate(boxes):
+            arr[b].lo[:] = list(lo)
+            arr[b].hi[:] = list(hi)
+        L = self._alloc_level(boxes)
+        nb = len(boxes)
+        a = (ctypes.c_void_p * nb)(*[L["A"].data_ptr() + 8 * o for o in L["offsets"]])
+        b_ = (ctypes.c_void_p * nb)(*[L["B"].data_ptr() + 8 * o for o in L["offsets"]])
+        self.ctx.call("ctuppm_regrid", self.pid, arr, nb, a, b_)
+        old = self.lv[1]
+        self.lv[1] = L
+        self.levels[1] = boxes
+        self._boxes[1] = arr
+        lo = [min(bx[0][d] for bx in boxes) for d in range(3)]
+        hi = [max(bx[1][d] for bx in boxes) for d in range(3)]
+        self.fine_lo = tuple(lo)
+        self.fine_n = tuple(hi[d] - lo[d] + 1 for d in range(3))
+        self._bind_workspace()
+        del old
 
     def dt(self) -> float:
         v = ctypes.c_double()
