@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3),
                 ("inflow", ctypes.c_double * 5), ("nspec", ctypes.c_int), ("pad", ctypes.c_int),
                 ("inflow_X", ctypes.c_double * MAXSPEC), ("scheme", ctypes.c_int), ("riemann", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("pad3", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("steepen", ctypes.c_int)]
 
 SCHEMES = {"ctu": 0, "mol2": 1, "mol3": 2}
 
@@ -101,6 +101,10 @@ def lib():
         L.orc_twoshock.restype = None
         L.orc_ppm_cell_cs.argtypes = [dp, ctypes.c_double, dp]
         L.orc_ppm_cell_cs.restype = None
+        L.orc_ppm_cell_steep.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_ppm_cell_steep.restype = None
+        L.orc_steep_eta.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_steep_eta.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -116,8 +120,9 @@ def _ip(seq):
 
 def make_params(gamma, dx, cfl=0.5, bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), grav_z=0.0,
                 inflow=(1.0, 0.0, 0.0, 0.0, 1.0), small_dens=1e-12, small_pres=1e-12, nspec=0,
-                inflow_X=(), scheme=0, riemann=0, limiter=0) -> Params:
+                inflow_X=(), scheme=0, riemann=0, limiter=0, steepen=0) -> Params:
     P = Params()
+    P.steepen = int(steepen)
     P.riemann = int(riemann)
     P.limiter = int(limiter)
     P.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
@@ -140,7 +145,8 @@ def params_of(prob, fine: bool = False) -> Params:
         dx = tuple(v / 2.0 for v in dx)
     return make_params(prob.gamma, dx, prob.cfl, prob.bc_lo, prob.bc_hi, prob.grav_z, prob.inflow,
                        prob.small_dens, prob.small_pres, getattr(prob, "nspec", 0), getattr(prob, "inflow_X", ()),
-                       getattr(prob, "scheme", 0), getattr(prob, "riemann", 0), getattr(prob, "limiter", 0))
+                       getattr(prob, "scheme", 0), getattr(prob, "riemann", 0), getattr(prob, "limiter", 0),
+                       getattr(prob, "steepen", 0))
 
 
 def grow(Uvalid: np.ndarray, fill=np.nan) -> np.ndarray:
@@ -239,13 +245,22 @@ def hllc(L: Sequence[float], R: Sequence[float], d: int, gamma: float) -> np.nda
     return F
 
 
-def ppm_cell(a: Sequence[float], phi: float = 1.0, limiter: int = 0) -> np.ndarray:
+def ppm_cell(a: Sequence[float], phi: float = 1.0, limiter: int = 0, eta: float = 0.0) -> np.ndarray:
     """(aL, aR, da, a6) of the middle cell of a five-cell stencil (limiter 0:
-    CW84, 1: Colella & Sekora 2008)."""
+    CW84, 1: Colella & Sekora 2008; eta: CW84 contact steepening weight)."""
     arr = np.ascontiguousarray(a, dtype=np.float64)
     out = np.zeros(4)
-    (lib().orc_ppm_cell_cs if limiter == 1 else lib().orc_ppm_cell)(_dp(arr), float(phi), _dp(out))
+    if limiter == 1:
+        lib().orc_ppm_cell_cs(_dp(arr), float(phi), _dp(out))
+    else:
+        lib().orc_ppm_cell_steep(_dp(arr), float(phi), float(eta), _dp(out))
     return out
+
+
+def steep_eta(r: Sequence[float], pm: float, pp: float, gamma: float) -> float:
+    """CW84 contact-steepening weight of the middle cell of a density stencil."""
+    arr = np.ascontiguousarray(r, dtype=np.float64)
+    return float(lib().orc_steep_eta(_dp(arr), float(pm), float(pp), float(gamma)))
 
 
 def iplus(aR, da, a6, sig) -> float:

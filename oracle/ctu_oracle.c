@@ -80,7 +80,7 @@ typedef struct {
     int scheme;       /* 0 unsplit CTU/PPM, 1 MOL with SSP-RK2, 2 MOL with SSP-RK3 */
     int riemann;      /* 0 HLLC, 1 two-shock approximate solver */
     int limiter;      /* 0 CW84, 1 Colella & Sekora 2008 extremum-preserving */
-    int pad3;
+    int steepen;      /* 1: CW84 contact steepening of the density (with limiter 0) */
 } orc_params;
 
 static int nvar_of(const orc_params *P) { return 5 + P->nspec; }
@@ -345,9 +345,12 @@ static double ppm_edge(double a0, double a1, double s0, double s1) {
 }
 
 /* Full reconstruction of one cell from the five-cell stencil a[0..4] (cell at
- * a[2]) and flattening coefficient phi: interface values, flattening, CW84
- * monotonicity (eq. 1.10), then the parabola's (aL, aR, da, a6). */
-void orc_ppm_cell(const double a[5], double phi, double out[4]) {
+ * a[2]), flattening coefficient phi and contact-steepening weight eta (0: none;
+ * CW84 section 1.3): interface values, steepening towards the edge values of
+ * the neighbours' linear profiles a[1] + dm a[1] / 2 and a[3] - dm a[3] / 2,
+ * flattening, CW84 monotonicity (eq. 1.10), then the parabola's
+ * (aL, aR, da, a6). */
+static void ppm_cw84(const double a[5], double phi, double eta, double out[4]) {
     const double C6 = 1.0 / 6.0;
     double sm = mc_slope(a[0], a[1], a[2]);
     double s0 = mc_slope(a[1], a[2], a[3]);
@@ -355,6 +358,12 @@ void orc_ppm_cell(const double a[5], double phi, double out[4]) {
     double ai = a[2];
     double aL = ppm_edge(a[1], a[2], sm, s0);
     double aR = ppm_edge(a[2], a[3], s0, sp);
+    if (eta > 0.0) {
+        const double aLd = a[1] + 0.5 * sm;
+        const double aRd = a[3] - 0.5 * sp;
+        aL = aL * (1.0 - eta) + eta * aLd;
+        aR = aR * (1.0 - eta) + eta * aRd;
+    }
     aL = phi * aL + (1.0 - phi) * ai;
     aR = phi * aR + (1.0 - phi) * ai;
     if ((aR - ai) * (ai - aL) <= 0.0) {
@@ -370,6 +379,30 @@ void orc_ppm_cell(const double a[5], double phi, double out[4]) {
     out[2] = aR - aL;
     out[3] = 6.0 * (ai - 0.5 * (aL + aR));
 }
+
+void orc_ppm_cell(const double a[5], double phi, double out[4]) { ppm_cw84(a, phi, 0.0, out); }
+
+/* CW84 contact detection for the density stencil r[0..4] (cell at r[2]) with
+ * the neighbours' pressures pm, pp: with second differences d2 = (r_{+1} -
+ * 2 r + r_{-1}) / 6 of the two neighbours, eta~ = -(d2_{+} - d2_{-}) /
+ * (r[3] - r[1]) where the d2 change sign and the jump exceeds 0.01 of the
+ * smaller neighbour (else 0), eta = clamp(20 (eta~ - 0.05), 0, 1), and 0 unless
+ * the pressure jump is small against the density jump: gamma K0 |r[3] -
+ * r[1]| / min(r[3], r[1]) >= |pp - pm| / min(pp, pm), K0 = 0.1. */
+double orc_steep_eta(const double r[5], double pm, double pp, double gamma) {
+    const double d2m = ((r[2] - 2.0 * r[1]) + r[0]) / 6.0;
+    const double d2p = ((r[4] - 2.0 * r[3]) + r[2]) / 6.0;
+    const double dr = r[3] - r[1];
+    double eta = 0.0;
+    if (d2p * d2m < 0.0 && fabs(dr) - 0.01 * omin(fabs(r[3]), fabs(r[1])) > 0.0) {
+        const double et = -(d2p - d2m) / dr;
+        eta = omax(0.0, omin(20.0 * (et - 0.05), 1.0));
+    }
+    if (gamma * 0.1 * fabs(dr) / omin(r[3], r[1]) < fabs(pp - pm) / omin(pp, pm)) eta = 0.0;
+    return eta;
+}
+
+void orc_ppm_cell_steep(const double a[5], double phi, double eta, double out[4]) { ppm_cw84(a, phi, eta, out); }
 
 /* ------------------------------------- extremum-preserving limiter (f3) */
 
@@ -439,10 +472,20 @@ static void ppm_cell_cs(const double a[5], double phi, double out[4]) {
     out[3] = 6.0 * (ai - 0.5 * (aL + aR));
 }
 
-/* The parabola of the chosen limiter. */
-static void ppm_cell(const double a[5], double phi, int limiter, double out[4]) {
+/* The parabola of the chosen limiter (eta: contact steepening, CW84 only). */
+static void ppm_cell(const double a[5], double phi, int limiter, double eta, double out[4]) {
     if (limiter == 1) ppm_cell_cs(a, phi, out);
-    else orc_ppm_cell(a, phi, out);
+    else ppm_cw84(a, phi, eta, out);
+}
+
+/* Steepening weight of cell (i, j, k) along the unit vector e from the
+ * primitive array q (density comp 0, pressure comp 4). */
+static double steep_eta_at(const double *q, const geom *g, const int e[3], int i, int j, int k, double gamma) {
+    double r[5];
+    for (int s = -2; s <= 2; ++s) r[s + 2] = q[gidx(g, 0, i + s * e[0], j + s * e[1], k + s * e[2])];
+    const double pm = q[gidx(g, 4, i - e[0], j - e[1], k - e[2])];
+    const double pp = q[gidx(g, 4, i + e[0], j + e[1], k + e[2])];
+    return orc_steep_eta(r, pm, pp, gamma);
 }
 
 /* Entry point of the CS08 parabola (pins). */
@@ -637,10 +680,11 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                     e[d] = 1;
                     double par[MAXV][4], a[5];
                     double phi = S.phi[hidx(g, 0, i, j, k)];
+                    const double eta = P->steepen ? steep_eta_at(S.q, g, e, i, j, k, P->gamma) : 0.0;
                     for (int m = 0; m < nv; ++m) {
                         for (int s = -2; s <= 2; ++s)
                             a[s + 2] = S.q[gidx(g, comp[m], i + s * e[0], j + s * e[1], k + s * e[2])];
-                        ppm_cell(a, phi, P->limiter, par[m]);
+                        ppm_cell(a, phi, P->limiter, m == 0 ? eta : 0.0, par[m]);
                     }
                     double rho = S.q[gidx(g, 0, i, j, k)];
                     double un = S.q[gidx(g, 1 + d, i, j, k)];
@@ -863,10 +907,11 @@ int orc_mol_stage(const double *Us, const double *U0, const int n[3], const orc_
                     e[d] = 1;
                     double up[MAXV], dn[MAXV], par[4], a[5];
                     const double ph = phi[hidx(g, 0, i, j, k)];
+                    const double eta = P->steepen ? steep_eta_at(q, g, e, i, j, k, P->gamma) : 0.0;
                     for (int m = 0; m < nv; ++m) {
                         for (int s = -2; s <= 2; ++s)
                             a[s + 2] = q[gidx(g, comp[m], i + s * e[0], j + s * e[1], k + s * e[2])];
-                        ppm_cell(a, ph, P->limiter, par);
+                        ppm_cell(a, ph, P->limiter, m == 0 ? eta : 0.0, par);
                         up[m] = par[1]; /* upper edge: left state of face c+1 */
                         dn[m] = par[0]; /* lower edge: right state of face c */
                     }

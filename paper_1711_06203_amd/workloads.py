@@ -54,6 +54,7 @@ class Problem:
     scheme: int = 0                         # 0 CTU/PPM, 1 MOL + SSP-RK2, 2 MOL + SSP-RK3
     riemann: int = 0                        # 0 HLLC, 1 two-shock approximate solver
     limiter: int = 0                        # 0 CW84, 1 Colella-Sekora extremum-preserving
+    steepen: int = 0                        # 1: CW84 contact steepening of the density
     # two-level problems only
     fine_boxes: Optional[List[Box]] = None   # fine-level index space
     U0_fine: Optional[np.ndarray] = None     # (5, nzf, nyf, nxf) over the fine bounding region
