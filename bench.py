@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--regrid", type=float, default=0.0, metavar="THRESHOLD",
                     help="cloud256: after timing, tag (density jump > THRESHOLD), cluster and regrid once, and "
                          "report the time of each part")
+    ap.add_argument("--steepen", action="store_true", help="CW84 contact steepening of the density")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
@@ -169,9 +170,13 @@ def main():
     if args.limiter != "cw84":
         prob.limiter = ctuppm.LIMITERS[args.limiter]
         wname += f"_{args.limiter}"
+    if args.steepen:
+        prob.steepen = 1
+        wname += "_steepened"
     # key of the stored counter summary of this workload
     tkey = args.workload + (f"s{args.nspec}" if args.nspec else "") + ("" if args.scheme == "ctu" else args.scheme) + (
-        "" if args.riemann == "hllc" else args.riemann) + ("" if args.limiter == "cw84" else args.limiter)
+        "" if args.riemann == "hllc" else args.riemann) + ("" if args.limiter == "cw84" else args.limiter) + (
+        "steep" if args.steepen else "")
     ctx = ctuppm.Context()
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
@@ -253,7 +258,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
-                   "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann, "limiter": args.limiter,
+                   "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann, "limiter": args.limiter, "steepen": bool(args.steepen),
                    "gamma": prob.gamma, "cfl": prob.cfl, "tuning": tuning and {k: tuning[k] for k in
                                                                                ("blocks_per_cu", "zseg", "ytile")}},
         "forms": {k: v for k, v in forms.items()},
@@ -270,7 +275,8 @@ def main():
     del solver
     torch.cuda.empty_cache()
     if (not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64
-            and args.scheme == "ctu" and args.riemann == "hllc" and args.limiter == "cw84"):
+            and args.scheme == "ctu" and args.riemann == "hllc" and args.limiter == "cw84"
+            and not args.steepen):
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

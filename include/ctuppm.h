@@ -99,7 +99,8 @@ typedef struct {
   int scheme;          /* CTUPPM_SCHEME_*; the MOL schemes are single-level */
   int riemann;         /* CTUPPM_RIEMANN_* */
   int limiter;         /* CTUPPM_LIMITER_* */
-  int pad3;
+  int steepen;         /* 1: contact steepening of the density (CW84 section 1.3; with
+                          CTUPPM_LIMITER_CW84 only) */
 } ctuppm_params;
 
 typedef struct ctuppm_ctx ctuppm_ctx;

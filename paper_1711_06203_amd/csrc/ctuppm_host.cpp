@@ -67,7 +67,7 @@ struct StepSet {
   int level = 0;
   int scheme = 0;   // shared by every problem of the set
   int riemann = 0;  // likewise
-  int limiter = 0;  // likewise
+  int limiter = 0;  // likewise (reconstruction variant: 0 CW84, 1 CS, 2 CW84 + steepening)
   int nboxes = 0;
   BoxRec* boxes = nullptr;
   March* units[kNumRegions] = {};
@@ -439,9 +439,10 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     if (ip == 0) {
       S->scheme = P->prm.scheme;
       S->riemann = P->prm.riemann;
-      S->limiter = P->prm.limiter;
+      S->limiter = P->prm.limiter == CTUPPM_LIMITER_CS ? 1 : (P->prm.steepen ? 2 : 0);
     }
-    if (P->prm.scheme != S->scheme || P->prm.riemann != S->riemann || P->prm.limiter != S->limiter)
+    const int var = P->prm.limiter == CTUPPM_LIMITER_CS ? 1 : (P->prm.steepen ? 2 : 0);
+    if (P->prm.scheme != S->scheme || P->prm.riemann != S->riemann || var != S->limiter)
       return fail(c, CTUPPM_EINVAL,
                   "problems stepped together must use the same scheme, Riemann solver and limiter");
     if (level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
@@ -1068,6 +1069,9 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
     return fail(c, CTUPPM_EINVAL, "unknown Riemann solver %d", prm->riemann);
   if (prm->limiter != CTUPPM_LIMITER_CW84 && prm->limiter != CTUPPM_LIMITER_CS)
     return fail(c, CTUPPM_EINVAL, "unknown limiter %d", prm->limiter);
+  if (prm->steepen != 0 && prm->steepen != 1) return fail(c, CTUPPM_EINVAL, "steepen must be 0 or 1");
+  if (prm->steepen && prm->limiter != CTUPPM_LIMITER_CW84)
+    return fail(c, CTUPPM_EINVAL, "contact steepening goes with the CW84 limiter");
   if (prm->scheme != CTUPPM_SCHEME_CTU && nlevels != 1)
     return fail(c, CTUPPM_EINVAL, "the method-of-lines schemes are single-level");
   for (int d = 0; d < 3; ++d) {
@@ -1112,6 +1116,7 @@ int ctuppm_problem_create(ctuppm_ctx* c, const ctuppm_params* prm, int nlevels, 
   h.scheme = prm->scheme;
   h.riemann = prm->riemann;
   h.limiter = prm->limiter;
+  h.steepen = prm->steepen;
   h.fail_step = -1;
   HIPCHK(c, hipMalloc((void**)&P->dP, sizeof(ProbDev)));
   HIPCHK(c, hipMemcpy(P->dP, &h, sizeof(ProbDev), hipMemcpyHostToDevice));

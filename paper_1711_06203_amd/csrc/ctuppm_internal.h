@@ -51,6 +51,8 @@ struct ProbDev {
   int scheme;                      // 0 CTU, 1 MOL + SSP-RK2, 2 MOL + SSP-RK3
   int riemann;                     // 0 HLLC, 1 two-shock
   int limiter;                     // 0 CW84, 1 Colella & Sekora
+  int steepen;                     // CW84 contact steepening of the density
+  int pad4;
   // running max of the signal speed as bit patterns (>= 0), one 128-byte
   // line per slot so blocks of one launch do not contend on one address
   unsigned long long smax[kSlots][16];
@@ -171,7 +173,7 @@ struct Launch {
   double c = 0.0;      // its weight
   int last = 1;        // MOL update: the step's last stage (test hook applies)
   int rs = 0;          // Riemann solver of the flux stages: 0 HLLC, 1 two-shock
-  int lim = 0;         // PPM limiter of the reconstruction stages: 0 CW84, 1 Colella & Sekora
+  int lim = 0;         // reconstruction variant: 0 CW84, 1 Colella & Sekora, 2 CW84 + contact steepening
 };
 
 hipError_t launch_stage(int stage, const Launch& L);

@@ -357,11 +357,17 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
       const int x[3] = {i, j, k};
       const int o = g.g(i, j, k), oh = g.h(i, j, k);
       const double phi = phiv[oh];
+      double eta = 0.0;
+      if (LIM & 2) {  // contact steepening weight from the density and the neighbours' pressures
+        const gdbl* r = q + o;
+        const gdbl* pr = q + 4 * g.gcomp + o;
+        eta = steep_eta(r[-2 * st], r[-st], r[0], r[st], r[2 * st], pr[-st], pr[st], P->gamma);
+      }
       Parab par[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const gdbl* a = q + comp[m] * g.gcomp + o;
-        par[m] = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+        par[m] = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, m == 0 ? eta : 0.0);
       }
       const double rho = q[o], un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
       if (x[D] <= nD - 1) {
@@ -690,11 +696,17 @@ __global__ __launch_bounds__(kBlock) void k_recon(const BoxRec* __restrict__ box
       const int x[3] = {i, j, k};
       const int o = g.g(i, j, k), oh = g.h(i, j, k);
       const double phi = phiv[oh];
+      double eta = 0.0;
+      if (LIM & 2) {
+        const gdbl* r = q + o;
+        const gdbl* pr = q + 4 * g.gcomp + o;
+        eta = steep_eta(r[-2 * st], r[-st], r[0], r[st], r[2 * st], pr[-st], pr[st], P->gamma);
+      }
       double up[5], dn[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         const gdbl* a = q + comp[m] * g.gcomp + o;
-        const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+        const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, m == 0 ? eta : 0.0);
         up[m] = par.aR;
         dn[m] = par.aL;
       }
@@ -1064,8 +1076,10 @@ hipError_t launch_stage(int stage, const Launch& L) {
   const March* mu = (const March*)L.work;
   const int n = L.nwork;
   hipStream_t s = L.stream;
-#define CTU_LIM(K, D) \
-  (L.lim ? K<D, 1><<<grid, block, 0, s>>>(L.boxes, mu, n) : K<D, 0><<<grid, block, 0, s>>>(L.boxes, mu, n))
+#define CTU_LIM(K, D)                                                                  \
+  (L.lim == 1   ? K<D, 1><<<grid, block, 0, s>>>(L.boxes, mu, n)                        \
+   : L.lim == 2 ? K<D, 2><<<grid, block, 0, s>>>(L.boxes, mu, n)                        \
+                : K<D, 0><<<grid, block, 0, s>>>(L.boxes, mu, n))
   switch (stage) {
     case kStFill: k_fill<<<grid, block, 0, s>>>(L.boxes, (const FillTag*)L.tags, ch, n, L.arr); break;
     case kStBcX: k_bc<0><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;

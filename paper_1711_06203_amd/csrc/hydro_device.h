@@ -36,13 +36,22 @@ CTU_DEV double mc_slope(double am, double a0, double ap) {
 // monotonicity; returns (aL, aR, da, a6).
 struct Parab { double aL, aR, da, a6; };
 
-CTU_DEV Parab ppm(double s0, double s1, double s2, double s3, double s4, double phi) {
+// With eta > 0 (contact steepening, CW84 section 1.3) the interface values
+// first move towards the edge values of the neighbours' linear profiles,
+// s1 + dl/2 and s3 - dr/2, by the weight eta.
+CTU_DEV Parab ppm(double s0, double s1, double s2, double s3, double s4, double phi, double eta = 0.0) {
   const double C6 = 1.0 / 6.0;
   const double dl = mc_slope(s0, s1, s2);
   const double dcen = mc_slope(s1, s2, s3);
   const double dr = mc_slope(s2, s3, s4);
   double aL = 0.5 * (s1 + s2) - C6 * (dcen - dl);
   double aR = 0.5 * (s2 + s3) - C6 * (dr - dcen);
+  if (eta > 0.0) {
+    const double aLd = s1 + 0.5 * dl;
+    const double aRd = s3 - 0.5 * dr;
+    aL = aL * (1.0 - eta) + eta * aLd;
+    aR = aR * (1.0 - eta) + eta * aRd;
+  }
   aL = phi * aL + (1.0 - phi) * s2;
   aR = phi * aR + (1.0 - phi) * s2;
   if ((aR - s2) * (s2 - aL) <= 0.0) {
@@ -122,11 +131,33 @@ CTU_DEV Parab ppm_cs(double s0, double s1, double s2, double s3, double s4, doub
   return p;
 }
 
-// The parabola of limiter LIM (0 CW84, 1 Colella & Sekora).
-template <int LIM>
-CTU_DEV Parab ppm_l(double s0, double s1, double s2, double s3, double s4, double phi) {
-  if (LIM == 1) return ppm_cs(s0, s1, s2, s3, s4, phi);
+// The parabola of reconstruction variant V: bit 0 the limiter (0 CW84, 1
+// Colella & Sekora); bit 1 contact steepening with weight eta (CW84 only).
+template <int V>
+CTU_DEV Parab ppm_l(double s0, double s1, double s2, double s3, double s4, double phi, double eta = 0.0) {
+  if (V & 1) return ppm_cs(s0, s1, s2, s3, s4, phi);
+  if (V & 2) return ppm(s0, s1, s2, s3, s4, phi, eta);
   return ppm(s0, s1, s2, s3, s4, phi);
+}
+
+// CW84 contact detector of a density stencil r0..r4 with the neighbours'
+// pressures pm, pp: eta~ = -(d2+ - d2-) / (r3 - r1) from the neighbours'
+// second differences d2 = (r+1 - 2 r + r-1)/6 where they change sign and the
+// jump exceeds 0.01 of the smaller neighbour; eta = clamp(20 (eta~ - 0.05),
+// 0, 1); zero unless gamma K0 |r3 - r1| / min(r3, r1) >= |pp - pm| / min(pp,
+// pm) with K0 = 0.1 (the pressure jump is small against the density jump).
+CTU_DEV double steep_eta(double r0, double r1, double r2, double r3, double r4, double pm, double pp,
+                         double gamma) {
+  const double d2m = ((r2 - 2.0 * r1) + r0) / 6.0;
+  const double d2p = ((r4 - 2.0 * r3) + r2) / 6.0;
+  const double dr = r3 - r1;
+  double eta = 0.0;
+  if (d2p * d2m < 0.0 && fabs(dr) - 0.01 * dmin(fabs(r3), fabs(r1)) > 0.0) {
+    const double et = -(d2p - d2m) / dr;
+    eta = dmax(0.0, dmin(20.0 * (et - 0.05), 1.0));
+  }
+  if (gamma * 0.1 * fabs(dr) / dmin(r3, r1) < fabs(pp - pm) / dmin(pp, pm)) eta = 0.0;
+  return eta;
 }
 
 // Averages of the parabola over the last sig of the cell (towards its right

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3), ("inflow", ctypes.c_double * 5),
                 ("nspec", ctypes.c_int), ("pad", ctypes.c_int), ("inflow_X", ctypes.c_double * 16),
                 ("scheme", ctypes.c_int), ("riemann", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("pad3", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("steepen", ctypes.c_int)]
 
 
 _lib = None
@@ -163,7 +163,7 @@ class Context:
         f = FORMS[form] if isinstance(form, str) else int(form)
         groups: Dict[tuple, List[int]] = {}
         for s in solvers:
-            key = (scheme_id(s.prob), riemann_id(s.prob), limiter_id(s.prob))
+            key = (scheme_id(s.prob), riemann_id(s.prob), limiter_id(s.prob), int(s.prob.steepen))
             groups.setdefault(key, []).append(s.pid)
         sets = [(ctypes.c_int * len(v))(*v) for _, v in sorted(groups.items())]
         for _ in range(nsteps):
@@ -220,6 +220,7 @@ def _params(prob: W.Problem) -> Params:
     P.scheme = scheme_id(prob)
     P.riemann = riemann_id(prob)
     P.limiter = limiter_id(prob)
+    P.steepen = int(prob.steepen)
     for s, x in enumerate(prob.inflow_X):
         P.inflow_X[s] = x
     return P
