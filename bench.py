@@ -107,6 +107,8 @@ def main():
                     help="cloud256: after timing, tag (density jump > THRESHOLD), cluster and regrid once, and "
                          "report the time of each part")
     ap.add_argument("--steepen", action="store_true", help="CW84 contact steepening of the density")
+    ap.add_argument("--concurrent-graph", action="store_true",
+                    help="graph form with the three directions of each phase on three streams (default: one chain)")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
     ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
@@ -178,6 +180,8 @@ def main():
         "" if args.riemann == "hllc" else args.riemann) + ("" if args.limiter == "cw84" else args.limiter) + (
         "steep" if args.steepen else "")
     ctx = ctuppm.Context()
+    if args.concurrent_graph:
+        ctx.set_concurrency(True)
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
     # zone-updates per step: the fine level takes two substeps per coarse step
@@ -259,7 +263,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
                    "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann, "limiter": args.limiter, "steepen": bool(args.steepen),
-                   "gamma": prob.gamma, "cfl": prob.cfl, "tuning": tuning and {k: tuning[k] for k in
+                   "gamma": prob.gamma, "cfl": prob.cfl, "concurrent_graph": bool(args.concurrent_graph), "tuning": tuning and {k: tuning[k] for k in
                                                                                ("blocks_per_cu", "zseg", "ytile")}},
         "forms": {k: v for k, v in forms.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

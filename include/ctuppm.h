@@ -231,6 +231,14 @@ int ctuppm_cluster(const unsigned char* tags, const int n[3], int blocking, doub
 int ctuppm_regrid(ctuppm_ctx* ctx, int pid, const ctuppm_box* fine_boxes, int nfine, double* const* Ua,
                   double* const* Ub);
 
+/* Graph form of single-level CTU steps: on, the captured step runs the three
+ * directions of each phase (tracing + normal flux, first and second
+ * transverse stage) on three streams, so the graph executes them
+ * concurrently; off (default), one chain, which measures faster on the 256^3
+ * workloads (the concurrent kernels share L2).  Results are the same either
+ * way (each kernel writes its own arrays); graphs are re-captured. */
+int ctuppm_set_concurrency(ctuppm_ctx* ctx, int on);
+
 /* Tuning of the launches: blocks per CU of the persistent batched launches
  * (0 = one block per work unit), and the z planes one work unit marches
  * through in the batched/graph forms and in the per-box form (>= 1).  Results

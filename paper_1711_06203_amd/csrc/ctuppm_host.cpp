@@ -129,6 +129,9 @@ struct TimedLaunch {
 struct ctuppm_ctx {
   hipStream_t stream = nullptr;
   hipStream_t capture = nullptr;
+  hipStream_t side[2] = {nullptr, nullptr};  // extra capture streams for the direction branches
+  hipEvent_t fj[12] = {};                      // fork / join events of a captured step
+  int concurrent = 0;                          // graphs run the three directions concurrently
   std::string err;
   std::map<int, std::unique_ptr<Problem>> probs;
   int next_id = 1;
@@ -718,6 +721,50 @@ int enqueue_mol(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
   return CTUPPM_OK;
 }
 
+// Fork the two side streams off s (event slot k), and join them back.
+int fork_side(ctuppm_ctx* c, hipStream_t s, int k) {
+  HIPCHK(c, hipEventRecord(c->fj[k], s));
+  for (auto& st : c->side) HIPCHK(c, hipStreamWaitEvent(st, c->fj[k], 0));
+  return CTUPPM_OK;
+}
+int join_side(ctuppm_ctx* c, hipStream_t s, int k) {
+  for (int i = 0; i < 2; ++i) {
+    HIPCHK(c, hipEventRecord(c->fj[k + i], c->side[i]));
+    HIPCHK(c, hipStreamWaitEvent(s, c->fj[k + i], 0));
+  }
+  return CTUPPM_OK;
+}
+
+// A CTU step of a set for graph capture, with the three directions of each
+// phase on three streams: tracing and normal fluxes of x, y, z; the first
+// transverse stage of x, y, z; the second of x, y, z.  Each phase reads only
+// what the previous phases wrote, so the captured graph runs the directions
+// concurrently (a tracing kernel's arithmetic overlaps another direction's
+// memory traffic, and kernel tails overlap).
+int enqueue_step_branched(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
+  int rc;
+  if ((rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks, S->nfch, true, false))) return rc;
+  for (int d = 0; d < 3; ++d)
+    if ((rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d], S->nbch[d], true, false))) return rc;
+  if ((rc = run_cells(c, S, s, kStC2P, -1, false))) return rc;
+  hipError_t e = launch_dt(S->probs, S->nprobs, s);
+  if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "dt launch: %s", hipGetErrorString(e));
+  if ((rc = run_cells(c, S, s, kStFlatten, -1, false))) return rc;
+  const hipStream_t str[3] = {s, c->side[0], c->side[1]};
+  const int phases[3][2] = {{kStTraceX, kStRiemX}, {kStT1X, -1}, {kStT2X, -1}};
+  for (int ph = 0; ph < 3; ++ph) {
+    if ((rc = fork_side(c, s, 3 * ph))) return rc;
+    for (int d = 0; d < 3; ++d)
+      for (int q = 0; q < 2; ++q)
+        if (phases[ph][q] >= 0 && (rc = run_cells(c, S, str[d], phases[ph][q] + d, -1, false))) return rc;
+    if ((rc = join_side(c, s, 3 * ph + 1))) return rc;
+  }
+  if ((rc = run_cells(c, S, s, kStUpdate, -1, false))) return rc;
+  e = launch_flip(S->probs, S->nprobs, s);
+  if (e != hipSuccess) return fail(c, CTUPPM_EHIP, "flip launch: %s", hipGetErrorString(e));
+  return CTUPPM_OK;
+}
+
 // Enqueue one step of a set on stream s.
 int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
   if (S->scheme != 0) return enqueue_mol(c, S, s, timed);
@@ -1018,6 +1065,10 @@ int ctuppm_ctx_create(void* hip_stream, ctuppm_ctx** out) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
     c->num_cus = cus;
   if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) return CTUPPM_EHIP;
+  for (auto& st : c->side)
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return CTUPPM_EHIP;
+  for (auto& e : c->fj)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return CTUPPM_EHIP;
   *out = c.release();
   return CTUPPM_OK;
 }
@@ -1038,6 +1089,10 @@ int ctuppm_ctx_destroy(ctuppm_ctx* c) {
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   if (c->capture) (void)hipStreamDestroy(c->capture);
+  for (auto& st : c->side)
+    if (st) (void)hipStreamDestroy(st);
+  for (auto& e : c->fj)
+    if (e) (void)hipEventDestroy(e);
   delete c;
   return CTUPPM_OK;
 }
@@ -1232,7 +1287,8 @@ int ctuppm_step(ctuppm_ctx* c, const int* pids, int npids, int form) {
   if (form == CTUPPM_FORM_GRAPH) {
     if (!S->exec) {
       HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_step(c, S, c->capture, false);
+      rc = (c->concurrent && S->scheme == 0) ? enqueue_step_branched(c, S, c->capture)
+                                             : enqueue_step(c, S, c->capture, false);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(c->capture, &g);
       if (rc) {
@@ -1516,6 +1572,20 @@ int ctuppm_regrid(ctuppm_ctx* c, int pid, const ctuppm_box* fine_boxes, int nfin
     P->clo[d] = clo[d];
     P->chi[d] = chi[d];
   }
+  return CTUPPM_OK;
+}
+
+int ctuppm_set_concurrency(ctuppm_ctx* c, int on) {
+  if (!c) return CTUPPM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->concurrent = on ? 1 : 0;
+  for (auto& kv : c->sets)  // graphs are re-captured
+    if (kv.second->exec) {
+      (void)hipGraphExecDestroy(kv.second->exec);
+      (void)hipGraphDestroy(kv.second->graph);
+      kv.second->exec = nullptr;
+      kv.second->graph = nullptr;
+    }
   return CTUPPM_OK;
 }
 

@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
             "ctuppm_set_fail_hook": [vp, ctypes.c_int, ctypes.c_int],
             "ctuppm_last_error": [vp],
             "ctuppm_tag": [vp, ctypes.c_int, ctypes.c_double, vp],
+            "ctuppm_set_concurrency": [vp, ctypes.c_int],
             "ctuppm_cluster": [vp, ip, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Box), ctypes.c_int,
                                ip],
             "ctuppm_regrid": [vp, ctypes.c_int, ctypes.POINTER(Box), ctypes.c_int, ctypes.POINTER(vp),
@@ -107,7 +108,8 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_bind_workspace", "ctuppm_set_fixed_dt", "ctuppm_step", "ctuppm_current_state",
             "ctuppm_get_dt", "ctuppm_status", "ctuppm_set_timing", "ctuppm_stage_times", "ctuppm_num_stages",
             "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning", "ctuppm_step_checked",
-            "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid"]
+            "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid",
+            "ctuppm_set_concurrency"]
 
 
 class Context:
@@ -153,6 +155,10 @@ class Context:
         cnt = (ctypes.c_longlong * n)()
         self.call("ctuppm_stage_times", ms, cnt, n)
         return {self._L.ctuppm_stage_name(s).decode(): (ms[s], cnt[s]) for s in range(n)}
+
+    def set_concurrency(self, on: bool):
+        """Graph form: run the three directions of each phase concurrently (default off)."""
+        self.call("ctuppm_set_concurrency", int(bool(on)))
 
     def set_tuning(self, blocks_per_cu: int = 0, zseg_batched: int = 1, zseg_per_box: int = 1, ytile: int = 0):
         self.call("ctuppm_set_tuning2", int(blocks_per_cu), int(zseg_batched), int(zseg_per_box), int(ytile))

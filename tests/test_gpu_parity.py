@@ -146,3 +146,21 @@ def test_retry_equals_explicit_half_steps(ctx):
     want = b.state()
     b.close()
     assert np.array_equal(got, want)
+
+
+def test_concurrent_graph_equals_serial_graph(ctx):
+    """The graph form with the three directions on three streams gives the
+    same bits as the single-chain graph and as the batched form."""
+    from paper_1711_06203_amd import ctuppm
+    probs = [W.kelvin_helmholtz(n=(40, 36, 20), box=(16, 16, 20), nspec=1), W.serving_request(seed=31, n=24)]
+    out = {}
+    for mode in ("serial", "concurrent", "batched"):
+        ctx.set_concurrency(mode == "concurrent")
+        solvers = [ctuppm.Solver(ctx, p) for p in probs]
+        ctx.step(solvers, "batched" if mode == "batched" else "graph", 6)
+        out[mode] = [s.state() for s in solvers]
+        for s in solvers:
+            s.close()
+    ctx.set_concurrency(False)
+    for a, b, c in zip(out["serial"], out["concurrent"], out["batched"]):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
