@@ -163,3 +163,47 @@ def test_kh256_cs_limiter_one_step_sampled(ctx):
     prob = W.kelvin_helmholtz(n=256, box=64)
     prob.limiter = 1
     _sampled(ctx, prob, 150, 6)
+
+
+@pytest.mark.slow
+def test_kh256_steepened_one_step_sampled(ctx):
+    prob = W.kelvin_helmholtz(n=256, box=64)
+    prob.steepen = 1
+    _sampled(ctx, prob, 150, 7)
+
+
+@pytest.mark.slow
+def test_cloud256_tags_and_regrid_sampled(ctx):
+    """Full-size two-level cloud: tags of the initial coarse state equal the
+    oracle's, and a regrid onto a larger patch gives, at sampled fine cells,
+    the old fine value inside the old patch and the oracle's coarse-to-fine
+    interpolation outside it."""
+    from paper_1711_06203_amd import ctuppm, regrid
+    prob = W.cloud_wind(n=256, box=64, fine_box=32)
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    P = oracle.params_of(prob)
+    tg = s.tag(0.05)
+    assert np.array_equal(tg, oracle.tag_cells(prob.U0, P, 0.05))
+    patch = ((70, 60, 64), (185, 190, 170))
+    s.regrid(regrid.fine_boxes(patch, 32))
+    got = s.state_fine()
+    s.step(1)
+    cnt = s.counters()
+    s.close()
+    ctx.torch.cuda.empty_cache()
+    assert not cnt[:5].any()
+    flo = np.array([2 * v for v in patch[0]])
+    fn = np.array([2 * (patch[1][d] - patch[0][d] + 1) for d in range(3)])
+    olo = np.array(prob.fine_lo)
+    on = np.array(prob.U0_fine.shape[1:][::-1])
+    rng = np.random.default_rng(9)
+    cells = [flo + rng.integers(fn) for _ in range(300)] + [flo, flo + fn - 1, olo, olo + on - 1, olo - 1, olo + on]
+    cells = [I for I in cells if np.all(I >= flo) and np.all(I < flo + fn)]  # inside the new patch
+    assert len(cells) >= 300
+    for I in cells:
+        g = got[:, I[2] - flo[2], I[1] - flo[1], I[0] - flo[0]]
+        if np.all(I >= olo) and np.all(I < olo + on):
+            w = prob.U0_fine[:, I[2] - olo[2], I[1] - olo[1], I[0] - olo[0]]
+        else:
+            w = oracle.cf_interp(prob.U0, (0, 0, 0), I[None, :])[:, 0]
+        assert np.array_equal(g, w), (I, g, w)

@@ -133,11 +133,10 @@ def test_retry_equals_explicit_half_steps(ctx):
     a.close()
     b = ctuppm.Solver(ctx, prob, form="batched")
     b.step(2)
-    dt2 = None
-    ref_state = b.state()
-    # dt of step 2 from the state after two steps, by the oracle's CFL rule
+    # dt of step 2: the oracle's CFL rule on its own state after two steps
     P = oracle.params_of(prob)
-    G = oracle.fill_domain(oracle.grow(ref_state), P)
+    U2, _, _ = oracle.run(prob.U0, P, 2)
+    G = oracle.fill_domain(oracle.grow(U2), P)
     dt2 = P.cfl / oracle.signal_speed(G, P)
     ctx.call("ctuppm_set_fixed_dt", b.pid, 0.5 * dt2)
     b.step(2)

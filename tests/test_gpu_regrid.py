@@ -37,9 +37,11 @@ def test_tags_equal_the_oracle(ctx):
     s = ctuppm.Solver(ctx, prob)
     s.step(3)
     got_state = s.state()
+    ref, _, _ = oracle.run_problem(prob, 3)  # the oracle's own state after three steps
+    _check(got_state, ref)
     for thr in (0.01, 0.05, 0.2):
         tg = s.tag(thr)
-        to = oracle.tag_cells(got_state, oracle.params_of(prob), thr)
+        to = oracle.tag_cells(ref, oracle.params_of(prob), thr)
         assert np.array_equal(tg, to), thr
         assert tg.any()
     assert np.array_equal(s.state(), got_state)  # tagging leaves the valid cells alone
