@@ -53,6 +53,14 @@ def test_kh256_one_step_sampled(ctx):
 
 
 @pytest.mark.slow
+def test_largest_box_edge_one_box_256_sampled(ctx):
+    """The whole 256^3 KH domain as one box, the largest edge accepted."""
+    prob = W.kelvin_helmholtz(n=256, box=256)
+    assert len(prob.boxes) == 1
+    _sampled(ctx, prob, 200, 11)
+
+
+@pytest.mark.slow
 def test_rt384_uneven_one_step_sampled(ctx):
     prob = W.rayleigh_taylor(n=384)
     assert len(prob.boxes) > 500
