@@ -9,7 +9,8 @@ conservative update.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line with the metric, the per-box and batched forms beside
 the graph form, the roofline of the dominant kernel (algorithmic bytes per
-launch over its event-timed average duration, against 8 TB/s) and the CPU
+launch over its event-timed average duration, against 8 TB/s, with what a
+plain copy, reduction and fill reach in the same run beside it) and the CPU
 oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -56,6 +57,32 @@ def measured_traffic(kernel: str, workload: str):
         return None
     v = vals.get(f"bytes_per_launch[{kernel}]")
     return float(v) if v else None
+
+
+def attainable_bandwidth(torch, gib: int = 2) -> dict:
+    """What plain streaming kernels reach on this GPU in the same run: a device
+    copy, a full reduction (read) and a fill (write) over `gib` GiB of FP64,
+    10 launches each, timed with events on the current stream."""
+    n = (gib << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, moved in (("copy", lambda: b.copy_(a), 2 * n * 8), ("read", lambda: a.sum(), n * 8),
+                            ("write", lambda: b.fill_(1.0), n * 8)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name] = moved / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    out["unit"] = "GB/s"
+    out["how"] = f"torch copy_ / sum / fill_ over {gib} GiB FP64, 10 launches each, HIP events"
+    return out
 
 
 def cpu_baseline(prob, seconds: float = 12.0):
@@ -278,6 +305,9 @@ def main():
     ctx.close()
     del solver
     torch.cuda.empty_cache()
+    att = attainable_bandwidth(torch)
+    out["roofline"]["attainable"] = att
+    out["roofline"]["frac_of_copy"] = achieved / att["copy"]
     if (not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64
             and args.scheme == "ctu" and args.riemann == "hllc" and args.limiter == "cw84"
             and not args.steepen):

@@ -42,6 +42,9 @@ struct ProbDev {
   double dx[3], rdx[3];
   double fixed_dt;                 // > 0: use this dt instead of the CFL one
   double dt;                       // dt of the current/last step
+  // per-direction factors of that dt, set with it once per step so no thread
+  // divides: dt/dx_d, (dt/dx_d)/3 (transverse stage 1), (dt/dx_d)/2 (stage 2)
+  double dtdx[3], dt3dx[3], dt2dx[3];
   unsigned long long cnt[5];       // dens floor, pres floor, traced floors, transverse fall-backs, failures
   int cur;                         // which of U[0], U[1] holds the current state
   int nsteps;

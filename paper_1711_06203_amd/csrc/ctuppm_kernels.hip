@@ -258,6 +258,18 @@ __global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes
   if (CFL && curP) flush_max(curP, smax, lds);
 }
 
+// The step's dt and its per-direction factors (the same roundings as writing
+// them out where they are used).
+CTU_DEV void set_dt(ProbDev* P, double dt) {
+  P->dt = dt;
+  for (int d = 0; d < 3; ++d) {
+    const double r = dt / P->dx[d];
+    P->dtdx[d] = r;
+    P->dt3dx[d] = r / 3.0;
+    P->dt2dx[d] = 0.5 * r;
+  }
+}
+
 __global__ void k_dt(ProbDev* const* probs, int nprobs) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nprobs) return;
@@ -268,7 +280,7 @@ __global__ void k_dt(ProbDev* const* probs, int nprobs) {
     P->smax[q][0] = 0ull;
   }
   const double s = __longlong_as_double((long long)bits);
-  P->dt = P->fixed_dt > 0.0 ? P->fixed_dt : P->cfl / s;
+  set_dt(P, P->fixed_dt > 0.0 ? P->fixed_dt : P->cfl / s);
 }
 
 __global__ void k_flip(ProbDev* const* probs, int nprobs) {
@@ -347,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
     gdbl* __restrict__ ql = g.ql(B.scr, D);
     gdbl* __restrict__ qr = g.qr(B.scr, D);
     const int st = g.gstride(D), sth = g.hstride(D);
-    const double dtdx = P->dt / P->dx[D];
+    const double dtdx = P->dtdx[D];
     const double hdtg = 0.5 * P->dt * P->grav_z;
     const bool grav = P->grav_z != 0.0;
     const double sd = P->small_dens, sp = P->small_pres;
@@ -493,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
       for (int which = 0; which < 2; ++which) {
         const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
         if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
-        const double c3 = (P->dt / P->dx[Bd]) / 3.0;
+        const double c3 = P->dt3dx[Bd];
         const int sb = g.hstride(Bd);
         const gdbl* __restrict__ Fb = g.fn(B.scr, Bd);
         double VL[5], VR[5], tL[5], tR[5], f[5];
@@ -542,8 +554,8 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
   const gdbl* __restrict__ qr = g.qr(B.scr, A);
   const gdbl* __restrict__ Fbc = g.f1(B.scr, pbc);
   const gdbl* __restrict__ Fcb = g.f1(B.scr, pcb);
-  const double c2b = 0.5 * (P->dt / P->dx[Bd]);
-  const double c2c = 0.5 * (P->dt / P->dx[Cd]);
+  const double c2b = P->dt2dx[Bd];
+  const double c2c = P->dt2dx[Cd];
   double sL[5], sR[5], UL[5], UR[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -616,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
     const gdbl* __restrict__ Fx = g.ff(B.scr, 0);
     const gdbl* __restrict__ Fy = g.ff(B.scr, 1);
     const gdbl* __restrict__ Fz = g.ff(B.scr, 2);
-    const double dtdx = P->dt / P->dx[0], dtdy = P->dt / P->dx[1], dtdz = P->dt / P->dx[2];
+    const double dtdx = P->dtdx[0], dtdy = P->dtdx[1], dtdz = P->dtdx[2];
     const bool grav = P->grav_z != 0.0;
     const double hdtg = 0.5 * P->dt * P->grav_z;
     const bool forced = P->fail_step == P->nsteps;
@@ -752,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void k_mol_update(const BoxRec* __restrict_
     const gdbl* __restrict__ Fx = g.fn(B.scr, 0);
     const gdbl* __restrict__ Fy = g.fn(B.scr, 1);
     const gdbl* __restrict__ Fz = g.fn(B.scr, 2);
-    const double dtdx = P->dt / P->dx[0], dtdy = P->dt / P->dx[1], dtdz = P->dt / P->dx[2];
+    const double dtdx = P->dtdx[0], dtdy = P->dtdx[1], dtdz = P->dtdx[2];
     const bool grav = P->grav_z != 0.0;
     const double dtg = P->dt * P->grav_z;
     const bool forced = last && P->fail_step == P->nsteps;
@@ -1052,8 +1064,8 @@ __global__ void k_dt2(ProbDev* Pc, ProbDev* Pf) {
   const double a = Pc->cfl / __longlong_as_double((long long)bc);
   const double b = 2.0 * (Pc->cfl / __longlong_as_double((long long)bf));
   const double dt = Pc->fixed_dt > 0.0 ? Pc->fixed_dt : (a < b ? a : b);
-  Pc->dt = dt;
-  Pf->dt = 0.5 * dt;
+  set_dt(Pc, dt);
+  set_dt(Pf, 0.5 * dt);
 }
 
 }  // namespace
