@@ -3,7 +3,7 @@
 Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It loads ``liboracle.so``, compiled from
 ``ctu_oracle.c`` (plain C, gcc -O2 -fopenmp -ffp-contract=off), which shares
-no code with the HIP path.  The two-level driver of the method (coarse
+no code with the HIP path.  The two-level step of the method (coarse
 advance, two fine substeps, average down, reflux; section 3.2) is written here
 in numpy on top of the C box advance.
 

@@ -1,6 +1,6 @@
 """Parity of the HIP path with the oracle for the extremum-preserving PPM
 limiter (Colella & Sekora 2008), alone and with the two-shock solver, in the
-CTU and MOL schemes and on two levels.  Tolerances as elsewhere; the build
+CTU and MOL schemes and on two levels.  Tolerances as elsewhere; the HIP path
 aims at bitwise equality and the tests report it."""
 import numpy as np
 import pytest

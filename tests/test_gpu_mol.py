@@ -3,7 +3,7 @@
 The method-of-lines formulation is the one of the paper's GPU proxy (section
 4).  Tolerances as for the CTU path: smooth inputs per-field max relative
 <= 1e-10, discontinuous inputs per-field L1 relative <= 1e-8, totals <= 1e-13;
-the build aims at bitwise equality and the tests report the largest
+the HIP path aims at bitwise equality and the tests report the largest
 difference seen.
 """
 import numpy as np

@@ -2,7 +2,7 @@
 
 Tolerances: smooth inputs after 10 steps, per-field max|g-o|/max|o| <= 1e-10;
 inputs with shocks or contacts, per-field L1 relative <= 1e-8; conserved
-totals <= 1e-13 relative; floor and failure counters equal (zero).  The build
+totals <= 1e-13 relative; floor and failure counters equal (zero).  The HIP path
 aims at bitwise equality (no contraction on either side); the tests report
 the largest difference seen.
 """

@@ -4,7 +4,7 @@ Species (mass fractions X_s, conserved rho X_s after rho E) are advected with
 the flow: traced and limited like the other primitives, carried by the
 contact family and by the HLLC star state (section 4: the GPU proxy advects
 13 species with the hydrodynamics).  Tolerances as for the hydro fields:
-discontinuous inputs per-field L1 relative <= 1e-8, totals <= 1e-13; the build
+discontinuous inputs per-field L1 relative <= 1e-8, totals <= 1e-13; the HIP path
 aims at bitwise equality and the tests report the largest difference.
 """
 import numpy as np

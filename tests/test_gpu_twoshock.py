@@ -1,7 +1,7 @@
 """Parity of the HIP path with the oracle for the two-shock Riemann solver
 (Colella 1982; Colella & Glaz 1985), in the CTU and MOL schemes, one and two
 levels.  Tolerances as elsewhere (L1 1e-8 on discontinuous inputs, totals
-1e-13); the build aims at bitwise equality and the tests report it."""
+1e-13); the HIP path aims at bitwise equality and the tests report it."""
 import numpy as np
 import pytest
 
