@@ -166,6 +166,59 @@ int ctuppm_step_checked(ctuppm_ctx* ctx, int pid, int form, int* retried);
  * every kernel still runs to completion. */
 int ctuppm_set_fail_hook(ctuppm_ctx* ctx, int pid, int step_index);
 
+/* ------------------------------------------------------- a step in pieces
+ * The paper states the problem a level at a time: fill the ghost cells of
+ * every box, take dt from the CFL condition, advance each level with its
+ * ghosts filled, then synchronise the levels -- average the fine level down
+ * and reflux the coarse cells beside it (sections 3 and 3.2).  These calls
+ * take one CTU step in those pieces, for callers that put their own work
+ * between them (a dt reduced over several problems or devices, their own
+ * boundary data, diagnostics).  Taken in the order below they give bitwise
+ * the state ctuppm_step gives:
+ *   single level:  fill_ghosts(0), compute_dt, advance_level(0)
+ *   two levels:    fill_ghosts(0), compute_dt, advance_level(0),
+ *                  { fill_ghosts(1), advance_level(1) } twice,
+ *                  average_down, reflux
+ * `form` is CTUPPM_FORM_PER_BOX or CTUPPM_FORM_BATCHED (two-level problems:
+ * batched only); the graph form is ctuppm_step's.  The CTU scheme only (the
+ * method-of-lines schemes fill ghosts inside their Runge-Kutta stages:
+ * CTUPPM_EINVAL).  All calls are asynchronous on the context stream.  Calls
+ * out of order return CTUPPM_ESTATE and enqueue nothing: advancing a level
+ * whose current state has changed since its ghosts were filled, advancing
+ * level 0 with no dt, a fine substep before the coarse advance or a third
+ * one, averaging down before the second fine substep, refluxing before
+ * averaging down; ctuppm_step, ctuppm_tag and ctuppm_regrid on a problem in
+ * the middle of such a step. */
+
+/* Ghost cells of level `level`'s current state: same-level copies (periodic
+ * images included) and physical boundaries; on level 1 also the cells outside
+ * the fine rectangle, interpolated from level 0 at the substep's time (after
+ * the coarse advance: time fraction 0, then 1/2). */
+int ctuppm_fill_ghosts(ctuppm_ctx* ctx, int pid, int level, int form);
+/* dt of the next step from the CFL condition over the valid cells of every
+ * level (two levels: the smaller of the coarse dt and twice the fine dt), or
+ * the fixed dt; kept for the next advance and, when dt_dev is not NULL,
+ * written to the device double *dt_dev. */
+int ctuppm_compute_dt(ctuppm_ctx* ctx, int pid, int form, double* dt_dev);
+/* Advance level `level` (ghost cells filled) by one step: cons->prim,
+ * flattening, PPM + tracing, normal fluxes, both transverse stages, update.
+ * Level 0 takes the dt of ctuppm_compute_dt, or the device double *dt_dev
+ * when dt_dev is not NULL (the caller's dt, positive and finite, read on the
+ * stream when the advance runs; a fine level then takes half of it); a
+ * single-level problem's new state becomes current.  On two levels,
+ * level 0 also records its fluxes on the coarse-fine faces and keeps its old
+ * and new states for the fine ghost cells; level 1 (dt_dev NULL) takes half
+ * the coarse dt and adds its fluxes to the register. */
+int ctuppm_advance_level(ctuppm_ctx* ctx, int pid, int level, int form, const double* dt_dev);
+/* Two levels, after the second fine substep: each coarse cell under the fine
+ * rectangle becomes the average of its 8 children (section 3.2). */
+int ctuppm_average_down(ctuppm_ctx* ctx, int pid);
+/* Two levels, after averaging down: the coarse cells beside the fine
+ * rectangle are corrected by the difference of the coarse flux and the summed
+ * fine fluxes on their faces (refluxing, section 3.2); the new coarse state
+ * becomes current and the step is complete. */
+int ctuppm_reflux(ctuppm_ctx* ctx, int pid);
+
 /* Which fab (0 = A, 1 = B) holds the current state of problem pid. */
 int ctuppm_current_state(ctuppm_ctx* ctx, int pid, int* which);
 /* dt of the last step (synchronises the stream). */

@@ -58,6 +58,16 @@ struct Problem {
   long long steps = 0;
   // two-level geometry: fine level = fine cells flo..fhi = coarse cells clo..chi
   int flo[3] = {0, 0, 0}, fhi[3] = {0, 0, 0}, clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
+  // a step taken in pieces (fill, dt, advance per level, average down, reflux)
+  int phase = 0;                     // 0 between steps; 1 coarse level advanced, fine substeps under way
+  int fine_done = 0;                 // fine substeps taken in this coarse step
+  bool filled[2] = {false, false};   // ghosts of the level's current state filled since it last changed
+  bool dt_ready = false;             // dt computed since the last advance
+  bool averaged = false;             // fine level averaged down in this coarse step
+  void state_changed() {
+    filled[0] = filled[1] = false;
+    dt_ready = false;
+  }
 };
 
 // Work lists of one set of problems stepped together in one form.
@@ -1045,6 +1055,57 @@ int step_two_level(ctuppm_ctx* c, int pid, int form) {
   }
   P->cur ^= 1;
   P->steps += 1;
+  P->state_changed();
+  return CTUPPM_OK;
+}
+
+// ------------------------------------------------------------ a step in pieces
+
+#define LCHK(expr)                                                                                  \
+  do {                                                                                              \
+    hipError_t _e = (expr);                                                                         \
+    if (_e != hipSuccess) return fail(c, CTUPPM_EHIP, "launch %s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+// The problem of a piece call, and the form its launches take.
+int piece_problem(ctuppm_ctx* c, int pid, int form, Problem** out) {
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (P->prm.scheme != CTUPPM_SCHEME_CTU)
+    return fail(c, CTUPPM_EINVAL, "problem %d: the method-of-lines schemes step with ctuppm_step only", pid);
+  if (form != CTUPPM_FORM_PER_BOX && form != CTUPPM_FORM_BATCHED)
+    return fail(c, CTUPPM_EINVAL, "a step in pieces takes the per-box or the batched form");
+  if (P->nlevels == 2 && form != CTUPPM_FORM_BATCHED)
+    return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched form");
+  *out = P;
+  return CTUPPM_OK;
+}
+
+int single_set(ctuppm_ctx* c, int pid, int form, StepSet** S) {
+  const std::vector<int> v{pid};
+  return build_set(c, v, form, S);
+}
+
+// The CFL pass over the valid cells of a single-level set, box by box in the per-box form.
+int cfl_pass(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
+  if (S->form != CTUPPM_FORM_PER_BOX) return run_cells(c, S, s, kStCfl, -1, c->timing);
+  for (int b = 0; b < S->nboxes; ++b) {
+    const int rc = run_cells(c, S, s, kStCfl, b, c->timing);
+    if (rc) return rc;
+  }
+  return CTUPPM_OK;
+}
+
+// cons->prim and the cell stages of a level, box by box in the per-box form.
+int advance_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
+  const int nst = int(sizeof(kCellStages) / sizeof(int));
+  const int nb = S->form == CTUPPM_FORM_PER_BOX ? S->nboxes : 1;
+  for (int b = 0; b < nb; ++b) {
+    const int box = S->form == CTUPPM_FORM_PER_BOX ? b : -1;
+    int rc = run_cells(c, S, s, kStC2POnly, box, c->timing);
+    for (int q = 0; q < nst && !rc; ++q) rc = run_cells(c, S, s, kCellStages[q], box, c->timing);
+    if (rc) return rc;
+  }
   return CTUPPM_OK;
 }
 
@@ -1276,6 +1337,8 @@ int ctuppm_step(ctuppm_ctx* c, const int* pids, int npids, int form) {
       if (v[i] == v[j]) return fail(c, CTUPPM_EINVAL, "problem %d listed twice", v[i]);
     Problem* P = get_problem(c, v[i]);
     if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", v[i]);
+    if (P->phase != 0)
+      return fail(c, CTUPPM_ESTATE, "problem %d is in the middle of a step taken in pieces", v[i]);
     if (P->nlevels == 2) {
       if (npids != 1) return fail(c, CTUPPM_EINVAL, "a two-level problem steps on its own");
       return step_two_level(c, v[i], form);
@@ -1308,7 +1371,147 @@ int ctuppm_step(ctuppm_ctx* c, const int* pids, int npids, int form) {
     Problem* P = get_problem(c, pid);
     P->cur ^= 1;
     P->steps += 1;
+    P->state_changed();
   }
+  return CTUPPM_OK;
+}
+
+int ctuppm_fill_ghosts(ctuppm_ctx* c, int pid, int level, int form) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = nullptr;
+  int rc = piece_problem(c, pid, form, &P);
+  if (rc) return rc;
+  if (level < 0 || level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
+  if (P->nlevels == 1) {
+    StepSet* S = nullptr;
+    if ((rc = single_set(c, pid, form, &S)) || (rc = fill_arr(c, S, c->stream, c->timing, kArrCur))) return rc;
+  } else {
+    TwoLevel* T = nullptr;
+    if ((rc = build_two_level(c, pid, &T))) return rc;
+    if (level == 0) {
+      if (P->phase != 0)
+        return fail(c, CTUPPM_ESTATE, "problem %d: the coarse step is under way (fine substeps, average down, reflux)",
+                    pid);
+      if ((rc = level_fill(c, T->cset, c->stream, c->timing))) return rc;
+    } else {
+      if (P->phase != 1 || P->fine_done >= 2)
+        return fail(c, CTUPPM_ESTATE, "problem %d: fine ghost cells are filled after the coarse advance, before "
+                    "each of the two fine substeps", pid);
+      if ((rc = level_fill(c, T->fset, c->stream, c->timing))) return rc;
+      LCHK(launch_cfinterp(T->args, T->ctags, T->cchunks, T->ncch, 0.5 * P->fine_done, c->stream));
+    }
+  }
+  P->filled[level] = true;
+  return CTUPPM_OK;
+}
+
+int ctuppm_compute_dt(ctuppm_ctx* c, int pid, int form, double* dt_dev) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = nullptr;
+  int rc = piece_problem(c, pid, form, &P);
+  if (rc) return rc;
+  if (P->phase != 0) return fail(c, CTUPPM_ESTATE, "problem %d: dt is computed between steps", pid);
+  if (P->nlevels == 1) {
+    StepSet* S = nullptr;
+    if ((rc = single_set(c, pid, form, &S)) || (rc = cfl_pass(c, S, c->stream))) return rc;
+    LCHK(launch_dt(S->probs, S->nprobs, c->stream));
+  } else {
+    TwoLevel* T = nullptr;
+    if ((rc = build_two_level(c, pid, &T))) return rc;
+    if ((rc = run_cells(c, T->cset, c->stream, kStCfl, -1, c->timing)) ||
+        (rc = run_cells(c, T->fset, c->stream, kStCfl, -1, c->timing)))
+      return rc;
+    LCHK(launch_dt2(P->dP, P->dPf, c->stream));
+  }
+  if (dt_dev) HIPCHK(c, hipMemcpyAsync(dt_dev, &P->dP->dt, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  P->dt_ready = true;
+  return CTUPPM_OK;
+}
+
+int ctuppm_advance_level(ctuppm_ctx* c, int pid, int level, int form, const double* dt_dev) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = nullptr;
+  int rc = piece_problem(c, pid, form, &P);
+  if (rc) return rc;
+  if (level < 0 || level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
+  hipStream_t s = c->stream;
+  if (level == 0) {
+    if (P->phase != 0) return fail(c, CTUPPM_ESTATE, "problem %d: the coarse step is under way", pid);
+    if (!P->filled[0])
+      return fail(c, CTUPPM_ESTATE, "problem %d: level 0 ghost cells not filled since the state changed", pid);
+    if (!dt_dev && !P->dt_ready) return fail(c, CTUPPM_ESTATE, "problem %d: no dt (compute it or pass one)", pid);
+  }
+  if (P->nlevels == 1) {
+    StepSet* S = nullptr;
+    if ((rc = single_set(c, pid, form, &S))) return rc;
+    if (dt_dev) LCHK(launch_set_dt(P->dP, nullptr, dt_dev, s));
+    if ((rc = advance_cells(c, S, s))) return rc;
+    LCHK(launch_flip(S->probs, S->nprobs, s));
+    P->cur ^= 1;
+    P->steps += 1;
+    P->state_changed();
+    return CTUPPM_OK;
+  }
+  TwoLevel* T = nullptr;
+  if ((rc = build_two_level(c, pid, &T))) return rc;
+  const TwoLevelArgs& A = T->args;
+  if (level == 0) {
+    if (dt_dev) LCHK(launch_set_dt(P->dP, P->dPf, dt_dev, s));
+    LCHK(launch_gather(A, T->gtags, T->gchunks, T->ngch, 0, s));
+    if ((rc = advance_cells(c, T->cset, s))) return rc;
+    LCHK(launch_reg_coarse(A, T->faces, T->nfaces, s));
+    LCHK(launch_gather(A, T->gtags, T->gchunks, T->ngch, 1, s));
+    P->phase = 1;
+    P->fine_done = 0;
+    P->state_changed();
+    return CTUPPM_OK;
+  }
+  if (dt_dev) return fail(c, CTUPPM_EINVAL, "the fine level takes half the coarse dt (pass NULL)");
+  if (P->phase != 1 || P->fine_done >= 2)
+    return fail(c, CTUPPM_ESTATE, "problem %d: a fine substep follows the coarse advance, twice", pid);
+  if (!P->filled[1])
+    return fail(c, CTUPPM_ESTATE, "problem %d: level 1 ghost cells not filled for this substep", pid);
+  if ((rc = advance_cells(c, T->fset, s))) return rc;
+  LCHK(launch_reg_fine(A, T->faces, T->nfaces, s));
+  LCHK(launch_flip(T->fset->probs, T->fset->nprobs, s));
+  P->fine_done += 1;
+  P->filled[1] = false;
+  return CTUPPM_OK;
+}
+
+int ctuppm_average_down(ctuppm_ctx* c, int pid) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (P->nlevels != 2) return fail(c, CTUPPM_EINVAL, "problem %d has one level", pid);
+  if (P->phase != 1 || P->fine_done != 2 || P->averaged)
+    return fail(c, CTUPPM_ESTATE, "problem %d: averaging down follows the second fine substep, once", pid);
+  TwoLevel* T = nullptr;
+  int rc = build_two_level(c, pid, &T);
+  if (rc) return rc;
+  LCHK(launch_avgdown(T->args, T->atags, T->achunks, T->nach, c->stream));
+  P->averaged = true;
+  return CTUPPM_OK;
+}
+
+int ctuppm_reflux(ctuppm_ctx* c, int pid) {
+  if (!c) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (P->nlevels != 2) return fail(c, CTUPPM_EINVAL, "problem %d has one level", pid);
+  if (P->phase != 1 || !P->averaged)
+    return fail(c, CTUPPM_ESTATE, "problem %d: refluxing follows averaging down", pid);
+  TwoLevel* T = nullptr;
+  int rc = build_two_level(c, pid, &T);
+  if (rc) return rc;
+  LCHK(launch_reflux(T->args, T->faces, T->nfaces, c->stream));
+  LCHK(launch_flip(T->cset->probs, T->cset->nprobs, c->stream));
+  P->phase = 0;
+  P->fine_done = 0;
+  P->averaged = false;
+  P->cur ^= 1;
+  P->steps += 1;
+  P->state_changed();
   return CTUPPM_OK;
 }
 
@@ -1419,6 +1622,7 @@ int ctuppm_tag(ctuppm_ctx* c, int pid, double threshold, unsigned char* tags) {
   if (!c || !tags || !(threshold >= 0.0)) return CTUPPM_EINVAL;
   Problem* P = get_problem(c, pid);
   if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (P->phase != 0) return fail(c, CTUPPM_ESTATE, "problem %d is in the middle of a step taken in pieces", pid);
   StepSet* S = nullptr;
   const std::vector<int> v{pid};
   int rc = build_set(c, v, CTUPPM_FORM_BATCHED, &S, 0);
@@ -1439,6 +1643,7 @@ int ctuppm_regrid(ctuppm_ctx* c, int pid, const ctuppm_box* fine_boxes, int nfin
   if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
   if (P->nlevels != 2) return fail(c, CTUPPM_EINVAL, "problem %d has no fine level", pid);
   if (!P->lev[0].bound || !P->lev[1].bound) return fail(c, CTUPPM_ESTATE, "problem %d: state not bound", pid);
+  if (P->phase != 0) return fail(c, CTUPPM_ESTATE, "problem %d is in the middle of a step taken in pieces", pid);
   for (int b = 0; b < nfine; ++b)
     if (!Ua[b] || !Ub[b]) return fail(c, CTUPPM_EINVAL, "null fab for fine box %d", b);
   int rc = check_level(c, P->prm, 1, fine_boxes, nfine);
@@ -1572,6 +1777,7 @@ int ctuppm_regrid(ctuppm_ctx* c, int pid, const ctuppm_box* fine_boxes, int nfin
     P->clo[d] = clo[d];
     P->chi[d] = chi[d];
   }
+  P->state_changed();
   return CTUPPM_OK;
 }
 

@@ -201,6 +201,7 @@ hipError_t launch_tag(const BoxRec* boxes, const March* units, int nunits, doubl
 hipError_t launch_prolong(const TwoLevelArgs& A, const BoxRec* newf, const BoxRec* oldf, const ProlongTag* tags,
                           const Chunk* chunks, int n, hipStream_t s);
 hipError_t launch_dt(ProbDev* const* probs, int nprobs, hipStream_t s);
+hipError_t launch_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt, hipStream_t s);
 hipError_t launch_flip(ProbDev* const* probs, int nprobs, hipStream_t s);
 const char* stage_name(int stage);
 

@@ -283,6 +283,15 @@ __global__ void k_dt(ProbDev* const* probs, int nprobs) {
   set_dt(P, P->fixed_dt > 0.0 ? P->fixed_dt : P->cfl / s);
 }
 
+// A caller's dt (a device double) for the next advance of a problem: the
+// coarse level takes it, a fine level half of it.
+__global__ void k_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double v = *dt;
+  set_dt(Pc, v);
+  if (Pf) set_dt(Pf, 0.5 * v);
+}
+
 __global__ void k_flip(ProbDev* const* probs, int nprobs) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nprobs) return;
@@ -1184,6 +1193,11 @@ hipError_t launch_prolong(const TwoLevelArgs& A, const BoxRec* newf, const BoxRe
 
 hipError_t launch_dt2(ProbDev* Pc, ProbDev* Pf, hipStream_t s) {
   k_dt2<<<1, 64, 0, s>>>(Pc, Pf);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt, hipStream_t s) {
+  k_set_dt<<<1, 64, 0, s>>>(Pc, Pf, dt);
   return hipGetLastError();
 }
 

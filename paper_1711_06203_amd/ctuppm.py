@@ -92,6 +92,11 @@ def lib() -> ctypes.CDLL:
                                ip],
             "ctuppm_regrid": [vp, ctypes.c_int, ctypes.POINTER(Box), ctypes.c_int, ctypes.POINTER(vp),
                               ctypes.POINTER(vp)],
+            "ctuppm_fill_ghosts": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+            "ctuppm_compute_dt": [vp, ctypes.c_int, ctypes.c_int, vp],
+            "ctuppm_advance_level": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp],
+            "ctuppm_average_down": [vp, ctypes.c_int],
+            "ctuppm_reflux": [vp, ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -109,7 +114,8 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_get_dt", "ctuppm_status", "ctuppm_set_timing", "ctuppm_stage_times", "ctuppm_num_stages",
             "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning", "ctuppm_step_checked",
             "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid",
-            "ctuppm_set_concurrency"]
+            "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
+            "ctuppm_average_down", "ctuppm_reflux"]
 
 
 class Context:
@@ -332,6 +338,49 @@ class Solver:
         r = ctypes.c_int()
         self.ctx.call("ctuppm_step_checked", self.pid, f, ctypes.byref(r))
         return bool(r.value)
+
+    # a step in pieces, in the paper's order: ghost fill, dt, advance per level,
+    # average down, reflux (the graph form is the whole step's, pieces run batched)
+    def _piece_form(self, form) -> int:
+        if form is None:
+            form = "per_box" if self.form == FORMS["per_box"] and len(self.levels) == 1 else "batched"
+        return FORMS[form] if isinstance(form, str) else int(form)
+
+    def fill_ghosts(self, level: int = 0, form=None):
+        self.ctx.call("ctuppm_fill_ghosts", self.pid, int(level), self._piece_form(form))
+
+    def compute_dt(self, out=None, form=None):
+        """dt of the next step from the CFL condition, kept for the next
+        advance and written into `out` (a one-element float64 device tensor)
+        when given."""
+        ptr = ctypes.c_void_p(out.data_ptr()) if out is not None else None
+        self.ctx.call("ctuppm_compute_dt", self.pid, self._piece_form(form), ptr)
+
+    def advance_level(self, level: int = 0, dt=None, form=None):
+        """Advance one level; dt None (the computed dt) or a one-element
+        float64 device tensor (level 0 only)."""
+        ptr = ctypes.c_void_p(dt.data_ptr()) if dt is not None else None
+        self.ctx.call("ctuppm_advance_level", self.pid, int(level), self._piece_form(form), ptr)
+
+    def average_down(self):
+        self.ctx.call("ctuppm_average_down", self.pid)
+
+    def reflux(self):
+        self.ctx.call("ctuppm_reflux", self.pid)
+
+    def step_in_pieces(self, nsteps: int = 1, form=None, dt=None):
+        """nsteps steps, each taken piece by piece; dt None (CFL) or a device tensor."""
+        for _ in range(nsteps):
+            self.fill_ghosts(0, form)
+            if dt is None:
+                self.compute_dt(form=form)
+            self.advance_level(0, dt, form)
+            if len(self.levels) == 2:
+                for _sub in range(2):
+                    self.fill_ghosts(1, form)
+                    self.advance_level(1, None, form)
+                self.average_down()
+                self.reflux()
 
     def set_fail_hook(self, step_index: int):
         self.ctx.call("ctuppm_set_fail_hook", self.pid, int(step_index))
