@@ -273,6 +273,8 @@ class Solver:
             self.fine_n = tuple(prob.U0_fine.shape[1:][::-1])
         self._bind_workspace()
         self.upload(prob.U0, prob.U0_fine)
+        self.fixed_dt = float(fixed_dt) if fixed_dt else None
+        self.steps_before = 0  # steps taken before a checkpoint this solver resumed from
         if fixed_dt:
             ctx.call("ctuppm_set_fixed_dt", self.pid, float(fixed_dt))
 
@@ -381,6 +383,24 @@ class Solver:
                     self.advance_level(1, None, form)
                 self.average_down()
                 self.reflux()
+
+    def checkpoint(self, path: str):
+        """Save the current state of every level and the problem (see
+        checkpoint.py), with the steps taken since the run began."""
+        from . import checkpoint
+        two = len(self.levels) == 2
+        checkpoint.save(path, self.prob, self.state(), self.state_fine() if two else None,
+                        self.fine_lo if two else None, self.levels[1] if two else None,
+                        steps_taken=self.steps_before + int(self.counters()[5]), fixed_dt=self.fixed_dt)
+
+    @classmethod
+    def resume(cls, ctx: Context, path: str, form="batched") -> "Solver":
+        """A solver whose state is the one saved in `path`."""
+        from . import checkpoint
+        prob, meta = checkpoint.load(path)
+        s = cls(ctx, prob, form=form, fixed_dt=meta["fixed_dt"])
+        s.steps_before = meta["steps_taken"]
+        return s
 
     def set_fail_hook(self, step_index: int):
         self.ctx.call("ctuppm_set_fail_hook", self.pid, int(step_index))
