@@ -189,7 +189,8 @@ def cluster(tags: np.ndarray, blocking: int = 4, efficiency: float = 0.7, max_ed
     t = np.ascontiguousarray(tags, dtype=np.uint8)
     nz, ny, nx = t.shape
     n = (ctypes.c_int * 3)(nx, ny, nz)
-    cap = max(16, t.size // max(1, blocking ** 3) + 1)
+    b = max(1, int(blocking))
+    cap = 16 + int(np.prod([-(-v // b) for v in (nx, ny, nz)]))  # boxes hold whole blocks: at most one per block
     out = (Box * cap)()
     nb = ctypes.c_int()
     rc = lib().ctuppm_cluster(t.ctypes.data_as(ctypes.c_void_p), n, int(blocking), float(efficiency), int(max_edge),
