@@ -138,7 +138,9 @@ def main():
                     help="graph form with the three directions of each phase on three streams (default: one chain)")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--box", type=int, default=64)
-    ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph"])
+    ap.add_argument("--form", default="graph", choices=["per_box", "batched", "graph", "waves"])
+    ap.add_argument("--wave-boxes", type=int, default=64,
+                    help="waves form: boxes per wave (the workspace holds this many boxes' stage scratch)")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests per arrival rate")
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
     ap.add_argument("--no-cpu", action="store_true")
@@ -209,6 +211,12 @@ def main():
     ctx = ctuppm.Context()
     if args.concurrent_graph:
         ctx.set_concurrency(True)
+    waves = args.form == "waves"
+    if waves:
+        if prob.fine_boxes is not None:
+            print("the waves form is single-level", file=sys.stderr)
+            sys.exit(2)
+        ctx.set_wave_boxes(args.wave_boxes)
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
     # zone-updates per step: the fine level takes two substeps per coarse step
@@ -232,7 +240,7 @@ def main():
     value = zones * args.steps / el
     forms = {args.form: value}
     for f in ("per_box", "batched", "graph"):
-        if two_level and f == "per_box":
+        if (two_level and f == "per_box") or waves:  # a waves-sized workspace holds no batched scratch
             continue
         if f not in forms and not args.skip_forms:
             k = max(3, args.steps // 5)
@@ -242,7 +250,7 @@ def main():
     # kernels and grids the graph replays), on the stream they run on
     tsteps = max(3, args.steps // 5)
     ctx.set_timing(True)
-    solver.step(tsteps, form="batched")
+    solver.step(tsteps, form="waves" if waves else "batched")
     ctx.set_timing(False)
     st = ctx.stage_times()
     sbytes = solver.stage_bytes()
@@ -290,7 +298,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "form": args.form, "zone_updates_per_step": zones, "boxes": len(prob.boxes),
                    "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann, "limiter": args.limiter, "steepen": bool(args.steepen),
-                   "gamma": prob.gamma, "cfl": prob.cfl, "concurrent_graph": bool(args.concurrent_graph), "tuning": tuning and {k: tuning[k] for k in
+                   "gamma": prob.gamma, "cfl": prob.cfl, "concurrent_graph": bool(args.concurrent_graph),
+                   "wave_boxes": args.wave_boxes if waves else None, "workspace_bytes": int(solver.ws.numel()), "tuning": tuning and {k: tuning[k] for k in
                                                                                ("blocks_per_cu", "zseg", "ytile")}},
         "forms": {k: v for k, v in forms.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

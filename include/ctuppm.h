@@ -57,8 +57,12 @@ enum {
 enum { CTUPPM_BC_PERIODIC = 0, CTUPPM_BC_OUTFLOW = 1, CTUPPM_BC_REFLECT = 2, CTUPPM_BC_INFLOW = 3 };
 /* Step forms: one launch per stage per box; one persistent launch per stage
  * over the boxes of every problem stepped; the batched launches replayed from
- * a captured hipGraph. */
-enum { CTUPPM_FORM_PER_BOX = 0, CTUPPM_FORM_BATCHED = 1, CTUPPM_FORM_GRAPH = 2 };
+ * a captured hipGraph; batched launches over waves of consecutive boxes (set
+ * by ctuppm_set_wave_boxes, 64 by default) that share as many stage scratch
+ * slots, so the workspace scales with the wave instead of the level (ghost
+ * fill and the CFL pass still run over all boxes at once; single-level
+ * problems). */
+enum { CTUPPM_FORM_PER_BOX = 0, CTUPPM_FORM_BATCHED = 1, CTUPPM_FORM_GRAPH = 2, CTUPPM_FORM_WAVES = 3 };
 /* Schemes: unsplit CTU/PPM; method of lines with SSP-RK2; with SSP-RK3. */
 enum { CTUPPM_SCHEME_CTU = 0, CTUPPM_SCHEME_MOL_RK2 = 1, CTUPPM_SCHEME_MOL_RK3 = 2 };
 /* Riemann solvers: HLLC (Toro, Spruce & Speares 1994, Davis speeds); the
@@ -179,8 +183,8 @@ int ctuppm_set_fail_hook(ctuppm_ctx* ctx, int pid, int step_index);
  *   two levels:    fill_ghosts(0), compute_dt, advance_level(0),
  *                  { fill_ghosts(1), advance_level(1) } twice,
  *                  average_down, reflux
- * `form` is CTUPPM_FORM_PER_BOX or CTUPPM_FORM_BATCHED (two-level problems:
- * batched only); the graph form is ctuppm_step's.  The CTU scheme only (the
+ * `form` is CTUPPM_FORM_PER_BOX, CTUPPM_FORM_BATCHED or CTUPPM_FORM_WAVES
+ * (two-level problems: batched only); the graph form is ctuppm_step's.  The CTU scheme only (the
  * method-of-lines schemes fill ghosts inside their Runge-Kutta stages:
  * CTUPPM_EINVAL).  All calls are asynchronous on the context stream.  Calls
  * out of order return CTUPPM_ESTATE and enqueue nothing: advancing a level
@@ -291,6 +295,11 @@ int ctuppm_regrid(ctuppm_ctx* ctx, int pid, const ctuppm_box* fine_boxes, int nf
  * workloads (the concurrent kernels share L2).  Results are the same either
  * way (each kernel writes its own arrays); graphs are re-captured. */
 int ctuppm_set_concurrency(ctuppm_ctx* ctx, int on);
+/* Boxes per wave of CTUPPM_FORM_WAVES (>= 1); synchronises the context
+ * stream.  Problems then need ctuppm_workspace_bytes(pid, CTUPPM_FORM_WAVES)
+ * bytes: their MOL stage fabs plus min(boxes, number of boxes) slots of the
+ * largest box's stage scratch. */
+int ctuppm_set_wave_boxes(ctuppm_ctx* ctx, int boxes);
 
 /* Tuning of the launches: blocks per CU of the persistent batched launches
  * (0 = one block per work unit), and the z planes one work unit marches

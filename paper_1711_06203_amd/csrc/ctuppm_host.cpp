@@ -154,6 +154,7 @@ struct ctuppm_ctx {
   long long acc_n[kNumStages] = {};
   int num_cus = 256;
   int blocks_per_cu = 0;  // 0: one block per work unit
+  int wave_boxes = 64;    // boxes per wave of the waves form (they share this many scratch slots)
   int zseg_batched = 1;   // planes per march unit, batched / graph forms
   int zseg_per_box = 1;   // planes per march unit, per-box form
   int ytile = 0;          // rows per tile of the march units (0: whole plane)
@@ -472,6 +473,8 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     const size_t wbytes = stage_fab_bytes(L.boxes, P->prm);
     size_t woff = 0;
     size_t off = wbytes;
+    size_t slot = 0;  // waves form: every box fits any of the shared scratch slots
+    for (const auto& b : L.boxes) slot = std::max(slot, box_scratch_bytes(b, P->prm.nspec));
     if (level == 1)  // level-1 scratch follows all level-0 scratch
       for (const auto& b : P->lev[0].boxes) off += box_scratch_bytes(b, P->prm.nspec);
     int dlo[3], dhi[3];
@@ -481,7 +484,9 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
       BoxRec r{};
       r.U[0] = L.Ua[b];
       r.U[1] = L.Ub[b];
-      r.scr = (double*)((char*)P->ws + (S->form == CTUPPM_FORM_PER_BOX ? wbytes : off));
+      r.scr = (double*)((char*)P->ws + (S->form == CTUPPM_FORM_PER_BOX ? wbytes
+                                         : S->form == CTUPPM_FORM_WAVES ? wbytes + (b % size_t(c->wave_boxes)) * slot
+                                                                        : off));
       off += box_scratch_bytes(bx, P->prm.nspec);
       r.P = dPl;
       r.level = level;
@@ -587,7 +592,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   S->nprobs = int(probs.size());
   // march units per region, per box in order; per-box launches use short z
   // segments so one box still fills the GPU
-  const int zseg = S->form == CTUPPM_FORM_PER_BOX ? c->zseg_per_box : c->zseg_batched;
+  const int zseg = S->form == CTUPPM_FORM_PER_BOX ? c->zseg_per_box : c->zseg_batched;  // waves: as batched
   for (int k = 0; k < kNumRegions; ++k) {
     S->box_beg[k].resize(S->nboxes);
     S->box_cnt[k].resize(S->nboxes);
@@ -662,6 +667,28 @@ int run_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int box, bool
                    timed, A);
 }
 
+// A stage over the boxes b0..b1-1 of a set (their units are contiguous).
+int run_range(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int b0, int b1, bool timed,
+              const StageArgs& A0 = StageArgs()) {
+  StageArgs A = A0;
+  A.rs = S->riemann;
+  A.lim = S->limiter;
+  const int k = stage_region(stage);
+  const int beg = S->box_beg[k][b0];
+  const int end = S->box_beg[k][b1 - 1] + S->box_cnt[k][b1 - 1];
+  return run_stage(c, s, stage, S->boxes, nullptr, S->units[k] + beg, end - beg, true, timed, A);
+}
+
+// Groups of boxes whose cell stages launch together: one per box (per-box
+// form), all boxes (batched), or waves of wave_boxes consecutive boxes
+// (waves form, the boxes of a wave use distinct scratch slots).
+std::vector<std::pair<int, int>> box_groups(const ctuppm_ctx* c, const StepSet* S) {
+  std::vector<std::pair<int, int>> g;
+  const int w = S->form == CTUPPM_FORM_PER_BOX ? 1 : S->form == CTUPPM_FORM_WAVES ? c->wave_boxes : S->nboxes;
+  for (int b = 0; b < S->nboxes; b += w) g.push_back({b, std::min(S->nboxes, b + w)});
+  return g;
+}
+
 // Ghost fill of the state array `arr` of every box of a set: same-level
 // copies, then the physical boundaries x, y, z.
 int fill_arr(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed, int arr) {
@@ -693,6 +720,7 @@ int fill_arr(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed, int arr) {
 // and the stage update; the last stage writes the other fab.
 int enqueue_mol(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
   const bool per_box = S->form == CTUPPM_FORM_PER_BOX;
+  const bool waves = S->form == CTUPPM_FORM_WAVES;
   const int nst = S->scheme == 1 ? 2 : 3;
   const int cells[] = {kStFlatten, kStReconX, kStReconY, kStReconZ, kStRiemX, kStRiemY, kStRiemZ};
   int rc;
@@ -705,7 +733,7 @@ int enqueue_mol(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
       if (per_box) {
         for (int b = 0; b < S->nboxes; ++b)
           if ((rc = run_cells(c, S, s, kStCfl, b, timed, A))) return rc;
-      } else if ((rc = run_cells(c, S, s, kStC2P, -1, timed, A))) {
+      } else if ((rc = run_cells(c, S, s, waves ? kStCfl : kStC2P, -1, timed, A))) {
         return rc;
       }
       hipError_t e = launch_dt(S->probs, S->nprobs, s);
@@ -717,6 +745,15 @@ int enqueue_mol(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
     U.comb = r > 0;
     U.c = nst == 2 ? 0.5 : (r == 1 ? 0.25 : 2.0 / 3.0);
     U.last = r == nst - 1;
+    if (waves) {
+      for (const auto& w : box_groups(c, S)) {
+        if ((rc = run_range(c, S, s, kStC2POnly, w.first, w.second, timed, A))) return rc;
+        for (int st : cells)
+          if ((rc = run_range(c, S, s, st, w.first, w.second, timed))) return rc;
+        if ((rc = run_range(c, S, s, kStMolUpdate, w.first, w.second, timed, U))) return rc;
+      }
+      continue;
+    }
     const int nb = per_box ? S->nboxes : 1;
     for (int b = 0; b < nb; ++b) {
       const int box = per_box ? b : -1;
@@ -779,6 +816,7 @@ int enqueue_step_branched(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
 int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
   if (S->scheme != 0) return enqueue_mol(c, S, s, timed);
   const bool per_box = S->form == CTUPPM_FORM_PER_BOX;
+  const bool waves = S->form == CTUPPM_FORM_WAVES;
   int rc;
   if (per_box) {
     for (int b = 0; b < S->nboxes; ++b)
@@ -795,7 +833,9 @@ int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
     if ((rc = run_stage(c, s, kStFill, S->boxes, S->ftags, S->fchunks, S->nfch, true, timed))) return rc;
     for (int d = 0; d < 3; ++d)
       if ((rc = run_stage(c, s, kStBcX + d, S->boxes, S->btags[d], S->bchunks[d], S->nbch[d], true, timed))) return rc;
-    if ((rc = run_cells(c, S, s, kStC2P, -1, timed))) return rc;
+    // the waves form converts each wave into its shared scratch right before
+    // the wave's stages, so only the CFL pass runs over all boxes here
+    if ((rc = run_cells(c, S, s, waves ? kStCfl : kStC2P, -1, timed))) return rc;
   }
   {
     hipError_t e = launch_dt(S->probs, S->nprobs, s);
@@ -807,6 +847,12 @@ int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed) {
       if ((rc = run_cells(c, S, s, kStC2POnly, b, timed))) return rc;
       for (int q = 0; q < nst; ++q)
         if ((rc = run_cells(c, S, s, kCellStages[q], b, timed))) return rc;
+    }
+  } else if (waves) {
+    for (const auto& w : box_groups(c, S)) {
+      if ((rc = run_range(c, S, s, kStC2POnly, w.first, w.second, timed))) return rc;
+      for (int q = 0; q < nst; ++q)
+        if ((rc = run_range(c, S, s, kCellStages[q], w.first, w.second, timed))) return rc;
     }
   } else {
     for (int q = 0; q < nst; ++q)
@@ -1025,7 +1071,8 @@ int enqueue_two_level(ctuppm_ctx* c, Problem* P, TwoLevel* T, hipStream_t s, boo
 
 int step_two_level(ctuppm_ctx* c, int pid, int form) {
   Problem* P = get_problem(c, pid);
-  if (form == CTUPPM_FORM_PER_BOX) return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched forms only");
+  if (form == CTUPPM_FORM_PER_BOX || form == CTUPPM_FORM_WAVES)
+    return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched forms only");
   if (!P->lev[0].bound || !P->lev[1].bound || !P->ws)
     return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
   size_t need = 0;
@@ -1073,8 +1120,8 @@ int piece_problem(ctuppm_ctx* c, int pid, int form, Problem** out) {
   if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
   if (P->prm.scheme != CTUPPM_SCHEME_CTU)
     return fail(c, CTUPPM_EINVAL, "problem %d: the method-of-lines schemes step with ctuppm_step only", pid);
-  if (form != CTUPPM_FORM_PER_BOX && form != CTUPPM_FORM_BATCHED)
-    return fail(c, CTUPPM_EINVAL, "a step in pieces takes the per-box or the batched form");
+  if (form != CTUPPM_FORM_PER_BOX && form != CTUPPM_FORM_BATCHED && form != CTUPPM_FORM_WAVES)
+    return fail(c, CTUPPM_EINVAL, "a step in pieces takes the per-box, batched or waves form");
   if (P->nlevels == 2 && form != CTUPPM_FORM_BATCHED)
     return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched form");
   *out = P;
@@ -1099,11 +1146,13 @@ int cfl_pass(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
 // cons->prim and the cell stages of a level, box by box in the per-box form.
 int advance_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
   const int nst = int(sizeof(kCellStages) / sizeof(int));
-  const int nb = S->form == CTUPPM_FORM_PER_BOX ? S->nboxes : 1;
-  for (int b = 0; b < nb; ++b) {
-    const int box = S->form == CTUPPM_FORM_PER_BOX ? b : -1;
-    int rc = run_cells(c, S, s, kStC2POnly, box, c->timing);
-    for (int q = 0; q < nst && !rc; ++q) rc = run_cells(c, S, s, kCellStages[q], box, c->timing);
+  const bool per_box = S->form == CTUPPM_FORM_PER_BOX;
+  for (const auto& g : box_groups(c, S)) {
+    int rc = per_box ? run_cells(c, S, s, kStC2POnly, g.first, c->timing)
+                     : run_range(c, S, s, kStC2POnly, g.first, g.second, c->timing);
+    for (int q = 0; q < nst && !rc; ++q)
+      rc = per_box ? run_cells(c, S, s, kCellStages[q], g.first, c->timing)
+                   : run_range(c, S, s, kCellStages[q], g.first, g.second, c->timing);
     if (rc) return rc;
   }
   return CTUPPM_OK;
@@ -1279,6 +1328,9 @@ int ctuppm_workspace_bytes(ctuppm_ctx* c, int pid, int form, size_t* bytes) {
     *bytes = wb + mx;
   } else if (form == CTUPPM_FORM_BATCHED || form == CTUPPM_FORM_GRAPH) {
     *bytes = wb + total + two_level_extra_bytes(P);
+  } else if (form == CTUPPM_FORM_WAVES) {
+    if (P->nlevels == 2) return fail(c, CTUPPM_EINVAL, "two-level problems step in the batched forms only");
+    *bytes = wb + std::min(size_t(c->wave_boxes), P->lev[0].boxes.size()) * mx;
   } else {
     return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
   }
@@ -1330,7 +1382,7 @@ int ctuppm_set_fixed_dt(ctuppm_ctx* c, int pid, double dt) {
 
 int ctuppm_step(ctuppm_ctx* c, const int* pids, int npids, int form) {
   if (!c || !pids || npids < 1) return CTUPPM_EINVAL;
-  if (form < CTUPPM_FORM_PER_BOX || form > CTUPPM_FORM_GRAPH) return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
+  if (form < CTUPPM_FORM_PER_BOX || form > CTUPPM_FORM_WAVES) return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
   std::vector<int> v(pids, pids + npids);
   for (size_t i = 0; i < v.size(); ++i) {
     for (size_t j = 0; j < i; ++j)
@@ -1778,6 +1830,17 @@ int ctuppm_regrid(ctuppm_ctx* c, int pid, const ctuppm_box* fine_boxes, int nfin
     P->chi[d] = chi[d];
   }
   P->state_changed();
+  return CTUPPM_OK;
+}
+
+int ctuppm_set_wave_boxes(ctuppm_ctx* c, int boxes) {
+  if (!c || boxes < 1) return CTUPPM_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->wave_boxes = boxes;
+  for (auto it = c->sets.begin(); it != c->sets.end();) {  // slot assignment changes
+    if (std::get<1>(it->first) == CTUPPM_FORM_WAVES) it = c->sets.erase(it);
+    else ++it;
+  }
   return CTUPPM_OK;
 }
 

@@ -19,8 +19,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libctuppm.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
-FORM_PER_BOX, FORM_BATCHED, FORM_GRAPH = 0, 1, 2
-FORMS = {"per_box": FORM_PER_BOX, "batched": FORM_BATCHED, "graph": FORM_GRAPH}
+FORM_PER_BOX, FORM_BATCHED, FORM_GRAPH, FORM_WAVES = 0, 1, 2, 3
+FORMS = {"per_box": FORM_PER_BOX, "batched": FORM_BATCHED, "graph": FORM_GRAPH, "waves": FORM_WAVES}
 SCHEME_CTU, SCHEME_MOL_RK2, SCHEME_MOL_RK3 = 0, 1, 2
 SCHEMES = {"ctu": SCHEME_CTU, "mol2": SCHEME_MOL_RK2, "mol3": SCHEME_MOL_RK3}
 RIEMANN_HLLC, RIEMANN_TWO_SHOCK = 0, 1
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
             "ctuppm_advance_level": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp],
             "ctuppm_average_down": [vp, ctypes.c_int],
             "ctuppm_reflux": [vp, ctypes.c_int],
+            "ctuppm_set_wave_boxes": [vp, ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -115,7 +116,7 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning", "ctuppm_step_checked",
             "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid",
             "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
-            "ctuppm_average_down", "ctuppm_reflux"]
+            "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes"]
 
 
 class Context:
@@ -161,6 +162,10 @@ class Context:
         cnt = (ctypes.c_longlong * n)()
         self.call("ctuppm_stage_times", ms, cnt, n)
         return {self._L.ctuppm_stage_name(s).decode(): (ms[s], cnt[s]) for s in range(n)}
+
+    def set_wave_boxes(self, boxes: int):
+        """Boxes per wave of the waves form (they share as many scratch slots)."""
+        self.call("ctuppm_set_wave_boxes", int(boxes))
 
     def set_concurrency(self, on: bool):
         """Graph form: run the three directions of each phase concurrently (default off)."""
@@ -295,7 +300,13 @@ class Solver:
     def _bind_workspace(self):
         ws = ctypes.c_size_t()
         best = 0
-        for f in ((FORM_BATCHED,) if len(self.levels) == 2 else (FORM_PER_BOX, FORM_BATCHED)):
+        if len(self.levels) == 2:
+            forms = (FORM_BATCHED,)
+        elif self.form == FORM_WAVES:  # the workspace scales with the wave, not the level
+            forms = (FORM_PER_BOX, FORM_WAVES)
+        else:
+            forms = (FORM_PER_BOX, FORM_BATCHED)
+        for f in forms:
             self.ctx.call("ctuppm_workspace_bytes", self.pid, f, ctypes.byref(ws))
             best = max(best, ws.value)
         self.ws = self.ctx.torch.empty((max(best, 256),), dtype=self.ctx.torch.uint8, device=self.dev)
@@ -346,7 +357,8 @@ class Solver:
     # average down, reflux (the graph form is the whole step's, pieces run batched)
     def _piece_form(self, form) -> int:
         if form is None:
-            form = "per_box" if self.form == FORMS["per_box"] and len(self.levels) == 1 else "batched"
+            single = len(self.levels) == 1
+            form = self.form if single and self.form in (FORM_PER_BOX, FORM_WAVES) else FORM_BATCHED
         return FORMS[form] if isinstance(form, str) else int(form)
 
     def fill_ghosts(self, level: int = 0, form=None):
