@@ -60,6 +60,45 @@ def test_largest_box_edge_one_box_256_sampled(ctx):
     _sampled(ctx, prob, 200, 11)
 
 
+def _fullsize_digests():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_sha256.txt")
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.split()
+    return out
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["kh256_10", "kh256_13species_1", "kh256_mol2_2", "cloud256_1"])
+def test_fullsize_states_bitwise(ctx, name):
+    """The whole state after a few steps of a full-size workload (KH 256^3 ten
+    steps, with 13 species, with MOL-RK2; the two-level cloud 256^3 + 256^3 one
+    coarse step) bit for bit the oracle's, compared through the SHA-256 digests
+    of the oracle's runs (tests/golden/make_fullsize_digests.py writes them)."""
+    import hashlib
+    import os
+    import sys
+    from paper_1711_06203_amd import ctuppm
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_fullsize_digests as G
+    want = _fullsize_digests()[name]
+    prob, steps = G.cases()[name]
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(steps)
+    states = [s.state()] + ([s.state_fine()] if prob.fine_boxes else [])
+    dt = s.dt()
+    cnt = s.counters()
+    s.close()
+    ctx.torch.cuda.empty_cache()
+    assert not cnt[:5].any()
+    assert dt == float.fromhex(want[0])
+    got = [hashlib.sha256(np.ascontiguousarray(a, dtype=np.float64).tobytes()).hexdigest() for a in states]
+    assert got == want[1:], name
+
+
 @pytest.mark.slow
 def test_rt384_uneven_one_step_sampled(ctx):
     prob = W.rayleigh_taylor(n=384)
