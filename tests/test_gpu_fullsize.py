@@ -138,6 +138,25 @@ def test_kh256_ten_steps_full(ctx):
 
 
 @pytest.mark.slow
+def test_rt384_two_steps_full(ctx):
+    """The batched uneven-box workload at full size (RT 384^3, 1436 boxes,
+    gravity, reflecting walls): the whole state after two graph steps bitwise
+    the oracle's."""
+    from paper_1711_06203_amd import ctuppm
+    prob = W.rayleigh_taylor(n=384)
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(2)
+    got = s.state()
+    cnt = s.counters()
+    s.close()
+    ctx.torch.cuda.empty_cache()
+    ref, _, rcnt = oracle.run_problem(prob, 2)
+    print(f"rt384 2 steps: bitwise={np.array_equal(got, ref)}", flush=True)
+    assert np.array_equal(got, ref)
+    assert not cnt[:5].any() and not rcnt.any()
+
+
+@pytest.mark.slow
 def test_rt96_twenty_steps(ctx):
     from paper_1711_06203_amd import ctuppm
     from gpu_helpers import l1_rel
