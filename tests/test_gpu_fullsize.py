@@ -157,6 +157,26 @@ def test_rt384_two_steps_full(ctx):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("variant", [dict(riemann=1), dict(limiter=1), dict(steepen=1), dict(scheme=2)],
+                         ids=["twoshock", "cs", "steepen", "mol3"])
+def test_kh256_variants_one_step_full(ctx, variant):
+    """Each scheme variant at the full KH 256^3 size: the whole state after
+    one graph step bitwise the oracle's, run beside it."""
+    from paper_1711_06203_amd import ctuppm
+    prob = W.kelvin_helmholtz(n=256, box=64)
+    for k, v in variant.items():
+        setattr(prob, k, v)
+    s = ctuppm.Solver(ctx, prob, form="graph")
+    s.step(1)
+    got = s.state()
+    s.close()
+    ctx.torch.cuda.empty_cache()
+    ref, _, rcnt = oracle.run_problem(prob, 1)
+    assert np.array_equal(got, ref), variant
+    assert not rcnt.any()
+
+
+@pytest.mark.slow
 def test_rt96_twenty_steps(ctx):
     from paper_1711_06203_amd import ctuppm
     from gpu_helpers import l1_rel
