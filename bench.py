@@ -154,8 +154,9 @@ def main():
         print(kernel_source_hash())
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the box decomposition would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the box decomposition would shard across GPUs, one halo exchange and one dt reduction per step)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
