@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
                 ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3),
                 ("inflow", ctypes.c_double * 5), ("nspec", ctypes.c_int), ("pad", ctypes.c_int),
                 ("inflow_X", ctypes.c_double * MAXSPEC), ("scheme", ctypes.c_int), ("riemann", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("steepen", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("steepen", ctypes.c_int),
+                ("faces_set", ctypes.c_int), ("face_lo", ctypes.c_int * 3), ("face_hi", ctypes.c_int * 3)]
 
 SCHEMES = {"ctu": 0, "mol2": 1, "mol3": 2}
 
@@ -143,10 +144,28 @@ def params_of(prob, fine: bool = False) -> Params:
     dx = prob.dx
     if fine:
         dx = tuple(v / 2.0 for v in dx)
-    return make_params(prob.gamma, dx, prob.cfl, prob.bc_lo, prob.bc_hi, prob.grav_z, prob.inflow,
-                       prob.small_dens, prob.small_pres, getattr(prob, "nspec", 0), getattr(prob, "inflow_X", ()),
-                       getattr(prob, "scheme", 0), getattr(prob, "riemann", 0), getattr(prob, "limiter", 0),
-                       getattr(prob, "steepen", 0))
+    P = make_params(prob.gamma, dx, prob.cfl, prob.bc_lo, prob.bc_hi, prob.grav_z, prob.inflow,
+                    prob.small_dens, prob.small_pres, getattr(prob, "nspec", 0), getattr(prob, "inflow_X", ()),
+                    getattr(prob, "scheme", 0), getattr(prob, "riemann", 0), getattr(prob, "limiter", 0),
+                    getattr(prob, "steepen", 0))
+    if fine:  # the fine rectangle lies inside the domain: none of its faces is a wall
+        return with_faces(P, (_FAR,) * 3, (_FAR,) * 3)
+    return P
+
+
+_FAR = -(1 << 30)
+
+
+def with_faces(P: Params, face_lo, face_hi) -> Params:
+    """A copy of P for a box whose domain boundaries lie at the box-local face
+    indices face_lo, face_hi (reflecting walls are imposed there)."""
+    Q = Params()
+    ctypes.memmove(ctypes.byref(Q), ctypes.byref(P), ctypes.sizeof(Params))
+    Q.faces_set = 1
+    for d in range(3):
+        Q.face_lo[d] = int(face_lo[d])
+        Q.face_hi[d] = int(face_hi[d])
+    return Q
 
 
 def grow(Uvalid: np.ndarray, fill=np.nan) -> np.ndarray:
@@ -286,10 +305,13 @@ def sample_step(Ufull_grown_filled: np.ndarray, P: Params, dt: float,
     G = Ufull_grown_filled
     if P.scheme != 0:
         raise ValueError("MOL schemes: use sample_step_mol on a periodic domain")
+    N = [G.shape[3] - 2 * NG, G.shape[2] - 2 * NG, G.shape[1] - 2 * NG]
     out = np.zeros((len(cells), G.shape[0]))
     for s, (i, j, k) in enumerate(cells):
         loc = np.ascontiguousarray(G[:, k:k + 2 * NG + 1, j:j + 2 * NG + 1, i:i + 2 * NG + 1])
-        Gn, _ = advance_box(loc, P, dt)
+        c = (i, j, k)  # the one-cell box is domain cell c: the domain's faces sit at -c and N - c
+        Pc = with_faces(P, [-c[d] for d in range(3)], [N[d] - c[d] for d in range(3)])
+        Gn, _ = advance_box(loc, Pc, dt)
         out[s] = Gn[:, NG, NG, NG]
     return out
 

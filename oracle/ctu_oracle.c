@@ -81,6 +81,10 @@ typedef struct {
     int riemann;      /* 0 HLLC, 1 two-shock approximate solver */
     int limiter;      /* 0 CW84, 1 Colella & Sekora 2008 extremum-preserving */
     int steepen;      /* 1: CW84 contact steepening of the density (with limiter 0) */
+    /* where the domain's faces lie in the box being advanced (box-local face
+     * index); faces_set = 0 means the box is the whole domain (faces 0 and n) */
+    int faces_set;
+    int face_lo[3], face_hi[3];
 } orc_params;
 
 static int nvar_of(const orc_params *P) { return 5 + P->nspec; }
@@ -320,6 +324,25 @@ static void riemann_n(const double *L, const double *R, int d, const orc_params 
 }
 
 /* Five-component entry point of the two-shock flux (pins). */
+/* Reflecting walls: a solid wall lets nothing through, so the Riemann
+ * problem on a face that lies on a reflecting domain boundary takes the
+ * mirror image of the inside state (normal velocity negated, everything else
+ * kept) as the outside state, as the PPM codes of the paper's lineage impose
+ * on their interface states.  States are permuted primitives (slot 1 normal).
+ * f is the box-local face index along d, n the box's cells. */
+static void wall_mirror(double *L, double *R, int d, int f, const int n[3], const orc_params *P) {
+    const int lo = P->faces_set ? P->face_lo[d] : 0;
+    const int hi = P->faces_set ? P->face_hi[d] : n[d];
+    const int nv = nvar_of(P);
+    if (f == lo && P->bc_lo[d] == BC_REFLECT) {
+        for (int m = 0; m < nv; ++m) L[m] = R[m];
+        L[1] = -R[1];
+    } else if (f == hi && P->bc_hi[d] == BC_REFLECT) {
+        for (int m = 0; m < nv; ++m) R[m] = L[m];
+        R[1] = -L[1];
+    }
+}
+
 void orc_twoshock(const double L[5], const double R[5], int d, const orc_params *P, double Fg[5]) {
     orc_params Q = *P;
     Q.nspec = 0;
@@ -723,6 +746,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                         L[m] = S.ql[d][hidx(g, m, i, j, k)];
                         R[m] = S.qr[d][hidx(g, m, i, j, k)];
                     }
+                    wall_mirror(L, R, d, c[d], n, P);
                     riemann_n(L, R, d, P, F);
                     for (int m = 0; m < nv; ++m) S.fn[d][hidx(g, m, i, j, k)] = F[m];
                 }
@@ -765,6 +789,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                             for (int m = 0; m < nv; ++m) st2[side][m] = s1[m];
                         }
                         double F[MAXV];
+                        wall_mirror(st2[0], st2[1], a, c[a], n, P);
                         riemann_n(st2[0], st2[1], a, P, F);
                         for (int m = 0; m < nv; ++m) S.f1[pidx][hidx(g, m, i, j, k)] = F[m];
                     }
@@ -808,6 +833,7 @@ int orc_advance_box(const double *U, const int n[3], const orc_params *P, double
                         for (int m = 0; m < nv; ++m) st2[side][m] = s1[m];
                     }
                     double F[MAXV];
+                    wall_mirror(st2[0], st2[1], a, c[a], n, P);
                     riemann_n(st2[0], st2[1], a, P, F);
                     for (int m = 0; m < nv; ++m) S.ff[a][hidx(g, m, i, j, k)] = F[m];
                 }
@@ -943,6 +969,7 @@ int orc_mol_stage(const double *Us, const double *U0, const int n[3], const orc_
                         L[m] = ql[d][hidx(g, m, i, j, k)];
                         R[m] = qr[d][hidx(g, m, i, j, k)];
                     }
+                    wall_mirror(L, R, d, c[d], n, P);
                     riemann_n(L, R, d, P, F);
                     for (int m = 0; m < nv; ++m) fn[d][hidx(g, m, i, j, k)] = F[m];
                 }

@@ -497,6 +497,10 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
       for (int d = 0; d < 3; ++d) {
         r.n[d] = box_n(bx, d);
         r.lo[d] = bx.lo[d];
+        // reflecting domain walls on the box's faces (a fine level lies inside the domain)
+        r.wall[d] = level == 0 ? ((bx.lo[d] == dlo[d] && P->prm.bc_lo[d] == CTUPPM_BC_REFLECT ? 1 : 0) |
+                                  (bx.hi[d] == dhi[d] && P->prm.bc_hi[d] == CTUPPM_BC_REFLECT ? 2 : 0))
+                               : 0;
       }
       boxes.push_back(r);
     }

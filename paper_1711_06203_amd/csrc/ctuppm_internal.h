@@ -71,6 +71,7 @@ struct BoxRec {
   int lo[3];        // level index of valid cell (0,0,0)
   int level;
   int ns;           // passive species of the problem
+  int wall[3];      // bit 0: the box's low face along d is a reflecting domain wall; bit 1: its high face
 };
 
 struct Chunk { int box; int start; };  // tag index, first item (ghost-fill work lists)

@@ -424,6 +424,28 @@ __global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ box
   });
 }
 
+// Reflecting walls: the Riemann problem on a face that lies on a reflecting
+// domain boundary takes the mirror image of the inside state as the outside
+// one (normal velocity negated), so the wall lets no mass through.  Side of
+// face fa along d of box B: 1 low wall (the left state is outside), 2 high
+// wall (the right state is outside), 0 none.
+CTU_DEV int wall_side(const BoxRec& B, int d, int fa) {
+  if (fa == 0 && (B.wall[d] & 1)) return 1;
+  if (fa == B.n[d] && (B.wall[d] & 2)) return 2;
+  return 0;
+}
+
+// Permuted primitive states (slot 1 the normal velocity).
+CTU_DEV void wall_mirror(int side, double L[5], double R[5]) {
+  const bool lo = side == 1, hi = side == 2;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const double l = L[m], r = R[m];
+    L[m] = lo ? (m == 1 ? -r : r) : l;
+    R[m] = hi ? (m == 1 ? -l : l) : r;
+  }
+}
+
 // Normal flux of every face 0..n along D (cells -1..n across).
 template <int D, int RS>
 __global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ boxes,
@@ -438,18 +460,21 @@ __global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ b
     gdbl* __restrict__ fn = g.fn(B.scr, D);
     march(kFace0 + D, B, M, [&](int i, int j, int k) {
       const int o = g.h(i, j, k);
+      const int side = wall_side(B, D, D == 0 ? i : (D == 1 ? j : k));
       double L[5], R[5], f[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
         L[m] = ql[m * g.hcomp + o];
         R[m] = qr[m * g.hcomp + o];
       }
+      wall_mirror(side, L, R);
       Wave W;
       rflux<RS>(L, R, P, f, W);
       store_flux<D>(fn, g.hcomp, o, f);
       for (int is = 0; is < g.ns; ++is) {
         const int mo = (kNV + is) * g.hcomp + o;
-        fn[mo] = species_flux(W, ql[mo], qr[mo]);
+        const double xl = ql[mo], xr = qr[mo];
+        fn[mo] = species_flux(W, side == 1 ? xr : xl, side == 2 ? xl : xr);
       }
     });
   });
@@ -528,6 +553,8 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
         const int kL = to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
         const int kR = to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
         fb += kL + kR;
+        const int side = wall_side(B, A, x[A]);
+        wall_mirror(side, tL, tR);
         Wave W;
         rflux<RS>(tL, tR, P, f, W);
         gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
@@ -540,7 +567,8 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
           const double xL = ql[c + o], xR = qr[c + o];
           const double wL = sL[0] * xL - c3 * (Fm[oL + sb] - Fm[oL]);
           const double wR = sR[0] * xR - c3 * (Fm[oR + sb] - Fm[oR]);
-          F1[c + o] = species_flux(W, kL ? xL : wL / VL[0], kR ? xR : wR / VR[0]);
+          const double yL = kL ? xL : wL / VL[0], yR = kR ? xR : wR / VR[0];
+          F1[c + o] = species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR);
         }
       }
     });
@@ -553,7 +581,8 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ bo
 // A, then the final HLLC flux (global component order).  fb counts states that
 // fell back to the uncorrected ones.
 template <int A, int RS>
-CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, gdbl* __restrict__ ff, int& fb) {
+CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, int fa, gdbl* __restrict__ ff,
+                        int& fb) {
   constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
   // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
   constexpr int pbc = 2 * Bd + (Cd == (Bd + 1) % 3 ? 0 : 1);
@@ -587,6 +616,8 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
   const int kL = to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
   const int kR = to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
   fb += kL + kR;
+  const int side = wall_side(B, A, fa);
+  wall_mirror(side, tL, tR);
   Wave W;
   rflux<RS>(tL, tR, P, f, W);
   store_flux<A>(ff, g.hcomp, o, f);
@@ -600,7 +631,8 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
     wR = wR - c2b * (F1[oR + sb] - F1[oR]);
     wL = wL - c2c * (F2[oL + sc] - F2[oL]);
     wR = wR - c2c * (F2[oR + sc] - F2[oR]);
-    ff[c + o] = species_flux(W, kL ? xL : wL / UL[0], kR ? xR : wR / UR[0]);
+    const double yL = kL ? xL : wL / UL[0], yR = kR ? xR : wR / UR[0];
+    ff[c + o] = species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR);
   }
 }
 
@@ -616,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ bo
     gdbl* __restrict__ ff = g.ff(B.scr, A);
     int fb = 0;
     march(kFin0 + A, B, M, [&](int i, int j, int k) {
-      final_flux<A, RS>(B, g, P, g.h(i, j, k), ff, fb);
+      final_flux<A, RS>(B, g, P, g.h(i, j, k), A == 0 ? i : (A == 1 ? j : k), ff, fb);
     });
     count(&B.P->cnt[3], (unsigned long long)fb);
   });
