@@ -54,6 +54,12 @@ enum {
   CTUPPM_EHIP = -3,    /* a HIP runtime call failed; see ctuppm_last_error */
   CTUPPM_ESTATE = -4   /* call out of order (e.g. step before bind) */
 };
+/* Physical boundaries, per side of each direction: periodic (both sides);
+ * outflow (ghost cells copy the edge cell); reflecting wall (ghost cells
+ * mirror the interior with the normal momentum negated, and every Riemann
+ * problem on the wall face takes the mirror image of the inside state as the
+ * outside state, so no mass crosses the wall); inflow (ghost cells hold
+ * `inflow`, `inflow_X`). */
 enum { CTUPPM_BC_PERIODIC = 0, CTUPPM_BC_OUTFLOW = 1, CTUPPM_BC_REFLECT = 2, CTUPPM_BC_INFLOW = 3 };
 /* Step forms: one launch per stage per box; one persistent launch per stage
  * over the boxes of every problem stepped; the batched launches replayed from
