@@ -262,6 +262,21 @@ def main():
     # algorithmic bytes of the stage per step over its launch time per step
     achieved = sbytes[dom] / (avg_ms * launches_per_step * 1e-3) / 1e9
     traffic = measured_traffic(dom, tkey)
+    # the whole step: measured HBM bytes of every stage (per launch, times its
+    # launches per step) over the timed step
+    step_bytes = 0.0
+    for k, (ms, n) in st.items():
+        if n:
+            b = measured_traffic(k, tkey)
+            if b is None:
+                step_bytes = None
+                break
+            step_bytes += b * n / tsteps
+    step_roof = None
+    if step_bytes:
+        step_gbs = step_bytes / (el / args.steps) / 1e9
+        step_roof = {"measured_bytes": step_bytes, "achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS,
+                     "how": "sum over stages of rocprofv3 bytes per launch x launches per step, over ms_per_step"}
     cnt = solver.counters()
     regrid_info = None
     if args.regrid > 0.0 and two_level:
@@ -305,7 +320,8 @@ def main():
         "forms": {k: v for k, v in forms.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": sbytes[dom] / launches_per_step, "avg_launch_ms": avg_ms},
+                     "algorithmic_bytes_per_launch": sbytes[dom] / launches_per_step, "avg_launch_ms": avg_ms,
+                     "whole_step": step_roof},
         "stage_ms": {k: round(v, 4) for k, v in stage_avg.items() if v},
         "counters": [int(c) for c in cnt],
     }
