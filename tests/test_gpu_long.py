@@ -67,3 +67,25 @@ def test_cloud256_hundred_coarse_steps(ctx):
     assert np.isfinite(Uc).all() and np.isfinite(Uf).all()
     assert not cnt[:5].any() and cnt[5] == 100
     assert Uc[0].min() > 0.0 and Uf[0].min() > 0.0
+
+
+def test_kh256_hundred_steps_same_in_every_form(ctx):
+    """The configured 100 KH steps give bitwise the same state in the graph,
+    batched, per-box and waves forms (the graph form's state after 100 steps
+    is the one the other forms must reproduce)."""
+    from paper_1711_06203_amd import ctuppm
+    prob = W.kelvin_helmholtz(n=256, box=64)
+    ref = None
+    ctx.set_wave_boxes(16)
+    for form in ("graph", "batched", "per_box", "waves"):
+        s = ctuppm.Solver(ctx, prob, form=form)
+        s.step(100)
+        got = s.state()
+        s.close()
+        ctx.torch.cuda.empty_cache()
+        print(f"kh256 100 steps, {form}: bitwise {ref is None or np.array_equal(got, ref)}", flush=True)
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got, ref), form
+    ctx.set_wave_boxes(64)
