@@ -7,6 +7,7 @@ through the wall at a rate far above round-off."""
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 from paper_1711_06203_amd import workloads as W
@@ -16,8 +17,10 @@ def _totals(U):
     return [math.fsum(U[m].ravel()) for m in range(U.shape[0])]
 
 
-def test_mass_and_tangential_momentum_conserved_between_walls_under_gravity():
+@pytest.mark.parametrize("riemann,limiter", [(0, 0), (1, 0), (0, 1)])
+def test_mass_and_tangential_momentum_conserved_between_walls_under_gravity(riemann, limiter):
     prob = W.rayleigh_taylor(n=(16, 8, 32), seed=3, boxes=[((0, 0, 0), (15, 7, 31))])
+    prob.riemann, prob.limiter = riemann, limiter
     U, _, cnt = oracle.run_problem(prob, 60)
     assert not cnt.any()
     t0, t1 = _totals(prob.U0), _totals(U)
@@ -43,6 +46,15 @@ def test_wall_faces_carry_no_mass():
     for p in (4, 5):  # stage-1 fluxes of the z faces
         f = st[f"f1{p}"][0, [1, nz + 1]][:, 1:-1, 1:-1]
         assert np.abs(f[np.isfinite(f)]).max() <= 1e-15 * flux_scale
+
+
+def test_method_of_lines_walls_conserve_mass():
+    prob = W.rayleigh_taylor(n=(16, 8, 32), seed=4, boxes=[((0, 0, 0), (15, 7, 31))])
+    prob.scheme = 1
+    U, _, cnt = oracle.run_problem(prob, 40)
+    assert not cnt.any()
+    m0, m1 = math.fsum(prob.U0[0].ravel()), math.fsum(U[0].ravel())
+    assert abs(m1 - m0) <= 1e-13 * m0
 
 
 def test_closed_box_conserves_mass_and_energy_without_gravity():
