@@ -301,6 +301,23 @@ int ctuppm_regrid(ctuppm_ctx* ctx, int pid, const ctuppm_box* fine_boxes, int nf
  * workloads (the concurrent kernels share L2).  Results are the same either
  * way (each kernel writes its own arrays); graphs are re-captured. */
 int ctuppm_set_concurrency(ctuppm_ctx* ctx, int on);
+/* Debugging and stage-by-stage checks: copy one intermediate array of box
+ * `box` of level `level`, as the last step taken in `form` left it in the
+ * workspace, to the device buffer `out` (asynchronous; *elems receives its
+ * length in doubles; out = NULL only reports the length).  Arrays: 0 the
+ * primitives (rho, u, v, w, p, c, X_1..X_nspec) over the grown box; 1 the
+ * flattening coefficient over cells -1..n; 2-4 the traced left states of the
+ * x, y, z faces, 5-7 the right states (permuted primitives: density, normal
+ * velocity, the two transverse velocities, pressure, species), 8-10 the
+ * normal fluxes, 11-16 the first transverse-stage fluxes F^{A|B} (pair index
+ * 2A + 0 for B = A+1, 2A + 1 for B = A+2, mod 3), 17-19 the final fluxes;
+ * each halo-1 array is [component][k][j][i] over cells -1..n (a face array
+ * holds face f of cell f's lower side), fluxes in global component order.
+ * In the per-box form every box shares one scratch (the last box stepped);
+ * in the waves form box b uses slot b mod the wave size. */
+int ctuppm_debug_stage(ctuppm_ctx* ctx, int pid, int level, int box, int array, int form, double* out,
+                       long long* elems);
+
 /* Boxes per wave of CTUPPM_FORM_WAVES (>= 1); synchronises the context
  * stream.  Problems then need ctuppm_workspace_bytes(pid, CTUPPM_FORM_WAVES)
  * bytes: their MOL stage fabs plus min(boxes, number of boxes) slots of the

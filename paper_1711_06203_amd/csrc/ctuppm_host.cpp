@@ -1837,6 +1837,50 @@ int ctuppm_regrid(ctuppm_ctx* c, int pid, const ctuppm_box* fine_boxes, int nfin
   return CTUPPM_OK;
 }
 
+int ctuppm_debug_stage(ctuppm_ctx* c, int pid, int level, int box, int array, int form, double* out,
+                       long long* elems) {
+  if (!c || !elems) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  if (level < 0 || level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
+  const auto& L = P->lev[level].boxes;
+  if (box < 0 || box >= int(L.size())) return fail(c, CTUPPM_EINVAL, "level %d has no box %d", level, box);
+  if (array < 0 || array > 19) return fail(c, CTUPPM_EINVAL, "unknown stage array %d", array);
+  if (form < CTUPPM_FORM_PER_BOX || form > CTUPPM_FORM_WAVES) return fail(c, CTUPPM_EINVAL, "unknown form %d", form);
+  if (!P->ws) return fail(c, CTUPPM_ESTATE, "problem %d: no workspace bound", pid);
+  // the box's scratch, laid out as the step of that form laid it out
+  const int ns = P->prm.nspec;
+  size_t off = stage_fab_bytes(P->lev[0].boxes, P->prm);
+  if (form == CTUPPM_FORM_WAVES) {
+    size_t slot = 0;
+    for (const auto& b : L) slot = std::max(slot, box_scratch_bytes(b, ns));
+    off += size_t(box % c->wave_boxes) * slot;
+  } else if (form != CTUPPM_FORM_PER_BOX) {
+    if (level == 1)
+      for (const auto& b : P->lev[0].boxes) off += box_scratch_bytes(b, ns);
+    for (int b = 0; b < box; ++b) off += box_scratch_bytes(L[b], ns);
+  }
+  const int n[3] = {box_n(L[box], 0), box_n(L[box], 1), box_n(L[box], 2)};
+  const long long grown = grown_cells(n), h1 = h1_cells(n);
+  const long long nq = kNV + 1 + ns, nv = kNV + ns;
+  long long first, count;  // in doubles from the scratch start
+  if (array == 0) {
+    first = 0;
+    count = nq * grown;
+  } else if (array == 1) {
+    first = nq * grown;
+    count = h1;
+  } else {
+    first = nq * grown + (1 + nv * (array - 2)) * h1;
+    count = nv * h1;
+  }
+  *elems = count;
+  if (!out) return CTUPPM_OK;
+  const double* src = (const double*)((const char*)P->ws + off) + first;
+  HIPCHK(c, hipMemcpyAsync(out, src, size_t(count) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return CTUPPM_OK;
+}
+
 int ctuppm_set_wave_boxes(ctuppm_ctx* c, int boxes) {
   if (!c || boxes < 1) return CTUPPM_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));

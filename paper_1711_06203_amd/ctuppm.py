@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
             "ctuppm_average_down": [vp, ctypes.c_int],
             "ctuppm_reflux": [vp, ctypes.c_int],
             "ctuppm_set_wave_boxes": [vp, ctypes.c_int],
+            "ctuppm_debug_stage": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                   llp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -116,7 +118,8 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_stage_name", "ctuppm_stage_bytes", "ctuppm_set_tuning", "ctuppm_step_checked",
             "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid",
             "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
-            "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes"]
+            "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes",
+            "ctuppm_debug_stage"]
 
 
 class Context:
@@ -414,6 +417,28 @@ class Solver:
         s = cls(ctx, prob, form=form, fixed_dt=meta["fixed_dt"])
         s.steps_before = meta["steps_taken"]
         return s
+
+    STAGE_ARRAYS = (["q", "phi"] + [f"ql{d}" for d in range(3)] + [f"qr{d}" for d in range(3)] +
+                    [f"fn{d}" for d in range(3)] + [f"f1{p}" for p in range(6)] + [f"ff{d}" for d in range(3)])
+
+    def stage_array(self, box: int, name: str, level: int = 0, form=None) -> np.ndarray:
+        """An intermediate array of one box as the last step left it (names as
+        in STAGE_ARRAYS), shaped (components, nz', ny', nx') over the grown box
+        (q) or cells -1..n (the others)."""
+        torch = self.ctx.torch
+        f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
+        f = FORM_BATCHED if f == FORM_GRAPH else f
+        a = self.STAGE_ARRAYS.index(name)
+        n = ctypes.c_longlong()
+        self.ctx.call("ctuppm_debug_stage", self.pid, level, box, a, f, None, ctypes.byref(n))
+        out = torch.empty((n.value,), dtype=torch.float64, device=self.dev)
+        self.ctx.call("ctuppm_debug_stage", self.pid, level, box, a, f, ctypes.c_void_p(out.data_ptr()),
+                      ctypes.byref(n))
+        lo, hi = self.levels[level][box]
+        e = [hi[d] - lo[d] + 1 for d in range(3)]
+        g = 2 * NG if a == 0 else 2
+        shape = (-1, e[2] + g, e[1] + g, e[0] + g)
+        return out.cpu().numpy().reshape(shape)
 
     def set_fail_hook(self, step_index: int):
         self.ctx.call("ctuppm_set_fail_hook", self.pid, int(step_index))
