@@ -84,3 +84,17 @@ def test_per_box_form_keeps_the_last_box(ctx):
     s.step(1)
     _compare(s, prob, len(prob.boxes) - 1, form="per_box")
     s.close()
+
+
+def test_waves_form_keeps_each_slots_last_box(ctx):
+    """Waves of three boxes: the last wave's boxes left their arrays in the
+    three scratch slots."""
+    from paper_1711_06203_amd import ctuppm
+    ctx.set_wave_boxes(3)
+    prob = W.kelvin_helmholtz(n=(40, 36, 20), box=(16, 16, 20), nspec=1)  # 9 boxes
+    s = ctuppm.Solver(ctx, prob, form="waves")
+    s.step(1)
+    for b in (6, 7, 8):
+        _compare(s, prob, b, form="waves")
+    s.close()
+    ctx.set_wave_boxes(64)
