@@ -13,13 +13,22 @@
  *   - All functions are extern "C", return an int status (CTUPPM_OK = 0, < 0 on
  *     error) and never throw; ctuppm_last_error() gives the message of the last
  *     failure on a context.
- *   - Device memory for the state and the stage workspace is owned by the
- *     caller (the Python binding allocates it with PyTorch).  The library keeps
- *     the raw pointers and never frees them.  The library itself allocates only
- *     small device metadata tables (box records, work lists, problem records)
- *     and frees them in ctuppm_problem_destroy / ctuppm_ctx_destroy.
+ *   - Every byte of device memory is the caller's (the Python binding
+ *     allocates it with PyTorch): the state fabs and one workspace per
+ *     problem.  The library keeps the raw pointers, never frees them and
+ *     allocates no device memory.  Its device tables (the problem's records
+ *     with dt, parity and counters, box records, work lists, ghost-fill and
+ *     boundary tags, two-level tables) live at the start of the problem's
+ *     workspace (ctuppm_workspace_meta_bytes() bytes, then the stage
+ *     scratch) and are written by asynchronous copies on the context stream
+ *     from pinned host staging buffers the context owns.
  *   - Work is enqueued asynchronously on the context's HIP stream (caller's);
- *     only ctuppm_get_dt, ctuppm_status and ctuppm_stage_times synchronise it.
+ *     only ctuppm_get_dt, ctuppm_status, ctuppm_rejections,
+ *     ctuppm_step_checked and ctuppm_stage_times synchronise it (and
+ *     ctuppm_current_state after guarded steps).  Device buffers handed to the
+ *     library must stay allocated until the stream has passed the last call
+ *     that uses them (stream-ordered freeing, as PyTorch's allocator does on
+ *     the same stream, is enough).
  *   - One context per host thread.
  *
  * State layout: one "fab" per box, FP64, [comp][k][j][i] over the box grown by
@@ -52,7 +61,9 @@ enum {
   CTUPPM_EINVAL = -1,  /* bad argument (shapes, overlapping boxes, unknown id) */
   CTUPPM_ENOMEM = -2,  /* workspace smaller than ctuppm_workspace_bytes() */
   CTUPPM_EHIP = -3,    /* a HIP runtime call failed; see ctuppm_last_error */
-  CTUPPM_ESTATE = -4   /* call out of order (e.g. step before bind) */
+  CTUPPM_ESTATE = -4,  /* call out of order (e.g. step before bind) */
+  CTUPPM_ERETRY = -5   /* a step was rejected by the retry criterion; the current state is an
+                          accepted one (U^n when nothing was committed) */
 };
 /* Physical boundaries, per side of each direction: periodic (both sides);
  * outflow (ghost cells copy the edge cell); reflecting wall (ghost cells
@@ -123,12 +134,15 @@ int ctuppm_ctx_destroy(ctuppm_ctx* ctx);
 /* Message of the last error on ctx (static storage of the context). */
 const char* ctuppm_last_error(ctuppm_ctx* ctx);
 
-/* Define a problem: nlevels (1 or 2; refinement ratio 2), boxes[l] an array of
- * nboxes[l] boxes of level l.  Boxes of a level must not overlap, must lie in
- * the level's domain, have edges of at most 256 cells, and periodic domain
- * extents must be >= CTUPPM_NGHOST.
- * A fine level must lie at least 3 coarse cells inside the domain (section 3.2,
- * subcycled levels synchronised by refluxing).  nspec must be 0..16, scheme a
+/* Define a problem (the box list of each level, section 3): nlevels (1 or 2;
+ * refinement ratio 2), boxes[l] an array of nboxes[l] boxes of level l.  Boxes
+ * of a level must not overlap, must lie in the level's domain, have edges of
+ * at most 256 cells, and periodic domain extents must be >= CTUPPM_NGHOST.
+ * The fine level is any set of disjoint boxes aligned to coarse cells (even
+ * first and odd last indices), each at least 3 coarse cells inside the domain
+ * (section 3 and its figure 1: fine boxes of several sizes, grouped in
+ * several patches; section 3.2: subcycled levels synchronised by refluxing).
+ * nspec must be 0..16, scheme a
  * CTUPPM_SCHEME_* value, riemann a CTUPPM_RIEMANN_* value, limiter a
  * CTUPPM_LIMITER_* value, and a two-level
  * problem uses CTUPPM_SCHEME_CTU (CTUPPM_EINVAL otherwise).  *pid_out
@@ -137,19 +151,37 @@ int ctuppm_problem_create(ctuppm_ctx* ctx, const ctuppm_params* params, int nlev
                           const ctuppm_box* const* boxes, const int* nboxes, int* pid_out);
 int ctuppm_problem_destroy(ctuppm_ctx* ctx, int pid);
 
-/* Doubles in one fab of a box with nspec species: (5 + nspec)(nx+8)(ny+8)(nz+8).
- * CTUPPM_EINVAL for an empty box or nspec outside 0..16. */
+/* Doubles in one fab of a box with nspec species: (5 + nspec)(nx+8)(ny+8)(nz+8)
+ * (a box's state with its ghost cells, section 3).  CTUPPM_EINVAL for an
+ * empty box or nspec outside 0..16.  Needs no context. */
 int ctuppm_fab_elems(const ctuppm_box* box, int nspec, long long* elems);
 
-/* Bytes of stage workspace a problem needs in a form (the batched and graph
- * forms need scratch for all boxes at once, the per-box form for the largest). */
+/* Bytes of workspace a problem needs in a form: its device tables, the
+ * Runge-Kutta stage fabs of the MOL schemes, the stage scratch (the batched
+ * and graph forms hold every box's at once, the per-box form the largest
+ * box's, the waves form one per box of a wave) and, with two levels, the
+ * coarse region and the flux register (section 3.2).  The state of each box
+ * is resident and handed over by pointer (section 4); this is the scratch the
+ * advance needs beside it.  Depends on the boxes, nspec, the scheme and the
+ * wave size, not on the tuning. */
 int ctuppm_workspace_bytes(ctuppm_ctx* ctx, int pid, int form, size_t* bytes);
+/* Bytes at the start of the workspace that hold the library's device tables
+ * (the stage scratch follows).  Callers that poison or inspect the scratch
+ * leave these bytes alone. */
+int ctuppm_workspace_meta_bytes(ctuppm_ctx* ctx, int pid, size_t* bytes);
 
-/* Hand the library the device pointers of level `level`: U_a[b], U_b[b] are
- * the two fabs of box b (CTUPPM state layout), 8-byte aligned, caller-owned.
- * The state is taken to be in the A fabs. */
+/* Hand the library the device pointers of level `level` (each box's resident
+ * state, passed by pointer as in section 4): U_a[b], U_b[b] are the two fabs
+ * of box b (CTUPPM state layout), 8-byte aligned, caller-owned.  The state is
+ * taken to be in the A fabs (asynchronously: after the work enqueued before).
+ * Nothing is changed when a pointer is null or misaligned (CTUPPM_EINVAL). */
 int ctuppm_bind_state(ctuppm_ctx* ctx, int pid, int level, double* const* U_a, double* const* U_b);
-/* Hand the library the problem's workspace (device, 256-byte aligned). */
+/* Hand the library the problem's workspace (device, 256-byte aligned, at
+ * least ctuppm_workspace_meta_bytes() bytes; CTUPPM_ENOMEM otherwise).  Its
+ * first bytes receive the problem's device tables.  Re-binding a new
+ * workspace moves the problem's records (parity, dt, counters) to it with an
+ * asynchronous device copy, so the old workspace must stay allocated until the
+ * stream has passed this call. */
 int ctuppm_bind_workspace(ctuppm_ctx* ctx, int pid, void* workspace, size_t bytes);
 
 /* Use a fixed dt (> 0) instead of the CFL time step; dt <= 0 restores CFL. */
@@ -164,16 +196,35 @@ int ctuppm_set_fixed_dt(ctuppm_ctx* ctx, int pid, double dt);
  * otherwise); a two-level problem steps on its own.  Asynchronous. */
 int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
 
-/* One step of a single-level problem with the retry criterion of the paper's
- * retry mechanism (section 3.2, a step redone on criteria evaluated during the
- * integration): after the step (synchronising), if any new cell failed
- * (rho < small_dens, p < small_pres or non-finite, counter [4] of
- * ctuppm_status), the step is rejected -- U^n is still intact in the other fab
- * -- and redone as two steps of half the rejected dt.  *retried = 1 then. */
+/* Guarded steps: the retry criterion of the paper's retry mechanism (section
+ * 3.2, a step redone on criteria evaluated during the integration) checked on
+ * the device.  Like ctuppm_step (single-level problems), but a problem whose
+ * new state failed anywhere (a cell with rho < small_dens, p < small_pres or a
+ * non-finite value, counter [4] of ctuppm_status) does not commit it: U^n stays
+ * current (it is intact in the other fab) and the device counts a rejection,
+ * which it also writes to host-mapped memory.  In the accepted case nothing
+ * synchronises.  Returns CTUPPM_ERETRY, enqueuing nothing, when the host
+ * already sees an unacknowledged rejection of a listed problem; the caller then
+ * calls ctuppm_rejections (which acknowledges) and redoes the step with a
+ * smaller dt (ctuppm_step_checked does that).  Steps enqueued after a rejected
+ * one start again from U^n. */
+int ctuppm_step_guarded(ctuppm_ctx* ctx, const int* pids, int npids, int form);
+/* Rejected guarded steps of problem pid so far (synchronises); acknowledges
+ * them, so ctuppm_step_guarded accepts the problem again. */
+int ctuppm_rejections(ctuppm_ctx* ctx, int pid, long long* rejected);
+/* One step of a single-level problem with the retry mechanism (section 3.2):
+ * a guarded step (synchronising for the verdict); if it is rejected, the
+ * interval of the rejected dt is redone as two guarded steps of half of it,
+ * and a rejected half again in two halves, down to an eighth of the dt.
+ * *retried = the number of halvings the deepest retry used (0: accepted at
+ * once).  CTUPPM_ERETRY when an eighth step is still rejected: the current
+ * state is then the last accepted one (U^n if no part of the interval was
+ * committed). */
 int ctuppm_step_checked(ctuppm_ctx* ctx, int pid, int form, int* retried);
 /* Test hook: the update flags one failed cell at step index step_index
- * (0-based count of accepted steps), -1 turns it off.  Forced from the host so
- * every kernel still runs to completion. */
+ * (0-based count of accepted steps), -1 turns it off; a guarded step rejected
+ * for it turns the hook off.  Forced from the host so every kernel still runs
+ * to completion. */
 int ctuppm_set_fail_hook(ctuppm_ctx* ctx, int pid, int step_index);
 
 /* ------------------------------------------------------- a step in pieces
@@ -229,14 +280,19 @@ int ctuppm_average_down(ctuppm_ctx* ctx, int pid);
  * becomes current and the step is complete. */
 int ctuppm_reflux(ctuppm_ctx* ctx, int pid);
 
-/* Which fab (0 = A, 1 = B) holds the current state of problem pid. */
+/* Which fab (0 = A, 1 = B) holds the current level-0 state of problem pid
+ * (the state resident per box, section 4; the steps alternate between the two
+ * fabs).  Synchronises after guarded steps, whose verdict only the device
+ * knows. */
 int ctuppm_current_state(ctuppm_ctx* ctx, int pid, int* which);
-/* dt of the last step (synchronises the stream). */
+/* dt of the last step, from the CFL condition or the fixed dt (synchronises
+ * the stream; CTUPPM_ESTATE before a workspace is bound). */
 int ctuppm_get_dt(ctuppm_ctx* ctx, int pid, double* dt_host);
 /* Counters (synchronises): [0] density floors, [1] pressure floors in
  * cons->prim, [2] floors on traced states, [3] transverse fall-backs,
  * [4] cells whose new state failed (rho < small_dens, p < small_pres or
- * non-finite), [5] steps taken. */
+ * non-finite: the criteria of the retry mechanism, section 3.2), [5] steps
+ * committed.  All zero before a workspace is bound. */
 int ctuppm_status(ctuppm_ctx* ctx, int pid, long long counters[6]);
 
 /* Per-stage timing of eager launches: enable (1) or disable (0).  While on,
@@ -282,15 +338,17 @@ int ctuppm_tag(ctuppm_ctx* ctx, int pid, double threshold, unsigned char* tags);
 int ctuppm_cluster(const unsigned char* tags, const int n[3], int blocking, double efficiency, int max_edge,
                    ctuppm_box* boxes, int capacity, int* nboxes);
 
-/* Replace the fine level of two-level problem pid by new boxes (one rectangle
- * tiled by boxes, the same rules as in ctuppm_problem_create) with new
- * caller-owned fabs Ua[b], Ub[b].  The new fine state goes to Ua: cells inside
- * the old fine rectangle are copied from the old fine state, the others are
- * interpolated conservatively from the current coarse state (MC-limited
- * linear, the coarse-fine ghost interpolation at the start of a step).  Call
- * between steps; the old fabs may be freed after the next synchronisation.
- * The workspace must then be re-bound with ctuppm_workspace_bytes() bytes
- * before the next step (CTUPPM_ENOMEM otherwise).  Asynchronous. */
+/* Replace the fine level of two-level problem pid by new boxes (the same
+ * rules as in ctuppm_problem_create; for instance the boxes ctuppm_cluster
+ * returns, scaled to the fine index space) with new caller-owned fabs Ua[b],
+ * Ub[b].  The new fine state goes to Ua: cells under an old fine box are
+ * copied from the old fine state, the others are interpolated conservatively
+ * from the current coarse state (MC-limited linear, the coarse-fine ghost
+ * interpolation at the start of a step).  Works in the stage scratch of the
+ * bound workspace (which must hold the batched form's bytes).  Call between
+ * steps; the old fabs may be freed once the stream has passed this call.  The
+ * workspace must then be re-bound with ctuppm_workspace_bytes() bytes before
+ * the next step (CTUPPM_ENOMEM otherwise).  Asynchronous. */
 int ctuppm_regrid(ctuppm_ctx* ctx, int pid, const ctuppm_box* fine_boxes, int nfine, double* const* Ua,
                   double* const* Ub);
 
@@ -314,7 +372,11 @@ int ctuppm_set_concurrency(ctuppm_ctx* ctx, int on);
  * each halo-1 array is [component][k][j][i] over cells -1..n (a face array
  * holds face f of cell f's lower side), fluxes in global component order.
  * In the per-box form every box shares one scratch (the last box stepped);
- * in the waves form box b uses slot b mod the wave size. */
+ * in the waves form box b uses slot b mod the wave size.  The stage arrays
+ * are the intermediates of the advance of section 3.2 (primitives, PPM face
+ * states, Riemann fluxes of the unsplit corner transport); a two-level
+ * problem takes the batched form only, and an array that would end past the
+ * bound workspace is refused (CTUPPM_ENOMEM) without a copy. */
 int ctuppm_debug_stage(ctuppm_ctx* ctx, int pid, int level, int box, int array, int form, double* out,
                        long long* elems);
 

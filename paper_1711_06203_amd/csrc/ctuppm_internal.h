@@ -55,7 +55,10 @@ struct ProbDev {
   int riemann;                     // 0 HLLC, 1 two-shock
   int limiter;                     // 0 CW84, 1 Colella & Sekora
   int steepen;                     // CW84 contact steepening of the density
-  int pad4;
+  int rejected;                    // guarded steps rejected (their new state failed)
+  unsigned long long fail_mark;    // failure count [4] when the last step was committed or rejected
+  int* hflag;                      // host-mapped copy of `rejected` (read by the host without a sync)
+  int pad5[2];
   // running max of the signal speed as bit patterns (>= 0), one 128-byte
   // line per slot so blocks of one launch do not contend on one address
   unsigned long long smax[kSlots][16];
@@ -79,7 +82,25 @@ struct Chunk { int box; int start; };  // tag index, first item (ghost-fill work
 // Column-march work unit: items [start, min(start+256, end)) of the (x, y)
 // plane of a box region (i fastest), for the box-local planes z in [z0, z1),
 // visited in order.
-struct March { int box; int start; int end; int z0; int z1; int pad; };
+struct March { int box; int start; int end; int z0; int z1; int pad; };  // 32-bit fields: shorts cost VGPRs
+
+// One launch covers the work of up to kMaxSeg problems: segment s holds the
+// problem's box records, its work list (march units or tag chunks, with box
+// and tag indices local to the problem), its tags and its record; items
+// beg[s] .. beg[s+1]-1 of the launch are items 0.. of segment s.  Passed by
+// value as a kernel argument, so a launch needs no device table of its own.
+constexpr int kMaxSeg = 16;
+struct Seg {
+  const BoxRec* boxes;
+  const void* work;
+  const void* tags;
+  ProbDev* P;
+};
+struct Segs {
+  int n;
+  int beg[kMaxSeg + 1];
+  Seg s[kMaxSeg];
+};
 
 // Same-level ghost copy: dst-local cells [lo, lo+ext) <- src-local (cell + off).
 struct FillTag { int dst, src; int lo[3]; int ext[3]; int off[3]; int pad; };
@@ -165,10 +186,7 @@ __host__ __device__ inline int stage_region(int stage) {
 }
 
 struct Launch {
-  const BoxRec* boxes;
-  const void* tags;    // FillTag / BcTag for fill stages
-  const void* work;    // Chunk list (fill stages) or March list (cell stages)
-  int nwork;
+  Segs segs;           // problems, their work lists and tags
   int grid;            // blocks (multiple of 8)
   hipStream_t stream;
   int arr = kArrCur;   // array read by fill / boundaries / cons->prim / MOL update
@@ -197,13 +215,17 @@ hipError_t launch_dt2(ProbDev* Pc, ProbDev* Pf, hipStream_t s);
 // Regridding: density-jump tags of level-0 valid cells into a dense domain
 // array (dn = domain extent, dlo = its first index), and the new fine state
 // of a regrid.
-hipError_t launch_tag(const BoxRec* boxes, const March* units, int nunits, double threshold, unsigned char* tags,
-                      const int dn[3], const int dlo[3], hipStream_t s);
+hipError_t launch_tag(const Segs& L, int grid, double threshold, unsigned char* tags, const int dn[3],
+                      const int dlo[3], hipStream_t s);
 hipError_t launch_prolong(const TwoLevelArgs& A, const BoxRec* newf, const BoxRec* oldf, const ProlongTag* tags,
                           const Chunk* chunks, int n, hipStream_t s);
-hipError_t launch_dt(ProbDev* const* probs, int nprobs, hipStream_t s);
+// dt of every problem of the segments from its signal-speed slots (or its fixed dt).
+hipError_t launch_dt(const Segs& L, hipStream_t s);
 hipError_t launch_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt, hipStream_t s);
-hipError_t launch_flip(ProbDev* const* probs, int nprobs, hipStream_t s);
+// Commit the new state of every problem of the segments (flip the current
+// fab, count the step).  guard = 1: a problem whose failure count grew during
+// the step keeps its old state and counts a rejection instead.
+hipError_t launch_flip(const Segs& L, int guard, hipStream_t s);
 const char* stage_name(int stage);
 
 }  // namespace ctu

@@ -38,6 +38,41 @@ CTU_DEV void for_each_chunk(int nchunks, F&& f) {
   for (int c = beg + local; c < end; c += per) f(c);
 }
 
+// Segment of launch item c (block-uniform: a scalar scan over the kernel
+// argument).
+CTU_DEV int seg_of(const Segs& L, int c) {
+  int s = 0;
+  while (s + 1 < L.n && c >= L.beg[s + 1]) ++s;
+  return s;
+}
+
+// The unit's record and box through restrict-qualified pointers: the
+// kernels' stores then cannot alias them, so their fields stay in registers
+// (without it the transverse kernel needs 30-40 more VGPRs).
+template <class F>
+CTU_DEV void unit_body(const March* __restrict__ w, const BoxRec* __restrict__ bx, int i, F&& f) {
+  const March M = w[i];
+  f(M, bx[M.box]);
+}
+
+// Visit the march units of a launch: f(unit, its box).
+template <class F>
+CTU_DEV void for_each_unit(const Segs& L, F&& f) {
+  for_each_chunk(L.beg[L.n], [&](int c) {
+    const int s = seg_of(L, c);
+    unit_body((const March*)L.s[s].work, L.s[s].boxes, c - L.beg[s], f);
+  });
+}
+
+// Visit the tag chunks of a launch: f(chunk, its segment).
+template <class F>
+CTU_DEV void for_each_tag_chunk(const Segs& L, F&& f) {
+  for_each_chunk(L.beg[L.n], [&](int c) {
+    const int s = seg_of(L, c);
+    f(((const Chunk*)L.s[s].work)[c - L.beg[s]], L.s[s]);
+  });
+}
+
 // Visit the (i, j, k) items of a march unit in region `kind`; f(i, j, k) is
 // called for the lane's (i, j) at every plane of the unit.  Lanes past the
 // plane's end skip all planes (no barrier inside f).
@@ -112,22 +147,19 @@ CTU_DEV double* state_arr(const BoxRec& B, int arr) {
 
 // ---------------------------------------------------------------- ghost fill
 
-__global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxes,
-                                                 const FillTag* __restrict__ tags,
-                                                 const Chunk* __restrict__ chunks, int nchunks, int arr) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const FillTag T = tags[ch.box];
+__global__ __launch_bounds__(kBlock) void k_fill(const Segs L, int arr) {
+  for_each_tag_chunk(L, [&](const Chunk& ch, const Seg& S) {
+    const FillTag T = ((const FillTag*)S.tags)[ch.box];
     const int t = ch.start + threadIdx.x;
     if (t >= T.ext[0] * T.ext[1] * T.ext[2]) return;
     const int i = T.lo[0] + t % T.ext[0];
     const int r = t / T.ext[0];
     const int j = T.lo[1] + r % T.ext[1];
     const int k = T.lo[2] + r / T.ext[1];
-    const BoxRec& D = boxes[T.dst];
-    const BoxRec& S = boxes[T.src];
-    const Geo gd(D.n, D.ns), gs(S.n, S.ns);
-    const gdbl* __restrict__ src = gp(state_arr(S, arr));
+    const BoxRec& D = S.boxes[T.dst];
+    const BoxRec& Sb = S.boxes[T.src];
+    const Geo gd(D.n, D.ns), gs(Sb.n, Sb.ns);
+    const gdbl* __restrict__ src = gp(state_arr(Sb, arr));
     gdbl* __restrict__ dst = gp(state_arr(D, arr));
     const int si = gs.g(i + T.off[0], j + T.off[1], k + T.off[2]);
     const int di = gd.g(i, j, k);
@@ -140,12 +172,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(const BoxRec* __restrict__ boxe
 // Physical boundary of one direction D: outflow copies the edge cell, reflect
 // mirrors with the normal momentum negated, inflow writes a fixed state.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
-                                               const BcTag* __restrict__ tags,
-                                               const Chunk* __restrict__ chunks, int nchunks, int arr) {
-  for_each_chunk(nchunks, [&](int c) {
-    const Chunk ch = chunks[c];
-    const BcTag& T = tags[ch.box];  // by reference: the inflow state is indexed at run time
+__global__ __launch_bounds__(kBlock) void k_bc(const Segs L, int arr) {
+  for_each_tag_chunk(L, [&](const Chunk& ch, const Seg& S) {
+    const BcTag& T = ((const BcTag*)S.tags)[ch.box];  // by reference: the inflow state is indexed at run time
     const int t = ch.start + threadIdx.x;
     if (t >= T.ext[0] * T.ext[1] * T.ext[2]) return;
     int x[3];
@@ -153,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_bc(const BoxRec* __restrict__ boxes,
     const int r = t / T.ext[0];
     x[1] = T.lo[1] + r % T.ext[1];
     x[2] = T.lo[2] + r / T.ext[1];
-    const BoxRec& B = boxes[T.box];
+    const BoxRec& B = S.boxes[T.box];
     const Geo g(B.n, B.ns);
     gdbl* __restrict__ U = gp(state_arr(B, arr));
     const int di = g.g(x[0], x[1], x[2]);
@@ -204,14 +233,11 @@ CTU_DEV void flush_max(ProbDev* P, double m, double* lds) {
 // the per-box form, whose boxes share one scratch, reduces first (CFL only)
 // and stores q box by box after dt is known.
 template <bool WQ, bool CFL>
-__global__ __launch_bounds__(kBlock) void k_c2p(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
-                                                int nunits, int arr) {
+__global__ __launch_bounds__(kBlock) void k_c2p(const Segs L, int arr) {
   __shared__ double lds[kBlock / 64];
   double smax = 0.0;
   ProbDev* curP = nullptr;
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     ProbDev* P = B.P;
     if (P != curP) {  // block-uniform: flush the running max of the previous problem
       if (CFL && curP) flush_max(curP, smax, lds);
@@ -270,10 +296,10 @@ CTU_DEV void set_dt(ProbDev* P, double dt) {
   }
 }
 
-__global__ void k_dt(ProbDev* const* probs, int nprobs) {
+__global__ void k_dt(const Segs L) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nprobs) return;
-  ProbDev* P = probs[t];
+  if (t >= L.n) return;
+  ProbDev* P = L.s[t].P;
   unsigned long long bits = 0ull;
   for (int q = 0; q < kSlots; ++q) {
     bits = P->smax[q][0] > bits ? P->smax[q][0] : bits;
@@ -292,12 +318,24 @@ __global__ void k_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt) {
   if (Pf) set_dt(Pf, 0.5 * v);
 }
 
-__global__ void k_flip(ProbDev* const* probs, int nprobs) {
+// Commit a step (flip the current fab, count it).  A guarded step whose
+// failure count grew is not committed: the old state stays current (it is
+// intact in the other fab), the rejection is counted and mirrored to the
+// host-mapped flag the host reads without synchronising.
+__global__ void k_flip(const Segs L, int guard) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nprobs) return;
-  ProbDev* P = probs[t];
-  P->cur ^= 1;
-  P->nsteps += 1;
+  if (t >= L.n) return;
+  ProbDev* P = L.s[t].P;
+  const unsigned long long nf = P->cnt[4];
+  if (guard && nf != P->fail_mark) {
+    P->rejected += 1;
+    if (P->fail_step == P->nsteps) P->fail_step = -1;  // the test hook fires once
+    if (P->hflag) __hip_atomic_store(P->hflag, P->rejected, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  } else {
+    P->cur ^= 1;
+    P->nsteps += 1;
+  }
+  P->fail_mark = nf;
 }
 
 // ---------------------------------------------------------------- flattening
@@ -312,11 +350,8 @@ CTU_DEV double shock_ind(const gdbl* __restrict__ p, const gdbl* __restrict__ un
   return f;
 }
 
-__global__ __launch_bounds__(kBlock) void k_flatten(const BoxRec* __restrict__ boxes,
-                                                    const March* __restrict__ units, int nunits) {
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+__global__ __launch_bounds__(kBlock) void k_flatten(const Segs L) {
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
     const gdbl* __restrict__ p = q + 4 * g.gcomp;
@@ -354,13 +389,10 @@ CTU_DEV void store_flux(gdbl* __restrict__ F, int hcomp, int o, const double f[5
 // state of the upper face and the right state of the lower face are stored
 // for faces 0..n.
 template <int D, int LIM>
-__global__ __launch_bounds__(kBlock) void k_trace(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
-                                                  int nunits) {
+__global__ __launch_bounds__(kBlock) void k_trace(const Segs L) {
   constexpr int zpos = 1 + (2 - D + 3) % 3;  // permuted slot of the z velocity
   constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
@@ -448,11 +480,8 @@ CTU_DEV void wall_mirror(int side, double L[5], double R[5]) {
 
 // Normal flux of every face 0..n along D (cells -1..n across).
 template <int D, int RS>
-__global__ __launch_bounds__(kBlock) void k_riemann(const BoxRec* __restrict__ boxes,
-                                                    const March* __restrict__ units, int nunits) {
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+__global__ __launch_bounds__(kBlock) void k_riemann(const Segs L) {
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ ql = g.ql(B.scr, D);
@@ -513,11 +542,8 @@ CTU_DEV int to_prim_or_keep(const double U[5], const double s0[5], double gm1, d
 // B-flux difference across their owner cell, for B = the two other
 // directions, then the Riemann flux -> F^{A|B}.
 template <int A, int RS>
-__global__ __launch_bounds__(kBlock) void k_trans1(const BoxRec* __restrict__ boxes,
-                                                   const March* __restrict__ units, int nunits) {
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+__global__ __launch_bounds__(kBlock) void k_trans1(const Segs L) {
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     const int sa = g.hstride(A);
@@ -638,11 +664,8 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
 
 // Stage 2 along A over faces 0..n (cells 0..n-1 across): final fluxes.
 template <int A, int RS>
-__global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ boxes,
-                                                   const March* __restrict__ units, int nunits) {
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+__global__ __launch_bounds__(kBlock) void k_trans2(const Segs L) {
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     gdbl* __restrict__ ff = g.ff(B.scr, A);
@@ -657,11 +680,8 @@ __global__ __launch_bounds__(kBlock) void k_trans2(const BoxRec* __restrict__ bo
 // Conservative update U^{n+1} = U^n + sum_d dt/dx_d (F_lo - F_hi) in the order
 // x, y, z, the trapezoid gravity corrector on rho w then rho E, and the
 // failure check (rho < small_dens, p < small_pres or a non-finite value).
-__global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ boxes,
-                                                   const March* __restrict__ units, int nunits) {
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+__global__ __launch_bounds__(kBlock) void k_update(const Segs L) {
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ U = gp(B.U[P->cur]);
@@ -729,12 +749,9 @@ __global__ __launch_bounds__(kBlock) void k_update(const BoxRec* __restrict__ bo
 // parabola is the left state of its upper face, the lower edge value the
 // right state of its lower face (both floored like the traced states).
 template <int D, int LIM>
-__global__ __launch_bounds__(kBlock) void k_recon(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
-                                                  int nunits) {
+__global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
   constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
@@ -791,12 +808,9 @@ __global__ __launch_bounds__(kBlock) void k_recon(const BoxRec* __restrict__ box
 // rho w) of Us; written as T, or as U0 + c (T - U0) with U0 the current fab
 // (the convex combinations of the SSP methods, in a form that keeps a
 // constant state exactly constant).  Failures are counted as in k_update.
-__global__ __launch_bounds__(kBlock) void k_mol_update(const BoxRec* __restrict__ boxes,
-                                                       const March* __restrict__ units, int nunits, int arr,
+__global__ __launch_bounds__(kBlock) void k_mol_update(const Segs L, int arr,
                                                        int out, int comb, double c, int last) {
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ Us = gp(state_arr(B, arr));
@@ -1020,12 +1034,9 @@ __global__ void k_reflux(TwoLevelArgs A, const RegFace* __restrict__ faces, int 
 
 // Tag a level-0 valid cell when its density jumps across it along some
 // direction by more than `thr` relative to the two neighbours (ghosts filled).
-__global__ __launch_bounds__(kBlock) void k_tag(const BoxRec* __restrict__ boxes, const March* __restrict__ units,
-                                                int nunits, double thr, unsigned char* __restrict__ tags, int dnx,
+__global__ __launch_bounds__(kBlock) void k_tag(const Segs L, double thr, unsigned char* __restrict__ tags, int dnx,
                                                 int dny, int dlx, int dly, int dlz) {
-  for_each_chunk(nunits, [&](int u) {
-    const March M = units[u];
-    const BoxRec& B = boxes[M.box];
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ U = gp(B.U[B.P->cur]);
     march(kValid, B, M, [&](int i, int j, int k) {
@@ -1123,36 +1134,31 @@ const char* stage_name(int s) {
 }
 
 hipError_t launch_stage(int stage, const Launch& L) {
-  if (L.nwork <= 0) return hipSuccess;
+  const Segs& G = L.segs;
+  if (G.n <= 0 || G.beg[G.n] <= 0) return hipSuccess;
   const dim3 grid(L.grid), block(kBlock);
-  const Chunk* ch = (const Chunk*)L.work;
-  const March* mu = (const March*)L.work;
-  const int n = L.nwork;
   hipStream_t s = L.stream;
-#define CTU_LIM(K, D)                                                                  \
-  (L.lim == 1   ? K<D, 1><<<grid, block, 0, s>>>(L.boxes, mu, n)                        \
-   : L.lim == 2 ? K<D, 2><<<grid, block, 0, s>>>(L.boxes, mu, n)                        \
-                : K<D, 0><<<grid, block, 0, s>>>(L.boxes, mu, n))
+#define CTU_LIM(K, D)                                                        \
+  (L.lim == 1   ? K<D, 1><<<grid, block, 0, s>>>(G)                          \
+   : L.lim == 2 ? K<D, 2><<<grid, block, 0, s>>>(G)                          \
+                : K<D, 0><<<grid, block, 0, s>>>(G))
   switch (stage) {
-    case kStFill: k_fill<<<grid, block, 0, s>>>(L.boxes, (const FillTag*)L.tags, ch, n, L.arr); break;
-    case kStBcX: k_bc<0><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;
-    case kStBcY: k_bc<1><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;
-    case kStBcZ: k_bc<2><<<grid, block, 0, s>>>(L.boxes, (const BcTag*)L.tags, ch, n, L.arr); break;
-    case kStC2P: k_c2p<true, true><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
-    case kStCfl: k_c2p<false, true><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
-    case kStC2POnly: k_c2p<true, false><<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr); break;
+    case kStFill: k_fill<<<grid, block, 0, s>>>(G, L.arr); break;
+    case kStBcX: k_bc<0><<<grid, block, 0, s>>>(G, L.arr); break;
+    case kStBcY: k_bc<1><<<grid, block, 0, s>>>(G, L.arr); break;
+    case kStBcZ: k_bc<2><<<grid, block, 0, s>>>(G, L.arr); break;
+    case kStC2P: k_c2p<true, true><<<grid, block, 0, s>>>(G, L.arr); break;
+    case kStCfl: k_c2p<false, true><<<grid, block, 0, s>>>(G, L.arr); break;
+    case kStC2POnly: k_c2p<true, false><<<grid, block, 0, s>>>(G, L.arr); break;
     case kStReconX: CTU_LIM(k_recon, 0); break;
     case kStReconY: CTU_LIM(k_recon, 1); break;
     case kStReconZ: CTU_LIM(k_recon, 2); break;
-    case kStMolUpdate:
-      k_mol_update<<<grid, block, 0, s>>>(L.boxes, mu, n, L.arr, L.out, L.comb, L.c, L.last);
-      break;
-    case kStFlatten: k_flatten<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStMolUpdate: k_mol_update<<<grid, block, 0, s>>>(G, L.arr, L.out, L.comb, L.c, L.last); break;
+    case kStFlatten: k_flatten<<<grid, block, 0, s>>>(G); break;
     case kStTraceX: CTU_LIM(k_trace, 0); break;
     case kStTraceY: CTU_LIM(k_trace, 1); break;
     case kStTraceZ: CTU_LIM(k_trace, 2); break;
-#define CTU_RS(K, D) \
-  (L.rs ? K<D, 1><<<grid, block, 0, s>>>(L.boxes, mu, n) : K<D, 0><<<grid, block, 0, s>>>(L.boxes, mu, n))
+#define CTU_RS(K, D) (L.rs ? K<D, 1><<<grid, block, 0, s>>>(G) : K<D, 0><<<grid, block, 0, s>>>(G))
     case kStRiemX: CTU_RS(k_riemann, 0); break;
     case kStRiemY: CTU_RS(k_riemann, 1); break;
     case kStRiemZ: CTU_RS(k_riemann, 2); break;
@@ -1163,7 +1169,7 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStT2Y: CTU_RS(k_trans2, 1); break;
     case kStT2Z: CTU_RS(k_trans2, 2); break;
 #undef CTU_RS
-    case kStUpdate: k_update<<<grid, block, 0, s>>>(L.boxes, mu, n); break;
+    case kStUpdate: k_update<<<grid, block, 0, s>>>(G); break;
     default: return hipErrorInvalidValue;
   }
 #undef CTU_LIM
@@ -1208,11 +1214,10 @@ hipError_t launch_reflux(const TwoLevelArgs& A, const RegFace* faces, int n, hip
   return hipGetLastError();
 }
 
-hipError_t launch_tag(const BoxRec* boxes, const March* units, int nunits, double threshold, unsigned char* tags,
-                      const int dn[3], const int dlo[3], hipStream_t s) {
-  if (nunits <= 0) return hipSuccess;
-  k_tag<<<(nunits + 7) / 8 * 8, kBlock, 0, s>>>(boxes, units, nunits, threshold, tags, dn[0], dn[1], dlo[0], dlo[1],
-                                                dlo[2]);
+hipError_t launch_tag(const Segs& L, int grid, double threshold, unsigned char* tags, const int dn[3],
+                      const int dlo[3], hipStream_t s) {
+  if (L.n <= 0 || L.beg[L.n] <= 0) return hipSuccess;
+  k_tag<<<grid, kBlock, 0, s>>>(L, threshold, tags, dn[0], dn[1], dlo[0], dlo[1], dlo[2]);
   return hipGetLastError();
 }
 
@@ -1233,15 +1238,15 @@ hipError_t launch_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_dt(ProbDev* const* probs, int nprobs, hipStream_t s) {
-  if (nprobs <= 0) return hipSuccess;
-  k_dt<<<(nprobs + 63) / 64, 64, 0, s>>>(probs, nprobs);
+hipError_t launch_dt(const Segs& L, hipStream_t s) {
+  if (L.n <= 0) return hipSuccess;
+  k_dt<<<1, 64, 0, s>>>(L);
   return hipGetLastError();
 }
 
-hipError_t launch_flip(ProbDev* const* probs, int nprobs, hipStream_t s) {
-  if (nprobs <= 0) return hipSuccess;
-  k_flip<<<(nprobs + 63) / 64, 64, 0, s>>>(probs, nprobs);
+hipError_t launch_flip(const Segs& L, int guard, hipStream_t s) {
+  if (L.n <= 0) return hipSuccess;
+  k_flip<<<1, 64, 0, s>>>(L, guard);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ from . import workloads as W
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libctuppm.so")
 
-OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EHIP, ESTATE, ERETRY = 0, -1, -2, -3, -4, -5
 FORM_PER_BOX, FORM_BATCHED, FORM_GRAPH, FORM_WAVES = 0, 1, 2, 3
 FORMS = {"per_box": FORM_PER_BOX, "batched": FORM_BATCHED, "graph": FORM_GRAPH, "waves": FORM_WAVES}
 SCHEME_CTU, SCHEME_MOL_RK2, SCHEME_MOL_RK3 = 0, 1, 2
@@ -31,7 +31,13 @@ NG = 4
 
 
 class CtuError(RuntimeError):
-    pass
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
+
+
+class Rejected(CtuError):
+    """A guarded step was rejected by the retry criterion (CTUPPM_ERETRY)."""
 
 
 class Box(ctypes.Structure):
@@ -69,6 +75,9 @@ def lib() -> ctypes.CDLL:
             "ctuppm_problem_destroy": [vp, ctypes.c_int],
             "ctuppm_fab_elems": [ctypes.POINTER(Box), ctypes.c_int, llp],
             "ctuppm_workspace_bytes": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)],
+            "ctuppm_workspace_meta_bytes": [vp, ctypes.c_int, ctypes.POINTER(sz)],
+            "ctuppm_step_guarded": [vp, ip, ctypes.c_int, ctypes.c_int],
+            "ctuppm_rejections": [vp, ctypes.c_int, llp],
             "ctuppm_bind_state": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp)],
             "ctuppm_bind_workspace": [vp, ctypes.c_int, vp, sz],
             "ctuppm_set_fixed_dt": [vp, ctypes.c_int, ctypes.c_double],
@@ -119,7 +128,7 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid",
             "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
             "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes",
-            "ctuppm_debug_stage"]
+            "ctuppm_debug_stage", "ctuppm_workspace_meta_bytes", "ctuppm_step_guarded", "ctuppm_rejections"]
 
 
 class Context:
@@ -139,7 +148,8 @@ class Context:
     def _check(self, rc, h=-1):
         if rc != OK:
             msg = self._L.ctuppm_last_error(self.h if h == -1 else h)
-            raise CtuError(f"ctuppm error {rc}: {msg.decode() if msg else ''}")
+            text = f"ctuppm error {rc}: {msg.decode() if msg else ''}"
+            raise (Rejected if rc == ERETRY else CtuError)(text, rc)
 
     def call(self, name, *args):
         self._check(getattr(self._L, name)(self.h, *args))
@@ -177,9 +187,11 @@ class Context:
     def set_tuning(self, blocks_per_cu: int = 0, zseg_batched: int = 1, zseg_per_box: int = 1, ytile: int = 0):
         self.call("ctuppm_set_tuning2", int(blocks_per_cu), int(zseg_batched), int(zseg_per_box), int(ytile))
 
-    def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1):
+    def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1, guarded: bool = False):
         """Advance several problems together: one batched launch set per step
-        for the problems of each (scheme, Riemann solver, limiter)."""
+        for the problems of each (scheme, Riemann solver, limiter).  guarded:
+        a problem whose new state fails keeps its old one (raises Rejected
+        once the host sees a rejection)."""
         f = FORMS[form] if isinstance(form, str) else int(form)
         groups: Dict[tuple, List[int]] = {}
         for s in solvers:
@@ -188,7 +200,7 @@ class Context:
         sets = [(ctypes.c_int * len(v))(*v) for _, v in sorted(groups.items())]
         for _ in range(nsteps):
             for pids in sets:
-                self.call("ctuppm_step", pids, len(pids), f)
+                self.call("ctuppm_step_guarded" if guarded else "ctuppm_step", pids, len(pids), f)
 
 
 def cluster(tags: np.ndarray, blocking: int = 4, efficiency: float = 0.7, max_edge: int = 64) -> List[W.Box]:
@@ -312,8 +324,15 @@ class Solver:
         for f in forms:
             self.ctx.call("ctuppm_workspace_bytes", self.pid, f, ctypes.byref(ws))
             best = max(best, ws.value)
-        self.ws = self.ctx.torch.empty((max(best, 256),), dtype=self.ctx.torch.uint8, device=self.dev)
-        self.ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel())
+        ws = self.ctx.torch.empty((max(best, 256),), dtype=self.ctx.torch.uint8, device=self.dev)
+        self.ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(ws.data_ptr()), ws.numel())
+        self.ws = ws  # the old workspace (records copied from it on the stream) is released after the bind
+
+    def meta_bytes(self) -> int:
+        """Bytes at the start of the workspace holding the library's device tables."""
+        v = ctypes.c_size_t()
+        self.ctx.call("ctuppm_workspace_meta_bytes", self.pid, ctypes.byref(v))
+        return v.value
 
     # backwards-compatible views of level 0
     @property
@@ -349,12 +368,25 @@ class Solver:
         f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
         self.ctx.step([self], f, nsteps)
 
-    def step_checked(self, form=None) -> bool:
-        """One step with the retry criterion; True if it was redone as two half steps."""
+    def step_checked(self, form=None) -> int:
+        """One step with the retry criterion; the number of halvings of dt its
+        deepest retry used (0: accepted at once).  Raises Rejected when even an
+        eighth of the step fails (the state is then the last accepted one)."""
         f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
         r = ctypes.c_int()
         self.ctx.call("ctuppm_step_checked", self.pid, f, ctypes.byref(r))
-        return bool(r.value)
+        return int(r.value)
+
+    def step_guarded(self, nsteps: int = 1, form=None):
+        """Guarded steps (no synchronisation): a failing step is not committed."""
+        f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
+        self.ctx.step([self], f, nsteps, guarded=True)
+
+    def rejections(self) -> int:
+        """Guarded steps rejected so far (synchronises; acknowledges them)."""
+        v = ctypes.c_longlong()
+        self.ctx.call("ctuppm_rejections", self.pid, ctypes.byref(v))
+        return int(v.value)
 
     # a step in pieces, in the paper's order: ghost fill, dt, advance per level,
     # average down, reflux (the graph form is the whole step's, pieces run batched)

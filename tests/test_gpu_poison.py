@@ -1,6 +1,6 @@
-"""Uninitialised reads: before every step the whole workspace (stage scratch,
-Runge-Kutta stage fabs, two-level buffers and flux register) is set to NaN
-bytes, the fab the step writes is set to NaN and so are the ghost cells of
+"""Uninitialised reads: before every step the whole workspace after the
+library's device tables (stage scratch, Runge-Kutta stage fabs, two-level
+buffers and flux register) is set to NaN bytes, the fab the step writes is set to NaN and so are the ghost cells of
 the current one.  A kernel that read a value the step had not written would
 carry a NaN (or a different value) into the result; every case must still
 equal the oracle bitwise."""
@@ -23,7 +23,7 @@ def ctx():
 
 def _poison(s):
     nan = float("nan")
-    s.ws.fill_(255)  # every byte 0xff: every double a NaN
+    s.ws[s.meta_bytes():].fill_(255)  # every byte 0xff: every double a NaN
     for lev, L in enumerate(s.lv):
         which = s.current() if lev == 0 else 0  # the fine level is back in its A fabs after a step
         cur, other = (L["A"], L["B"]) if which == 0 else (L["B"], L["A"])
