@@ -209,6 +209,23 @@ int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
  * smaller dt (ctuppm_step_checked does that).  Steps enqueued after a rejected
  * one start again from U^n. */
 int ctuppm_step_guarded(ctuppm_ctx* ctx, const int* pids, int npids, int form);
+/* For callers that cannot allocate device memory at the time of the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): one step of a single-level problem as ctuppm_step takes it in
+ * the batched form, with the stage scratch in the library's static device
+ * array of CTUPPM_STATIC_SCRATCH_BYTES (one per GPU, held until the process
+ * ends) instead of the workspace.  The caller still passes the state (bound
+ * fabs) and a bound workspace, of which only the device tables and the MOL
+ * stage fabs are used (a workspace bound for any form is enough; the tables
+ * are uploaded when the state and the workspace are bound, CTUPPM_ESTATE if
+ * they are not there).  Enqueues kernels only: no allocation, no copy, no
+ * memset.  CTUPPM_EINVAL when the problem's stage scratch (every box's, as in
+ * the batched form) exceeds CTUPPM_STATIC_SCRATCH_BYTES or it has two levels.
+ * Every call on one GPU shares the array and leaves its contents behind
+ * (nothing in it needs to start at zero); calls that overlap on one GPU, on
+ * different streams or from different contexts, race. */
+#define CTUPPM_STATIC_SCRATCH_BYTES (64u << 20)
+int ctuppm_step_static(ctuppm_ctx* ctx, int pid);
 /* Rejected guarded steps of problem pid so far (synchronises); acknowledges
  * them, so ctuppm_step_guarded accepts the problem again. */
 int ctuppm_rejections(ctuppm_ctx* ctx, int pid, long long* rejected);

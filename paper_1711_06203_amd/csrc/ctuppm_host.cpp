@@ -29,7 +29,8 @@ using namespace ctu;
 
 namespace {
 
-constexpr int kRecForms = 3;      // box records per form: own scratch, one shared scratch, wave slots
+constexpr int kRecForms = 4;      // box records per form: own scratch, one shared scratch, wave slots, static scratch
+constexpr int kFormStatic = 4;    // internal form of ctuppm_step_static: batched, stage scratch in the static array
 constexpr int kMaxProblems = 4096;  // host-mapped rejection flags per context
 constexpr int kMaxRetryDepth = 3;   // ctuppm_step_checked halves a rejected step at most this often
 
@@ -186,6 +187,7 @@ struct ctuppm_ctx {
   int zseg_per_box = 1;   // planes per march unit, per-box form
   int ytile = 0;          // rows per tile of the march units (0: whole plane)
   std::vector<Staging> staging;
+  void* static_ptr = nullptr;  // this device's static stage scratch (ctuppm_step_static)
   int* hflags = nullptr;   // host-mapped rejection counters, one slot per problem
   int* dflags = nullptr;   // their device address
   std::vector<int> free_slots;
@@ -483,7 +485,9 @@ struct SegRun {
   }
 };
 
-int rec_form(int form) { return form == CTUPPM_FORM_PER_BOX ? 1 : (form == CTUPPM_FORM_WAVES ? 2 : 0); }
+int rec_form(int form) {
+  return form == CTUPPM_FORM_PER_BOX ? 1 : (form == CTUPPM_FORM_WAVES ? 2 : (form == kFormStatic ? 3 : 0));
+}
 int zvar(int form) { return form == CTUPPM_FORM_PER_BOX ? 1 : 0; }
 
 ProbDev* level_rec(Problem* P, int level) { return level == 0 ? P->dP : P->dPf; }
@@ -957,6 +961,9 @@ size_t scratch_base(const Problem* P) { return meta_total(P) + stage_fab_bytes(P
 int ensure_tables(ctuppm_ctx* c, Problem* P) {
   if (P->tables_ok) return CTUPPM_OK;
   if (!P->ws) return fail(c, CTUPPM_ESTATE, "problem %d: no workspace bound", P->id);
+  if (P->ws_bytes < meta_total(P))
+    return fail(c, CTUPPM_ENOMEM, "problem %d: workspace %zu < %zu bytes of device tables", P->id, P->ws_bytes,
+                meta_total(P));
   for (int l = 0; l < P->nlevels; ++l)
     if (!P->lev[l].bound) return fail(c, CTUPPM_ESTATE, "problem %d: level %d state not bound", P->id, l);
   Packer K;
@@ -975,7 +982,7 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
     size_t slot = 0;  // waves form: every box fits any of the shared scratch slots
     for (const auto& b : B) slot = std::max(slot, box_scratch_bytes(b, ns));
     std::vector<BoxRec> recs[kRecForms];
-    size_t off = level_off, woff = meta_total(P);
+    size_t off = level_off, woff = meta_total(P), soff = 0;
     for (int b = 0; b < nb; ++b) {
       BoxRec r{};
       r.U[0] = L.Ua[b];
@@ -1000,6 +1007,10 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
       recs[1].push_back(r);
       r.scr = (double*)((char*)P->ws + sbase + size_t(b % c->wave_boxes) * slot);
       recs[2].push_back(r);
+      // the static array in the batched layout (used only when it all fits)
+      r.scr = c->static_ptr && l == 0 ? (double*)((char*)c->static_ptr + soff) : nullptr;
+      recs[3].push_back(r);
+      soff += box_scratch_bytes(B[b], ns);
       off += box_scratch_bytes(B[b], ns);
     }
     level_off = off;
@@ -1076,6 +1087,17 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
   return CTUPPM_OK;
 }
 
+// Upload the tables as soon as the state and the workspace are bound, so the
+// steps that follow (ctuppm_step_static in particular) find them in place; a
+// failure here is reported by the first step instead.
+void eager_tables(ctuppm_ctx* c, Problem* P) {
+  if (!P->ws) return;
+  for (int l = 0; l < P->nlevels; ++l)
+    if (!P->lev[l].bound) return;
+  const std::string keep = c->err;
+  if (ensure_tables(c, P) != CTUPPM_OK) c->err = keep;
+}
+
 // ---------------------------------------------------------------- step sets
 
 // The set of problems `pids` stepped together in `form` on level `level`.
@@ -1086,8 +1108,8 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     if (level >= P->nlevels) return fail(c, CTUPPM_EINVAL, "problem %d has no level %d", pid, level);
     if (!P->lev[level].bound || !P->ws)
       return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
-    size_t need = 0;
-    if (ctuppm_workspace_bytes(c, pid, form, &need) != CTUPPM_OK) return CTUPPM_EINVAL;
+    size_t need = scratch_base(P);  // the static form's scratch is the library's
+    if (form != kFormStatic && ctuppm_workspace_bytes(c, pid, form, &need) != CTUPPM_OK) return CTUPPM_EINVAL;
     if (P->ws_bytes < need)
       return fail(c, CTUPPM_ENOMEM, "problem %d: workspace %zu < %zu bytes", pid, P->ws_bytes, need);
     const int rc = ensure_tables(c, P);
@@ -1552,6 +1574,7 @@ int ctuppm_ctx_create(void* hip_stream, ctuppm_ctx** out) {
   if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) return CTUPPM_EHIP;
   c->dflags = (int*)d;
   for (int s = kMaxProblems - 1; s >= 0; --s) c->free_slots.push_back(s);
+  if (static_scratch(dev, &c->static_ptr) != hipSuccess) return CTUPPM_EHIP;
   *out = c.release();
   return CTUPPM_OK;
 }
@@ -1744,7 +1767,10 @@ int ctuppm_bind_state(ctuppm_ctx* c, int pid, int level, double* const* Ua, doub
   invalidate(c, P);
   P->state_changed();
   // parity back to A (asynchronous, after everything enqueued before)
-  return set_field(c, P, level, &ProbDev::cur, 0);
+  const int rc = set_field(c, P, level, &ProbDev::cur, 0);
+  if (rc) return rc;
+  eager_tables(c, P);
+  return CTUPPM_OK;
 }
 
 int ctuppm_bind_workspace(ctuppm_ctx* c, int pid, void* ws, size_t bytes) {
@@ -1772,6 +1798,7 @@ int ctuppm_bind_workspace(ctuppm_ctx* c, int pid, void* ws, size_t bytes) {
   P->dP = (ProbDev*)ws;
   P->dPf = P->nlevels == 2 ? (ProbDev*)((char*)ws + rb) : nullptr;
   invalidate(c, P);
+  eager_tables(c, P);
   return CTUPPM_OK;
 }
 
@@ -1806,6 +1833,26 @@ int ctuppm_step_guarded(ctuppm_ctx* c, const int* pids, int npids, int form) {
                   pid);
   }
   return step_set(c, v, form, 1);
+}
+
+int ctuppm_step_static(ctuppm_ctx* c, int pid) {
+  if (!c) return CTUPPM_EINVAL;
+  std::vector<int> v;
+  int two = 0;
+  int rc = check_step_list(c, &pid, 1, CTUPPM_FORM_BATCHED, v, &two);
+  if (rc) return rc;
+  if (two) return fail(c, CTUPPM_EINVAL, "the static step is for single-level problems");
+  Problem* P = get_problem(c, pid);
+  size_t need = 0;
+  for (const auto& b : P->lev[0].boxes) need += box_scratch_bytes(b, P->prm.nspec);
+  if (need > kStaticScratchBytes)
+    return fail(c, CTUPPM_EINVAL, "problem %d: stage scratch of %zu bytes exceeds the static %zu bytes", pid, need,
+                kStaticScratchBytes);
+  if (!c->static_ptr) return fail(c, CTUPPM_EHIP, "no static scratch on this device");
+  if (!P->ws || !P->lev[0].bound) return fail(c, CTUPPM_ESTATE, "problem %d: state or workspace not bound", pid);
+  if (!P->tables_ok)
+    return fail(c, CTUPPM_ESTATE, "problem %d: device tables not uploaded (re-bind the workspace)", pid);
+  return step_set(c, v, kFormStatic, 0);
 }
 
 int ctuppm_rejections(ctuppm_ctx* c, int pid, long long* rejected) {

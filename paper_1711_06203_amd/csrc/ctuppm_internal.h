@@ -227,5 +227,11 @@ hipError_t launch_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt, hipStream_t
 // the step keeps its old state and counts a rejection instead.
 hipError_t launch_flip(const Segs& L, int guard, hipStream_t s);
 const char* stage_name(int stage);
+// Stage scratch of the allocation-free step (a file-scope device array of
+// kStaticScratchBytes): its address on device `dev`, which must be the
+// current device (taken once per device with hipGetSymbolAddress).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(int dev, void** ptr);
 
 }  // namespace ctu

@@ -14,6 +14,8 @@
 // Ghost fills run over 256-item chunks of their copy tags.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ctuppm_internal.h"
 #include "hydro_device.h"
 
@@ -1248,6 +1250,34 @@ hipError_t launch_flip(const Segs& L, int guard, hipStream_t s) {
   if (L.n <= 0) return hipSuccess;
   k_flip<<<1, 64, 0, s>>>(L, guard);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------ static stage scratch
+//
+// Stage scratch of ctuppm_step_static, for callers that cannot allocate: a
+// file-scope device array every GPU the library runs on holds until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol); the address hipGetSymbolAddress
+// gives for the current device, taken once per device, is what the box
+// records hold.
+namespace {
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(int dev, void** ptr) {
+  *ptr = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_static_ptr[dev] = p;
+  }
+  *ptr = g_static_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace ctu

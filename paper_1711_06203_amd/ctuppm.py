@@ -77,6 +77,7 @@ def lib() -> ctypes.CDLL:
             "ctuppm_workspace_bytes": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(sz)],
             "ctuppm_workspace_meta_bytes": [vp, ctypes.c_int, ctypes.POINTER(sz)],
             "ctuppm_step_guarded": [vp, ip, ctypes.c_int, ctypes.c_int],
+            "ctuppm_step_static": [vp, ctypes.c_int],
             "ctuppm_rejections": [vp, ctypes.c_int, llp],
             "ctuppm_bind_state": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp)],
             "ctuppm_bind_workspace": [vp, ctypes.c_int, vp, sz],
@@ -128,7 +129,8 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid",
             "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
             "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes",
-            "ctuppm_debug_stage", "ctuppm_workspace_meta_bytes", "ctuppm_step_guarded", "ctuppm_rejections"]
+            "ctuppm_debug_stage", "ctuppm_workspace_meta_bytes", "ctuppm_step_guarded", "ctuppm_rejections",
+            "ctuppm_step_static"]
 
 
 class Context:
