@@ -428,21 +428,37 @@ def _face_sl(d, lo, hi, idx):
 
 
 def two_level_step(Gc: np.ndarray, Gf: np.ndarray, clo, chi, Pc: Params, Pf: Params):
-    """One coarse step of the two-level method.
+    """One coarse step of the two-level method with one fine patch.
 
     Gc: whole-domain coarse grown array; Gf: grown array of the fine patch,
     which covers coarse cells clo..chi (inclusive), i.e. fine cells
     2 clo .. 2 chi + 1.  The patch must lie at least 3 coarse cells inside the
     domain.  Returns (Gc, Gf, dt_c, counters); the arrays are updated copies."""
-    clo = np.asarray(clo, dtype=np.int64)
-    chi = np.asarray(chi, dtype=np.int64)
-    flo = 2 * clo
-    nf = 2 * (chi - clo + 1)
+    Gc_new, Gfs, dt_c, cnt = two_level_step_patches(Gc, [(Gf, clo, chi)], Pc, Pf)
+    return Gc_new, Gfs[0], dt_c, cnt
+
+
+def two_level_step_patches(Gc: np.ndarray, patches, Pc: Params, Pf: Params):
+    """One coarse step of the two-level method (section 3.2) with a fine level
+    made of several rectangular patches (section 3, figure 1).
+
+    patches: list of (Gf, clo, chi), Gf the grown array of a patch covering
+    coarse cells clo..chi (inclusive); the patches are disjoint and lie at
+    least 3 coarse cells inside the domain.  A fine ghost cell inside another
+    patch takes that patch's value at the same time; the others are
+    interpolated from the coarse level.  The flux register holds the coarse
+    faces between a patch and an uncovered coarse cell only.  Returns (Gc,
+    [Gf], dt_c, counters) with updated copies."""
+    P = []
+    for Gf, clo, chi in patches:
+        clo = np.asarray(clo, dtype=np.int64)
+        chi = np.asarray(chi, dtype=np.int64)
+        P.append({"G": np.array(Gf, dtype=np.float64, copy=True), "clo": clo, "chi": chi,
+                  "flo": 2 * clo, "nf": 2 * (chi - clo + 1)})
     Gc = np.array(Gc, dtype=np.float64, copy=True)
-    Gf = np.array(Gf, dtype=np.float64, copy=True)
     fill_domain(Gc, Pc)
     s_c = signal_speed(Gc, Pc)
-    s_f = signal_speed(Gf, Pf)
+    s_f = max(signal_speed(p["G"], Pf) for p in P)
     a = Pc.cfl / s_c
     b = 2.0 * (Pc.cfl / s_f)
     dt_c = a if a < b else b
@@ -451,70 +467,119 @@ def two_level_step(Gc: np.ndarray, Gf: np.ndarray, clo, chi, Pc: Params, Pf: Par
     Uc_old = Gc.copy()
     Gc_new, c1, st = advance_box(Gc, Pc, dt_c, stages=True)
     cnt += c1
-    # flux register on the 6 patch faces: the coarse flux dt_c F_c now, the
-    # fine sum S = sum over substeps of the four sub-face fluxes dt_f F_f
-    # (summed as a pairwise tree), and R = dt_c F_c - S / 4 at reflux time
-    Fc = {}
-    S = {}
-    for d in range(3):
-        for side, face in ((0, int(clo[d])), (1, int(chi[d]) + 1)):
-            Fc[(d, side)] = dt_c * st[f"ff{d}"][_face_sl(d, clo, chi, face)]
-            S[(d, side)] = np.zeros_like(Fc[(d, side)])
-    # coarse region for interpolation: patch footprint grown by 3 coarse cells
-    rlo = clo - 3
-    rhi = chi + 3
+    # coarse cells under some patch
+    ncz, ncy, ncx = (Gc.shape[1] - 2 * NG, Gc.shape[2] - 2 * NG, Gc.shape[3] - 2 * NG)
+    covered = np.zeros((ncz, ncy, ncx), dtype=bool)
+    for p in P:
+        covered[p["clo"][2]:p["chi"][2] + 1, p["clo"][1]:p["chi"][1] + 1, p["clo"][0]:p["chi"][0] + 1] = True
+    # flux register on the patch faces: the coarse flux dt_c F_c now, the fine
+    # sum S = sum over substeps of the four sub-face fluxes dt_f F_f (summed as
+    # a pairwise tree), and R = dt_c F_c - S / 4 at reflux time; `mask` marks
+    # the faces whose outside coarse cell no patch covers
+    for p in P:
+        clo, chi = p["clo"], p["chi"]
+        p["Fc"], p["S"], p["mask"] = {}, {}, {}
+        for d in range(3):
+            for side, face in ((0, int(clo[d])), (1, int(chi[d]) + 1)):
+                p["Fc"][(d, side)] = dt_c * st[f"ff{d}"][_face_sl(d, clo, chi, face)]
+                p["S"][(d, side)] = np.zeros_like(p["Fc"][(d, side)])
+                out = int(clo[d]) - 1 if side == 0 else int(chi[d]) + 1
+                sl = [None] * 3
+                for e in range(3):
+                    sl[2 - e] = slice(out, out + 1) if e == d else slice(int(clo[e]), int(chi[e]) + 1)
+                p["mask"][(d, side)] = ~covered[tuple(sl)][None]
+    # coarse region for interpolation: the patches' bounding box grown by 3 coarse cells
+    rlo = np.min([p["clo"] for p in P], axis=0) - 3
+    rhi = np.max([p["chi"] for p in P], axis=0) + 3
+
     def region(G):
         return G[:, NG + rlo[2]:NG + rhi[2] + 1, NG + rlo[1]:NG + rhi[1] + 1, NG + rlo[0]:NG + rhi[0] + 1]
     Rn, Rn1 = region(Uc_old), region(Gc_new)
-    # fine ghost cells (global fine indices), in grown-array order
-    gz, gy, gx = np.meshgrid(np.arange(-NG, nf[2] + NG), np.arange(-NG, nf[1] + NG), np.arange(-NG, nf[0] + NG),
-                             indexing="ij")
-    ghost = ~((gx >= 0) & (gx < nf[0]) & (gy >= 0) & (gy < nf[1]) & (gz >= 0) & (gz < nf[2]))
-    loc = np.stack([gx[ghost], gy[ghost], gz[ghost]], axis=1)
-    fine_idx = loc + flo
+    # ghost cells of every patch (box-local and global fine indices), in
+    # grown-array order, and the patch (if any) whose valid cells hold each
+    for p in P:
+        nf = p["nf"]
+        gz, gy, gx = np.meshgrid(np.arange(-NG, nf[2] + NG), np.arange(-NG, nf[1] + NG),
+                                 np.arange(-NG, nf[0] + NG), indexing="ij")
+        ghost = ~((gx >= 0) & (gx < nf[0]) & (gy >= 0) & (gy < nf[1]) & (gz >= 0) & (gz < nf[2]))
+        p["gloc"] = np.stack([gx[ghost], gy[ghost], gz[ghost]], axis=1)
+        glob = p["gloc"] + p["flo"]
+        src = np.full(len(glob), -1, dtype=np.int64)
+        for q, o in enumerate(P):
+            inside = np.all((glob >= o["flo"]) & (glob < o["flo"] + o["nf"]), axis=1)
+            src[inside] = q
+        p["gsrc"] = src
     for sub, theta in enumerate((0.0, 0.5)):
-        vals = fine_ghost_values(Rn, Rn1, theta, rlo, fine_idx)
-        for m in range(Gf.shape[0]):
-            Gf[m][loc[:, 2] + NG, loc[:, 1] + NG, loc[:, 0] + NG] = vals[m]
-        Gf_new, c2, stf = advance_box(Gf, Pf, dt_f, stages=True)
-        cnt += c2
-        # register: add the four fine sub-faces of each coarse face as
-        # ((t00 + t10) + (t01 + t11)), t = dt_f F_f, first transverse index fastest
-        for d in range(3):
-            t1, t2 = [e for e in range(3) if e != d]
-            for side, face in ((0, 0), (1, int(nf[d]))):
-                sl = [slice(None)] * 4
-                for e in range(3):
-                    sl[3 - e] = slice(face + 1, face + 2) if e == d else slice(1, nf[e] + 1)
-                Fd = stf[f"ff{d}"][tuple(sl)]
-
-                def sub(q1, q2):
-                    sl2 = [slice(None)] * 4
+        # every patch's ghosts first (from the other patches' current valid
+        # cells, else from the coarse level), then every patch's advance
+        for p in P:
+            loc, src = p["gloc"], p["gsrc"]
+            glob = loc + p["flo"]
+            interp = src < 0
+            vals = fine_ghost_values(Rn, Rn1, theta, rlo, glob[interp])
+            G = p["G"]
+            for m in range(G.shape[0]):
+                G[m][loc[interp, 2] + NG, loc[interp, 1] + NG, loc[interp, 0] + NG] = vals[m]
+            for q, o in enumerate(P):
+                sel = src == q
+                if not sel.any():
+                    continue
+                ol = glob[sel] - o["flo"]
+                for m in range(G.shape[0]):
+                    G[m][loc[sel, 2] + NG, loc[sel, 1] + NG, loc[sel, 0] + NG] = \
+                        o["G"][m][ol[:, 2] + NG, ol[:, 1] + NG, ol[:, 0] + NG]
+        new = []
+        for p in P:
+            Gf_new, c2, stf = advance_box(p["G"], Pf, dt_f, stages=True)
+            cnt += c2
+            nf = p["nf"]
+            # register: add the four fine sub-faces of each coarse face as
+            # ((t00 + t10) + (t01 + t11)), t = dt_f F_f, first transverse index fastest
+            for d in range(3):
+                t1, t2 = [e for e in range(3) if e != d]
+                for side, face in ((0, 0), (1, int(nf[d]))):
+                    sl = [slice(None)] * 4
                     for e in range(3):
-                        if e != d:
-                            sl2[3 - e] = slice(q1 if e == t1 else q2, None, 2)
-                    return dt_f * Fd[tuple(sl2)]
-                S[(d, side)] = S[(d, side)] + ((sub(0, 0) + sub(1, 0)) + (sub(0, 1) + sub(1, 1)))
-        Gf = Gf_new
+                        sl[3 - e] = slice(face + 1, face + 2) if e == d else slice(1, nf[e] + 1)
+                    Fd = stf[f"ff{d}"][tuple(sl)]
+
+                    def sub_face(q1, q2):
+                        sl2 = [slice(None)] * 4
+                        for e in range(3):
+                            if e != d:
+                                sl2[3 - e] = slice(q1 if e == t1 else q2, None, 2)
+                        return dt_f * Fd[tuple(sl2)]
+                    p["S"][(d, side)] = p["S"][(d, side)] + ((sub_face(0, 0) + sub_face(1, 0))
+                                                             + (sub_face(0, 1) + sub_face(1, 1)))
+            new.append(Gf_new)
+        for p, G in zip(P, new):
+            p["G"] = G
     # average down onto covered coarse cells: 1/8 of the eight children summed
     # as a pairwise tree ((000 + 100) + (010 + 110)) + ((001 + 101) + (011 + 111))
-    fv = Gf[:, NG:NG + nf[2], NG:NG + nf[1], NG:NG + nf[0]]
-    ch = lambda i, j, k: fv[:, k::2, j::2, i::2]
-    avg = 0.125 * (((ch(0, 0, 0) + ch(1, 0, 0)) + (ch(0, 1, 0) + ch(1, 1, 0)))
-                   + ((ch(0, 0, 1) + ch(1, 0, 1)) + (ch(0, 1, 1) + ch(1, 1, 1))))
-    Gc_new[:, NG + clo[2]:NG + chi[2] + 1, NG + clo[1]:NG + chi[1] + 1, NG + clo[0]:NG + chi[0] + 1] = avg
-    # reflux the uncovered neighbours of the patch faces, x then y then z
+    for p in P:
+        nf, clo, chi = p["nf"], p["clo"], p["chi"]
+        fv = p["G"][:, NG:NG + nf[2], NG:NG + nf[1], NG:NG + nf[0]]
+        ch = lambda i, j, k: fv[:, k::2, j::2, i::2]
+        avg = 0.125 * (((ch(0, 0, 0) + ch(1, 0, 0)) + (ch(0, 1, 0) + ch(1, 1, 0)))
+                       + ((ch(0, 0, 1) + ch(1, 0, 1)) + (ch(0, 1, 1) + ch(1, 1, 1))))
+        Gc_new[:, NG + clo[2]:NG + chi[2] + 1, NG + clo[1]:NG + chi[1] + 1, NG + clo[0]:NG + chi[0] + 1] = avg
+    # reflux the uncovered neighbours of the patch faces: x then y then z, the
+    # low side of the fine level before the high side, so a coarse cell beside
+    # the fine level on several sides takes its corrections in that order
     for d in range(3):
         rdx = 1.0 / Pc.dx[d]
         for side in (0, 1):
-            cell = int(clo[d]) - 1 if side == 0 else int(chi[d]) + 1
-            sl = [slice(None)] * 4
-            for e in range(3):
-                sl[3 - e] = slice(NG + cell, NG + cell + 1) if e == d else slice(NG + clo[e], NG + chi[e] + 1)
-            R = Fc[(d, side)] - 0.25 * S[(d, side)]
-            cur = Gc_new[tuple(sl)]
-            Gc_new[tuple(sl)] = cur + R * rdx if side == 0 else cur - R * rdx
-    return Gc_new, Gf, dt_c, cnt
+            for p in P:
+                clo, chi = p["clo"], p["chi"]
+                cell = int(clo[d]) - 1 if side == 0 else int(chi[d]) + 1
+                sl = [slice(None)] * 4
+                for e in range(3):
+                    sl[3 - e] = slice(NG + cell, NG + cell + 1) if e == d else slice(NG + clo[e], NG + chi[e] + 1)
+                R = p["Fc"][(d, side)] - 0.25 * p["S"][(d, side)]
+                cur = Gc_new[tuple(sl)]
+                upd = cur + R * rdx if side == 0 else cur - R * rdx
+                Gc_new[tuple(sl)] = np.where(p["mask"][(d, side)], upd, cur)
+    return Gc_new, [p["G"] for p in P], dt_c, cnt
 
 
 def tag_cells(Uvalid: np.ndarray, P: Params, threshold: float) -> np.ndarray:
@@ -558,29 +623,66 @@ def regrid_fine(Uc: np.ndarray, Uf_old: np.ndarray, old_lo, new_lo, new_n) -> np
     return vals
 
 
+def regrid_patches(Uc: np.ndarray, old, new):
+    """New fine patches (fine index lo, extent (nx, ny, nz)) of a regrid: cells
+    under an old patch (list of (fine index lo, valid state)) keep its values,
+    the others are interpolated from the coarse valid state Uc (cf_interp).
+    Returns one array per new patch."""
+    out = []
+    for lo, n in new:
+        lo = np.asarray(lo)
+        nx, ny, nz = n
+        gz, gy, gx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        fidx = np.stack([gx.ravel() + lo[0], gy.ravel() + lo[1], gz.ravel() + lo[2]], axis=1)
+        vals = cf_interp(Uc, (0, 0, 0), fidx).reshape((Uc.shape[0], nz, ny, nx))
+        for olo, U in old:
+            olo = np.asarray(olo)
+            on = np.asarray(U.shape[1:][::-1])
+            a = np.maximum(olo, lo)
+            b = np.minimum(olo + on, lo + np.asarray(n))
+            if np.all(b > a):
+                dst = (slice(None),) + tuple(slice(a[d] - lo[d], b[d] - lo[d]) for d in (2, 1, 0))
+                src = (slice(None),) + tuple(slice(a[d] - olo[d], b[d] - olo[d]) for d in (2, 1, 0))
+                vals[dst] = U[src]
+        out.append(vals)
+    return out
+
+
+def fine_patches(prob):
+    """The fine patches of a two-level problem as (fine index lo, valid state)."""
+    pat = getattr(prob, "fine_patches", None)
+    if pat:
+        return [(tuple(int(v) for v in lo), np.asarray(U)) for lo, U in pat]
+    return [(tuple(int(v) for v in prob.fine_lo), np.asarray(prob.U0_fine))]
+
+
 def run_two_level_from(prob, Uc: np.ndarray, Uf: np.ndarray, fine_lo, nsteps: int):
     """run_two_level from given coarse and fine states (fine rectangle at fine_lo)."""
     import dataclasses
-    p2 = dataclasses.replace(prob, U0=Uc, U0_fine=Uf, fine_lo=tuple(int(v) for v in fine_lo))
+    p2 = dataclasses.replace(prob, U0=Uc, U0_fine=Uf, fine_lo=tuple(int(v) for v in fine_lo), fine_patches=None)
     return run_two_level(p2, nsteps)
 
 
 def run_two_level(prob, nsteps: int):
-    """Two-level run of a workloads.Problem with fine_boxes / U0_fine set; the
-    fine level must be one rectangle (the union of its boxes).  Returns
-    (coarse valid, fine valid, dts, counters)."""
+    """Two-level run of a workloads.Problem with fine patches (fine_patches, or
+    the one rectangle U0_fine at fine_lo).  Returns (coarse valid, fine valid,
+    dts, counters); the fine valid state is one array for one patch, a list of
+    arrays (in patch order) for several."""
     Pc = params_of(prob)
     Pf = params_of(prob, fine=True)
-    flo = np.array(prob.fine_lo)
-    nf = np.array(prob.U0_fine.shape[1:][::-1])
-    clo = flo // 2
-    chi = (flo + nf) // 2 - 1
     Gc = grow(prob.U0)
-    Gf = grow(prob.U0_fine)
+    pats = []
+    for flo, U in fine_patches(prob):
+        flo = np.array(flo)
+        nf = np.array(U.shape[1:][::-1])
+        pats.append([grow(U), flo // 2, (flo + nf) // 2 - 1])
     dts = []
     cnt = np.zeros(NCNT, dtype=np.int64)
     for _ in range(nsteps):
-        Gc, Gf, dt, c = two_level_step(Gc, Gf, clo, chi, Pc, Pf)
+        Gc, Gfs, dt, c = two_level_step_patches(Gc, pats, Pc, Pf)
+        for p, G in zip(pats, Gfs):
+            p[0] = G
         dts.append(dt)
         cnt += c
-    return valid(Gc), valid(Gf), np.array(dts), cnt
+    fine = [valid(p[0]) for p in pats]
+    return valid(Gc), (fine[0] if len(fine) == 1 else fine), np.array(dts), cnt

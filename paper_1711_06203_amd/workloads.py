@@ -59,6 +59,9 @@ class Problem:
     fine_boxes: Optional[List[Box]] = None   # fine-level index space
     U0_fine: Optional[np.ndarray] = None     # (5, nzf, nyf, nxf) over the fine bounding region
     fine_lo: Optional[Tuple[int, int, int]] = None  # fine index of U0_fine[..., 0, 0, 0]
+    # a fine level of several rectangular patches: (fine index lo, state); when
+    # set, fine_boxes tile every patch and U0_fine / fine_lo are not used
+    fine_patches: Optional[List[Tuple[Tuple[int, int, int], np.ndarray]]] = None
 
     @property
     def dx(self) -> Tuple[float, float, float]:
@@ -341,6 +344,76 @@ def cloud_wind(n=256, box=64, fine_box=32, fine_region=None, gamma=5.0 / 3.0, st
     prob.U0_fine = Uf
     prob.fine_lo = flo
     return prob
+
+
+def two_clouds(n=256, box=64, fine_box=32, patches=None, gamma=5.0 / 3.0, steps=100, nspec=0) -> Problem:
+    """Two dense clouds (rho 10, radius 0.1, at rest, p = 1) at x = 0.3 and
+    x = 0.7 of a Mach-2 wind along x (the cloud problem's physics), each
+    refined by its own fine patch: a fine level of two rectangles (section 3,
+    figure 1: fine boxes over separate regions of the coarse level).
+    ``patches``: coarse cell ranges ((lo), (hi)) half-open, default two cubes
+    of n/4 cells around the clouds."""
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    wind = 2.0 * math.sqrt(gamma)
+    centres = ((0.3, 0.5, 0.5), (0.7, 0.5, 0.5))
+
+    def state(x, y, z):
+        inc = np.zeros(np.shape(x), dtype=bool)
+        for cx, cy, cz in centres:
+            inc |= (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 < 0.01
+        rho = np.where(inc, 10.0, 1.0)
+        u = np.where(inc, 0.0, wind)
+        return conserved(gamma, rho, u, 0.0, 0.0, 1.0, material_species(inc, y, nspec))
+
+    x, y, z = cell_centres(nn)
+    be = (box, box, box) if np.isscalar(box) else tuple(box)
+    fbe = (fine_box,) * 3 if np.isscalar(fine_box) else tuple(fine_box)
+    prob = Problem("two_clouds", nn, gamma, state(x, y, z), regular_boxes(nn, be),
+                   (BC_INFLOW, BC_PERIODIC, BC_PERIODIC), (BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC),
+                   cfl=0.5, inflow=(1.0, wind, 0.0, 0.0, 1.0), steps=steps, nspec=nspec)
+    if nspec:
+        prob.inflow_X = tuple(float(np.asarray(a).ravel()[0])
+                              for a in material_species(np.zeros(1, bool), np.full(1, 0.5), nspec))
+    if patches is None:
+        q = nn[0] // 4
+        patches = []
+        for cx, cy, cz in centres:
+            c = (int(round(cx * nn[0])), int(round(cy * nn[1])), int(round(cz * nn[2])))
+            patches.append((tuple(c[d] - q // 2 for d in range(3)), tuple(c[d] + q // 2 for d in range(3))))
+    prob.fine_patches, prob.fine_boxes = refine_patches(patches, nn, fbe, state)
+    return prob
+
+
+def refine_patches(patches, n, fine_edge, state):
+    """Fine patches (ratio 2) over half-open coarse ranges, their initial states
+    from ``state(x, y, z)`` at fine cell centres, and the fine boxes tiling them."""
+    nf = tuple(2 * v for v in n)
+    pats, boxes = [], []
+    for clo, chi in patches:
+        flo = tuple(2 * c for c in clo)
+        fn = tuple(2 * (chi[d] - clo[d]) for d in range(3))
+        axes = [(np.arange(flo[d], flo[d] + fn[d], dtype=np.float64) + 0.5) / nf[d] for d in range(3)]
+        zf, yf, xf = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        pats.append((flo, state(xf, yf, zf)))
+        boxes += regular_boxes(fn, fine_edge, origin=flo)
+    return pats, boxes
+
+
+def patch_list(prob: Problem):
+    """The fine patches of a two-level problem as (fine index lo, state)."""
+    if prob.fine_patches:
+        return [(tuple(lo), U) for lo, U in prob.fine_patches]
+    return [(tuple(prob.fine_lo), prob.U0_fine)]
+
+
+def patch_of_box(patches, box: Box) -> int:
+    """Index of the patch whose cells hold a fine box."""
+    lo, hi = box
+    for q, (plo, U) in enumerate(patches):
+        pn = U.shape[1:][::-1]
+        if all(plo[d] <= lo[d] and hi[d] < plo[d] + pn[d] for d in range(3)):
+            return q
+    raise ValueError(f"fine box {box} lies in no patch")
 
 
 # ----------------------------------------------------------------------------

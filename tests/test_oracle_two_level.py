@@ -125,3 +125,77 @@ def test_fine_ghosts_interpolate_in_time():
         want = np.stack([(1 - theta) * (fields[0][0][m] + fields[0][1][m] @ centre.T)
                          + theta * (fields[1][0][m] + fields[1][1][m] @ centre.T) for m in range(5)])
         np.testing.assert_allclose(got, want, rtol=0, atol=2e-13)
+
+
+# ---------------------------------------------------------------- several patches
+
+def _patches_problem(n=24, patches=(((8, 8, 8), (16, 16, 16)),), field=None, vel=(1.0, 0.5, 0.25)):
+    """Two-level problem whose fine level is the given half-open coarse ranges."""
+    x, y, z = W.cell_centres((n, n, n))
+    f = field or (lambda x, y, z: 1.0 + 0.2 * np.sin(2 * np.pi * (x + y + z)))
+    p = W.Problem("tlp", (n, n, n), 1.4, W.conserved(1.4, f(x, y, z), *vel, 1.0),
+                  W.regular_boxes((n, n, n), (n // 2,) * 3))
+    p.fine_patches, p.fine_boxes = W.refine_patches(patches, (n, n, n), (8, 8, 8),
+                                                lambda x, y, z: W.conserved(1.4, f(x, y, z), *vel, 1.0))
+    return p
+
+
+def _composite_total(p, Uc, Ufs, m):
+    """Composite integral of component m: uncovered coarse cells plus fine cells / 8."""
+    cov = np.zeros(Uc.shape[1:], bool)
+    fine = []
+    for (flo, _), Uf in zip(p.fine_patches, Ufs):
+        c = np.array(flo) // 2
+        nc = np.array(Uf.shape[1:][::-1]) // 2
+        cov[c[2]:c[2] + nc[2], c[1]:c[1] + nc[1], c[0]:c[0] + nc[0]] = True
+        fine.append(Uf[m].ravel() / 8.0)
+    return math.fsum(np.concatenate([Uc[m][~cov].ravel()] + fine))
+
+
+def test_split_patches_equal_one_rectangle():
+    """A patch cut into touching rectangles (fine ghosts from the neighbour
+    patch, no register on the faces between them) gives bitwise the state of
+    the one rectangle."""
+    whole = _patches_problem(patches=[((8, 8, 8), (16, 16, 16))])
+    Uc1, Uf1, d1, _ = oracle.run_two_level(whole, 4)
+    for cuts in ([((8, 8, 8), (12, 16, 16)), ((12, 8, 8), (16, 16, 16))],
+                 [((8, 8, 8), (12, 12, 16)), ((12, 8, 8), (16, 12, 16)),
+                  ((8, 12, 8), (12, 16, 16)), ((12, 12, 8), (16, 16, 16))]):
+        split = _patches_problem(patches=cuts)
+        Uc2, Ufs, d2, _ = oracle.run_two_level(split, 4)
+        assert np.array_equal(Uc1, Uc2) and np.array_equal(d1, d2)
+        for (flo, _), Uf in zip(split.fine_patches, Ufs):
+            o = np.array(flo) - np.array(whole.fine_patches[0][0])
+            n = np.array(Uf.shape[1:][::-1])
+            assert np.array_equal(Uf, Uf1[:, o[2]:o[2] + n[2], o[1]:o[1] + n[1], o[0]:o[0] + n[0]])
+
+
+def test_separated_patches_uniform_state_bitwise():
+    p = _patches_problem(n=32, patches=[((4, 6, 8), (12, 14, 16)), ((18, 10, 12), (26, 20, 22))],
+                         field=lambda x, y, z: np.full_like(x, 0.7), vel=(0.4, -0.3, 0.2))
+    Uc, Ufs, dts, cnt = oracle.run_two_level(p, 3)
+    for m in range(5):
+        assert np.all(Uc[m] == p.U0[m].flat[0])
+        for Uf in Ufs:
+            assert np.all(Uf[m] == p.U0[m].flat[0])
+    assert not cnt.any()
+
+
+@pytest.mark.parametrize("patches", [
+    [((6, 8, 8), (12, 16, 16)), ((13, 8, 8), (19, 16, 16))],    # a gap of one coarse cell: refluxed from both sides
+    [((6, 6, 8), (12, 12, 16)), ((12, 12, 8), (18, 18, 16))],   # diagonal neighbours: corner cells beside both
+])
+def test_patches_composite_conservation(patches):
+    p = _patches_problem(patches=patches)
+    t0 = [_composite_total(p, p.U0, [U for _, U in p.fine_patches], m) for m in range(5)]
+    Uc, Ufs, dts, cnt = oracle.run_two_level(p, 5)
+    scale = math.fsum(np.abs(p.U0[0]).ravel())
+    for m in range(5):
+        assert abs(_composite_total(p, Uc, Ufs, m) - t0[m]) <= 1e-13 * scale
+    # covered coarse cells are the average of their children
+    for (flo, _), Uf in zip(p.fine_patches, Ufs):
+        c = np.array(flo) // 2
+        nf = np.array(Uf.shape[1:][::-1])
+        cov = Uc[:, c[2]:c[2] + nf[2] // 2, c[1]:c[1] + nf[1] // 2, c[0]:c[0] + nf[0] // 2]
+        avg = Uf.reshape(5, nf[2] // 2, 2, nf[1] // 2, 2, nf[0] // 2, 2).mean(axis=(2, 4, 6))
+        np.testing.assert_allclose(cov, avg, rtol=1e-14, atol=1e-15)

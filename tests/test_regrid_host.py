@@ -73,18 +73,53 @@ def test_cluster_empty_and_bad_arguments():
         ctuppm.cluster(np.ones((8, 8, 8), dtype=bool), blocking=0)
 
 
-def test_patch_from_tags_is_the_buffered_bounding_rectangle():
+def test_patches_from_tags_cover_the_buffered_tags_disjointly():
     _lib_or_skip()
     from paper_1711_06203_amd import regrid
     tags = np.zeros((32, 32, 32), dtype=bool)
-    tags[10:12, 8:9, 12:20] = True
+    tags[10:12, 8:9, 12:20] = True    # (z, y, x)
     tags[14:16, 20:22, 12:14] = True
-    lo, hi = regrid.patch_from_tags(tags, buffer=2, blocking=4)
-    # clusters aligned to 4: x 12..19, y 8..11 / 20..23, z 8..11 / 12..15; buffer 2
-    assert lo == (10, 6, 6) and hi == (21, 25, 17)
-    fb = regrid.fine_boxes((lo, hi), fine_box=16)
+    tags[2, 2, 2] = True              # near the corner: clipped to the margin
+    patches = regrid.patches_from_tags(tags, buffer=2, blocking=4)
+    assert len(patches) >= 2          # the two blobs are not merged into one rectangle
+    grown = regrid.dilate(tags, 2)
+    cover = np.zeros_like(tags)
+    for q, (lo, hi) in enumerate(patches):
+        for d in range(3):
+            assert regrid.MARGIN <= lo[d] <= hi[d] <= 31 - regrid.MARGIN
+        box = cover[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+        assert not box.any()          # disjoint
+        box[...] = True
+    inner = np.zeros_like(tags)
+    m = regrid.MARGIN
+    inner[m:32 - m, m:32 - m, m:32 - m] = True
+    assert not (grown & inner & ~cover).any()
+    # dilation by a cube of half-width 2
+    one = np.zeros((9, 9, 9), dtype=bool)
+    one[4, 4, 4] = True
+    assert np.array_equal(np.argwhere(regrid.dilate(one, 2)).min(0), [2, 2, 2])
+    assert regrid.dilate(one, 2).sum() == 125
+    fb, rects = regrid.fine_level(patches, fine_box=16)
     vol = sum(np.prod([b[1][d] - b[0][d] + 1 for d in range(3)]) for b in fb)
-    assert vol == 8 * np.prod([hi[d] - lo[d] + 1 for d in range(3)])
+    assert vol == 8 * sum(np.prod([hi[d] - lo[d] + 1 for d in range(3)]) for lo, hi in patches)
+
+
+def test_oracle_regrid_patches_copies_every_old_patch():
+    n = (16, 16, 16)
+    x, y, z = W.cell_centres(n)
+    Uc = np.stack([1.0 - 0.2 * x + 0.3 * y + 0.05 * z] * 5)
+    rng = np.random.default_rng(1)
+    old = [((8, 8, 8), rng.uniform(0.5, 1.5, (5, 4, 4, 4))), ((16, 8, 8), rng.uniform(0.5, 1.5, (5, 4, 4, 6)))]
+    new = [((6, 6, 8), (16, 8, 4))]   # fine x 6..21, y 6..13, z 8..11
+    (Uf,) = oracle.regrid_patches(Uc, old, new)
+    np.testing.assert_array_equal(Uf[:, 0:4, 2:6, 2:6], old[0][1])
+    np.testing.assert_array_equal(Uf[:, 0:4, 2:6, 10:16], old[1][1][:, :, :, 0:6])
+    fx, fy, fz = W.cell_centres((32, 32, 32))
+    exact = (1.0 - 0.2 * fx + 0.3 * fy + 0.05 * fz)[8:12, 6:14, 6:22]
+    mask = np.ones(exact.shape, dtype=bool)
+    mask[0:4, 2:6, 2:6] = False
+    mask[0:4, 2:6, 10:16] = False
+    np.testing.assert_allclose(Uf[0][mask], exact[mask], rtol=0, atol=1e-14)
 
 
 def test_oracle_tags_the_cells_beside_a_jump():
