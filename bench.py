@@ -221,12 +221,12 @@ def main():
     solver = ctuppm.Solver(ctx, prob, form=args.form)
     two_level = prob.fine_boxes is not None
     # zone-updates per step: the fine level takes two substeps per coarse step
-    zones = prob.zones + (2 * int(prob.U0_fine[0].size) if two_level else 0)
+    zones = prob.zones + (2 * sum(int(U[0].size) for _, U in W.patch_list(prob)) if two_level else 0)
     tuning = None
     if args.tune:
         from paper_1711_06203_amd import autotune
         tuning = autotune.tune(ctx, [solver], steps=3, cache=None)
-        solver.upload(prob.U0, prob.U0_fine)
+        solver.upload(prob.U0, patches=W.patch_list(prob) if two_level else None)
 
     def timed(form, steps, warm):
         solver.step(warm, form=form)
@@ -285,16 +285,16 @@ def main():
         t0 = time.perf_counter()
         tags = solver.tag(args.regrid)
         t1 = time.perf_counter()
-        patch = regrid.patch_from_tags(tags, buffer=2)
+        patches = regrid.patches_from_tags(tags, buffer=2)
         t2 = time.perf_counter()
-        boxes = regrid.fine_boxes(patch, 32) if patch else None
+        boxes, rects = regrid.fine_level(patches, 32) if patches else (None, None)
         if boxes:
-            solver.regrid(boxes)
+            solver.regrid(boxes, rects)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         solver.step(1)
         torch.cuda.synchronize()
-        regrid_info = {"threshold": args.regrid, "tagged_cells": int(tags.sum()), "patch": patch,
+        regrid_info = {"threshold": args.regrid, "tagged_cells": int(tags.sum()), "patches": patches,
                        "fine_boxes": len(boxes) if boxes else 0, "tag_ms": (t1 - t0) * 1e3,
                        "cluster_ms": (t2 - t1) * 1e3, "regrid_ms": (t3 - t2) * 1e3,
                        "counters_after_step": [int(c) for c in solver.counters()]}

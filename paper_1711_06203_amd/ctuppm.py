@@ -265,7 +265,8 @@ class Solver:
     """One problem resident on the GPU: two fabs per box (per level), one
     workspace, all allocated with torch and handed to the library.  A problem
     with ``fine_boxes`` has a second level (ratio 2) whose initial state is
-    ``U0_fine`` over the fine rectangle starting at ``fine_lo``."""
+    given per patch (``fine_patches``) or as ``U0_fine`` over the rectangle
+    starting at ``fine_lo``."""
 
     def __init__(self, ctx: Context, prob: W.Problem, form="batched", fixed_dt: Optional[float] = None):
         torch = ctx.torch
@@ -291,11 +292,11 @@ class Solver:
         self.nv = 5 + int(prob.nspec)
         self.dev = dev
         self.lv = [self._alloc_level(boxes) for boxes in self.levels]
-        if nl == 2:  # the fine rectangle: first fine index and extent
-            self.fine_lo = tuple(prob.fine_lo)
-            self.fine_n = tuple(prob.U0_fine.shape[1:][::-1])
+        pats = W.patch_list(prob) if nl == 2 else None
+        if nl == 2:  # the fine patches, and their bounding box
+            self._set_patches([(tuple(lo), tuple(U.shape[1:][::-1])) for lo, U in pats])
         self._bind_workspace()
-        self.upload(prob.U0, prob.U0_fine)
+        self.upload(prob.U0, patches=pats)
         self.fixed_dt = float(fixed_dt) if fixed_dt else None
         self.steps_before = 0  # steps taken before a checkpoint this solver resumed from
         if fixed_dt:
@@ -352,15 +353,30 @@ class Solver:
         b = (ctypes.c_void_p * nb)(*[L["B"].data_ptr() + 8 * o for o in L["offsets"]])
         self.ctx.call("ctuppm_bind_state", self.pid, level, a, b)
 
-    def upload(self, Uvalid: np.ndarray, Ufine: Optional[np.ndarray] = None):
-        """Copy a level-0 state (5 + nspec, nz, ny, nx) (and the fine
-        rectangle's state) into the A fabs; ghosts NaN."""
-        for level, (U, origin) in enumerate([(Uvalid, (0, 0, 0)), (Ufine, getattr(self, "fine_lo", None))][:len(self.lv)]):
-            if U.shape[0] != self.nv:
-                raise ValueError(f"state has {U.shape[0]} components, the problem {self.nv}")
+    def _set_patches(self, patches):
+        """Fine patches as (fine index lo, extent); the bounding box of them all."""
+        self.patches = [(tuple(lo), tuple(n)) for lo, n in patches]
+        lo = [min(p[0][d] for p in self.patches) for d in range(3)]
+        hi = [max(p[0][d] + p[1][d] for p in self.patches) for d in range(3)]
+        self.fine_lo = tuple(lo)
+        self.fine_n = tuple(hi[d] - lo[d] for d in range(3))
+
+    def upload(self, Uvalid: np.ndarray, Ufine: Optional[np.ndarray] = None, patches=None):
+        """Copy a level-0 state (5 + nspec, nz, ny, nx) and the fine level's
+        state (the array Ufine over the fine bounding box, or per patch a
+        (fine index lo, state) pair) into the A fabs; ghosts NaN."""
+        fine = patches if patches is not None else (
+            [(self.fine_lo, Ufine)] if Ufine is not None and len(self.lv) == 2 else None)
+        for level in range(len(self.lv)):
             L = self.lv[level]
             host = np.full(L["total"], np.nan)
             for box, off, shape in zip(L["boxes"], L["offsets"], L["shapes"]):
+                if level == 0:
+                    U, origin = Uvalid, (0, 0, 0)
+                else:
+                    origin, U = fine[W.patch_of_box(fine, box)]
+                if U.shape[0] != self.nv:
+                    raise ValueError(f"state has {U.shape[0]} components, the problem {self.nv}")
                 host[off:off + int(np.prod(shape))] = W.grown_fab(U, box, origin=origin).ravel()
             L["A"].copy_(self.ctx.torch.from_numpy(host))
             L["B"].fill_(float("nan"))
@@ -494,8 +510,19 @@ class Solver:
         return W.gather_valid(self.fabs(0), self.prob.boxes, self.prob.n)
 
     def state_fine(self) -> np.ndarray:
-        """Valid cells of the fine rectangle's current state."""
+        """Valid cells of the fine level's current state over the bounding box
+        of its boxes (NaN where no fine box lies)."""
         return W.gather_valid(self.fabs(1), self.levels[1], self.fine_n, origin=self.fine_lo)
+
+    def state_patches(self) -> List[np.ndarray]:
+        """The fine level's current state, one array per patch."""
+        fabs = self.fabs(1)
+        out = []
+        for lo, n in self.patches:
+            sel = [q for q, b in enumerate(self.levels[1])
+                   if all(lo[d] <= b[0][d] and b[1][d] < lo[d] + n[d] for d in range(3))]
+            out.append(W.gather_valid([fabs[q] for q in sel], [self.levels[1][q] for q in sel], n, origin=lo))
+        return out
 
     def tag(self, threshold: float) -> np.ndarray:
         """Level-0 refinement tags (nz, ny, nx) from the density-jump criterion."""
@@ -505,9 +532,11 @@ class Solver:
         self.ctx.call("ctuppm_tag", self.pid, float(threshold), ctypes.c_void_p(t.data_ptr()))
         return t.cpu().numpy().reshape(nz, ny, nx).astype(bool)
 
-    def regrid(self, fine_boxes: Sequence[W.Box]):
-        """Move the fine level onto new boxes (one rectangle): new fabs, the new
-        fine state computed on the device, the workspace re-bound."""
+    def regrid(self, fine_boxes: Sequence[W.Box], patches=None):
+        """Move the fine level onto new boxes: new fabs, the new fine state
+        computed on the device, the workspace re-bound.  ``patches``: the
+        rectangles (fine index lo, extent) the boxes tile, for state_patches
+        (default: each box its own patch)."""
         boxes = [tuple(map(tuple, b)) for b in fine_boxes]
         arr = (Box * len(boxes))()
         for b, (lo, hi) in enumerate(boxes):
@@ -522,10 +551,8 @@ class Solver:
         self.lv[1] = L
         self.levels[1] = boxes
         self._boxes[1] = arr
-        lo = [min(bx[0][d] for bx in boxes) for d in range(3)]
-        hi = [max(bx[1][d] for bx in boxes) for d in range(3)]
-        self.fine_lo = tuple(lo)
-        self.fine_n = tuple(hi[d] - lo[d] + 1 for d in range(3))
+        self._set_patches(patches if patches is not None else
+                          [(b[0], tuple(b[1][d] - b[0][d] + 1 for d in range(3))) for b in boxes])
         self._bind_workspace()
         del old
 

@@ -72,10 +72,11 @@ def _fullsize_digests():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", ["kh256_10", "kh256_13species_1", "kh256_mol2_2", "cloud256_1"])
+@pytest.mark.parametrize("name", ["kh256_10", "kh256_13species_1", "kh256_mol2_2", "cloud256_1", "two_clouds256_1"])
 def test_fullsize_states_bitwise(ctx, name):
     """The whole state after a few steps of a full-size workload (KH 256^3 ten
     steps, with 13 species, with MOL-RK2; the two-level cloud 256^3 + 256^3 one
+    coarse step; two clouds with a fine patch each, 2 x 128^3 fine cells, one
     coarse step) bit for bit the oracle's, compared through the SHA-256 digests
     of the oracle's runs (tests/golden/make_fullsize_digests.py writes them)."""
     import hashlib
@@ -88,7 +89,7 @@ def test_fullsize_states_bitwise(ctx, name):
     prob, steps = G.cases()[name]
     s = ctuppm.Solver(ctx, prob, form="graph")
     s.step(steps)
-    states = [s.state()] + ([s.state_fine()] if prob.fine_boxes else [])
+    states = [s.state()] + (s.state_patches() if prob.fine_boxes else [])
     dt = s.dt()
     cnt = s.counters()
     s.close()

@@ -78,30 +78,41 @@ def test_regrid_then_step_equals_the_oracle(ctx):
     s.close()
 
 
+def _oracle_patches(prob, Uc, patches, nsteps):
+    """The oracle's two-level run from a coarse state and fine patches [(lo, U)]."""
+    import dataclasses
+    p2 = dataclasses.replace(prob, U0=Uc, fine_patches=patches, U0_fine=None, fine_lo=None)
+    Uc2, Ufs, _, _ = oracle.run_two_level(p2, nsteps)
+    Ufs = [Ufs] if isinstance(Ufs, np.ndarray) else Ufs
+    return Uc2, [(lo, U) for (lo, _), U in zip(patches, Ufs)]
+
+
 def test_adapt_follows_the_tags(ctx):
-    """Tag -> cluster -> regrid in a loop; the oracle takes the same patches
-    (computed from its own tags) and the states agree."""
+    """Tag -> cluster -> regrid in a loop, every cluster a fine patch of its
+    own; the oracle takes the same patches (computed from its own tags) and
+    the states agree, patch by patch."""
     from paper_1711_06203_amd import ctuppm, regrid
-    prob = W.cloud_wind(n=32, box=16, fine_box=16, fine_region=((12, 12, 12), (20, 20, 20)))
+    prob = W.two_clouds(n=48, box=16, fine_box=8)
     s = ctuppm.Solver(ctx, prob)
-    Uc, Uf, flo = prob.U0, prob.U0_fine, prob.fine_lo
+    Uc, pats = prob.U0, [(tuple(lo), U) for lo, U in prob.fine_patches]
     moved = 0
     for cycle in range(3):
         s.step(2)
-        Uc, Uf, _, _ = oracle.run_two_level_from(prob, Uc, Uf, flo, 2)
-        patch_o = regrid.patch_from_tags(oracle.tag_cells(Uc, oracle.params_of(prob), 0.05), buffer=2)
-        boxes = regrid.adapt(s, 0.05, buffer=2, fine_box=16)
-        cur = (tuple(v // 2 for v in flo), tuple((flo[d] + Uf.shape[3 - d]) // 2 - 1 for d in range(3)))
-        if patch_o is not None and patch_o != cur:
-            assert boxes is not None
-            new_lo = tuple(2 * v for v in patch_o[0])
-            new_n = tuple(2 * (patch_o[1][d] - patch_o[0][d] + 1) for d in range(3))
-            Uf = oracle.regrid_fine(Uc, Uf, flo, new_lo, new_n)
-            flo = new_lo
+        Uc, pats = _oracle_patches(prob, Uc, pats, 2)
+        new_o = regrid.patches_from_tags(oracle.tag_cells(Uc, oracle.params_of(prob), 0.05), buffer=2)
+        got = regrid.adapt(s, 0.05, buffer=2, fine_box=8)
+        cur = [(tuple(lo[d] // 2 for d in range(3)), tuple((lo[d] + U.shape[3 - d]) // 2 - 1 for d in range(3)))
+               for lo, U in pats]
+        if new_o and sorted(new_o) != sorted(cur):
+            assert got is not None and sorted(got) == sorted(new_o)
+            rects = [(tuple(2 * c for c in lo), tuple(2 * (hi[d] - lo[d] + 1) for d in range(3))) for lo, hi in got]
+            Ufs = oracle.regrid_patches(Uc, pats, rects)
+            pats = [(lo, U) for (lo, _), U in zip(rects, Ufs)]
             moved += 1
         else:
-            assert boxes is None
+            assert got is None
         _check(s.state(), Uc)
-        _check(s.state_fine(), Uf)
-    assert moved >= 1
+        for g, (lo, U) in zip(s.state_patches(), pats):
+            _check(g, U)
+    assert moved >= 1 and len(pats) >= 2
     s.close()
