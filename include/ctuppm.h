@@ -403,6 +403,13 @@ int ctuppm_debug_stage(ctuppm_ctx* ctx, int pid, int level, int box, int array, 
  * largest box's stage scratch. */
 int ctuppm_set_wave_boxes(ctuppm_ctx* ctx, int boxes);
 
+/* Kernels of the CTU cell stages: on (1, the default), the tracing of the
+ * three directions runs in one kernel that reads each cell's primitives and
+ * flattening coefficient once, and the first transverse stage of the three
+ * directions in one kernel that reads each normal flux array once; off (0),
+ * one kernel per direction.  Results are the same bits either way (each face
+ * takes the same arithmetic); captured graphs are dropped. */
+int ctuppm_set_fused(ctuppm_ctx* ctx, int on);
 /* Tuning of the launches: blocks per CU of the persistent batched launches
  * (0 = one block per work unit), and the z planes one work unit marches
  * through in the batched/graph forms and in the per-box form (>= 1).  Results

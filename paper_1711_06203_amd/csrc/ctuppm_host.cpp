@@ -186,6 +186,7 @@ struct ctuppm_ctx {
   int zseg_batched = 1;   // planes per march unit, batched / graph / waves forms
   int zseg_per_box = 1;   // planes per march unit, per-box form
   int ytile = 0;          // rows per tile of the march units (0: whole plane)
+  int fused = 1;          // CTU cell stages: tracing and stage 1 of the three directions in one kernel each
   std::vector<Staging> staging;
   void* static_ptr = nullptr;  // this device's static stage scratch (ctuppm_step_static)
   int* hflags = nullptr;   // host-mapped rejection counters, one slot per problem
@@ -1024,7 +1025,9 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
         for (int b = 0; b < nb; ++b) {
           int org[3], ext[3];
           region_of(k, recs[0][b].n, org, ext);
-          march_region(u, b, org, ext, zs[z], c->ytile);
+          // cons->prim (the only stage over the grown cells) is pointwise: two
+          // planes per unit give each thread two independent cells
+          march_region(u, b, org, ext, k == kGrown ? 2 * zs[z] : zs[z], c->ytile);
           T.upre[z][k][b + 1] = int(u.size());
           cap += max_units(recs[0][b].n, k);
         }
@@ -1146,9 +1149,19 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
   return CTUPPM_OK;
 }
 
-const int kCellStages[] = {kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
-                           kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate};
-constexpr int kNumCellStages = int(sizeof(kCellStages) / sizeof(int));
+// Cell stages of a CTU step after cons->prim: one kernel per direction, or
+// (fused, the default) the flattening with the tracing of the three
+// directions in one kernel and the first transverse stage of the three
+// directions in another.  Both give the same bits.
+const int kCellStagesSplit[] = {kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
+                                kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate};
+const int kCellStagesFused[] = {kStTrace3, kStRiemX, kStRiemY, kStRiemZ, kStT1All,
+                                kStT2X, kStT2Y, kStT2Z, kStUpdate};
+
+std::vector<int> cell_stages(const ctuppm_ctx* c) {
+  if (c->fused) return std::vector<int>(std::begin(kCellStagesFused), std::end(kCellStagesFused));
+  return std::vector<int>(std::begin(kCellStagesSplit), std::end(kCellStagesSplit));
+}
 
 // Groups of boxes whose cell stages launch together: one per box (per-box
 // form), all boxes (batched), or waves of wave_boxes consecutive boxes
@@ -1278,8 +1291,8 @@ int enqueue_step(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed, int guard
   if ((rc = run_probs(c, S, s, false, 0))) return rc;
   for (const auto& g : box_groups(c, S)) {
     if ((per_box || waves) && (rc = run_range(c, S, s, kStC2POnly, g.first, g.second, timed))) return rc;
-    for (int q = 0; q < kNumCellStages; ++q)
-      if ((rc = run_range(c, S, s, kCellStages[q], g.first, g.second, timed))) return rc;
+    for (int st : cell_stages(c))
+      if ((rc = run_range(c, S, s, st, g.first, g.second, timed))) return rc;
   }
   return run_probs(c, S, s, true, guard);
 }
@@ -1347,16 +1360,16 @@ int enqueue_two_level(ctuppm_ctx* c, Problem* P, TwoLevel* T, hipStream_t s, boo
   if ((rc = run_all(c, F, s, kStCfl, timed))) return rc;
   TLCHK(launch_dt2(P->dP, P->dPf, s));
   TLCHK(launch_gather(A, W.gtags, W.gch, W.ngch, 0, s));
-  for (int q = 0; q < kNumCellStages; ++q)
-    if ((rc = run_all(c, C, s, kCellStages[q], timed))) return rc;
+  for (int st : cell_stages(c))
+    if ((rc = run_all(c, C, s, st, timed))) return rc;
   TLCHK(launch_reg_coarse(A, W.faces, W.nfaces, s));
   TLCHK(launch_gather(A, W.gtags, W.gch, W.ngch, 1, s));
   for (int sub = 0; sub < 2; ++sub) {
     if ((rc = fill_arr(c, F, s, timed, kArrCur))) return rc;
     if ((rc = cf_fill(c, P, s, sub == 0 ? 0.0 : 0.5))) return rc;
     if ((rc = run_all(c, F, s, kStC2POnly, timed))) return rc;
-    for (int q = 0; q < kNumCellStages; ++q)
-      if ((rc = run_all(c, F, s, kCellStages[q], timed))) return rc;
+    for (int st : cell_stages(c))
+      if ((rc = run_all(c, F, s, st, timed))) return rc;
     TLCHK(launch_reg_fine(A, W.faces, W.nfaces, s));
     if ((rc = run_probs(c, F, s, true, 0))) return rc;
   }
@@ -1438,7 +1451,10 @@ int cfl_pass(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
 int advance_cells(ctuppm_ctx* c, StepSet* S, hipStream_t s) {
   for (const auto& g : box_groups(c, S)) {
     int rc = run_range(c, S, s, kStC2POnly, g.first, g.second, c->timing);
-    for (int q = 0; q < kNumCellStages && !rc; ++q) rc = run_range(c, S, s, kCellStages[q], g.first, g.second, c->timing);
+    for (int st : cell_stages(c)) {
+      if (rc) break;
+      rc = run_range(c, S, s, st, g.first, g.second, c->timing);
+    }
     if (rc) return rc;
   }
   return CTUPPM_OK;
@@ -2355,6 +2371,13 @@ int ctuppm_set_concurrency(ctuppm_ctx* c, int on) {
   return CTUPPM_OK;
 }
 
+int ctuppm_set_fused(ctuppm_ctx* c, int on) {
+  if (!c) return CTUPPM_EINVAL;
+  c->fused = on ? 1 : 0;
+  for (auto& kv : c->probs) drop_sets(c, kv.first);  // captured graphs hold the old kernels
+  return CTUPPM_OK;
+}
+
 int ctuppm_set_tuning(ctuppm_ctx* c, int bpc, int zb, int zp) {
   return ctuppm_set_tuning2(c, bpc, zb, zp, c ? c->ytile : 0);
 }
@@ -2427,6 +2450,25 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
         break;
       }
       case kStUpdate: tot += 2 * nv * W * valid + nv * W * (fin(0) + fin(1) + fin(2)); break;
+      case kStTrace3: {
+        // q over the union of the three directions' stencils of cells -1..n
+        // (cells -1..n extended by 2 along one direction at a time), phi
+        // written once, the face states of the three directions
+        const double ext = (n0 + 6) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 6) * (n2 + 2) +
+                           (n0 + 2) * (n1 + 2) * (n2 + 6) - 2 * cells1;
+        // the flattening reads the pressure one cell further along each direction
+        const double pext = (n0 + 8) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 8) * (n2 + 2) +
+                            (n0 + 2) * (n1 + 2) * (n2 + 8) - 2 * cells1;
+        tot += (nq - 1) * W * ext + W * pext + W * cells1 + 2 * nv * W * (face(0) + face(1) + face(2));
+        break;
+      }
+      case kStT1All:
+        // the three directions' face states and normal fluxes once each, the six stage-1 fluxes
+        for (int a = 0; a < 3; ++a) {
+          const int b = (a + 1) % 3, cc = (a + 2) % 3;
+          tot += 2 * nv * W * face(a) + nv * W * face(a) + nv * W * (half(a, b) + half(a, cc));
+        }
+        break;
       default: break;
     }
   }

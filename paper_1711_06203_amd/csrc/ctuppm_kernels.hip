@@ -352,26 +352,30 @@ CTU_DEV double shock_ind(const gdbl* __restrict__ p, const gdbl* __restrict__ un
   return f;
 }
 
+// Flattening coefficient of the cell at grown offset o: the minimum over the
+// directions of 1 - max(shock indicator here, at the neighbour on the side of
+// lower pressure).
+CTU_DEV double flatten_cell(const Geo& g, const gdbl* __restrict__ q, int o) {
+  const gdbl* __restrict__ p = q + 4 * g.gcomp;
+  double phi = 1.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int st = g.gstride(d);
+    const gdbl* __restrict__ un = q + (1 + d) * g.gcomp;
+    const int s = (p[o + st] - p[o - st]) > 0.0 ? 1 : -1;
+    const double fd = dmax(shock_ind(p, un, o, st), shock_ind(p, un, o - s * st, st));
+    const double v = 1.0 - fd;
+    phi = d == 0 ? v : dmin(phi, v);
+  }
+  return phi;
+}
+
 __global__ __launch_bounds__(kBlock) void k_flatten(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
-    const gdbl* __restrict__ p = q + 4 * g.gcomp;
     gdbl* __restrict__ phiout = g.phi(B.scr);
-    march(kCells1, B, M, [&](int i, int j, int k) {
-      const int o = g.g(i, j, k);
-      double phi = 1.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int st = g.gstride(d);
-        const gdbl* __restrict__ un = q + (1 + d) * g.gcomp;
-        const int s = (p[o + st] - p[o - st]) > 0.0 ? 1 : -1;
-        const double fd = dmax(shock_ind(p, un, o, st), shock_ind(p, un, o - s * st, st));
-        const double v = 1.0 - fd;
-        phi = d == 0 ? v : dmin(phi, v);
-      }
-      phiout[g.h(i, j, k)] = phi;
-    });
+    march(kCells1, B, M, [&](int i, int j, int k) { phiout[g.h(i, j, k)] = flatten_cell(g, q, g.g(i, j, k)); });
   });
 }
 
@@ -386,73 +390,100 @@ CTU_DEV void store_flux(gdbl* __restrict__ F, int hcomp, int o, const double f[5
   F[4 * hcomp + o] = f[4];
 }
 
-// One thread per cell of -1..n: parabolas of the five permuted primitives,
-// tracing to both faces along D, floors and the gravity predictor; the left
-// state of the upper face and the right state of the lower face are stored
-// for faces 0..n.
+// Tracing of one cell (of -1..n) along D: parabolas of the five permuted
+// primitives, tracing to both faces, floors and the gravity predictor; the
+// left state of the upper face and the right state of the lower face are
+// stored for faces 0..n.
 template <int D, int LIM>
-__global__ __launch_bounds__(kBlock) void k_trace(const Segs L) {
+CTU_DEV void trace_cell(const BoxRec& B, const Geo& g, const ProbDev* P, int i, int j, int k, double phi,
+                        unsigned long long& floors) {
   constexpr int zpos = 1 + (2 - D + 3) % 3;  // permuted slot of the z velocity
   constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
+  const gdbl* __restrict__ q = g.q(B.scr);
+  gdbl* __restrict__ ql = g.ql(B.scr, D);
+  gdbl* __restrict__ qr = g.qr(B.scr, D);
+  const int st = g.gstride(D), sth = g.hstride(D);
+  const double dtdx = P->dtdx[D];
+  const double hdtg = 0.5 * P->dt * P->grav_z;
+  const bool grav = P->grav_z != 0.0;
+  const double sd = P->small_dens, sp = P->small_pres;
+  const int nD = B.n[D];
+  const int x[3] = {i, j, k};
+  const int o = g.g(i, j, k), oh = g.h(i, j, k);
+  double eta = 0.0;
+  if (LIM & 2) {  // contact steepening weight from the density and the neighbours' pressures
+    const gdbl* r = q + o;
+    const gdbl* pr = q + 4 * g.gcomp + o;
+    eta = steep_eta(r[-2 * st], r[-st], r[0], r[st], r[2 * st], pr[-st], pr[st], P->gamma);
+  }
+  Parab par[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const gdbl* a = q + comp[m] * g.gcomp + o;
+    par[m] = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, m == 0 ? eta : 0.0);
+  }
+  const double rho = q[o], un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
+  if (x[D] <= nD - 1) {
+    double up[5];
+    trace_up(par, rho, un, cs, dtdx, up);
+    if (up[0] < sd) { up[0] = sd; ++floors; }
+    if (up[4] < sp) { up[4] = sp; ++floors; }
+    if (grav) up[zpos] = up[zpos] + hdtg;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
+  }
+  if (g.ns > 0) {
+    const double lm = un - cs, l0 = un, lp = un + cs;
+    const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, spp = fabs(lp) * dtdx;
+    for (int is = 0; is < g.ns; ++is) {
+      const gdbl* a = q + (6 + is) * g.gcomp + o;
+      const Parab px = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+      if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
+      if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
+    }
+  }
+  if (x[D] >= 0) {
+    double dn[5];
+    trace_dn(par, rho, un, cs, dtdx, dn);
+    if (dn[0] < sd) { dn[0] = sd; ++floors; }
+    if (dn[4] < sp) { dn[4] = sp; ++floors; }
+    if (grav) dn[zpos] = dn[zpos] + hdtg;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
+  }
+}
+
+// One thread per cell of -1..n, tracing along D.
+template <int D, int LIM>
+__global__ __launch_bounds__(kBlock) void k_trace(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
+    const Geo g(B.n, B.ns);
+    unsigned long long floors = 0;
+    const gdbl* __restrict__ phiv = g.phi(B.scr);
+    march(kCells1, B, M, [&](int i, int j, int k) {
+      trace_cell<D, LIM>(B, g, B.P, i, j, k, phiv[g.h(i, j, k)], floors);
+    });
+    count(&B.P->cnt[2], floors);
+  });
+}
+
+// One thread per cell of -1..n: the flattening coefficient (also stored, for
+// stage dumps), then tracing along x, then y, then z, so the cell's
+// primitives are read once for the flattening and the three directions (the
+// separate kernels read them four times).
+template <int LIM>
+__global__ __launch_bounds__(kBlock) void k_trace3(const Segs L) {
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
-    const gdbl* __restrict__ phiv = g.phi(B.scr);
-    gdbl* __restrict__ ql = g.ql(B.scr, D);
-    gdbl* __restrict__ qr = g.qr(B.scr, D);
-    const int st = g.gstride(D), sth = g.hstride(D);
-    const double dtdx = P->dtdx[D];
-    const double hdtg = 0.5 * P->dt * P->grav_z;
-    const bool grav = P->grav_z != 0.0;
-    const double sd = P->small_dens, sp = P->small_pres;
-    const int nD = B.n[D];
+    gdbl* __restrict__ phiout = g.phi(B.scr);
     unsigned long long floors = 0;
     march(kCells1, B, M, [&](int i, int j, int k) {
-      const int x[3] = {i, j, k};
-      const int o = g.g(i, j, k), oh = g.h(i, j, k);
-      const double phi = phiv[oh];
-      double eta = 0.0;
-      if (LIM & 2) {  // contact steepening weight from the density and the neighbours' pressures
-        const gdbl* r = q + o;
-        const gdbl* pr = q + 4 * g.gcomp + o;
-        eta = steep_eta(r[-2 * st], r[-st], r[0], r[st], r[2 * st], pr[-st], pr[st], P->gamma);
-      }
-      Parab par[5];
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        const gdbl* a = q + comp[m] * g.gcomp + o;
-        par[m] = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, m == 0 ? eta : 0.0);
-      }
-      const double rho = q[o], un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
-      if (x[D] <= nD - 1) {
-        double up[5];
-        trace_up(par, rho, un, cs, dtdx, up);
-        if (up[0] < sd) { up[0] = sd; ++floors; }
-        if (up[4] < sp) { up[4] = sp; ++floors; }
-        if (grav) up[zpos] = up[zpos] + hdtg;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
-      }
-      if (g.ns > 0) {
-        const double lm = un - cs, l0 = un, lp = un + cs;
-        const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, spp = fabs(lp) * dtdx;
-        for (int is = 0; is < g.ns; ++is) {
-          const gdbl* a = q + (6 + is) * g.gcomp + o;
-          const Parab px = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-          if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
-          if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
-        }
-      }
-      if (x[D] >= 0) {
-        double dn[5];
-        trace_dn(par, rho, un, cs, dtdx, dn);
-        if (dn[0] < sd) { dn[0] = sd; ++floors; }
-        if (dn[4] < sp) { dn[4] = sp; ++floors; }
-        if (grav) dn[zpos] = dn[zpos] + hdtg;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
-      }
+      const double phi = flatten_cell(g, q, g.g(i, j, k));
+      phiout[g.h(i, j, k)] = phi;
+      trace_cell<0, LIM>(B, g, B.P, i, j, k, phi, floors);
+      trace_cell<1, LIM>(B, g, B.P, i, j, k, phi, floors);
+      trace_cell<2, LIM>(B, g, B.P, i, j, k, phi, floors);
     });
     count(&B.P->cnt[2], floors);
   });
@@ -540,65 +571,87 @@ CTU_DEV int to_prim_or_keep(const double U[5], const double s0[5], double gm1, d
   return 0;
 }
 
-// Stage 1: face states along A corrected by dt/(3 dx_B) times the normal
-// B-flux difference across their owner cell, for B = the two other
-// directions, then the Riemann flux -> F^{A|B}.
+// Stage 1 at one face along A: the face states corrected by dt/(3 dx_B)
+// times the normal B-flux difference across their owner cell, for B = the
+// two other directions, then the Riemann flux -> F^{A|B}.  fb counts states
+// that fell back to the uncorrected ones.
+template <int A, int RS>
+CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, const ProbDev* P, int i, int j, int k,
+                         unsigned long long& fb) {
+  const int sa = g.hstride(A);
+  const gdbl* __restrict__ ql = g.ql(B.scr, A);
+  const gdbl* __restrict__ qr = g.qr(B.scr, A);
+  const int x[3] = {i, j, k};
+  const int o = g.h(i, j, k);
+  double sL[5], sR[5], UL[5], UR[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    sL[m] = ql[m * g.hcomp + o];
+    sR[m] = qr[m * g.hcomp + o];
+  }
+  to_cons<A>(sL, P->rgm1, UL);
+  to_cons<A>(sR, P->rgm1, UR);
+#pragma unroll
+  for (int which = 0; which < 2; ++which) {
+    const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
+    if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
+    const double c3 = P->dt3dx[Bd];
+    const int sb = g.hstride(Bd);
+    const gdbl* __restrict__ Fb = g.fn(B.scr, Bd);
+    double VL[5], VR[5], tL[5], tR[5], f[5];
+    const int oL = o - sa, oR = o;  // owner cells of the left and right states
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const gdbl* Fm = Fb + m * g.hcomp;
+      VL[m] = UL[m] - c3 * (Fm[oL + sb] - Fm[oL]);
+      VR[m] = UR[m] - c3 * (Fm[oR + sb] - Fm[oR]);
+    }
+    const int kL = to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+    const int kR = to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+    fb += kL + kR;
+    const int side = wall_side(B, A, x[A]);
+    wall_mirror(side, tL, tR);
+    Wave W;
+    rflux<RS>(tL, tR, P, f, W);
+    gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
+    store_flux<A>(F1, g.hcomp, o, f);
+    // species: rho X corrected by the same flux difference, back to X with
+    // the corrected density (or the traced X where the state fell back)
+    for (int is = 0; is < g.ns; ++is) {
+      const int c = (kNV + is) * g.hcomp;
+      const gdbl* Fm = Fb + c;
+      const double xL = ql[c + o], xR = qr[c + o];
+      const double wL = sL[0] * xL - c3 * (Fm[oL + sb] - Fm[oL]);
+      const double wR = sR[0] * xR - c3 * (Fm[oR + sb] - Fm[oR]);
+      const double yL = kL ? xL : wL / VL[0], yR = kR ? xR : wR / VR[0];
+      F1[c + o] = species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR);
+    }
+  }
+}
+
+// Stage 1 along A over faces 0..n (cells -1..n across).
 template <int A, int RS>
 __global__ __launch_bounds__(kBlock) void k_trans1(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
-    const int sa = g.hstride(A);
-    const gdbl* __restrict__ ql = g.ql(B.scr, A);
-    const gdbl* __restrict__ qr = g.qr(B.scr, A);
     unsigned long long fb = 0;
-    march(kFace0 + A, B, M, [&](int i, int j, int k) {
-      const int x[3] = {i, j, k};
-      const int o = g.h(i, j, k);
-      double sL[5], sR[5], UL[5], UR[5];
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        sL[m] = ql[m * g.hcomp + o];
-        sR[m] = qr[m * g.hcomp + o];
-      }
-      to_cons<A>(sL, P->rgm1, UL);
-      to_cons<A>(sR, P->rgm1, UR);
-#pragma unroll
-      for (int which = 0; which < 2; ++which) {
-        const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
-        if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
-        const double c3 = P->dt3dx[Bd];
-        const int sb = g.hstride(Bd);
-        const gdbl* __restrict__ Fb = g.fn(B.scr, Bd);
-        double VL[5], VR[5], tL[5], tR[5], f[5];
-        const int oL = o - sa, oR = o;  // owner cells of the left and right states
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-          const gdbl* Fm = Fb + m * g.hcomp;
-          VL[m] = UL[m] - c3 * (Fm[oL + sb] - Fm[oL]);
-          VR[m] = UR[m] - c3 * (Fm[oR + sb] - Fm[oR]);
-        }
-        const int kL = to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
-        const int kR = to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
-        fb += kL + kR;
-        const int side = wall_side(B, A, x[A]);
-        wall_mirror(side, tL, tR);
-        Wave W;
-        rflux<RS>(tL, tR, P, f, W);
-        gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
-        store_flux<A>(F1, g.hcomp, o, f);
-        // species: rho X corrected by the same flux difference, back to X with
-        // the corrected density (or the traced X where the state fell back)
-        for (int is = 0; is < g.ns; ++is) {
-          const int c = (kNV + is) * g.hcomp;
-          const gdbl* Fm = Fb + c;
-          const double xL = ql[c + o], xR = qr[c + o];
-          const double wL = sL[0] * xL - c3 * (Fm[oL + sb] - Fm[oL]);
-          const double wR = sR[0] * xR - c3 * (Fm[oR + sb] - Fm[oR]);
-          const double yL = kL ? xL : wL / VL[0], yR = kR ? xR : wR / VR[0];
-          F1[c + o] = species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR);
-        }
-      }
+    march(kFace0 + A, B, M, [&](int i, int j, int k) { trans1_face<A, RS>(B, g, B.P, i, j, k, fb); });
+    count(&B.P->cnt[3], fb);
+  });
+}
+
+// Stage 1 along x, then y, then z, one thread per cell of -1..n (the lower
+// A-face of the cell, where the cell is not at -1 along A): each normal flux
+// array is read once instead of by two of the per-direction kernels.
+template <int RS>
+__global__ __launch_bounds__(kBlock) void k_trans1_all(const Segs L) {
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
+    const Geo g(B.n, B.ns);
+    unsigned long long fb = 0;
+    march(kCells1, B, M, [&](int i, int j, int k) {
+      if (i >= 0) trans1_face<0, RS>(B, g, B.P, i, j, k, fb);
+      if (j >= 0) trans1_face<1, RS>(B, g, B.P, i, j, k, fb);
+      if (k >= 0) trans1_face<2, RS>(B, g, B.P, i, j, k, fb);
     });
     count(&B.P->cnt[3], fb);
   });
@@ -1131,7 +1184,7 @@ const char* stage_name(int s) {
       "fill", "bc_x", "bc_y", "bc_z", "cons2prim_cfl", "cfl", "cons2prim", "dt", "flatten",
       "trace_x", "trace_y", "trace_z", "riemann_x", "riemann_y", "riemann_z",
       "trans1_x", "trans1_y", "trans1_z", "trans2_x", "trans2_y", "trans2_z", "update", "flip",
-      "recon_x", "recon_y", "recon_z", "mol_update"};
+      "recon_x", "recon_y", "recon_z", "mol_update", "trace_xyz", "trans1_xyz"};
   return (s >= 0 && s < kNumStages) ? names[s] : "?";
 }
 
@@ -1160,6 +1213,15 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStTraceX: CTU_LIM(k_trace, 0); break;
     case kStTraceY: CTU_LIM(k_trace, 1); break;
     case kStTraceZ: CTU_LIM(k_trace, 2); break;
+    case kStTrace3:
+      if (L.lim == 1) k_trace3<1><<<grid, block, 0, s>>>(G);
+      else if (L.lim == 2) k_trace3<2><<<grid, block, 0, s>>>(G);
+      else k_trace3<0><<<grid, block, 0, s>>>(G);
+      break;
+    case kStT1All:
+      if (L.rs) k_trans1_all<1><<<grid, block, 0, s>>>(G);
+      else k_trans1_all<0><<<grid, block, 0, s>>>(G);
+      break;
 #define CTU_RS(K, D) (L.rs ? K<D, 1><<<grid, block, 0, s>>>(G) : K<D, 0><<<grid, block, 0, s>>>(G))
     case kStRiemX: CTU_RS(k_riemann, 0); break;
     case kStRiemY: CTU_RS(k_riemann, 1); break;

@@ -78,6 +78,7 @@ def lib() -> ctypes.CDLL:
             "ctuppm_workspace_meta_bytes": [vp, ctypes.c_int, ctypes.POINTER(sz)],
             "ctuppm_step_guarded": [vp, ip, ctypes.c_int, ctypes.c_int],
             "ctuppm_step_static": [vp, ctypes.c_int],
+            "ctuppm_set_fused": [vp, ctypes.c_int],
             "ctuppm_rejections": [vp, ctypes.c_int, llp],
             "ctuppm_bind_state": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp)],
             "ctuppm_bind_workspace": [vp, ctypes.c_int, vp, sz],
@@ -130,7 +131,7 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
             "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes",
             "ctuppm_debug_stage", "ctuppm_workspace_meta_bytes", "ctuppm_step_guarded", "ctuppm_rejections",
-            "ctuppm_step_static"]
+            "ctuppm_step_static", "ctuppm_set_fused"]
 
 
 class Context:
@@ -181,6 +182,11 @@ class Context:
     def set_wave_boxes(self, boxes: int):
         """Boxes per wave of the waves form (they share as many scratch slots)."""
         self.call("ctuppm_set_wave_boxes", int(boxes))
+
+    def set_fused(self, on: bool):
+        """CTU cell stages: tracing and transverse stage 1 of the three
+        directions in one kernel each (default) or one kernel per direction."""
+        self.call("ctuppm_set_fused", int(bool(on)))
 
     def set_concurrency(self, on: bool):
         """Graph form: run the three directions of each phase concurrently (default off)."""
