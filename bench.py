@@ -85,6 +85,53 @@ def attainable_bandwidth(torch, gib: int = 2) -> dict:
     return out
 
 
+def host_cpu() -> dict:
+    """Model name and core counts of the host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    model = info.get("Model name")
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    def num(k):
+        try:
+            return int(info[k])
+        except (KeyError, ValueError):
+            return None
+    sockets, cores, tpc = num("Socket(s)"), num("Core(s) per socket"), num("Thread(s) per core")
+    return {"cpu_model": model, "sockets": sockets, "physical_cores": sockets * cores if sockets and cores else None,
+            "threads_per_core": tpc, "logical_cpus": num("CPU(s)"),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def measured_valu(kernel: str, workload: str):
+    """VALU wave-instructions per launch of `kernel` from the committed
+    rocprofv3 SQ counter summary, or None when the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(f"valu_insts_per_launch[{kernel}]")
+    return float(v) if v else None
+
+
 def cpu_baseline(prob, seconds: float = 12.0):
     """Oracle on one 64^3 box of the same initial state (ghosts from the
     filled whole-domain state), advanced repeatedly until ~`seconds` pass."""
@@ -105,10 +152,12 @@ def cpu_baseline(prob, seconds: float = 12.0):
         if el >= seconds:
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    return {"value": n ** 3 * reps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} advances of one 64^3 box (72^3 grown) of the 256^3 KH initial state "
-                      f"({prob.nspec} species), "
-                      f"{el:.1f} s wall, OpenMP threads={threads}"}
+    out = {"value": n ** 3 * reps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{reps} advances of one 64^3 box (72^3 grown) of the 256^3 KH initial state "
+                     f"({prob.nspec} species), "
+                     f"{el:.1f} s wall, OpenMP threads={threads}"}
+    out.update(host_cpu())
+    return out
 
 
 def main():
@@ -142,6 +191,10 @@ def main():
     ap.add_argument("--wave-boxes", type=int, default=64,
                     help="waves form: boxes per wave (the workspace holds this many boxes' stage scratch)")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests per arrival rate")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="kh256: skip the serving leg (a Poisson stream at 0.8 of the batched capacity, served "
+                         "batched and per box)")
+    ap.add_argument("--serving-requests", type=int, default=500, help="requests of the serving leg")
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -327,18 +380,71 @@ def main():
     }
     if regrid_info:
         out["regrid"] = regrid_info
+    # the headline rate against the method's algorithmic floor: 80 bytes per
+    # zone-update (read and write the 5 conserved doubles once), or 131 with
+    # the ghost cells of 64^3 boxes stored and filled
+    out["roofline"]["alg_frac_80B"] = value * 80.0 / (HBM_PEAK_GBS * 1e9)
+    out["roofline"]["alg_frac_131B"] = value * 131.0 / (HBM_PEAK_GBS * 1e9)
+    valu = measured_valu(dom, tkey)
+    out["roofline"]["valu_busy"] = (
+        None if valu is None else {"frac": valu * 4.0 / (1024 * 2.4e9 * avg_ms * 1e-3), "valu_insts_per_launch": valu,
+                                    "how": "rocprofv3 SQ_INSTS_VALU per launch x 4 cycles / (1024 SIMDs x 2.4 GHz x "
+                                           "launch time)"})
     solver.close()
-    ctx.close()
     del solver
     torch.cuda.empty_cache()
     att = attainable_bandwidth(torch)
+    att["probe"] = {k: ctx.bandwidth_probe(k) for k in ("copy", "read", "write")}
+    att["probe"]["how"] = ("the library's streaming kernel, 16-byte accesses, grid-stride, best of 4 grids, "
+                           "2 GiB FP64, 10 launches each")
     out["roofline"]["attainable"] = att
-    out["roofline"]["frac_of_copy"] = achieved / att["copy"]
+    out["roofline"]["frac_of_copy"] = achieved / max(att["copy"], att["probe"]["copy"])
+    if step_roof:
+        step_roof["frac_of_copy"] = step_roof["achieved"] / max(att["copy"], att["probe"]["copy"])
+    if (not args.no_serving and args.workload == "kh256" and args.n == 256 and args.box == 64
+            and args.scheme == "ctu" and args.riemann == "hllc" and args.limiter == "cw84" and not args.steepen):
+        out["serving"] = serving_leg(ctx, args.serving_requests)
+    ctx.close()
     if (not args.no_cpu and args.workload == "kh256" and args.n == 256 and args.box == 64
             and args.scheme == "ctu" and args.riemann == "hllc" and args.limiter == "cw84"
             and not args.steepen):
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def serving_leg(ctx, nreq: int) -> dict:
+    """The serving workload beside the headline.  Capacity: 120 requests
+    present at t = 0, served batched and, the same requests, per box (every
+    stage launched per box of every problem).  Latency: one Poisson stream of
+    `nreq` requests at 0.8 of the batched capacity, served both ways."""
+    import numpy as np
+    from paper_1711_06203_amd import serving
+    out = {"workload": "serving_periodic_N^3_N_in_32-128_50_steps", "hbm_budget_bytes": 64e9,
+           "capacity": {}, "load": 0.8, "requests": nreq}
+    sat = serving.poisson_requests(120, rate=0.0, seed=11)
+    for form in ("batched", "per_box"):
+        srv = serving.Server(ctx, hbm_budget=64e9, form=form)
+        t0 = time.perf_counter()
+        res = srv.run(sat, realtime=True)
+        el = time.perf_counter() - t0
+        out["capacity"][form] = {"requests_per_s": len(res) / el, "zone_updates_per_s": srv.zone_updates / el,
+                                 "mean_batch": float(np.mean(srv.batch_sizes))}
+    rate = 0.8 * out["capacity"]["batched"]["requests_per_s"]
+    out["arrival_rate_per_s"] = rate
+    stream = serving.poisson_requests(nreq, rate=rate, seed=92)
+    for form in ("batched", "per_box"):
+        srv = serving.Server(ctx, hbm_budget=64e9, form=form)
+        t0 = time.perf_counter()
+        res = srv.run(stream, realtime=True)
+        el = time.perf_counter() - t0
+        st = serving.latency_stats(res)
+        out[form] = {"zone_updates_per_s": srv.zone_updates / el, "requests_per_s": len(res) / el,
+                     "p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_batch": float(np.mean(srv.batch_sizes)),
+                     "rejected_steps": int(sum(r.rejected for r in res.values())), "wall_s": el}
+        print(json.dumps({"serving_leg": form, **out[form]}), file=sys.stderr, flush=True)
+    out["served_over_per_box"] = (out["capacity"]["batched"]["zone_updates_per_s"]
+                                  / out["capacity"]["per_box"]["zone_updates_per_s"])
+    return out
 
 
 def bench_serving(args):

@@ -209,6 +209,12 @@ int ctuppm_step(ctuppm_ctx* ctx, const int* pids, int npids, int form);
  * smaller dt (ctuppm_step_checked does that).  Steps enqueued after a rejected
  * one start again from U^n. */
 int ctuppm_step_guarded(ctuppm_ctx* ctx, const int* pids, int npids, int form);
+/* Rejected guarded steps of problem pid as the device has reported them so
+ * far through host-mapped memory, without synchronising (exact for every
+ * step whose completion the caller has observed, e.g. through an event
+ * recorded after it); acknowledges them like ctuppm_rejections, but does not
+ * update ctuppm_current_state's view of the parity. */
+int ctuppm_rejections_seen(ctuppm_ctx* ctx, int pid, long long* rejected);
 /* For callers that cannot allocate device memory at the time of the call
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): one step of a single-level problem as ctuppm_step takes it in
@@ -410,6 +416,14 @@ int ctuppm_set_wave_boxes(ctuppm_ctx* ctx, int boxes);
  * one kernel per direction.  Results are the same bits either way (each face
  * takes the same arithmetic); captured graphs are dropped. */
 int ctuppm_set_fused(ctuppm_ctx* ctx, int on);
+/* Measurement: the HBM bandwidth plain streaming reaches on this GPU, the
+ * ceiling the stage kernels are compared with.  kind 0 copies `bytes` from src
+ * to dst (counted read + write), 1 reads src, 2 writes dst; 16-byte accesses
+ * in grid-stride loops, `reps` timed launches at each of a few grid sizes
+ * (synchronises); *gbs receives the best rate in GB/s (1e9 bytes).  Buffers
+ * are caller-owned device memory, 16-byte aligned, bytes a multiple of 16. */
+int ctuppm_bandwidth_probe(ctuppm_ctx* ctx, int kind, const void* src, void* dst, size_t bytes, int reps,
+                           double* gbs);
 /* Tuning of the launches: blocks per CU of the persistent batched launches
  * (0 = one block per work unit), and the z planes one work unit marches
  * through in the batched/graph forms and in the per-box form (>= 1).  Results

@@ -1890,6 +1890,15 @@ int ctuppm_rejections(ctuppm_ctx* c, int pid, long long* rejected) {
   return CTUPPM_OK;
 }
 
+int ctuppm_rejections_seen(ctuppm_ctx* c, int pid, long long* rejected) {
+  if (!c || !rejected) return CTUPPM_EINVAL;
+  Problem* P = get_problem(c, pid);
+  if (!P) return fail(c, CTUPPM_EINVAL, "unknown problem %d", pid);
+  *rejected = host_rejections(c, P);
+  P->acked = int(*rejected);
+  return CTUPPM_OK;
+}
+
 int ctuppm_fill_ghosts(ctuppm_ctx* c, int pid, int level, int form) {
   if (!c) return CTUPPM_EINVAL;
   Problem* P = nullptr;
@@ -2375,6 +2384,33 @@ int ctuppm_set_fused(ctuppm_ctx* c, int on) {
   if (!c) return CTUPPM_EINVAL;
   c->fused = on ? 1 : 0;
   for (auto& kv : c->probs) drop_sets(c, kv.first);  // captured graphs hold the old kernels
+  return CTUPPM_OK;
+}
+
+int ctuppm_bandwidth_probe(ctuppm_ctx* c, int kind, const void* src, void* dst, size_t bytes, int reps,
+                           double* gbs) {
+  if (!c || !gbs || kind < 0 || kind > 2 || reps < 1 || bytes < 16 || (bytes & 15)) return CTUPPM_EINVAL;
+  if ((kind != 2 && !src) || (kind != 1 && !dst) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
+    return fail(c, CTUPPM_EINVAL, "bandwidth probe: null or misaligned buffer");
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return fail(c, CTUPPM_EHIP, "hipEventCreate failed");
+  double best = 0.0;
+  // a few grid sizes (blocks per CU); the best rate is the ceiling
+  for (int per_cu : {4, 8, 16, 32}) {
+    const int blocks = per_cu * c->num_cus;
+    LCHK(launch_probe(kind, src, dst, bytes, blocks, c->stream));  // warm
+    HIPCHK(c, hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps; ++r) LCHK(launch_probe(kind, src, dst, bytes, blocks, c->stream));
+    HIPCHK(c, hipEventRecord(b, c->stream));
+    HIPCHK(c, hipEventSynchronize(b));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, a, b));
+    const double moved = double(bytes) * (kind == 0 ? 2.0 : 1.0);
+    best = std::max(best, moved * reps / (double(ms) * 1e-3) / 1e9);
+  }
+  c->event_pool.push_back(a);
+  c->event_pool.push_back(b);
+  *gbs = best;
   return CTUPPM_OK;
 }
 

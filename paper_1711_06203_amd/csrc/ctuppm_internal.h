@@ -228,6 +228,9 @@ hipError_t launch_set_dt(ProbDev* Pc, ProbDev* Pf, const double* dt, hipStream_t
 // the step keeps its old state and counts a rejection instead.
 hipError_t launch_flip(const Segs& L, int guard, hipStream_t s);
 const char* stage_name(int stage);
+// Streaming probe over `bytes` (a multiple of 16): kind 0 copies src to dst,
+// 1 reads src, 2 writes dst; `blocks` blocks of 256 threads, grid-stride.
+hipError_t launch_probe(int kind, const void* src, void* dst, size_t bytes, int blocks, hipStream_t s);
 // Stage scratch of the allocation-free step (a file-scope device array of
 // kStaticScratchBytes): its address on device `dev`, which must be the
 // current device (taken once per device with hipGetSymbolAddress).

@@ -1314,6 +1314,41 @@ hipError_t launch_flip(const Segs& L, int guard, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ bandwidth probes
+//
+// What plain streaming reaches on this GPU, as the ceiling the stage kernels
+// are measured against: grid-stride loops of 16-byte accesses (two doubles
+// per lane), a copy (read + write), a read (summed per lane; the sum is stored
+// only if it equals a value it never takes, so the loads stay) and a write.
+namespace {
+using v2 = double __attribute__((ext_vector_type(2)));
+using gv2 = __attribute__((address_space(1))) v2;
+
+__global__ __launch_bounds__(kBlock) void k_probe(int kind, const void* __restrict__ a, void* __restrict__ b,
+                                                  long long n, double never) {
+  const gv2* __restrict__ src = (const gv2*)a;
+  gv2* __restrict__ dst = (gv2*)b;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (kind == 0) {
+      dst[i] = src[i];
+    } else if (kind == 1) {
+      const v2 v = src[i];
+      acc += v.x + v.y;
+    } else {
+      dst[i] = v2{never, never};
+    }
+  }
+  if (kind == 1 && acc == never) dst[0] = v2{acc, acc};
+}
+}  // namespace
+
+hipError_t launch_probe(int kind, const void* src, void* dst, size_t bytes, int blocks, hipStream_t s) {
+  k_probe<<<blocks, kBlock, 0, s>>>(kind, src, dst, (long long)(bytes / 16), -1.25e300);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------ static stage scratch
 //
 // Stage scratch of ctuppm_step_static, for callers that cannot allocate: a

@@ -79,7 +79,9 @@ def lib() -> ctypes.CDLL:
             "ctuppm_step_guarded": [vp, ip, ctypes.c_int, ctypes.c_int],
             "ctuppm_step_static": [vp, ctypes.c_int],
             "ctuppm_set_fused": [vp, ctypes.c_int],
+            "ctuppm_bandwidth_probe": [vp, ctypes.c_int, vp, vp, sz, ctypes.c_int, dp],
             "ctuppm_rejections": [vp, ctypes.c_int, llp],
+            "ctuppm_rejections_seen": [vp, ctypes.c_int, llp],
             "ctuppm_bind_state": [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp)],
             "ctuppm_bind_workspace": [vp, ctypes.c_int, vp, sz],
             "ctuppm_set_fixed_dt": [vp, ctypes.c_int, ctypes.c_double],
@@ -130,8 +132,8 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_set_fail_hook", "ctuppm_set_tuning2", "ctuppm_tag", "ctuppm_cluster", "ctuppm_regrid",
             "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
             "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes",
-            "ctuppm_debug_stage", "ctuppm_workspace_meta_bytes", "ctuppm_step_guarded", "ctuppm_rejections",
-            "ctuppm_step_static", "ctuppm_set_fused"]
+            "ctuppm_debug_stage", "ctuppm_workspace_meta_bytes", "ctuppm_step_guarded", "ctuppm_rejections", "ctuppm_rejections_seen",
+            "ctuppm_step_static", "ctuppm_set_fused", "ctuppm_bandwidth_probe"]
 
 
 class Context:
@@ -143,10 +145,18 @@ class Context:
             raise CtuError("no GPU visible: the CTU/PPM library runs on the MI355X only")
         self.torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._side = None
         h = ctypes.c_void_p()
         self._L = lib()
         self._check(self._L.ctuppm_ctx_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None)
         self.h = h
+
+    @property
+    def side_stream(self):
+        """A second torch stream (default priority) for uploads beside the steps."""
+        if self._side is None:
+            self._side = self.torch.cuda.Stream()
+        return self._side
 
     def _check(self, rc, h=-1):
         if rc != OK:
@@ -182,6 +192,20 @@ class Context:
     def set_wave_boxes(self, boxes: int):
         """Boxes per wave of the waves form (they share as many scratch slots)."""
         self.call("ctuppm_set_wave_boxes", int(boxes))
+
+    def bandwidth_probe(self, kind: str, gib: int = 2, reps: int = 10) -> float:
+        """GB/s a plain streaming kernel of the library reaches: 'copy' (read +
+        write), 'read' or 'write', over `gib` GiB buffers."""
+        torch = self.torch
+        n = (gib << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a) if kind != "read" else a
+        k = {"copy": 0, "read": 1, "write": 2}[kind]
+        v = ctypes.c_double()
+        self.call("ctuppm_bandwidth_probe", k, ctypes.c_void_p(a.data_ptr()),
+                  ctypes.c_void_p(b.data_ptr()), n * 8, int(reps), ctypes.byref(v))
+        del a, b
+        return v.value
 
     def set_fused(self, on: bool):
         """CTU cell stages: tracing and transverse stage 1 of the three
@@ -274,7 +298,11 @@ class Solver:
     given per patch (``fine_patches``) or as ``U0_fine`` over the rectangle
     starting at ``fine_lo``."""
 
-    def __init__(self, ctx: Context, prob: W.Problem, form="batched", fixed_dt: Optional[float] = None):
+    def __init__(self, ctx: Context, prob: W.Problem, form="batched", fixed_dt: Optional[float] = None,
+                 side_stream=None):
+        """side_stream: allocate and upload on this torch stream (pinned host
+        memory, no host wait) and make the context's stream wait for it with
+        an event, so admitting a problem does not stall work in flight."""
         torch = ctx.torch
         self.ctx, self.prob = ctx, prob
         self.form = FORMS[form] if isinstance(form, str) else int(form)
@@ -297,12 +325,28 @@ class Solver:
         dev = torch.device("cuda", torch.cuda.current_device())
         self.nv = 5 + int(prob.nspec)
         self.dev = dev
-        self.lv = [self._alloc_level(boxes) for boxes in self.levels]
         pats = W.patch_list(prob) if nl == 2 else None
         if nl == 2:  # the fine patches, and their bounding box
             self._set_patches([(tuple(lo), tuple(U.shape[1:][::-1])) for lo, U in pats])
-        self._bind_workspace()
-        self.upload(prob.U0, patches=pats)
+        if side_stream is None:
+            self.lv = [self._alloc_level(boxes) for boxes in self.levels]
+            self._bind_workspace()
+            self.upload(prob.U0, patches=pats)
+        else:
+            compute = ctx.stream
+            with torch.cuda.stream(side_stream):
+                self.lv = [self._alloc_level(boxes) for boxes in self.levels]
+                ws = self._alloc_workspace()
+                self._fill_fabs(prob.U0, pats, pinned=True)
+            ev = torch.cuda.Event()
+            ev.record(side_stream)
+            compute.wait_event(ev)
+            for t in [ws] + [L[k] for L in self.lv for k in ("A", "B")]:
+                t.record_stream(compute)  # freed memory is reused only after the context's work
+            self.ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(ws.data_ptr()), ws.numel())
+            self.ws = ws
+            for level in range(len(self.lv)):
+                self._bind(level)
         self.fixed_dt = float(fixed_dt) if fixed_dt else None
         self.steps_before = 0  # steps taken before a checkpoint this solver resumed from
         if fixed_dt:
@@ -322,6 +366,11 @@ class Solver:
         return {"boxes": boxes, "offsets": offsets, "shapes": shapes, "total": off, "A": A, "B": B}
 
     def _bind_workspace(self):
+        ws = self._alloc_workspace()
+        self.ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(ws.data_ptr()), ws.numel())
+        self.ws = ws  # the old workspace (records copied from it on the stream) is released after the bind
+
+    def _alloc_workspace(self):
         ws = ctypes.c_size_t()
         best = 0
         if len(self.levels) == 2:
@@ -333,9 +382,7 @@ class Solver:
         for f in forms:
             self.ctx.call("ctuppm_workspace_bytes", self.pid, f, ctypes.byref(ws))
             best = max(best, ws.value)
-        ws = self.ctx.torch.empty((max(best, 256),), dtype=self.ctx.torch.uint8, device=self.dev)
-        self.ctx.call("ctuppm_bind_workspace", self.pid, ctypes.c_void_p(ws.data_ptr()), ws.numel())
-        self.ws = ws  # the old workspace (records copied from it on the stream) is released after the bind
+        return self.ctx.torch.empty((max(best, 256),), dtype=self.ctx.torch.uint8, device=self.dev)
 
     def meta_bytes(self) -> int:
         """Bytes at the start of the workspace holding the library's device tables."""
@@ -373,6 +420,14 @@ class Solver:
         (fine index lo, state) pair) into the A fabs; ghosts NaN."""
         fine = patches if patches is not None else (
             [(self.fine_lo, Ufine)] if Ufine is not None and len(self.lv) == 2 else None)
+        self._fill_fabs(Uvalid, fine)
+        for level in range(len(self.lv)):
+            self._bind(level)
+
+    def _fill_fabs(self, Uvalid, fine, pinned: bool = False):
+        """A fabs <- the state (ghosts NaN), B fabs <- NaN, on the current torch
+        stream; pinned: through pinned host memory without a host wait."""
+        torch = self.ctx.torch
         for level in range(len(self.lv)):
             L = self.lv[level]
             host = np.full(L["total"], np.nan)
@@ -384,9 +439,12 @@ class Solver:
                 if U.shape[0] != self.nv:
                     raise ValueError(f"state has {U.shape[0]} components, the problem {self.nv}")
                 host[off:off + int(np.prod(shape))] = W.grown_fab(U, box, origin=origin).ravel()
-            L["A"].copy_(self.ctx.torch.from_numpy(host))
+            t = torch.from_numpy(host)
+            if pinned:
+                L["A"].copy_(t.pin_memory(), non_blocking=True)
+            else:
+                L["A"].copy_(t)
             L["B"].fill_(float("nan"))
-            self._bind(level)
 
     def step(self, nsteps: int = 1, form=None):
         f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
@@ -405,6 +463,12 @@ class Solver:
         """Guarded steps (no synchronisation): a failing step is not committed."""
         f = self.form if form is None else (FORMS[form] if isinstance(form, str) else int(form))
         self.ctx.step([self], f, nsteps, guarded=True)
+
+    def rejections_seen(self) -> int:
+        """Guarded steps rejected as far as the host sees without a sync."""
+        v = ctypes.c_longlong()
+        self.ctx.call("ctuppm_rejections_seen", self.pid, ctypes.byref(v))
+        return int(v.value)
 
     def rejections(self) -> int:
         """Guarded steps rejected so far (synchronises; acknowledges them)."""

@@ -9,6 +9,16 @@ soon as its steps are done: its state is copied back and its memory freed,
 which makes room for the next arrivals.  Latency is measured on the host from
 arrival to result.
 
+Nothing here waits for the GPU in the common case.  A new problem's memory is
+allocated and its initial state uploaded from pinned host memory on a side
+stream, which the step stream waits for with an event; its device tables
+are written by the library's asynchronous copies.  Steps are guarded (a
+step whose new state fails is not committed, the retry criterion of the
+paper's section 3.2); the host learns of a rejection from host-mapped memory
+and only then synchronises, redoing that problem's step in halves.  A problem
+is done when the event recorded after its last step has passed; the host
+keeps at most two steps in flight ahead of it.
+
 All device work goes through the C ABI (``ctuppm.Context.step`` over the
 active problems); this module only schedules.
 """
@@ -49,6 +59,7 @@ class Request:
     prob: W.Problem
     arrival: float          # seconds after the start of the run
     steps: int
+    fail_step: Optional[int] = None  # test hook: the update flags a failed cell at this step, once
 
 
 @dataclasses.dataclass
@@ -60,6 +71,8 @@ class Result:
     finished: float
     state: Optional[np.ndarray]
     steps: int
+    rejected: int = 0       # guarded steps the retry criterion rejected (redone in halves)
+    failed: bool = False    # even an eighth of a step failed: the state is the last accepted one
 
     @property
     def latency(self) -> float:
@@ -68,43 +81,71 @@ class Result:
 
 class Server:
     def __init__(self, ctx: ctuppm.Context, hbm_budget: float = 64e9, form: str = "batched",
-                 keep_states: bool = False, max_active: Optional[int] = None):
+                 keep_states: bool = False, max_active: Optional[int] = None, inflight: int = 2):
         self.ctx = ctx
         self.budget = float(hbm_budget)
         self.form = form
         self.keep_states = keep_states
         self.max_active = max_active
+        self.inflight = inflight
         self.used = 0
         self.active: List[dict] = []
+        self.finishing: List[dict] = []
         self.results: Dict[int, Result] = {}
         self.batch_sizes: List[int] = []
         self.zone_updates = 0
+        self.steps_events: List = []
 
     def _admit(self, req: Request, now: float) -> None:
-        solver = ctuppm.Solver(self.ctx, req.prob, form=self.form)
+        solver = ctuppm.Solver(self.ctx, req.prob, form=self.form, side_stream=self.ctx.side_stream)
+        if req.fail_step is not None:
+            solver.set_fail_hook(req.fail_step)
         need = footprint_bytes(req.prob)
         self.used += need
-        self.active.append({"req": req, "solver": solver, "done": 0, "need": need, "admitted": now})
+        self.active.append({"req": req, "solver": solver, "done": 0, "need": need, "admitted": now,
+                            "rejected": 0, "failed": False})
 
     def _retire(self, slot: dict, now_fn: Callable[[], float]) -> None:
         s = slot["solver"]
         state = s.state() if self.keep_states else None
-        if not self.keep_states:
-            self.ctx.torch.cuda.current_stream().synchronize()
         req = slot["req"]
         self.results[req.rid] = Result(req.rid, req.prob.n[0], req.arrival, slot["admitted"], now_fn(), state,
-                                       slot["done"])
+                                       slot["done"], slot["rejected"], slot["failed"])
         s.close()
         del slot["solver"]
         self.used -= slot["need"]
 
+    def _resolve(self, a: dict) -> bool:
+        """Synchronise and count the problem's committed steps; when a guarded
+        step of it was rejected, redo the interval with the checked step
+        (halving dt).  True if the problem has new rejections."""
+        s = a["solver"]
+        before = a["rejected"]
+        a["rejected"] = s.rejections()  # synchronises, acknowledges
+        a["done"] = int(s.counters()[5])
+        if a["rejected"] > before and a["done"] < a["req"].steps:
+            try:
+                s.step_checked()
+            except ctuppm.Rejected:
+                a["failed"] = True
+                a["done"] = a["req"].steps
+                return True
+            a["done"] = int(s.counters()[5])
+        return a["rejected"] > before
+
+    def _resolve_rejections(self) -> None:
+        for a in self.active:
+            self._resolve(a)
+
     def run(self, requests: Sequence[Request], realtime: bool = True) -> Dict[int, Result]:
         """Serve the requests; with realtime, arrivals follow the wall clock."""
+        torch = self.ctx.torch
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         t0 = time.perf_counter()
         now = (lambda: time.perf_counter() - t0) if realtime else (lambda: float("inf"))
+        stamp = now if realtime else (lambda: 0.0)
         qi = 0
-        while qi < len(pending) or self.active:
+        while qi < len(pending) or self.active or self.finishing:
             t = now()
             # admission: FIFO while the budget (and slot cap) allows
             while qi < len(pending) and pending[qi].arrival <= t:
@@ -118,22 +159,45 @@ class Server:
                     break
                 self._admit(req, t if realtime else 0.0)
                 qi += 1
+            # results whose last step has run on the device (a problem whose
+            # in-flight steps were rejected goes back to the active set)
+            done = [f for f in self.finishing if f["event"].query()]
+            self.finishing = [f for f in self.finishing if f not in done]
+            for f in done:
+                if f["solver"].rejections_seen() != f["rejected"]:
+                    self._resolve(f)
+                    if f["done"] < f["req"].steps:
+                        self.active.append(f)
+                        continue
+                self._retire(f, stamp)
             if not self.active:
-                if qi < len(pending) and realtime:
+                if self.finishing:
+                    self.finishing[0]["event"].synchronize()
+                elif qi < len(pending) and realtime:
                     time.sleep(max(0.0, min(pending[qi].arrival - now(), 0.01)))
                 continue
-            # one step of every active problem, batched
+            # one guarded step of every active problem, batched
             solvers = [a["solver"] for a in self.active]
-            self.ctx.step(solvers, self.form, 1)
-            self.batch_sizes.append(len(solvers))
+            try:
+                self.ctx.step(solvers, self.form, 1, guarded=True)
+            except ctuppm.Rejected:
+                self._resolve_rejections()
+            else:
+                self.batch_sizes.append(len(solvers))
+                for a in self.active:
+                    a["done"] += 1
+                    self.zone_updates += a["req"].prob.zones
+            ev = torch.cuda.Event()
+            ev.record(self.ctx.stream)
+            self.steps_events.append(ev)
+            if len(self.steps_events) > self.inflight:
+                self.steps_events.pop(0).synchronize()
             for a in self.active:
-                a["done"] += 1
-                self.zone_updates += a["req"].prob.zones
-            finished = [a for a in self.active if a["done"] >= a["req"].steps]
-            if finished:
-                for a in finished:
-                    self._retire(a, now if realtime else (lambda: 0.0))
-                self.active = [a for a in self.active if a["done"] < a["req"].steps]
+                if a["done"] >= a["req"].steps:
+                    a["event"] = ev
+                    self.finishing.append(a)
+            self.active = [a for a in self.active if a["done"] < a["req"].steps]
+        torch.cuda.synchronize()
         return self.results
 
 

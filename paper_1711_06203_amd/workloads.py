@@ -246,14 +246,27 @@ def rayleigh_taylor(n=384, seed=20260103, box_seed=None, gamma=1.4, steps=200, b
 
 
 def _fourier_field(rng: np.random.Generator, x, y, z, modes=8):
+    """Sum of `modes` seeded modes a_m sin(2 pi k_m . x + phase_m), k_m in
+    {-2..2}^3 without 0, normalised by the sum of the amplitudes."""
     ks = [k for k in np.ndindex(5, 5, 5) if k != (2, 2, 2)]
-    f = np.zeros_like(x)
     amps = rng.uniform(0.5, 1.0, size=modes)
     phases = rng.uniform(0.0, 2.0 * np.pi, size=modes)
     picks = rng.integers(len(ks), size=modes)
+    # sin(a + b + c) = Im(e^{ia} e^{ib} e^{ic}): each mode is a (z, y) plane
+    # pattern times an x profile, so the sum is one matrix product (x, y, z
+    # are the cell-centre grids of cell_centres, each varying along one axis)
+    x1, y1, z1 = x[0, 0, :], y[0, :, 0], z[:, 0, 0]
+    zy = np.empty((z1.size * y1.size, 2 * modes))
+    xp = np.empty((2 * modes, x1.size))
     for m in range(modes):
         kx, ky, kz = (c - 2 for c in ks[int(picks[m])])
-        f = f + amps[m] * np.sin(2.0 * np.pi * (kx * x + ky * y + kz * z) + phases[m])
+        ex = np.exp(1j * (2.0 * np.pi * kx * x1 + phases[m]))
+        p = amps[m] * (np.exp(1j * (2.0 * np.pi * kz * z1))[:, None] * np.exp(1j * (2.0 * np.pi * ky * y1))[None, :])
+        zy[:, 2 * m] = p.real.ravel()
+        zy[:, 2 * m + 1] = p.imag.ravel()
+        xp[2 * m] = ex.imag
+        xp[2 * m + 1] = ex.real
+    f = (zy @ xp).reshape(z1.size, y1.size, x1.size)
     return f / amps.sum()
 
 

@@ -52,6 +52,36 @@ def test_served_results_equal_alone_and_oracle(ctx):
     assert max(max_rel(res[0].state, ref)) <= 1e-10
 
 
+def test_a_rejected_step_is_redone_and_reported(ctx):
+    """A served problem whose update fails once (host-set hook) is not
+    committed there: the rejection is reported with its result, the step is
+    taken again, and the result still equals the problem advanced alone."""
+    from paper_1711_06203_amd import serving
+    reqs = []
+    for r in range(4):
+        prob = W.serving_request(seed=3000 + r, n=(16, 24)[r % 2], steps=8)
+        reqs.append(serving.Request(r, prob, 0.0, 8, fail_step=3 if r == 1 else None))
+    srv = serving.Server(ctx, hbm_budget=1e12, keep_states=True)
+    res = srv.run(reqs, realtime=False)
+    assert res[1].rejected >= 1 and not res[1].failed
+    assert all(res[r].rejected == 0 for r in (0, 2, 3))
+    for req in reqs:
+        assert res[req.rid].steps == 8
+        assert np.array_equal(res[req.rid].state, _alone(ctx, req.prob, 8)), req.rid
+
+
+def test_admission_overlaps_steps_in_flight(ctx):
+    """Admitting a problem while others are stepping enqueues its upload on a
+    side stream: the served results are unchanged."""
+    from paper_1711_06203_amd import serving
+    reqs = [serving.Request(r, W.serving_request(seed=4000 + r, n=(32, 16)[r % 2], steps=5), 0.002 * r, 5)
+            for r in range(6)]
+    srv = serving.Server(ctx, hbm_budget=1e12, keep_states=True)
+    res = srv.run(reqs, realtime=True)
+    for req in reqs:
+        assert np.array_equal(res[req.rid].state, _alone(ctx, req.prob, 5)), req.rid
+
+
 def test_admission_respects_hbm_budget(ctx):
     from paper_1711_06203_amd import serving
     reqs = [serving.Request(r, W.serving_request(seed=2000 + r, n=24, steps=3), 0.0, 3) for r in range(5)]
