@@ -416,7 +416,8 @@ def serving_leg(ctx, nreq: int) -> dict:
     """The serving workload beside the headline.  Capacity: 120 requests
     present at t = 0, served batched and, the same requests, per box (every
     stage launched per box of every problem).  Latency: one Poisson stream of
-    `nreq` requests at 0.8 of the batched capacity, served both ways."""
+    `nreq` requests at 0.8 of the batched capacity, served batched, per box,
+    and batched with synchronous admissions."""
     import numpy as np
     from paper_1711_06203_amd import serving
     out = {"workload": "serving_periodic_N^3_N_in_32-128_50_steps", "hbm_budget_bytes": 64e9,
@@ -432,16 +433,21 @@ def serving_leg(ctx, nreq: int) -> dict:
     rate = 0.8 * out["capacity"]["batched"]["requests_per_s"]
     out["arrival_rate_per_s"] = rate
     stream = serving.poisson_requests(nreq, rate=rate, seed=92)
-    for form in ("batched", "per_box"):
-        srv = serving.Server(ctx, hbm_budget=64e9, form=form)
+    # the stream served batched, per box, and batched with each admission
+    # uploading on the step stream and waiting for it
+    for name, form, asyn in (("batched", "batched", True), ("per_box", "per_box", True),
+                             ("batched_sync_admission", "batched", False)):
+        srv = serving.Server(ctx, hbm_budget=64e9, form=form, async_admission=asyn)
         t0 = time.perf_counter()
         res = srv.run(stream, realtime=True)
         el = time.perf_counter() - t0
         st = serving.latency_stats(res)
-        out[form] = {"zone_updates_per_s": srv.zone_updates / el, "requests_per_s": len(res) / el,
+        out[name] = {"zone_updates_per_s": srv.zone_updates / el, "requests_per_s": len(res) / el,
                      "p50_s": st["p50_s"], "p99_s": st["p99_s"], "mean_batch": float(np.mean(srv.batch_sizes)),
+                     "admission_ms_p50": 1e3 * float(np.percentile(srv.admit_s, 50)),
+                     "admission_ms_max": 1e3 * float(np.max(srv.admit_s)),
                      "rejected_steps": int(sum(r.rejected for r in res.values())), "wall_s": el}
-        print(json.dumps({"serving_leg": form, **out[form]}), file=sys.stderr, flush=True)
+        print(json.dumps({"serving_leg": name, **out[name]}), file=sys.stderr, flush=True)
     out["served_over_per_box"] = (out["capacity"]["batched"]["zone_updates_per_s"]
                                   / out["capacity"]["per_box"]["zone_updates_per_s"])
     return out

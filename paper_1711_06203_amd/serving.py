@@ -81,7 +81,10 @@ class Result:
 
 class Server:
     def __init__(self, ctx: ctuppm.Context, hbm_budget: float = 64e9, form: str = "batched",
-                 keep_states: bool = False, max_active: Optional[int] = None, inflight: int = 2):
+                 keep_states: bool = False, max_active: Optional[int] = None, inflight: int = 2,
+                 async_admission: bool = True):
+        """async_admission False: each admission uploads on the step stream and
+        waits for it (a comparison point for the side-stream admission)."""
         self.ctx = ctx
         self.budget = float(hbm_budget)
         self.form = form
@@ -95,9 +98,17 @@ class Server:
         self.batch_sizes: List[int] = []
         self.zone_updates = 0
         self.steps_events: List = []
+        self.async_admission = async_admission
+        self.admit_s: List[float] = []  # host time of each admission
 
     def _admit(self, req: Request, now: float) -> None:
-        solver = ctuppm.Solver(self.ctx, req.prob, form=self.form, side_stream=self.ctx.side_stream)
+        t0 = time.perf_counter()
+        if self.async_admission:
+            solver = ctuppm.Solver(self.ctx, req.prob, form=self.form, side_stream=self.ctx.side_stream)
+        else:
+            solver = ctuppm.Solver(self.ctx, req.prob, form=self.form)
+            self.ctx.torch.cuda.current_stream().synchronize()
+        self.admit_s.append(time.perf_counter() - t0)
         if req.fail_step is not None:
             solver.set_fail_hook(req.fail_step)
         need = footprint_bytes(req.prob)
