@@ -342,30 +342,44 @@ __global__ void k_flip(const Segs L, int guard) {
 
 // ---------------------------------------------------------------- flattening
 
-// CW84 shock indicator of the cell at offset o along stride st (direction d).
-CTU_DEV double shock_ind(const gdbl* __restrict__ p, const gdbl* __restrict__ un, int o, int st) {
-  const double dp1 = p[o + st] - p[o - st];
-  const double dp2 = p[o + 2 * st] - p[o - 2 * st];
+// CW84 shock indicator of a cell from the pressures two cells either side of
+// it (pm2, pm1, pp1, pp2) and the normal velocities of its neighbours.
+CTU_DEV double shock_ind(double pm2, double pm1, double pp1, double pp2, double um1, double up1) {
+  const double dp1 = pp1 - pm1;
+  const double dp2 = pp2 - pm2;
   double f = 0.0;
-  if (fabs(dp1) > 0.33 * dmin(p[o + st], p[o - st]) && un[o - st] - un[o + st] > 0.0)
+  if (fabs(dp1) > 0.33 * dmin(pp1, pm1) && um1 - up1 > 0.0)
     f = dmin(1.0, dmax(0.0, 10.0 * (fabs(dp1) / dmax(fabs(dp2), 1e-300) - 0.75)));
   return f;
 }
 
 // Flattening coefficient of the cell at grown offset o: the minimum over the
 // directions of 1 - max(shock indicator here, at the neighbour on the side of
-// lower pressure).
+// lower pressure).  Every pressure and velocity either neighbour's indicator
+// could need is loaded before any arithmetic, so a wave waits for memory once.
 CTU_DEV double flatten_cell(const Geo& g, const gdbl* __restrict__ q, int o) {
   const gdbl* __restrict__ p = q + 4 * g.gcomp;
-  double phi = 1.0;
+  double pv[3][7], uv[3][5];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int st = g.gstride(d);
     const gdbl* __restrict__ un = q + (1 + d) * g.gcomp;
-    const int s = (p[o + st] - p[o - st]) > 0.0 ? 1 : -1;
-    const double fd = dmax(shock_ind(p, un, o, st), shock_ind(p, un, o - s * st, st));
-    const double v = 1.0 - fd;
-    phi = d == 0 ? v : dmin(phi, v);
+#pragma unroll
+    for (int t = 0; t < 7; ++t) pv[d][t] = p[o + (t - 3) * st];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) uv[d][t] = un[o + (t - 2) * st];
+  }
+  double phi = 1.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double* v = pv[d];
+    const double* u = uv[d];
+    const int c = (v[4] - v[2]) > 0.0 ? 2 : 4;  // the neighbour on the side of lower pressure
+    const double f0 = shock_ind(v[1], v[2], v[4], v[5], u[1], u[3]);
+    const double f1 = shock_ind(v[c - 2], v[c - 1], v[c + 1], v[c + 2], u[c - 2], u[c]);
+    const double fd = dmax(f0, f1);
+    const double w = 1.0 - fd;
+    phi = d == 0 ? w : dmin(phi, w);
   }
   return phi;
 }
@@ -411,18 +425,22 @@ CTU_DEV void trace_cell(const BoxRec& B, const Geo& g, const ProbDev* P, int i, 
   const int x[3] = {i, j, k};
   const int o = g.g(i, j, k), oh = g.h(i, j, k);
   double eta = 0.0;
-  if (LIM & 2) {  // contact steepening weight from the density and the neighbours' pressures
-    const gdbl* r = q + o;
-    const gdbl* pr = q + 4 * g.gcomp + o;
-    eta = steep_eta(r[-2 * st], r[-st], r[0], r[st], r[2 * st], pr[-st], pr[st], P->gamma);
-  }
-  Parab par[5];
+  // the five stencils and the sound speed are loaded before any arithmetic
+  double sv[5][5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const gdbl* a = q + comp[m] * g.gcomp + o;
-    par[m] = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, m == 0 ? eta : 0.0);
+#pragma unroll
+    for (int t = 0; t < 5; ++t) sv[m][t] = a[(t - 2) * st];
   }
-  const double rho = q[o], un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
+  const double cs = q[5 * g.gcomp + o];
+  if (LIM & 2)  // contact steepening weight from the density and the neighbours' pressures
+    eta = steep_eta(sv[0][0], sv[0][1], sv[0][2], sv[0][3], sv[0][4], sv[4][1], sv[4][3], P->gamma);
+  Parab par[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+    par[m] = ppm_l<LIM>(sv[m][0], sv[m][1], sv[m][2], sv[m][3], sv[m][4], phi, m == 0 ? eta : 0.0);
+  const double rho = sv[0][2], un = sv[1][2];
   if (x[D] <= nD - 1) {
     double up[5];
     trace_up(par, rho, un, cs, dtdx, up);
