@@ -2334,25 +2334,39 @@ int ctuppm_debug_stage(ctuppm_ctx* c, int pid, int level, int box, int array, in
   const int n[3] = {box_n(L[box], 0), box_n(L[box], 1), box_n(L[box], 2)};
   const long long grown = grown_cells(n), h1 = h1_cells(n);
   const long long nq = kNV + 1 + ns, nv = kNV + ns;
-  long long first, count;  // in doubles from the scratch start
+  const long long plane = (long long)(n[0] + 2) * (n[1] + 2), pplane = h1_plane(n);  // dense / padded
+  long long first, ncomp;  // in doubles from the scratch start; components
   if (array == 0) {
     first = 0;
-    count = nq * grown;
+    ncomp = nq;
   } else if (array == 1) {
     first = nq * grown;
-    count = h1;
+    ncomp = 1;
   } else {
     first = nq * grown + (1 + nv * (array - 2)) * h1;
-    count = nv * h1;
+    ncomp = nv;
   }
+  const long long count = array == 0 ? nq * grown : ncomp * plane * (n[2] + 2);  // dense, as returned
   *elems = count;
-  const size_t end = off + size_t(first + count) * sizeof(double);
+  const size_t end = off + size_t(first + (array == 0 ? count : ncomp * h1)) * sizeof(double);
   if (end > P->ws_bytes)
     return fail(c, CTUPPM_ENOMEM, "problem %d: array %d of box %d in form %d ends at byte %zu of a %zu-byte workspace",
                 pid, array, box, form, end, P->ws_bytes);
   if (!out) return CTUPPM_OK;
   const double* src = (const double*)((const char*)P->ws + off) + first;
-  HIPCHK(c, hipMemcpyAsync(out, src, size_t(count) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (array == 0) {
+    HIPCHK(c, hipMemcpyAsync(out, src, size_t(count) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return CTUPPM_OK;
+  }
+  // halo-1 arrays: drop the plane padding; the left states (arrays 2..4) are
+  // stored at the cell below each face, so face f is read from f - stride
+  if (array >= 2 && array <= 4) {
+    const int d = array - 2;
+    src -= d == 0 ? 1 : (d == 1 ? (n[0] + 2) : pplane);
+  }
+  HIPCHK(c, hipMemcpy2DAsync(out, size_t(plane) * sizeof(double), src, size_t(pplane) * sizeof(double),
+                             size_t(plane) * sizeof(double), size_t(ncomp * (n[2] + 2)), hipMemcpyDeviceToDevice,
+                             c->stream));
   return CTUPPM_OK;
 }
 

@@ -141,13 +141,16 @@ struct TwoLevelArgs {
 
 // Scratch layout per box, in doubles, with nv = 5 + nspec components:
 // q ((6 + nspec) x grown: rho, u, v, w, p, c, X_s), phi (1 x halo-1),
-// ql[3], qr[3], fn[3], f1[6], ff[3] (nv x halo-1 each).
+// ql[3], qr[3], fn[3], f1[6], ff[3] (nv x halo-1 each).  A halo-1 plane
+// (cells -1..n in x and y) is padded to a multiple of 16 doubles, so every
+// plane and every component starts on a 128-byte line: a wave storing 64
+// consecutive cells of a plane then writes whole lines (partial-line stores
+// cost HBM write bandwidth).
 __host__ __device__ inline long long grown_cells(const int n[3]) {
   return (long long)(n[0] + 2 * kNG) * (n[1] + 2 * kNG) * (n[2] + 2 * kNG);
 }
-__host__ __device__ inline long long h1_cells(const int n[3]) {
-  return (long long)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
-}
+__host__ __device__ inline int h1_plane(const int n[3]) { return ((n[0] + 2) * (n[1] + 2) + 15) & ~15; }
+__host__ __device__ inline long long h1_cells(const int n[3]) { return (long long)h1_plane(n) * (n[2] + 2); }
 __host__ __device__ inline long long scratch_doubles(const int n[3], int nspec) {
   return (6 + nspec) * grown_cells(n) + (1 + 18 * (kNV + nspec)) * h1_cells(n);
 }

@@ -29,6 +29,9 @@ namespace {
 // goes in scalar registers.
 using gdbl = __attribute__((address_space(1))) double;
 CTU_DEV gdbl* gp(double* p) { return (gdbl*)p; }
+// LDS doubles, volatile: values a thread parks there are re-read from LDS
+// (not kept in registers), through ds_* instructions.
+using ldbl = __attribute__((address_space(3))) volatile double;
 
 template <class F>
 CTU_DEV void for_each_chunk(int nchunks, F&& f) {
@@ -102,7 +105,7 @@ struct Geo {
     gplane = gx * (n[1] + 2 * kNG);
     gcomp = gplane * (n[2] + 2 * kNG);
     hx = n[0] + 2;
-    hplane = hx * (n[1] + 2);
+    hplane = h1_plane(n);
     hcomp = hplane * (n[2] + 2);
   }
   CTU_DEV int g(int i, int j, int k) const { return (k + kNG) * gplane + (j + kNG) * gx + (i + kNG); }
@@ -117,7 +120,10 @@ struct Geo {
   }
   CTU_DEV gdbl* q(double* s) const { return gp(s); }
   CTU_DEV gdbl* phi(double* s) const { return gp(s) + (long long)(kNV + 1 + ns) * gcomp; }
-  CTU_DEV gdbl* ql(double* s, int d) const { return h1arr(s, d); }
+  // ql(d) is indexed by face (element f: the left state of face f along d)
+  // but stored at the cell below the face, f - 1, so the tracing of a cell
+  // writes its own, line-aligned index; the pointer is offset accordingly.
+  CTU_DEV gdbl* ql(double* s, int d) const { return h1arr(s, d) - hstride(d); }
   CTU_DEV gdbl* qr(double* s, int d) const { return h1arr(s, 3 + d); }
   CTU_DEV gdbl* fn(double* s, int d) const { return h1arr(s, 6 + d); }
   CTU_DEV gdbl* f1(double* s, int p) const { return h1arr(s, 9 + p); }
@@ -407,68 +413,107 @@ CTU_DEV void store_flux(gdbl* __restrict__ F, int hcomp, int o, const double f[5
 // Tracing of one cell (of -1..n) along D: parabolas of the five permuted
 // primitives, tracing to both faces, floors and the gravity predictor; the
 // left state of the upper face and the right state of the lower face are
-// stored for faces 0..n.
-template <int D, int LIM>
-CTU_DEV void trace_cell(const BoxRec& B, const Geo& g, const ProbDev* P, int i, int j, int k, double phi,
-                        unsigned long long& floors) {
-  constexpr int zpos = 1 + (2 - D + 3) % 3;  // permuted slot of the z velocity
+// stored for faces 0..n.  It comes in pieces -- the loads of the stencils,
+// the parabolas, the two traced states, the stores -- so that a kernel
+// tracing several directions can order them: a wave with stores in flight
+// that waits for a later load waits for those stores as well (one counter
+// covers both), so the merged kernel issues all its global stores after its
+// last load.
+struct Stencil {
+  double sv[5][5];  // the five permuted primitives at offsets -2..2 along D
+  double cs;        // the sound speed of the cell
+};
+
+template <int D>
+CTU_DEV void trace_load(const Geo& g, const gdbl* __restrict__ q, int o, Stencil& S) {
   constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
+  const int st = g.gstride(D);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const gdbl* a = q + comp[m] * g.gcomp + o;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) S.sv[m][t] = a[(t - 2) * st];
+  }
+  S.cs = q[5 * g.gcomp + o];
+}
+
+// The parabolas of the five permuted primitives of a cell along D.
+template <int D, int LIM>
+CTU_DEV void trace_parab(const ProbDev* P, const Stencil& S, double phi, Parab par[5]) {
+  double eta = 0.0;
+  if (LIM & 2)  // contact steepening weight from the density and the neighbours' pressures
+    eta = steep_eta(S.sv[0][0], S.sv[0][1], S.sv[0][2], S.sv[0][3], S.sv[0][4], S.sv[4][1], S.sv[4][3], P->gamma);
+#pragma unroll
+  for (int m = 0; m < 5; ++m)
+    par[m] = ppm_l<LIM>(S.sv[m][0], S.sv[m][1], S.sv[m][2], S.sv[m][3], S.sv[m][4], phi, m == 0 ? eta : 0.0);
+}
+
+// The left state of the upper face (UP) or the right state of the lower face,
+// floors and gravity predictor applied.  Both are computed for every cell of
+// -1..n; floors are counted only on the states of faces 0..n (xd is the
+// cell's index along D, nd the box's extent).
+template <int D, bool UP>
+CTU_DEV void trace_face(const ProbDev* P, const Parab par[5], double rho, double un, double cs, int xd, int nd,
+                        double v[5], unsigned long long& floors) {
+  constexpr int zpos = 1 + (2 - D + 3) % 3;  // permuted slot of the z velocity
+  const double dtdx = P->dtdx[D];
+  const unsigned long long f = UP ? xd <= nd - 1 : xd >= 0;
+  if (UP) trace_up(par, rho, un, cs, dtdx, v);
+  else trace_dn(par, rho, un, cs, dtdx, v);
+  if (v[0] < P->small_dens) { v[0] = P->small_dens; floors += f; }
+  if (v[4] < P->small_pres) { v[4] = P->small_pres; floors += f; }
+  if (P->grav_z != 0.0) v[zpos] = v[zpos] + 0.5 * P->dt * P->grav_z;
+}
+
+// Stores of the cell's two traced states, unconditionally: the upper state
+// of cell n (a face n + 1) and the lower state of cell -1 (a face -1) land in
+// their own slots of the halo-1 arrays and are never read; storing them
+// lets a wave write whole, line-aligned runs of every array.
+template <int D>
+CTU_DEV void trace_store(const BoxRec& B, const Geo& g, int oh, const double up[5], const double dn[5]) {
+  gdbl* __restrict__ ql = g.ql(B.scr, D);
+  gdbl* __restrict__ qr = g.qr(B.scr, D);
+  const int sth = g.hstride(D);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
+}
+
+// The species of the cell along D: parabolas with the hydro flattening,
+// traced with the hydro wave speeds of the cell.
+template <int D, int LIM>
+CTU_DEV void trace_species(const BoxRec& B, const Geo& g, const ProbDev* P, int xd, int o, int oh, double phi) {
   const gdbl* __restrict__ q = g.q(B.scr);
   gdbl* __restrict__ ql = g.ql(B.scr, D);
   gdbl* __restrict__ qr = g.qr(B.scr, D);
   const int st = g.gstride(D), sth = g.hstride(D);
   const double dtdx = P->dtdx[D];
-  const double hdtg = 0.5 * P->dt * P->grav_z;
-  const bool grav = P->grav_z != 0.0;
-  const double sd = P->small_dens, sp = P->small_pres;
-  const int nD = B.n[D];
+  const double un = q[(1 + D) * g.gcomp + o], cs = q[5 * g.gcomp + o];
+  const double lm = un - cs, l0 = un, lp = un + cs;
+  const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, spp = fabs(lp) * dtdx;
+  for (int is = 0; is < g.ns; ++is) {
+    const gdbl* a = q + (6 + is) * g.gcomp + o;
+    const Parab px = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+    if (xd <= B.n[D] - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
+    if (xd >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
+  }
+}
+
+template <int D, int LIM>
+CTU_DEV void trace_cell(const BoxRec& B, const Geo& g, const ProbDev* P, int i, int j, int k, double phi,
+                        unsigned long long& floors) {
   const int x[3] = {i, j, k};
   const int o = g.g(i, j, k), oh = g.h(i, j, k);
-  double eta = 0.0;
-  // the five stencils and the sound speed are loaded before any arithmetic
-  double sv[5][5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const gdbl* a = q + comp[m] * g.gcomp + o;
-#pragma unroll
-    for (int t = 0; t < 5; ++t) sv[m][t] = a[(t - 2) * st];
-  }
-  const double cs = q[5 * g.gcomp + o];
-  if (LIM & 2)  // contact steepening weight from the density and the neighbours' pressures
-    eta = steep_eta(sv[0][0], sv[0][1], sv[0][2], sv[0][3], sv[0][4], sv[4][1], sv[4][3], P->gamma);
+  Stencil S;
   Parab par[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m)
-    par[m] = ppm_l<LIM>(sv[m][0], sv[m][1], sv[m][2], sv[m][3], sv[m][4], phi, m == 0 ? eta : 0.0);
-  const double rho = sv[0][2], un = sv[1][2];
-  if (x[D] <= nD - 1) {
-    double up[5];
-    trace_up(par, rho, un, cs, dtdx, up);
-    if (up[0] < sd) { up[0] = sd; ++floors; }
-    if (up[4] < sp) { up[4] = sp; ++floors; }
-    if (grav) up[zpos] = up[zpos] + hdtg;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
-  }
-  if (g.ns > 0) {
-    const double lm = un - cs, l0 = un, lp = un + cs;
-    const double sm = fabs(lm) * dtdx, s0 = fabs(l0) * dtdx, spp = fabs(lp) * dtdx;
-    for (int is = 0; is < g.ns; ++is) {
-      const gdbl* a = q + (6 + is) * g.gcomp + o;
-      const Parab px = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-      if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
-      if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
-    }
-  }
-  if (x[D] >= 0) {
-    double dn[5];
-    trace_dn(par, rho, un, cs, dtdx, dn);
-    if (dn[0] < sd) { dn[0] = sd; ++floors; }
-    if (dn[4] < sp) { dn[4] = sp; ++floors; }
-    if (grav) dn[zpos] = dn[zpos] + hdtg;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
-  }
+  double up[5], dn[5];
+  trace_load<D>(g, g.q(B.scr), o, S);
+  trace_parab<D, LIM>(P, S, phi, par);
+  trace_face<D, true>(P, par, S.sv[0][2], S.sv[1][2], S.cs, x[D], B.n[D], up, floors);
+  trace_face<D, false>(P, par, S.sv[0][2], S.sv[1][2], S.cs, x[D], B.n[D], dn, floors);
+  trace_store<D>(B, g, oh, up, dn);
+  if (g.ns > 0) trace_species<D, LIM>(B, g, P, x[D], o, oh, phi);
 }
 
 // One thread per cell of -1..n, tracing along D.
@@ -488,20 +533,67 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Segs L) {
 // One thread per cell of -1..n: the flattening coefficient (also stored, for
 // stage dumps), then tracing along x, then y, then z, so the cell's
 // primitives are read once for the flattening and the three directions (the
-// separate kernels read them four times).
+// separate kernels read them four times).  The traced states of x and y wait
+// in LDS (each thread its own slots) until the loads of z have returned: a
+// wave whose stores are still in flight waits for them as well when it waits
+// for a later load, so every global store of the cell is issued after its
+// last load.
 template <int LIM>
 __global__ __launch_bounds__(kBlock) void k_trace3(const Segs L) {
+  // 40 KB: the up and dn states of x and y, [direction][component][thread];
+  // volatile, so the compiler keeps them in LDS rather than in registers
+  __shared__ double held_lds[2 * 10 * kBlock];
+  ldbl* held = (ldbl*)held_lds;
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
+    const ProbDev* P = B.P;
     const gdbl* __restrict__ q = g.q(B.scr);
     gdbl* __restrict__ phiout = g.phi(B.scr);
     unsigned long long floors = 0;
+    const int t = threadIdx.x;
     march(kCells1, B, M, [&](int i, int j, int k) {
-      const double phi = flatten_cell(g, q, g.g(i, j, k));
-      phiout[g.h(i, j, k)] = phi;
-      trace_cell<0, LIM>(B, g, B.P, i, j, k, phi, floors);
-      trace_cell<1, LIM>(B, g, B.P, i, j, k, phi, floors);
-      trace_cell<2, LIM>(B, g, B.P, i, j, k, phi, floors);
+      const int o = g.g(i, j, k), oh = g.h(i, j, k);
+      const double phi = flatten_cell(g, q, o);
+      Stencil S;
+      Parab par[5];
+      double v[5];
+      // x, then y: both traced states parked in LDS
+      trace_load<0>(g, q, o, S);
+      trace_parab<0, LIM>(P, S, phi, par);
+      trace_face<0, true>(P, par, S.sv[0][2], S.sv[1][2], S.cs, i, B.n[0], v, floors);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) held[m * kBlock + t] = v[m];
+      trace_face<0, false>(P, par, S.sv[0][2], S.sv[1][2], S.cs, i, B.n[0], v, floors);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) held[(5 + m) * kBlock + t] = v[m];
+      trace_load<1>(g, q, o, S);
+      trace_parab<1, LIM>(P, S, phi, par);
+      trace_face<1, true>(P, par, S.sv[0][2], S.sv[1][2], S.cs, j, B.n[1], v, floors);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) held[(10 + m) * kBlock + t] = v[m];
+      trace_face<1, false>(P, par, S.sv[0][2], S.sv[1][2], S.cs, j, B.n[1], v, floors);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) held[(15 + m) * kBlock + t] = v[m];
+      // z, the last loads: from here on the cell only stores
+      trace_load<2>(g, q, o, S);
+      trace_parab<2, LIM>(P, S, phi, par);
+      double up[5], dn[5];
+      trace_face<2, true>(P, par, S.sv[0][2], S.sv[1][2], S.cs, k, B.n[2], up, floors);
+      trace_face<2, false>(P, par, S.sv[0][2], S.sv[1][2], S.cs, k, B.n[2], dn, floors);
+      trace_store<2>(B, g, oh, up, dn);
+      phiout[oh] = phi;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) { up[m] = held[(10 * d + m) * kBlock + t]; dn[m] = held[(10 * d + 5 + m) * kBlock + t]; }
+        if (d == 0) trace_store<0>(B, g, oh, up, dn);
+        else trace_store<1>(B, g, oh, up, dn);
+      }
+      if (g.ns > 0) {
+        trace_species<0, LIM>(B, g, P, i, o, oh, phi);
+        trace_species<1, LIM>(B, g, P, j, o, oh, phi);
+        trace_species<2, LIM>(B, g, P, k, o, oh, phi);
+      }
     });
     count(&B.P->cnt[2], floors);
   });

@@ -47,7 +47,7 @@ def footprint_bytes(prob: W.Problem) -> int:
     for lo, hi in prob.boxes:
         n = [hi[d] - lo[d] + 1 for d in range(3)]
         grown = (n[0] + 2 * NG) * (n[1] + 2 * NG) * (n[2] + 2 * NG)
-        h1 = (n[0] + 2) * (n[1] + 2) * (n[2] + 2)
+        h1 = ((n[0] + 2) * (n[1] + 2) + 15) // 16 * 16 * (n[2] + 2)  # halo-1 planes padded to 16 doubles
         total += 2 * nv * grown * 8 + (((nv + 1) * grown + (1 + 18 * nv) * h1) * 8 + 255) // 256 * 256
         total += stage_fabs * ((nv * grown * 8 + 255) // 256 * 256)
     return total
