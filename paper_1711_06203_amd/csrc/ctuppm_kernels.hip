@@ -401,6 +401,16 @@ __global__ __launch_bounds__(kBlock) void k_flatten(const Segs L) {
 
 // ------------------------------------------------------ PPM + tracing along D
 
+// The same with streaming (non-temporal) stores, for fluxes that only a later
+// launch reads: they do not displace lines the current launch reads again.
+template <int D>
+CTU_DEV void store_flux_nt(gdbl* __restrict__ F, int hcomp, int o, const double f[5]) {
+  __builtin_nontemporal_store(f[0], &F[o]);
+  __builtin_nontemporal_store(f[1], &F[(1 + D) * hcomp + o]);
+  __builtin_nontemporal_store(f[2], &F[(1 + (D + 1) % 3) * hcomp + o]);
+  __builtin_nontemporal_store(f[3], &F[(1 + (D + 2) % 3) * hcomp + o]);
+  __builtin_nontemporal_store(f[4], &F[4 * hcomp + o]);
+}
 template <int D>
 CTU_DEV void store_flux(gdbl* __restrict__ F, int hcomp, int o, const double f[5]) {
   F[o] = f[0];
@@ -424,7 +434,7 @@ struct Stencil {
   double cs;        // the sound speed of the cell
 };
 
-template <int D>
+template <int D, bool CS = true>
 CTU_DEV void trace_load(const Geo& g, const gdbl* __restrict__ q, int o, Stencil& S) {
   constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
   const int st = g.gstride(D);
@@ -434,7 +444,7 @@ CTU_DEV void trace_load(const Geo& g, const gdbl* __restrict__ q, int o, Stencil
 #pragma unroll
     for (int t = 0; t < 5; ++t) S.sv[m][t] = a[(t - 2) * st];
   }
-  S.cs = q[5 * g.gcomp + o];
+  if (CS) S.cs = q[5 * g.gcomp + o];
 }
 
 // The parabolas of the five permuted primitives of a cell along D.
@@ -468,16 +478,17 @@ CTU_DEV void trace_face(const ProbDev* P, const Parab par[5], double rho, double
 // Stores of the cell's two traced states, unconditionally: the upper state
 // of cell n (a face n + 1) and the lower state of cell -1 (a face -1) land in
 // their own slots of the halo-1 arrays and are never read; storing them
-// lets a wave write whole, line-aligned runs of every array.
+// lets a wave write whole, line-aligned runs of every array.  The stores
+// stream (non-temporal): only later launches read the states.
 template <int D>
 CTU_DEV void trace_store(const BoxRec& B, const Geo& g, int oh, const double up[5], const double dn[5]) {
   gdbl* __restrict__ ql = g.ql(B.scr, D);
   gdbl* __restrict__ qr = g.qr(B.scr, D);
   const int sth = g.hstride(D);
 #pragma unroll
-  for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
+  for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(up[m], &ql[m * g.hcomp + oh + sth]);
 #pragma unroll
-  for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
+  for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(dn[m], &qr[m * g.hcomp + oh]);
 }
 
 // The species of the cell along D: parabolas with the hydro flattening,
@@ -495,8 +506,8 @@ CTU_DEV void trace_species(const BoxRec& B, const Geo& g, const ProbDev* P, int 
   for (int is = 0; is < g.ns; ++is) {
     const gdbl* a = q + (6 + is) * g.gcomp + o;
     const Parab px = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-    if (xd <= B.n[D] - 1) ql[(kNV + is) * g.hcomp + oh + sth] = species_up(px, lp, l0, spp, s0);
-    if (xd >= 0) qr[(kNV + is) * g.hcomp + oh] = species_dn(px, lm, l0, sm, s0);
+    if (xd <= B.n[D] - 1) __builtin_nontemporal_store(species_up(px, lp, l0, spp, s0), &ql[(kNV + is) * g.hcomp + oh + sth]);
+    if (xd >= 0) __builtin_nontemporal_store(species_dn(px, lm, l0, sm, s0), &qr[(kNV + is) * g.hcomp + oh]);
   }
 }
 
@@ -696,8 +707,10 @@ CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, const ProbDev* P, int i,
   double sL[5], sR[5], UL[5], UR[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    sL[m] = ql[m * g.hcomp + o];
-    sR[m] = qr[m * g.hcomp + o];
+    // read once: streaming loads leave the L2 to the normal fluxes, which
+    // the faces of the neighbouring plane read again
+    sL[m] = __builtin_nontemporal_load(&ql[m * g.hcomp + o]);
+    sR[m] = __builtin_nontemporal_load(&qr[m * g.hcomp + o]);
   }
   to_cons<A>(sL, P->rgm1, UL);
   to_cons<A>(sR, P->rgm1, UR);
@@ -724,17 +737,17 @@ CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, const ProbDev* P, int i,
     Wave W;
     rflux<RS>(tL, tR, P, f, W);
     gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
-    store_flux<A>(F1, g.hcomp, o, f);
+    store_flux_nt<A>(F1, g.hcomp, o, f);
     // species: rho X corrected by the same flux difference, back to X with
     // the corrected density (or the traced X where the state fell back)
     for (int is = 0; is < g.ns; ++is) {
       const int c = (kNV + is) * g.hcomp;
       const gdbl* Fm = Fb + c;
-      const double xL = ql[c + o], xR = qr[c + o];
+      const double xL = __builtin_nontemporal_load(&ql[c + o]), xR = __builtin_nontemporal_load(&qr[c + o]);
       const double wL = sL[0] * xL - c3 * (Fm[oL + sb] - Fm[oL]);
       const double wR = sR[0] * xR - c3 * (Fm[oR + sb] - Fm[oR]);
       const double yL = kL ? xL : wL / VL[0], yR = kR ? xR : wR / VR[0];
-      F1[c + o] = species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR);
+      __builtin_nontemporal_store(species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR), &F1[c + o]);
     }
   }
 }
@@ -868,7 +881,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Segs L) {
         double du = dtdx * (Fx[mo] - Fx[mo + 1]);
         du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
         du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
-        un[m] = U[m * g.gcomp + og] + du;
+        un[m] = __builtin_nontemporal_load(&U[m * g.gcomp + og]) + du;  // read once here
       }
       if (grav) {
         un[3] = un[3] + hdtg * (U[og] + un[0]);
@@ -885,15 +898,15 @@ __global__ __launch_bounds__(kBlock) void k_update(const Segs L) {
       }
       if (forced && i == 0 && j == 0 && k == 0) bad = true;  // host-set test hook
 #pragma unroll
-      for (int m = 0; m < 5; ++m) Un[m * g.gcomp + og] = un[m];
+      for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(un[m], &Un[m * g.gcomp + og]);  // read next step
       for (int m = kNV; m < g.nv; ++m) {
         const int mo = m * g.hcomp + o;
         double du = dtdx * (Fx[mo] - Fx[mo + 1]);
         du = du + dtdy * (Fy[mo] - Fy[mo + g.hx]);
         du = du + dtdz * (Fz[mo] - Fz[mo + g.hplane]);
-        const double v = U[m * g.gcomp + og] + du;
+        const double v = __builtin_nontemporal_load(&U[m * g.gcomp + og]) + du;
         bad = bad || !isfinite(v);
-        Un[m * g.gcomp + og] = v;
+        __builtin_nontemporal_store(v, &Un[m * g.gcomp + og]);
       }
       nbad += bad ? 1ull : 0ull;
     });
@@ -915,7 +928,6 @@ __global__ __launch_bounds__(kBlock) void k_update(const Segs L) {
 // right state of its lower face (both floored like the traced states).
 template <int D, int LIM>
 __global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
-  constexpr int comp[5] = {0, 1 + D, 1 + (D + 1) % 3, 1 + (D + 2) % 3, 4};
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const ProbDev* P = B.P;
     const Geo g(B.n, B.ns);
@@ -931,37 +943,33 @@ __global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
       const int x[3] = {i, j, k};
       const int o = g.g(i, j, k), oh = g.h(i, j, k);
       const double phi = phiv[oh];
-      double eta = 0.0;
-      if (LIM & 2) {
-        const gdbl* r = q + o;
-        const gdbl* pr = q + 4 * g.gcomp + o;
-        eta = steep_eta(r[-2 * st], r[-st], r[0], r[st], r[2 * st], pr[-st], pr[st], P->gamma);
-      }
+      // the edge values as face states: the tracing's loads and parabolas,
+      // then every store, unconditionally and streaming (the upper state of
+      // cell n and the lower state of cell -1 are never read)
+      Stencil S;
+      Parab par[5];
+      trace_load<D, false>(g, q, o, S);
+      trace_parab<D, LIM>(P, S, phi, par);
       double up[5], dn[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
-        const gdbl* a = q + comp[m] * g.gcomp + o;
-        const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, m == 0 ? eta : 0.0);
-        up[m] = par.aR;
-        dn[m] = par.aL;
+        up[m] = par[m].aR;
+        dn[m] = par[m].aL;
       }
-      if (x[D] <= nD - 1) {
-        if (up[0] < sd) { up[0] = sd; ++floors; }
-        if (up[4] < sp) { up[4] = sp; ++floors; }
+      const unsigned long long fu = x[D] <= nD - 1, fd = x[D] >= 0;
+      if (up[0] < sd) { up[0] = sd; floors += fu; }
+      if (up[4] < sp) { up[4] = sp; floors += fu; }
+      if (dn[0] < sd) { dn[0] = sd; floors += fd; }
+      if (dn[4] < sp) { dn[4] = sp; floors += fd; }
 #pragma unroll
-        for (int m = 0; m < 5; ++m) ql[m * g.hcomp + oh + sth] = up[m];
-      }
-      if (x[D] >= 0) {
-        if (dn[0] < sd) { dn[0] = sd; ++floors; }
-        if (dn[4] < sp) { dn[4] = sp; ++floors; }
+      for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(up[m], &ql[m * g.hcomp + oh + sth]);
 #pragma unroll
-        for (int m = 0; m < 5; ++m) qr[m * g.hcomp + oh] = dn[m];
-      }
+      for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(dn[m], &qr[m * g.hcomp + oh]);
       for (int is = 0; is < g.ns; ++is) {
         const gdbl* a = q + (6 + is) * g.gcomp + o;
         const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-        if (x[D] <= nD - 1) ql[(kNV + is) * g.hcomp + oh + sth] = par.aR;
-        if (x[D] >= 0) qr[(kNV + is) * g.hcomp + oh] = par.aL;
+        if (x[D] <= nD - 1) __builtin_nontemporal_store(par.aR, &ql[(kNV + is) * g.hcomp + oh + sth]);
+        if (x[D] >= 0) __builtin_nontemporal_store(par.aL, &qr[(kNV + is) * g.hcomp + oh]);
       }
     });
     count(&B.P->cnt[2], floors);
@@ -1022,7 +1030,7 @@ __global__ __launch_bounds__(kBlock) void k_mol_update(const Segs L, int arr,
       }
       if (forced && i == 0 && j == 0 && k == 0) bad = true;  // host-set test hook
 #pragma unroll
-      for (int m = 0; m < 5; ++m) Un[m * g.gcomp + og] = t[m];
+      for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(t[m], &Un[m * g.gcomp + og]);
       for (int m = kNV; m < g.nv; ++m) {
         const int mo = m * g.hcomp + o;
         double du = dtdx * (Fx[mo] - Fx[mo + 1]);
@@ -1034,7 +1042,7 @@ __global__ __launch_bounds__(kBlock) void k_mol_update(const Segs L, int arr,
           v = a + c * (v - a);
         }
         bad = bad || !isfinite(v);
-        Un[m * g.gcomp + og] = v;
+        __builtin_nontemporal_store(v, &Un[m * g.gcomp + og]);
       }
       nbad += bad ? 1ull : 0ull;
     });
