@@ -332,6 +332,8 @@ void march_region(std::vector<March>& out, int box, const int org[3], const int 
 
 // Most march units one box region can have under any tuning (one row per
 // tile, one plane per unit).
+constexpr int kDeepPlanes = 4;  // planes per unit of the merged tracing, per tuned plane
+
 long long max_units(const int n[3], int kind) {
   int org[3], ext[3];
   region_of(kind, n, org, ext);
@@ -1026,8 +1028,10 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
           int org[3], ext[3];
           region_of(k, recs[0][b].n, org, ext);
           // cons->prim (the only stage over the grown cells) is pointwise: two
-          // planes per unit give each thread two independent cells
-          march_region(u, b, org, ext, k == kGrown ? 2 * zs[z] : zs[z], c->ytile);
+          // planes per unit give each thread two independent cells; the
+          // merged tracing marches kDeepPlanes times as many planes
+          const int planes = k == kGrown ? 2 * zs[z] : (k == kCells1Deep ? kDeepPlanes * zs[z] : zs[z]);
+          march_region(u, b, org, ext, planes, c->ytile);
           T.upre[z][k][b + 1] = int(u.size());
           cap += max_units(recs[0][b].n, k);
         }
