@@ -196,6 +196,8 @@ def main():
                          "batched and per box)")
     ap.add_argument("--serving-requests", type=int, default=500, help="requests of the serving leg")
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
+    ap.add_argument("--tune-stages", action="store_true",
+                    help="autotune the planes per work unit of each stage before timing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-forms", action="store_true", help="time only the requested form")
@@ -279,6 +281,11 @@ def main():
     if args.tune:
         from paper_1711_06203_amd import autotune
         tuning = autotune.tune(ctx, [solver], steps=3, cache=None)
+        solver.upload(prob.U0, patches=W.patch_list(prob) if two_level else None)
+    stage_tuning = None
+    if args.tune_stages:
+        from paper_1711_06203_amd import autotune
+        stage_tuning = autotune.tune_stages(ctx, [solver], steps=3, cache=None)
         solver.upload(prob.U0, patches=W.patch_list(prob) if two_level else None)
 
     def timed(form, steps, warm):
@@ -369,7 +376,8 @@ def main():
                    "species": prob.nspec, "scheme": args.scheme, "riemann": args.riemann, "limiter": args.limiter, "steepen": bool(args.steepen),
                    "gamma": prob.gamma, "cfl": prob.cfl, "concurrent_graph": bool(args.concurrent_graph),
                    "wave_boxes": args.wave_boxes if waves else None, "workspace_bytes": int(solver.ws.numel()), "tuning": tuning and {k: tuning[k] for k in
-                                                                               ("blocks_per_cu", "zseg", "ytile")}},
+                                                                               ("blocks_per_cu", "zseg", "ytile")},
+                   "stage_planes": stage_tuning and stage_tuning["planes"]},
         "forms": {k: v for k, v in forms.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

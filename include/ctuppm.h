@@ -434,6 +434,16 @@ int ctuppm_set_tuning(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int 
  * grouped into (0: the whole plane), which sets how far apart in the work list
  * a unit and its z neighbour are. */
 int ctuppm_set_tuning2(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int zseg_per_box, int ytile);
+/* Per-stage tuning: the z planes one work unit of `stage` (an index below
+ * ctuppm_num_stages()) marches through, 1..64, multiplied by the zseg of the
+ * form.  Stages that run over the same work region share the setting:
+ * ctuppm_stage_planes returns the stage's setting and its group (stages with
+ * equal groups share it).  Defaults: 2 for cons->prim, 4 for the merged
+ * tracing, 1 elsewhere.  Results do not depend on it; work lists and graphs
+ * are rebuilt on the next step.  CTUPPM_EINVAL for a stage without work units
+ * (ghost fill, boundaries, dt, commit) or planes outside 1..64. */
+int ctuppm_set_stage_planes(ctuppm_ctx* ctx, int stage, int planes);
+int ctuppm_stage_planes(ctuppm_ctx* ctx, int stage, int* planes, int* group);
 
 #ifdef __cplusplus
 }

@@ -1,13 +1,20 @@
-"""Autotuner of the launch shapes of the batched form.
+"""Autotuners of the launch shapes of the batched form.
 
-Tunables (``ctuppm_set_tuning2``): blocks per CU of the launches (0 = one
-block per work unit, else a persistent grid of that many blocks per CU
-walking the units), the z planes a work unit marches through, and the rows
-per tile the units of a plane are grouped into.  Every
-choice gives bitwise the same results (each cell's arithmetic is fixed), so
-the tuner only times: it runs a few event-timed eager steps per candidate on
-the caller's problems and keeps the fastest.  Choices are cached in a JSON
-file keyed by the workload's box-size signature.
+``tune``: one setting for every stage (``ctuppm_set_tuning2``): blocks per
+CU of the launches (0 = one block per work unit, else a persistent grid of
+that many blocks per CU walking the units), the z planes a work unit marches
+through, and the rows per tile the units of a plane are grouped into.
+
+``tune_stages``: the planes per work unit of each stage on its own
+(``ctuppm_set_stage_planes``; stages over the same work region share one
+setting).  Every stage group is timed at every candidate from the library's
+per-stage timing of whole steps, each group takes its fastest, and the
+combination is kept only if a timed step confirms it.
+
+Every choice gives bitwise the same results (each cell's arithmetic is
+fixed), so the tuners only time: a few event-timed eager steps per candidate
+on the caller's problems.  Choices are cached in a JSON file keyed by the
+workload's box-size signature.
 """
 from __future__ import annotations
 
@@ -81,3 +88,81 @@ def tune(ctx: ctuppm.Context, solvers: Sequence[ctuppm.Solver], candidates: Iter
         except OSError:
             pass
     return dict(out, cached=False)
+
+
+STAGE_CANDIDATES: Tuple[int, ...] = (1, 2, 4, 8)
+
+
+def _stage_ms(ctx: ctuppm.Context, solvers, steps: int) -> Dict[str, float]:
+    """Per-stage milliseconds per step of eager batched steps (one warm-up step
+    first: it rebuilds work lists after a tuning change)."""
+    ctx.step(solvers, "batched", 1)
+    ctx.torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.step(solvers, "batched", steps)
+    ctx.set_timing(False)
+    return {k: ms / steps for k, (ms, n) in ctx.stage_times().items() if n}
+
+
+def _load(cache: Optional[str]) -> dict:
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                return json.load(f)
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def tune_stages(ctx: ctuppm.Context, solvers: Sequence[ctuppm.Solver],
+                candidates: Iterable[int] = STAGE_CANDIDATES, steps: int = 3, cache: Optional[str] = CACHE,
+                use_cache: bool = True) -> dict:
+    """Pick the planes per work unit of every stage group for these problems;
+    applies and returns {"planes": {stage: planes}, ...}.  The problems are
+    advanced by the timing steps."""
+    key = "stages:" + signature(solvers)
+    db = _load(cache)
+    if use_cache and key in db:
+        for st, p in db[key]["planes"].items():
+            ctx.set_stage_planes(st, p)
+        return dict(db[key], cached=True)
+    start = _stage_ms(ctx, solvers, steps)
+    groups: Dict[int, List[str]] = {}
+    before: Dict[str, int] = {}
+    for st in start:
+        try:
+            p, g = ctx.stage_planes(st)
+        except ctuppm.CtuError:
+            continue  # no work units (ghost fill, boundaries, dt, commit)
+        groups.setdefault(g, []).append(st)
+        before[st] = p
+    lead = {g: sts[0] for g, sts in groups.items()}
+    trials: Dict[int, Dict[str, float]] = {}
+    for p in candidates:
+        for g in groups:
+            ctx.set_stage_planes(lead[g], p)
+        trials[p] = _stage_ms(ctx, solvers, steps)
+    best: Dict[int, int] = {}
+    for g, sts in groups.items():
+        best[g] = min(trials, key=lambda p: sum(trials[p].get(st, 0.0) for st in sts))
+    for g, p in best.items():
+        ctx.set_stage_planes(lead[g], p)
+    tuned = sum(_stage_ms(ctx, solvers, steps).values())
+    base_total = sum(start.values())
+    planes = {st: best[g] for g, sts in groups.items() for st in sts}
+    if tuned > base_total:  # the groups interact through the caches: keep the starting setting
+        for st, p in before.items():
+            ctx.set_stage_planes(st, p)
+        planes = dict(before)
+    out = {"planes": planes, "ms_per_step": min(tuned, base_total), "start_ms_per_step": base_total,
+           "trials": {str(p): t for p, t in trials.items()}, "signature": key,
+           "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    if cache:
+        db[key] = {"planes": planes, "ms_per_step": out["ms_per_step"]}
+        try:
+            with open(cache, "w") as f:
+                json.dump(db, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return dict(out, cached=False)
+

@@ -186,6 +186,11 @@ struct ctuppm_ctx {
   int zseg_batched = 1;   // planes per march unit, batched / graph / waves forms
   int zseg_per_box = 1;   // planes per march unit, per-box form
   int ytile = 0;          // rows per tile of the march units (0: whole plane)
+  // planes per march unit of each work region, times the zseg of the form:
+  // cons->prim two (each thread converts two independent cells), the merged
+  // tracing four (measured: 2.31 -> 2.13 ms at KH 256^3), the rest one
+  int region_planes[kNumRegions] = {1, 2, 1, 1, 1, 1, 1, 1, 1, 4};
+  static_assert(kNumRegions == 10 && kGrown == 1 && kCells1T == 9, "one default per work region");
   int fused = 1;          // CTU cell stages: tracing and stage 1 of the three directions in one kernel each
   std::vector<Staging> staging;
   void* static_ptr = nullptr;  // this device's static stage scratch (ctuppm_step_static)
@@ -332,8 +337,6 @@ void march_region(std::vector<March>& out, int box, const int org[3], const int 
 
 // Most march units one box region can have under any tuning (one row per
 // tile, one plane per unit).
-constexpr int kDeepPlanes = 4;  // planes per unit of the merged tracing, per tuned plane
-
 long long max_units(const int n[3], int kind) {
   int org[3], ext[3];
   region_of(kind, n, org, ext);
@@ -1027,11 +1030,7 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
         for (int b = 0; b < nb; ++b) {
           int org[3], ext[3];
           region_of(k, recs[0][b].n, org, ext);
-          // cons->prim (the only stage over the grown cells) is pointwise: two
-          // planes per unit give each thread two independent cells; the
-          // merged tracing marches kDeepPlanes times as many planes
-          const int planes = k == kGrown ? 2 * zs[z] : (k == kCells1Deep ? kDeepPlanes * zs[z] : zs[z]);
-          march_region(u, b, org, ext, planes, c->ytile);
+          march_region(u, b, org, ext, c->region_planes[k] * zs[z], c->ytile);
           T.upre[z][k][b + 1] = int(u.size());
           cap += max_units(recs[0][b].n, k);
         }
@@ -2443,6 +2442,25 @@ int ctuppm_set_tuning2(ctuppm_ctx* c, int bpc, int zb, int zp, int ytile) {
   c->zseg_batched = zb;
   c->zseg_per_box = zp;
   for (auto& kv : c->probs) invalidate(c, kv.second.get());  // work lists and graphs depend on the tuning
+  return CTUPPM_OK;
+}
+
+int ctuppm_set_stage_planes(ctuppm_ctx* c, int stage, int planes) {
+  if (!c) return CTUPPM_EINVAL;
+  if (stage < 0 || stage >= kNumStages || stage_region(stage) < 0)
+    return fail(c, CTUPPM_EINVAL, "stage %d has no work units", stage);
+  if (planes < 1 || planes > 64) return fail(c, CTUPPM_EINVAL, "planes per unit %d outside 1..64", planes);
+  c->region_planes[stage_region(stage)] = planes;
+  for (auto& kv : c->probs) invalidate(c, kv.second.get());  // work lists and graphs depend on it
+  return CTUPPM_OK;
+}
+
+int ctuppm_stage_planes(ctuppm_ctx* c, int stage, int* planes, int* group) {
+  if (!c || !planes || !group) return CTUPPM_EINVAL;
+  if (stage < 0 || stage >= kNumStages || stage_region(stage) < 0)
+    return fail(c, CTUPPM_EINVAL, "stage %d has no work units", stage);
+  *group = stage_region(stage);
+  *planes = c->region_planes[*group];
   return CTUPPM_OK;
 }
 

@@ -18,17 +18,18 @@ constexpr int kSlots = 64;   // signal-speed max accumulators per problem (sprea
 //   kValid  cells [0, n)            kGrown cells [-4, n+4)   kCells1 cells [-1, n]
 //   kFaceD  faces [0, n] along D, cells [-1, n] across
 //   kFinD   faces [0, n] along D, cells [0, n) across
-//   kCells1Deep  cells [-1, n] like kCells1, in units of more planes (the
-//   merged tracing: a block marching through consecutive planes finds the z
-//   stencils of the next plane in its caches)
-enum Region : int { kValid = 0, kGrown, kCells1, kFace0, kFace1, kFace2, kFin0, kFin1, kFin2, kCells1Deep, kNumRegions };
+//   kCells1T  cells [-1, n] like kCells1: the merged tracing's own region, so
+//   its work units can march through more planes than stage 1's (a block
+//   marching through consecutive planes finds the z stencils of the next
+//   plane in its caches)
+enum Region : int { kValid = 0, kGrown, kCells1, kFace0, kFace1, kFace2, kFin0, kFin1, kFin2, kCells1T, kNumRegions };
 
 __host__ __device__ inline void region_of(int kind, const int n[3], int org[3], int ext[3]) {
   for (int d = 0; d < 3; ++d) {
     switch (kind) {
       case kValid: org[d] = 0; ext[d] = n[d]; break;
       case kGrown: org[d] = -kNG; ext[d] = n[d] + 2 * kNG; break;
-      case kCells1: case kCells1Deep: org[d] = -1; ext[d] = n[d] + 2; break;
+      case kCells1: case kCells1T: org[d] = -1; ext[d] = n[d] + 2; break;
       case kFace0: case kFace1: case kFace2:
         if (d == kind - kFace0) { org[d] = 0; ext[d] = n[d] + 1; } else { org[d] = -1; ext[d] = n[d] + 2; }
         break;
@@ -178,7 +179,7 @@ __host__ __device__ inline int stage_region(int stage) {
     case kStCfl: return kValid;
     case kStFlatten: return kCells1;
     case kStT1All: return kCells1;
-    case kStTrace3: return kCells1Deep;
+    case kStTrace3: return kCells1T;
     case kStTraceX: case kStTraceY: case kStTraceZ: return kCells1;
     case kStReconX: case kStReconY: case kStReconZ: return kCells1;
     case kStMolUpdate: return kValid;

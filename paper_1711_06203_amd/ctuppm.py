@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -96,6 +96,8 @@ def lib() -> ctypes.CDLL:
             "ctuppm_stage_bytes": [vp, ctypes.c_int, ctypes.c_int, dp],
             "ctuppm_set_tuning": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int],
             "ctuppm_set_tuning2": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+            "ctuppm_set_stage_planes": [vp, ctypes.c_int, ctypes.c_int],
+            "ctuppm_stage_planes": [vp, ctypes.c_int, ip, ip],
             "ctuppm_step_checked": [vp, ctypes.c_int, ctypes.c_int, ip],
             "ctuppm_set_fail_hook": [vp, ctypes.c_int, ctypes.c_int],
             "ctuppm_last_error": [vp],
@@ -133,7 +135,8 @@ EXPORTED = ["ctuppm_ctx_create", "ctuppm_ctx_destroy", "ctuppm_last_error", "ctu
             "ctuppm_set_concurrency", "ctuppm_fill_ghosts", "ctuppm_compute_dt", "ctuppm_advance_level",
             "ctuppm_average_down", "ctuppm_reflux", "ctuppm_set_wave_boxes",
             "ctuppm_debug_stage", "ctuppm_workspace_meta_bytes", "ctuppm_step_guarded", "ctuppm_rejections", "ctuppm_rejections_seen",
-            "ctuppm_step_static", "ctuppm_set_fused", "ctuppm_bandwidth_probe"]
+            "ctuppm_step_static", "ctuppm_set_fused", "ctuppm_bandwidth_probe", "ctuppm_set_stage_planes",
+            "ctuppm_stage_planes"]
 
 
 class Context:
@@ -218,6 +221,25 @@ class Context:
 
     def set_tuning(self, blocks_per_cu: int = 0, zseg_batched: int = 1, zseg_per_box: int = 1, ytile: int = 0):
         self.call("ctuppm_set_tuning2", int(blocks_per_cu), int(zseg_batched), int(zseg_per_box), int(ytile))
+
+    def stage_id(self, stage) -> int:
+        """Index of a stage given by name (as in stage_times) or index."""
+        if isinstance(stage, int):
+            return stage
+        names = [self._L.ctuppm_stage_name(s).decode() for s in range(self._L.ctuppm_num_stages())]
+        if stage not in names:
+            raise CtuError(f"unknown stage {stage!r}", EINVAL)
+        return names.index(stage)
+
+    def set_stage_planes(self, stage, planes: int):
+        """Planes per work unit of one stage (shared with the stages of its group)."""
+        self.call("ctuppm_set_stage_planes", self.stage_id(stage), int(planes))
+
+    def stage_planes(self, stage) -> Tuple[int, int]:
+        """(planes per work unit, group) of a stage."""
+        p, g = ctypes.c_int(), ctypes.c_int()
+        self.call("ctuppm_stage_planes", self.stage_id(stage), ctypes.byref(p), ctypes.byref(g))
+        return p.value, g.value
 
     def step(self, solvers: Sequence["Solver"], form="batched", nsteps: int = 1, guarded: bool = False):
         """Advance several problems together: one batched launch set per step
