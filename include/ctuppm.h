@@ -435,8 +435,10 @@ int ctuppm_set_tuning(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int 
  * a unit and its z neighbour are. */
 int ctuppm_set_tuning2(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int zseg_per_box, int ytile);
 /* Per-stage tuning: the z planes one work unit of `stage` (an index below
- * ctuppm_num_stages()) marches through, 1..64, multiplied by the zseg of the
- * form.  Stages that run over the same work region share the setting:
+ * ctuppm_num_stages()) marches through in the batched, graph and waves forms,
+ * 1..64, multiplied by zseg_batched (the per-box form, whose launches cover
+ * one box each, keeps one plane, two for cons->prim, times zseg_per_box).
+ * Stages that run over the same work region share the setting:
  * ctuppm_stage_planes returns the stage's setting and its group (stages with
  * equal groups share it).  Defaults: 2 for cons->prim, 4 for the merged
  * tracing, 1 elsewhere.  Results do not depend on it; work lists and graphs

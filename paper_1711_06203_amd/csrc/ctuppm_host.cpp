@@ -186,7 +186,8 @@ struct ctuppm_ctx {
   int zseg_batched = 1;   // planes per march unit, batched / graph / waves forms
   int zseg_per_box = 1;   // planes per march unit, per-box form
   int ytile = 0;          // rows per tile of the march units (0: whole plane)
-  // planes per march unit of each work region, times the zseg of the form:
+  // planes per march unit of each work region in the batched, graph and
+  // waves forms, times their zseg:
   // cons->prim two (each thread converts two independent cells), the merged
   // tracing four (measured: 2.31 -> 2.13 ms at KH 256^3), the rest one
   int region_planes[kNumRegions] = {1, 2, 1, 1, 1, 1, 1, 1, 1, 4};
@@ -1030,7 +1031,10 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
         for (int b = 0; b < nb; ++b) {
           int org[3], ext[3];
           region_of(k, recs[0][b].n, org, ext);
-          march_region(u, b, org, ext, c->region_planes[k] * zs[z], c->ytile);
+          // per-stage planes in the batched forms; a per-box launch covers one
+          // box, where deeper units would leave CUs idle
+          const int planes = z == 0 ? c->region_planes[k] : (k == kGrown ? 2 : 1);
+          march_region(u, b, org, ext, planes * zs[z], c->ytile);
           T.upre[z][k][b + 1] = int(u.size());
           cap += max_units(recs[0][b].n, k);
         }
