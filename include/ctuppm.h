@@ -409,11 +409,12 @@ int ctuppm_debug_stage(ctuppm_ctx* ctx, int pid, int level, int box, int array, 
  * largest box's stage scratch. */
 int ctuppm_set_wave_boxes(ctuppm_ctx* ctx, int boxes);
 
-/* Kernels of the CTU cell stages: on (1, the default), the tracing of the
- * three directions runs in one kernel that reads each cell's primitives and
- * flattening coefficient once, and the first transverse stage of the three
- * directions in one kernel that reads each normal flux array once; off (0),
- * one kernel per direction.  Results are the same bits either way (each face
+/* Kernels of the cell stages: on (1, the default), the flattening and the
+ * tracing (CTU) or the edge-value face states (method of lines) of the three
+ * directions run in one kernel that reads each cell's primitives once, and
+ * the first transverse stage of the three directions (CTU) in one kernel that
+ * reads each normal flux array once; off (0), a flattening kernel and one
+ * kernel per direction.  Results are the same bits either way (each face
  * takes the same arithmetic); captured graphs are dropped. */
 int ctuppm_set_fused(ctuppm_ctx* ctx, int on);
 /* Measurement: the HBM bandwidth plain streaming reaches on this GPU, the

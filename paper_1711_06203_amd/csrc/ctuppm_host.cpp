@@ -1206,7 +1206,11 @@ int fill_arr(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed, int arr) {
 int enqueue_mol(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed, int guard) {
   const bool per_box = S->form == CTUPPM_FORM_PER_BOX;
   const int nst = S->scheme == 1 ? 2 : 3;
-  const int cells[] = {kStFlatten, kStReconX, kStReconY, kStReconZ, kStRiemX, kStRiemY, kStRiemZ};
+  // face states: flattening and the three directions in one kernel (fused,
+  // the default) or one kernel each
+  static const std::vector<int> fused = {kStRecon3, kStRiemX, kStRiemY, kStRiemZ};
+  static const std::vector<int> split = {kStFlatten, kStReconX, kStReconY, kStReconZ, kStRiemX, kStRiemY, kStRiemZ};
+  const std::vector<int>& cells = c->fused ? fused : split;
   int rc;
   for (int r = 0; r < nst; ++r) {
     const int arr = r == 0 ? kArrCur : (r == 1 ? kArrW0 : kArrW1);
@@ -2536,6 +2540,16 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
         const double pext = (n0 + 8) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 8) * (n2 + 2) +
                             (n0 + 2) * (n1 + 2) * (n2 + 8) - 2 * cells1;
         tot += (nq - 1) * W * ext + W * pext + W * cells1 + 2 * nv * W * (face(0) + face(1) + face(2));
+        break;
+      }
+      case kStRecon3: {
+        // as the merged tracing, per Runge-Kutta stage: the union of the three
+        // directions' stencils, the flattening's pressures, phi, the face states
+        const double ext = (n0 + 6) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 6) * (n2 + 2) +
+                           (n0 + 2) * (n1 + 2) * (n2 + 6) - 2 * cells1;
+        const double pext = (n0 + 8) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 8) * (n2 + 2) +
+                            (n0 + 2) * (n1 + 2) * (n2 + 8) - 2 * cells1;
+        tot += nst * ((nq - 1) * W * ext + W * pext + W * cells1 + 2 * nv * W * (face(0) + face(1) + face(2)));
         break;
       }
       case kStT1All:

@@ -164,7 +164,7 @@ enum Stage : int {
   kStFill = 0, kStBcX, kStBcY, kStBcZ, kStC2P, kStCfl, kStC2POnly, kStDt, kStFlatten,
   kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ, kStT1X, kStT1Y, kStT1Z,
   kStT2X, kStT2Y, kStT2Z, kStUpdate, kStFlip,
-  kStReconX, kStReconY, kStReconZ, kStMolUpdate, kStTrace3, kStT1All, kNumStages
+  kStReconX, kStReconY, kStReconZ, kStMolUpdate, kStTrace3, kStT1All, kStRecon3, kNumStages
 };
 
 // State array a stage reads (fill, boundaries, cons->prim, MOL stages) or
@@ -179,7 +179,7 @@ __host__ __device__ inline int stage_region(int stage) {
     case kStCfl: return kValid;
     case kStFlatten: return kCells1;
     case kStT1All: return kCells1;
-    case kStTrace3: return kCells1T;
+    case kStTrace3: case kStRecon3: return kCells1T;
     case kStTraceX: case kStTraceY: case kStTraceZ: return kCells1;
     case kStReconX: case kStReconY: case kStReconZ: return kCells1;
     case kStMolUpdate: return kValid;

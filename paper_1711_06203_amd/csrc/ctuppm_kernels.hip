@@ -923,9 +923,47 @@ __global__ __launch_bounds__(kBlock) void k_update(const Segs L) {
 // preserving Runge-Kutta method (Shu & Osher 1988) of order 2 or 3 advances
 // the state, with a ghost fill before every stage.
 
-// Face states along D from cells -1..n: the upper edge value of each cell's
-// parabola is the left state of its upper face, the lower edge value the
-// right state of its lower face (both floored like the traced states).
+// Method-of-lines face states of a cell along D: the edge values of its
+// parabolas (the upper one the left state of the face above, the lower one
+// the right state of the face below), floored; floors are counted only on
+// the states of faces 0..n (xd the cell's index along D, nd the extent).
+template <int D, int LIM>
+CTU_DEV void recon_eval(const ProbDev* P, const Stencil& S, double phi, int xd, int nd, double up[5], double dn[5],
+                        unsigned long long& floors) {
+  Parab par[5];
+  trace_parab<D, LIM>(P, S, phi, par);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    up[m] = par[m].aR;
+    dn[m] = par[m].aL;
+  }
+  const double sd = P->small_dens, sp = P->small_pres;
+  const unsigned long long fu = xd <= nd - 1, fd = xd >= 0;
+  if (up[0] < sd) { up[0] = sd; floors += fu; }
+  if (up[4] < sp) { up[4] = sp; floors += fu; }
+  if (dn[0] < sd) { dn[0] = sd; floors += fd; }
+  if (dn[4] < sp) { dn[4] = sp; floors += fd; }
+}
+
+// The species edge values of a cell along D (the hydro flattening).
+template <int D, int LIM>
+CTU_DEV void recon_species(const BoxRec& B, const Geo& g, int xd, int o, int oh, double phi) {
+  const gdbl* __restrict__ q = g.q(B.scr);
+  gdbl* __restrict__ ql = g.ql(B.scr, D);
+  gdbl* __restrict__ qr = g.qr(B.scr, D);
+  const int st = g.gstride(D), sth = g.hstride(D);
+  for (int is = 0; is < g.ns; ++is) {
+    const gdbl* a = q + (6 + is) * g.gcomp + o;
+    const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
+    if (xd <= B.n[D] - 1) __builtin_nontemporal_store(par.aR, &ql[(kNV + is) * g.hcomp + oh + sth]);
+    if (xd >= 0) __builtin_nontemporal_store(par.aL, &qr[(kNV + is) * g.hcomp + oh]);
+  }
+}
+
+// One thread per cell of -1..n: method-of-lines face states along D (the
+// flattening coefficient from the flattening launch).  The loads come before
+// the arithmetic and every store after it, unconditionally and streaming (the
+// upper state of cell n and the lower state of cell -1 are never read).
 template <int D, int LIM>
 __global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
@@ -933,43 +971,65 @@ __global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
     const gdbl* __restrict__ phiv = g.phi(B.scr);
-    gdbl* __restrict__ ql = g.ql(B.scr, D);
-    gdbl* __restrict__ qr = g.qr(B.scr, D);
-    const int st = g.gstride(D), sth = g.hstride(D);
-    const double sd = P->small_dens, sp = P->small_pres;
-    const int nD = B.n[D];
     unsigned long long floors = 0;
     march(kCells1, B, M, [&](int i, int j, int k) {
       const int x[3] = {i, j, k};
       const int o = g.g(i, j, k), oh = g.h(i, j, k);
       const double phi = phiv[oh];
-      // the edge values as face states: the tracing's loads and parabolas,
-      // then every store, unconditionally and streaming (the upper state of
-      // cell n and the lower state of cell -1 are never read)
       Stencil S;
-      Parab par[5];
-      trace_load<D, false>(g, q, o, S);
-      trace_parab<D, LIM>(P, S, phi, par);
       double up[5], dn[5];
+      trace_load<D, false>(g, q, o, S);
+      recon_eval<D, LIM>(P, S, phi, x[D], B.n[D], up, dn, floors);
+      trace_store<D>(B, g, oh, up, dn);
+      if (g.ns > 0) recon_species<D, LIM>(B, g, x[D], o, oh, phi);
+    });
+    count(&B.P->cnt[2], floors);
+  });
+}
+
+// One thread per cell of -1..n: the flattening coefficient (also stored, for
+// stage dumps), then the method-of-lines face states along x, y and z from
+// the same primitives, read once; the states of x and y wait in LDS until the
+// loads of z have returned, as in the merged tracing.
+template <int LIM>
+__global__ __launch_bounds__(kBlock) void k_recon3(const Segs L) {
+  __shared__ double held_lds[2 * 10 * kBlock];
+  ldbl* held = (ldbl*)held_lds;
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
+    const ProbDev* P = B.P;
+    const Geo g(B.n, B.ns);
+    const gdbl* __restrict__ q = g.q(B.scr);
+    gdbl* __restrict__ phiout = g.phi(B.scr);
+    unsigned long long floors = 0;
+    const int t = threadIdx.x;
+    march(kCells1, B, M, [&](int i, int j, int k) {
+      const int o = g.g(i, j, k), oh = g.h(i, j, k);
+      const double phi = flatten_cell(g, q, o);
+      Stencil S;
+      double up[5], dn[5];
+      trace_load<0, false>(g, q, o, S);
+      recon_eval<0, LIM>(P, S, phi, i, B.n[0], up, dn, floors);
 #pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        up[m] = par[m].aR;
-        dn[m] = par[m].aL;
+      for (int m = 0; m < 5; ++m) { held[m * kBlock + t] = up[m]; held[(5 + m) * kBlock + t] = dn[m]; }
+      trace_load<1, false>(g, q, o, S);
+      recon_eval<1, LIM>(P, S, phi, j, B.n[1], up, dn, floors);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) { held[(10 + m) * kBlock + t] = up[m]; held[(15 + m) * kBlock + t] = dn[m]; }
+      trace_load<2, false>(g, q, o, S);
+      recon_eval<2, LIM>(P, S, phi, k, B.n[2], up, dn, floors);
+      trace_store<2>(B, g, oh, up, dn);
+      phiout[oh] = phi;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+#pragma unroll
+        for (int m = 0; m < 5; ++m) { up[m] = held[(10 * d + m) * kBlock + t]; dn[m] = held[(10 * d + 5 + m) * kBlock + t]; }
+        if (d == 0) trace_store<0>(B, g, oh, up, dn);
+        else trace_store<1>(B, g, oh, up, dn);
       }
-      const unsigned long long fu = x[D] <= nD - 1, fd = x[D] >= 0;
-      if (up[0] < sd) { up[0] = sd; floors += fu; }
-      if (up[4] < sp) { up[4] = sp; floors += fu; }
-      if (dn[0] < sd) { dn[0] = sd; floors += fd; }
-      if (dn[4] < sp) { dn[4] = sp; floors += fd; }
-#pragma unroll
-      for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(up[m], &ql[m * g.hcomp + oh + sth]);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(dn[m], &qr[m * g.hcomp + oh]);
-      for (int is = 0; is < g.ns; ++is) {
-        const gdbl* a = q + (6 + is) * g.gcomp + o;
-        const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-        if (x[D] <= nD - 1) __builtin_nontemporal_store(par.aR, &ql[(kNV + is) * g.hcomp + oh + sth]);
-        if (x[D] >= 0) __builtin_nontemporal_store(par.aL, &qr[(kNV + is) * g.hcomp + oh]);
+      if (g.ns > 0) {
+        recon_species<0, LIM>(B, g, i, o, oh, phi);
+        recon_species<1, LIM>(B, g, j, o, oh, phi);
+        recon_species<2, LIM>(B, g, k, o, oh, phi);
       }
     });
     count(&B.P->cnt[2], floors);
@@ -1302,7 +1362,7 @@ const char* stage_name(int s) {
       "fill", "bc_x", "bc_y", "bc_z", "cons2prim_cfl", "cfl", "cons2prim", "dt", "flatten",
       "trace_x", "trace_y", "trace_z", "riemann_x", "riemann_y", "riemann_z",
       "trans1_x", "trans1_y", "trans1_z", "trans2_x", "trans2_y", "trans2_z", "update", "flip",
-      "recon_x", "recon_y", "recon_z", "mol_update", "trace_xyz", "trans1_xyz"};
+      "recon_x", "recon_y", "recon_z", "mol_update", "trace_xyz", "trans1_xyz", "recon_xyz"};
   return (s >= 0 && s < kNumStages) ? names[s] : "?";
 }
 
@@ -1327,6 +1387,11 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStReconY: CTU_LIM(k_recon, 1); break;
     case kStReconZ: CTU_LIM(k_recon, 2); break;
     case kStMolUpdate: k_mol_update<<<grid, block, 0, s>>>(G, L.arr, L.out, L.comb, L.c, L.last); break;
+    case kStRecon3:
+      if (L.lim == 1) k_recon3<1><<<grid, block, 0, s>>>(G);
+      else if (L.lim == 2) k_recon3<2><<<grid, block, 0, s>>>(G);
+      else k_recon3<0><<<grid, block, 0, s>>>(G);
+      break;
     case kStFlatten: k_flatten<<<grid, block, 0, s>>>(G); break;
     case kStTraceX: CTU_LIM(k_trace, 0); break;
     case kStTraceY: CTU_LIM(k_trace, 1); break;

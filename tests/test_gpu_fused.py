@@ -1,7 +1,9 @@
-"""The merged CTU kernels (tracing of x, y, z in one kernel; the first
-transverse stage of x, y, z in one kernel) against the one-kernel-per-direction
-form: bitwise the same states for every scheme variant, boundary kind, box
-layout and the two-level step, and both equal the oracle."""
+"""The merged kernels (CTU: flattening and tracing of x, y, z in one kernel,
+the first transverse stage of x, y, z in one kernel; method of lines:
+flattening and the face states of x, y, z in one kernel) against the
+one-kernel-per-direction form: bitwise the same states for every scheme
+variant, boundary kind, box layout and the two-level step, and both equal
+the oracle."""
 import numpy as np
 import pytest
 
@@ -34,6 +36,9 @@ CASES = {
     "rt_walls_gravity": lambda: W.rayleigh_taylor(n=48, seed=5, boxes=W.uneven_boxes((48, 48, 48), 5, edges=(16, 32))),
     "sod_outflow": lambda: W.sod(n=(24, 16, 16), steps=4, boxes_edge=(8, 8, 16)),
     "cloud_two_level": lambda: W.cloud_wind(n=32, box=16, fine_box=8, fine_region=((10, 10, 10), (22, 22, 22)), nspec=1),
+    "mol2_species": lambda: _kh(scheme=1),
+    "mol3_cs_twoshock": lambda: _kh(scheme=2, limiter=1, riemann=1),
+    "mol2_steepen": lambda: _kh(scheme=1, steepen=1),
 }
 
 
