@@ -192,6 +192,7 @@ struct ctuppm_ctx {
   // tracing four (measured: 2.31 -> 2.13 ms at KH 256^3), the rest one
   int region_planes[kNumRegions] = {1, 2, 1, 1, 1, 1, 1, 1, 1, 4};
   static_assert(kNumRegions == 10 && kGrown == 1 && kCells1T == 9, "one default per work region");
+  bool region_set[kNumRegions] = {};  // set by the caller: used as given (defaults adapt to the level size)
   int fused = 1;          // CTU cell stages: tracing and stage 1 of the three directions in one kernel each
   std::vector<Staging> staging;
   void* static_ptr = nullptr;  // this device's static stage scratch (ctuppm_step_static)
@@ -335,6 +336,8 @@ void march_region(std::vector<March>& out, int box, const int org[3], const int 
     }
   }
 }
+
+constexpr int kMinUnitsPerCu = 8;  // deeper work units only while a level keeps this many per CU
 
 // Most march units one box region can have under any tuning (one row per
 // tile, one plane per unit).
@@ -1025,18 +1028,28 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
     const int zs[2] = {c->zseg_batched, c->zseg_per_box};
     for (int z = 0; z < 2; ++z)
       for (int k = 0; k < kNumRegions; ++k) {
+        // per-stage planes in the batched forms; a default is halved while the
+        // level would have fewer than kMinUnitsPerCu units per CU (deeper
+        // units leave CUs idle on small levels), a caller's setting is used as
+        // given; a per-box launch covers one box: one plane (two for
+        // cons->prim)
+        int planes = z == 0 ? c->region_planes[k] : (k == kGrown ? 2 : 1);
         std::vector<March> u;
-        T.upre[z][k].assign(nb + 1, 0);
         long long cap = 0;
-        for (int b = 0; b < nb; ++b) {
-          int org[3], ext[3];
-          region_of(k, recs[0][b].n, org, ext);
-          // per-stage planes in the batched forms; a per-box launch covers one
-          // box, where deeper units would leave CUs idle
-          const int planes = z == 0 ? c->region_planes[k] : (k == kGrown ? 2 : 1);
-          march_region(u, b, org, ext, planes * zs[z], c->ytile);
-          T.upre[z][k][b + 1] = int(u.size());
-          cap += max_units(recs[0][b].n, k);
+        for (;;) {
+          u.clear();
+          T.upre[z][k].assign(nb + 1, 0);
+          cap = 0;
+          for (int b = 0; b < nb; ++b) {
+            int org[3], ext[3];
+            region_of(k, recs[0][b].n, org, ext);
+            march_region(u, b, org, ext, planes * zs[z], c->ytile);
+            T.upre[z][k][b + 1] = int(u.size());
+            cap += max_units(recs[0][b].n, k);
+          }
+          if (z != 0 || c->region_set[k] || planes == 1 || (long long)u.size() >= (long long)kMinUnitsPerCu * c->num_cus)
+            break;
+          planes /= 2;
         }
         T.units[z][k] = K.put(u);
         K.reserve_bytes(packed<March>(cap) - packed<March>((long long)u.size()));
@@ -2459,6 +2472,7 @@ int ctuppm_set_stage_planes(ctuppm_ctx* c, int stage, int planes) {
     return fail(c, CTUPPM_EINVAL, "stage %d has no work units", stage);
   if (planes < 1 || planes > 64) return fail(c, CTUPPM_EINVAL, "planes per unit %d outside 1..64", planes);
   c->region_planes[stage_region(stage)] = planes;
+  c->region_set[stage_region(stage)] = true;
   for (auto& kv : c->probs) invalidate(c, kv.second.get());  // work lists and graphs depend on it
   return CTUPPM_OK;
 }
