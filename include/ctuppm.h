@@ -442,9 +442,11 @@ int ctuppm_set_tuning2(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int
  * Stages that run over the same work region share the setting:
  * ctuppm_stage_planes returns the stage's setting and its group (stages with
  * equal groups share it).  Defaults: 2 for cons->prim, 4 for the merged
- * tracing and the merged method-of-lines face states, 1 elsewhere; a default
- * is halved on a level that would otherwise have fewer than 8 work units per
- * CU, a value set here is used as given.  Results do not depend on it; work lists and graphs
+ * tracing and the merged method-of-lines face states, 1 elsewhere.  Problems
+ * stepped together whose merged-tracing work units at that depth would number
+ * fewer than 8 per CU run their stages left at the defaults with one plane
+ * per unit (two for cons->prim); a value set here is used as given.  Results
+ * do not depend on it; work lists and graphs
  * are rebuilt on the next step.  CTUPPM_EINVAL for a stage without work units
  * (ghost fill, boundaries, dt, commit) or planes outside 1..64. */
 int ctuppm_set_stage_planes(ctuppm_ctx* ctx, int stage, int planes);

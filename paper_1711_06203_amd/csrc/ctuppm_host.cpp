@@ -44,10 +44,13 @@ struct Level {
 // the host-side ranges of the work lists: box b's units of region k (variant
 // z) are upre[z][k][b] .. upre[z][k][b+1]-1, its fill chunks fpre[b] ..
 // fpre[b+1]-1, its boundary chunks along d bpre[d][b] .. bpre[d][b+1]-1.
+// Unit variants: 0 the batched forms, with the per-stage planes; 1 the
+// per-box form; 2 the batched forms for launches too small for deep units.
+constexpr int kUnitVariants = 3;
 struct LevelTables {
   BoxRec* recs[kRecForms] = {};
-  March* units[2][kNumRegions] = {};
-  std::vector<int> upre[2][kNumRegions];
+  March* units[kUnitVariants][kNumRegions] = {};
+  std::vector<int> upre[kUnitVariants][kNumRegions];
   FillTag* ftags = nullptr;
   Chunk* fch = nullptr;
   std::vector<int> fpre;
@@ -125,6 +128,7 @@ struct StepSet {
   int riemann = 0;  // likewise
   int limiter = 0;  // likewise (reconstruction variant: 0 CW84, 1 CS, 2 CW84 + steepening)
   int nboxes = 0;
+  int zvar = 0;     // work-unit variant of its launches (LevelTables)
   hipGraph_t graph[2] = {nullptr, nullptr};  // captured step, unguarded / guarded
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   ~StepSet() {
@@ -498,7 +502,6 @@ struct SegRun {
 int rec_form(int form) {
   return form == CTUPPM_FORM_PER_BOX ? 1 : (form == CTUPPM_FORM_WAVES ? 2 : (form == kFormStatic ? 3 : 0));
 }
-int zvar(int form) { return form == CTUPPM_FORM_PER_BOX ? 1 : 0; }
 
 ProbDev* level_rec(Problem* P, int level) { return level == 0 ? P->dP : P->dPf; }
 
@@ -510,7 +513,7 @@ int run_range(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int b0, int b
   SegRun R{c, s, stage, S->form != CTUPPM_FORM_PER_BOX, timed, A0};
   R.A.rs = S->riemann;
   R.A.lim = S->limiter;
-  const int rf = rec_form(S->form), zv = zvar(S->form);
+  const int rf = rec_form(S->form), zv = S->zvar;
   for (size_t ip = 0; ip < S->probs.size(); ++ip) {
     const int off = S->box_off[ip], nb = S->box_off[ip + 1] - off;
     const int lb0 = std::max(0, b0 - off), lb1 = std::min(nb, b1 - off);
@@ -934,7 +937,7 @@ void meta_bytes(ctuppm_ctx* c, Problem* P) {
         const int n[3] = {box_n(b, 0), box_n(b, 1), box_n(b, 2)};
         u += max_units(n, k);
       }
-      t += 2 * packed<March>(u);
+      t += kUnitVariants * packed<March>(u);
     }
     std::vector<FillTag> ft;
     std::vector<Chunk> fch;
@@ -1025,31 +1028,22 @@ int ensure_tables(ctuppm_ctx* c, Problem* P) {
     }
     level_off = off;
     for (int f = 0; f < kRecForms; ++f) T.recs[f] = K.put(recs[f]);
-    const int zs[2] = {c->zseg_batched, c->zseg_per_box};
-    for (int z = 0; z < 2; ++z)
+    const int zs[kUnitVariants] = {c->zseg_batched, c->zseg_per_box, c->zseg_batched};
+    for (int z = 0; z < kUnitVariants; ++z)
       for (int k = 0; k < kNumRegions; ++k) {
-        // per-stage planes in the batched forms; a default is halved while the
-        // level would have fewer than kMinUnitsPerCu units per CU (deeper
-        // units leave CUs idle on small levels), a caller's setting is used as
-        // given; a per-box launch covers one box: one plane (two for
-        // cons->prim)
-        int planes = z == 0 ? c->region_planes[k] : (k == kGrown ? 2 : 1);
+        // variant 0: the per-stage planes; 1 (per box) and 2 (small batched
+        // launches): one plane, two for cons->prim, unless the caller set the
+        // stage's planes
+        const int planes = z == 0 || c->region_set[k] ? c->region_planes[k] : (k == kGrown ? 2 : 1);
         std::vector<March> u;
+        T.upre[z][k].assign(nb + 1, 0);
         long long cap = 0;
-        for (;;) {
-          u.clear();
-          T.upre[z][k].assign(nb + 1, 0);
-          cap = 0;
-          for (int b = 0; b < nb; ++b) {
-            int org[3], ext[3];
-            region_of(k, recs[0][b].n, org, ext);
-            march_region(u, b, org, ext, planes * zs[z], c->ytile);
-            T.upre[z][k][b + 1] = int(u.size());
-            cap += max_units(recs[0][b].n, k);
-          }
-          if (z != 0 || c->region_set[k] || planes == 1 || (long long)u.size() >= (long long)kMinUnitsPerCu * c->num_cus)
-            break;
-          planes /= 2;
+        for (int b = 0; b < nb; ++b) {
+          int org[3], ext[3];
+          region_of(k, recs[0][b].n, org, ext);
+          march_region(u, b, org, ext, planes * zs[z], c->ytile);
+          T.upre[z][k][b + 1] = int(u.size());
+          cap += max_units(recs[0][b].n, k);
         }
         T.units[z][k] = K.put(u);
         K.reserve_bytes(packed<March>(cap) - packed<March>((long long)u.size()));
@@ -1164,6 +1158,12 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     S->box_off.push_back(S->box_off.back() + int(P->lev[level].boxes.size()));
   }
   S->nboxes = S->box_off.back();
+  // deep work units only when the set's launches keep kMinUnitsPerCu units per
+  // CU at the depth of the merged tracing (a few small problems stepped alone
+  // leave CUs idle with them; many stepped together do not)
+  long long deep = 0;
+  for (Problem* P : S->probs) deep += P->lt[level].upre[0][kCells1T].back();
+  S->zvar = S->form == CTUPPM_FORM_PER_BOX ? 1 : (deep < (long long)kMinUnitsPerCu * c->num_cus ? 2 : 0);
   *out = S.get();
   c->sets[key] = std::move(S);
   return CTUPPM_OK;
