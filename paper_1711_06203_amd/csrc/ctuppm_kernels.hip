@@ -32,6 +32,14 @@ CTU_DEV gdbl* gp(double* p) { return (gdbl*)p; }
 // LDS doubles, volatile: values a thread parks there are re-read from LDS
 // (not kept in registers), through ds_* instructions.
 using ldbl = __attribute__((address_space(3))) volatile double;
+// The problem record as the stage kernels read it: through the constant
+// address space, since it is the same for a whole block and no kernel writes
+// the fields it reads this way (counters and the signal-speed maxima are
+// updated through the ordinary pointer).  The reads become scalar loads into
+// scalar registers; as flat loads they would also make a wave wait for its
+// earlier stores.
+using CProb = __attribute__((address_space(4))) const ProbDev;
+CTU_DEV CProb* cprob(const ProbDev* P) { return (CProb*)P; }
 
 template <class F>
 CTU_DEV void for_each_chunk(int nchunks, F&& f) {
@@ -136,7 +144,7 @@ CTU_DEV void count(unsigned long long* c, unsigned long long v) {
 
 // Interface flux of the Riemann solver RS (0 HLLC, 1 two-shock), permuted order.
 template <int RS>
-CTU_DEV void rflux(const double L[5], const double R[5], const ProbDev* P, double F[5], Wave& W) {
+CTU_DEV void rflux(const double L[5], const double R[5], CProb* P, double F[5], Wave& W) {
   if (RS == 1) twoshock(L, R, P->gamma, P->rgm1, P->small_dens, P->small_pres, F, W);
   else hllc(L, R, P->gamma, P->rgm1, F, W);
 }
@@ -144,7 +152,7 @@ CTU_DEV void rflux(const double L[5], const double R[5], const ProbDev* P, doubl
 // The state array `arr` of a box (current fab, Runge-Kutta stage fab, or the
 // fab that receives the new state).
 CTU_DEV double* state_arr(const BoxRec& B, int arr) {
-  const int cur = B.P->cur;
+  const int cur = cprob(B.P)->cur;
   switch (arr) {
     case kArrW0: return B.W[0];
     case kArrW1: return B.W[1];
@@ -255,9 +263,10 @@ __global__ __launch_bounds__(kBlock) void k_c2p(const Segs L, int arr) {
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ U = gp(state_arr(B, arr));
     gdbl* __restrict__ q = g.q(B.scr);
-    const bool summed = P->scheme != 0;
-    const double gamma = P->gamma, gm1 = P->gm1, sd = P->small_dens, sp = P->small_pres;
-    const double rdx = P->rdx[0], rdy = P->rdx[1], rdz = P->rdx[2];
+    CProb* Pc = cprob(P);
+    const bool summed = Pc->scheme != 0;
+    const double gamma = Pc->gamma, gm1 = Pc->gm1, sd = Pc->small_dens, sp = Pc->small_pres;
+    const double rdx = Pc->rdx[0], rdy = Pc->rdx[1], rdz = Pc->rdx[2];
     unsigned long long hd = 0, hp = 0;
     march(WQ ? kGrown : kValid, B, M, [&](int i, int j, int k) {
       const int o = g.g(i, j, k);
@@ -449,7 +458,7 @@ CTU_DEV void trace_load(const Geo& g, const gdbl* __restrict__ q, int o, Stencil
 
 // The parabolas of the five permuted primitives of a cell along D.
 template <int D, int LIM>
-CTU_DEV void trace_parab(const ProbDev* P, const Stencil& S, double phi, Parab par[5]) {
+CTU_DEV void trace_parab(CProb* P, const Stencil& S, double phi, Parab par[5]) {
   double eta = 0.0;
   if (LIM & 2)  // contact steepening weight from the density and the neighbours' pressures
     eta = steep_eta(S.sv[0][0], S.sv[0][1], S.sv[0][2], S.sv[0][3], S.sv[0][4], S.sv[4][1], S.sv[4][3], P->gamma);
@@ -463,7 +472,7 @@ CTU_DEV void trace_parab(const ProbDev* P, const Stencil& S, double phi, Parab p
 // -1..n; floors are counted only on the states of faces 0..n (xd is the
 // cell's index along D, nd the box's extent).
 template <int D, bool UP>
-CTU_DEV void trace_face(const ProbDev* P, const Parab par[5], double rho, double un, double cs, int xd, int nd,
+CTU_DEV void trace_face(CProb* P, const Parab par[5], double rho, double un, double cs, int xd, int nd,
                         double v[5], unsigned long long& floors) {
   constexpr int zpos = 1 + (2 - D + 3) % 3;  // permuted slot of the z velocity
   const double dtdx = P->dtdx[D];
@@ -494,7 +503,7 @@ CTU_DEV void trace_store(const BoxRec& B, const Geo& g, int oh, const double up[
 // The species of the cell along D: parabolas with the hydro flattening,
 // traced with the hydro wave speeds of the cell.
 template <int D, int LIM>
-CTU_DEV void trace_species(const BoxRec& B, const Geo& g, const ProbDev* P, int xd, int o, int oh, double phi) {
+CTU_DEV void trace_species(const BoxRec& B, const Geo& g, CProb* P, int xd, int o, int oh, double phi) {
   const gdbl* __restrict__ q = g.q(B.scr);
   gdbl* __restrict__ ql = g.ql(B.scr, D);
   gdbl* __restrict__ qr = g.qr(B.scr, D);
@@ -512,7 +521,7 @@ CTU_DEV void trace_species(const BoxRec& B, const Geo& g, const ProbDev* P, int 
 }
 
 template <int D, int LIM>
-CTU_DEV void trace_cell(const BoxRec& B, const Geo& g, const ProbDev* P, int i, int j, int k, double phi,
+CTU_DEV void trace_cell(const BoxRec& B, const Geo& g, CProb* P, int i, int j, int k, double phi,
                         unsigned long long& floors) {
   const int x[3] = {i, j, k};
   const int o = g.g(i, j, k), oh = g.h(i, j, k);
@@ -535,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Segs L) {
     unsigned long long floors = 0;
     const gdbl* __restrict__ phiv = g.phi(B.scr);
     march(kCells1, B, M, [&](int i, int j, int k) {
-      trace_cell<D, LIM>(B, g, B.P, i, j, k, phiv[g.h(i, j, k)], floors);
+      trace_cell<D, LIM>(B, g, cprob(B.P), i, j, k, phiv[g.h(i, j, k)], floors);
     });
     count(&B.P->cnt[2], floors);
   });
@@ -557,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_trace3(const Segs L) {
   ldbl* held = (ldbl*)held_lds;
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
-    const ProbDev* P = B.P;
+    CProb* P = cprob(B.P);
     const gdbl* __restrict__ q = g.q(B.scr);
     gdbl* __restrict__ phiout = g.phi(B.scr);
     unsigned long long floors = 0;
@@ -636,7 +645,7 @@ CTU_DEV void wall_mirror(int side, double L[5], double R[5]) {
 template <int D, int RS>
 __global__ __launch_bounds__(kBlock) void k_riemann(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
+    CProb* P = cprob(B.P);
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ ql = g.ql(B.scr, D);
     const gdbl* __restrict__ qr = g.qr(B.scr, D);
@@ -697,7 +706,7 @@ CTU_DEV int to_prim_or_keep(const double U[5], const double s0[5], double gm1, d
 // two other directions, then the Riemann flux -> F^{A|B}.  fb counts states
 // that fell back to the uncorrected ones.
 template <int A, int RS>
-CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, const ProbDev* P, int i, int j, int k,
+CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, CProb* P, int i, int j, int k,
                          unsigned long long& fb) {
   const int sa = g.hstride(A);
   const gdbl* __restrict__ ql = g.ql(B.scr, A);
@@ -758,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
     unsigned long long fb = 0;
-    march(kFace0 + A, B, M, [&](int i, int j, int k) { trans1_face<A, RS>(B, g, B.P, i, j, k, fb); });
+    march(kFace0 + A, B, M, [&](int i, int j, int k) { trans1_face<A, RS>(B, g, cprob(B.P), i, j, k, fb); });
     count(&B.P->cnt[3], fb);
   });
 }
@@ -772,9 +781,9 @@ __global__ __launch_bounds__(kBlock) void k_trans1_all(const Segs L) {
     const Geo g(B.n, B.ns);
     unsigned long long fb = 0;
     march(kCells1, B, M, [&](int i, int j, int k) {
-      if (i >= 0) trans1_face<0, RS>(B, g, B.P, i, j, k, fb);
-      if (j >= 0) trans1_face<1, RS>(B, g, B.P, i, j, k, fb);
-      if (k >= 0) trans1_face<2, RS>(B, g, B.P, i, j, k, fb);
+      if (i >= 0) trans1_face<0, RS>(B, g, cprob(B.P), i, j, k, fb);
+      if (j >= 0) trans1_face<1, RS>(B, g, cprob(B.P), i, j, k, fb);
+      if (k >= 0) trans1_face<2, RS>(B, g, cprob(B.P), i, j, k, fb);
     });
     count(&B.P->cnt[3], fb);
   });
@@ -785,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_trans1_all(const Segs L) {
 // A, then the final HLLC flux (global component order).  fb counts states that
 // fell back to the uncorrected ones.
 template <int A, int RS>
-CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, int fa, gdbl* __restrict__ ff,
+CTU_DEV void final_flux(const BoxRec& B, const Geo& g, CProb* P, int o, int fa, gdbl* __restrict__ ff,
                         int& fb) {
   constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
   // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
@@ -844,7 +853,7 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, const ProbDev* P, int o, 
 template <int A, int RS>
 __global__ __launch_bounds__(kBlock) void k_trans2(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
+    CProb* P = cprob(B.P);
     const Geo g(B.n, B.ns);
     gdbl* __restrict__ ff = g.ff(B.scr, A);
     int fb = 0;
@@ -860,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void k_trans2(const Segs L) {
 // failure check (rho < small_dens, p < small_pres or a non-finite value).
 __global__ __launch_bounds__(kBlock) void k_update(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
+    CProb* P = cprob(B.P);
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ U = gp(B.U[P->cur]);
     gdbl* __restrict__ Un = gp(B.U[P->cur ^ 1]);
@@ -928,7 +937,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Segs L) {
 // the right state of the face below), floored; floors are counted only on
 // the states of faces 0..n (xd the cell's index along D, nd the extent).
 template <int D, int LIM>
-CTU_DEV void recon_eval(const ProbDev* P, const Stencil& S, double phi, int xd, int nd, double up[5], double dn[5],
+CTU_DEV void recon_eval(CProb* P, const Stencil& S, double phi, int xd, int nd, double up[5], double dn[5],
                         unsigned long long& floors) {
   Parab par[5];
   trace_parab<D, LIM>(P, S, phi, par);
@@ -967,7 +976,7 @@ CTU_DEV void recon_species(const BoxRec& B, const Geo& g, int xd, int o, int oh,
 template <int D, int LIM>
 __global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
+    CProb* P = cprob(B.P);
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
     const gdbl* __restrict__ phiv = g.phi(B.scr);
@@ -996,7 +1005,7 @@ __global__ __launch_bounds__(kBlock) void k_recon3(const Segs L) {
   __shared__ double held_lds[2 * 10 * kBlock];
   ldbl* held = (ldbl*)held_lds;
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
+    CProb* P = cprob(B.P);
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ q = g.q(B.scr);
     gdbl* __restrict__ phiout = g.phi(B.scr);
@@ -1044,7 +1053,7 @@ __global__ __launch_bounds__(kBlock) void k_recon3(const Segs L) {
 __global__ __launch_bounds__(kBlock) void k_mol_update(const Segs L, int arr,
                                                        int out, int comb, double c, int last) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
-    const ProbDev* P = B.P;
+    CProb* P = cprob(B.P);
     const Geo g(B.n, B.ns);
     const gdbl* __restrict__ Us = gp(state_arr(B, arr));
     const gdbl* __restrict__ U0 = gp(B.U[P->cur]);
