@@ -127,6 +127,7 @@ struct StepSet {
   int scheme = 0;   // shared by every problem of the set
   int riemann = 0;  // likewise
   int limiter = 0;  // likewise (reconstruction variant: 0 CW84, 1 CS, 2 CW84 + steepening)
+  int species = 0;  // 1 when a problem of the set carries passive species
   int nboxes = 0;
   int zvar = 0;     // work-unit variant of its launches (LevelTables)
   hipGraph_t graph[2] = {nullptr, nullptr};  // captured step, unguarded / guarded
@@ -440,6 +441,7 @@ struct StageArgs {
   int last = 1;
   int rs = 0;
   int lim = 0;
+  int sp = 0;
 };
 
 // Launch one stage over a segment list with optional timing.
@@ -457,6 +459,7 @@ int launch_segs(ctuppm_ctx* c, hipStream_t s, int stage, const Segs& G, bool per
   L.last = A.last;
   L.rs = A.rs;
   L.lim = A.lim;
+  L.sp = A.sp;
   hipEvent_t a = nullptr, b = nullptr;
   if (timed) {
     a = take_event(c);
@@ -513,6 +516,7 @@ int run_range(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int b0, int b
   SegRun R{c, s, stage, S->form != CTUPPM_FORM_PER_BOX, timed, A0};
   R.A.rs = S->riemann;
   R.A.lim = S->limiter;
+  R.A.sp = S->species;
   const int rf = rec_form(S->form), zv = S->zvar;
   for (size_t ip = 0; ip < S->probs.size(); ++ip) {
     const int off = S->box_off[ip], nb = S->box_off[ip + 1] - off;
@@ -1154,6 +1158,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
     if (P->prm.scheme != S->scheme || P->prm.riemann != S->riemann || var != S->limiter)
       return fail(c, CTUPPM_EINVAL,
                   "problems stepped together must use the same scheme, Riemann solver and limiter");
+    if (P->prm.nspec > 0) S->species = 1;
     S->probs.push_back(P);
     S->box_off.push_back(S->box_off.back() + int(P->lev[level].boxes.size()));
   }

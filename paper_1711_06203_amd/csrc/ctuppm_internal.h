@@ -205,6 +205,7 @@ struct Launch {
   int last = 1;        // MOL update: the step's last stage (test hook applies)
   int rs = 0;          // Riemann solver of the flux stages: 0 HLLC, 1 two-shock
   int lim = 0;         // reconstruction variant: 0 CW84, 1 Colella & Sekora, 2 CW84 + contact steepening
+  int sp = 0;          // a problem of the launch carries passive species (merged stage 1)
 };
 
 hipError_t launch_stage(int stage, const Launch& L);

@@ -501,9 +501,10 @@ CTU_DEV void trace_store(const BoxRec& B, const Geo& g, int oh, const double up[
 }
 
 // The species of the cell along D: parabolas with the hydro flattening,
-// traced with the hydro wave speeds of the cell.
+// traced with the hydro wave speeds of the cell.  Stored unconditionally, as
+// the hydro states (the unread slots of cells n and -1 keep the runs whole).
 template <int D, int LIM>
-CTU_DEV void trace_species(const BoxRec& B, const Geo& g, CProb* P, int xd, int o, int oh, double phi) {
+CTU_DEV void trace_species(const BoxRec& B, const Geo& g, CProb* P, int o, int oh, double phi) {
   const gdbl* __restrict__ q = g.q(B.scr);
   gdbl* __restrict__ ql = g.ql(B.scr, D);
   gdbl* __restrict__ qr = g.qr(B.scr, D);
@@ -515,8 +516,67 @@ CTU_DEV void trace_species(const BoxRec& B, const Geo& g, CProb* P, int xd, int 
   for (int is = 0; is < g.ns; ++is) {
     const gdbl* a = q + (6 + is) * g.gcomp + o;
     const Parab px = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-    if (xd <= B.n[D] - 1) __builtin_nontemporal_store(species_up(px, lp, l0, spp, s0), &ql[(kNV + is) * g.hcomp + oh + sth]);
-    if (xd >= 0) __builtin_nontemporal_store(species_dn(px, lm, l0, sm, s0), &qr[(kNV + is) * g.hcomp + oh]);
+    __builtin_nontemporal_store(species_up(px, lp, l0, spp, s0), &ql[(kNV + is) * g.hcomp + oh + sth]);
+    __builtin_nontemporal_store(species_dn(px, lm, l0, sm, s0), &qr[(kNV + is) * g.hcomp + oh]);
+  }
+}
+
+// The species of the cell along x, y and z at once (the merged kernels):
+// TRACE = characteristic tracing with the hydro wave speeds of the cell, else
+// the method-of-lines edge values.  A species' 13 stencil values are loaded
+// before the stores of the previous species are issued, so no wave waits
+// for its own stores to read the next species; every store is unconditional.
+template <int LIM, bool TRACE>
+CTU_DEV void species3(const BoxRec& B, const Geo& g, CProb* P, int o, int oh, double phi) {
+  const gdbl* __restrict__ q = g.q(B.scr);
+  const int st[3] = {g.gstride(0), g.gstride(1), g.gstride(2)};
+  double un[3], cs = 0.0;
+  if (TRACE) {
+    cs = q[5 * g.gcomp + o];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) un[d] = q[(1 + d) * g.gcomp + o];
+  }
+  // v[0] the cell; v[1 + 4d ..] the stencil neighbours -2, -1, +1, +2 along d
+  auto load = [&](int is, double v[13]) {
+    const gdbl* a = q + (6 + is) * g.gcomp + o;
+    v[0] = a[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      v[1 + 4 * d] = a[-2 * st[d]]; v[2 + 4 * d] = a[-st[d]];
+      v[3 + 4 * d] = a[st[d]]; v[4 + 4 * d] = a[2 * st[d]];
+    }
+  };
+  double cur[13], nxt[13];
+  load(0, cur);
+#pragma unroll 1
+  for (int is = 0; is < g.ns; ++is) {
+    if (is + 1 < g.ns) load(is + 1, nxt);
+    double up[3], dn[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const Parab px = ppm_l<LIM>(cur[1 + 4 * d], cur[2 + 4 * d], cur[0], cur[3 + 4 * d], cur[4 + 4 * d], phi);
+      if (TRACE) {
+        // the wave speeds of the cell along d, as the single-direction tracing
+        const double dtdx = P->dtdx[d];
+        const double lm = un[d] - cs, l0 = un[d], lp = un[d] + cs;
+        up[d] = species_up(px, lp, l0, fabs(lp) * dtdx, fabs(l0) * dtdx);
+        dn[d] = species_dn(px, lm, l0, fabs(lm) * dtdx, fabs(l0) * dtdx);
+      } else {
+        up[d] = px.aR;
+        dn[d] = px.aL;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      gdbl* __restrict__ ql = g.ql(B.scr, d);
+      gdbl* __restrict__ qr = g.qr(B.scr, d);
+      __builtin_nontemporal_store(up[d], &ql[(kNV + is) * g.hcomp + oh + g.hstride(d)]);
+      __builtin_nontemporal_store(dn[d], &qr[(kNV + is) * g.hcomp + oh]);
+    }
+    if (is + 1 < g.ns) {
+#pragma unroll
+      for (int m = 0; m < 13; ++m) cur[m] = nxt[m];
+    }
   }
 }
 
@@ -533,7 +593,7 @@ CTU_DEV void trace_cell(const BoxRec& B, const Geo& g, CProb* P, int i, int j, i
   trace_face<D, true>(P, par, S.sv[0][2], S.sv[1][2], S.cs, x[D], B.n[D], up, floors);
   trace_face<D, false>(P, par, S.sv[0][2], S.sv[1][2], S.cs, x[D], B.n[D], dn, floors);
   trace_store<D>(B, g, oh, up, dn);
-  if (g.ns > 0) trace_species<D, LIM>(B, g, P, x[D], o, oh, phi);
+  if (g.ns > 0) trace_species<D, LIM>(B, g, P, o, oh, phi);
 }
 
 // One thread per cell of -1..n, tracing along D.
@@ -557,9 +617,10 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Segs L) {
 // in LDS (each thread its own slots) until the loads of z have returned: a
 // wave whose stores are still in flight waits for them as well when it waits
 // for a later load, so every global store of the cell is issued after its
-// last load.
+// last load.  Three waves per SIMD (the LDS allows four): the register
+// budget that keeps the species loop from lowering the occupancy to two.
 template <int LIM>
-__global__ __launch_bounds__(kBlock) void k_trace3(const Segs L) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace3(const Segs L) {
   // 40 KB: the up and dn states of x and y, [direction][component][thread];
   // volatile, so the compiler keeps them in LDS rather than in registers
   __shared__ double held_lds[2 * 10 * kBlock];
@@ -609,11 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_trace3(const Segs L) {
         if (d == 0) trace_store<0>(B, g, oh, up, dn);
         else trace_store<1>(B, g, oh, up, dn);
       }
-      if (g.ns > 0) {
-        trace_species<0, LIM>(B, g, P, i, o, oh, phi);
-        trace_species<1, LIM>(B, g, P, j, o, oh, phi);
-        trace_species<2, LIM>(B, g, P, k, o, oh, phi);
-      }
+      if (g.ns > 0) species3<LIM, true>(B, g, P, o, oh, phi);
     });
     count(&B.P->cnt[2], floors);
   });
@@ -704,8 +761,10 @@ CTU_DEV int to_prim_or_keep(const double U[5], const double s0[5], double gm1, d
 // Stage 1 at one face along A: the face states corrected by dt/(3 dx_B)
 // times the normal B-flux difference across their owner cell, for B = the
 // two other directions, then the Riemann flux -> F^{A|B}.  fb counts states
-// that fell back to the uncorrected ones.
-template <int A, int RS>
+// that fell back to the uncorrected ones.  SP: the launch holds problems with
+// species, whose face states are read once for both directions B after the
+// hydro fluxes of both (without SP every problem of the launch has none).
+template <int A, int RS, bool SP>
 CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, CProb* P, int i, int j, int k,
                          unsigned long long& fb) {
   const int sa = g.hstride(A);
@@ -723,10 +782,17 @@ CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, CProb* P, int i, int j, 
   }
   to_cons<A>(sL, P->rgm1, UL);
   to_cons<A>(sR, P->rgm1, UR);
+  const int side = wall_side(B, A, x[A]);
+  // what the species correction of each direction B needs from the hydro one
+  bool on[2];
+  Wave Ws[2];
+  double rL[2], rR[2];
+  int keepL[2], keepR[2];
 #pragma unroll
   for (int which = 0; which < 2; ++which) {
     const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
-    if (x[Bd] < 0 || x[Bd] >= B.n[Bd]) continue;
+    on[which] = x[Bd] >= 0 && x[Bd] < B.n[Bd];
+    if (!on[which]) continue;
     const double c3 = P->dt3dx[Bd];
     const int sb = g.hstride(Bd);
     const gdbl* __restrict__ Fb = g.fn(B.scr, Bd);
@@ -741,22 +807,37 @@ CTU_DEV void trans1_face(const BoxRec& B, const Geo& g, CProb* P, int i, int j, 
     const int kL = to_prim_or_keep<A>(VL, sL, P->gm1, P->small_dens, P->small_pres, tL);
     const int kR = to_prim_or_keep<A>(VR, sR, P->gm1, P->small_dens, P->small_pres, tR);
     fb += kL + kR;
-    const int side = wall_side(B, A, x[A]);
     wall_mirror(side, tL, tR);
     Wave W;
     rflux<RS>(tL, tR, P, f, W);
     gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
     store_flux_nt<A>(F1, g.hcomp, o, f);
-    // species: rho X corrected by the same flux difference, back to X with
-    // the corrected density (or the traced X where the state fell back)
-    for (int is = 0; is < g.ns; ++is) {
-      const int c = (kNV + is) * g.hcomp;
-      const gdbl* Fm = Fb + c;
-      const double xL = __builtin_nontemporal_load(&ql[c + o]), xR = __builtin_nontemporal_load(&qr[c + o]);
+    if (SP) {
+      Ws[which] = W;
+      rL[which] = VL[0]; rR[which] = VR[0];
+      keepL[which] = kL; keepR[which] = kR;
+    }
+  }
+  if (!SP) return;
+  // species: rho X corrected by the same flux differences as the density,
+  // back to X with the corrected density (or the traced X where the state
+  // fell back)
+  const int oL = o - sa, oR = o;
+  for (int is = 0; is < g.ns; ++is) {
+    const int c = (kNV + is) * g.hcomp;
+    const double xL = __builtin_nontemporal_load(&ql[c + o]), xR = __builtin_nontemporal_load(&qr[c + o]);
+#pragma unroll
+    for (int which = 0; which < 2; ++which) {
+      if (!on[which]) continue;
+      const int Bd = which == 0 ? (A + 1) % 3 : (A + 2) % 3;
+      const double c3 = P->dt3dx[Bd];
+      const int sb = g.hstride(Bd);
+      const gdbl* Fm = g.fn(B.scr, Bd) + c;
       const double wL = sL[0] * xL - c3 * (Fm[oL + sb] - Fm[oL]);
       const double wR = sR[0] * xR - c3 * (Fm[oR + sb] - Fm[oR]);
-      const double yL = kL ? xL : wL / VL[0], yR = kR ? xR : wR / VR[0];
-      __builtin_nontemporal_store(species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR), &F1[c + o]);
+      const double yL = keepL[which] ? xL : wL / rL[which], yR = keepR[which] ? xR : wR / rR[which];
+      gdbl* __restrict__ F1 = g.f1(B.scr, 2 * A + which);
+      __builtin_nontemporal_store(species_flux(Ws[which], side == 1 ? yR : yL, side == 2 ? yL : yR), &F1[c + o]);
     }
   }
 }
@@ -767,23 +848,24 @@ __global__ __launch_bounds__(kBlock) void k_trans1(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
     unsigned long long fb = 0;
-    march(kFace0 + A, B, M, [&](int i, int j, int k) { trans1_face<A, RS>(B, g, cprob(B.P), i, j, k, fb); });
+    march(kFace0 + A, B, M, [&](int i, int j, int k) { trans1_face<A, RS, true>(B, g, cprob(B.P), i, j, k, fb); });
     count(&B.P->cnt[3], fb);
   });
 }
 
 // Stage 1 along x, then y, then z, one thread per cell of -1..n (the lower
 // A-face of the cell, where the cell is not at -1 along A): each normal flux
-// array is read once instead of by two of the per-direction kernels.
-template <int RS>
+// array is read once instead of by two of the per-direction kernels.  SP as
+// for trans1_face.
+template <int RS, bool SP>
 __global__ __launch_bounds__(kBlock) void k_trans1_all(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
     const Geo g(B.n, B.ns);
     unsigned long long fb = 0;
     march(kCells1, B, M, [&](int i, int j, int k) {
-      if (i >= 0) trans1_face<0, RS>(B, g, cprob(B.P), i, j, k, fb);
-      if (j >= 0) trans1_face<1, RS>(B, g, cprob(B.P), i, j, k, fb);
-      if (k >= 0) trans1_face<2, RS>(B, g, cprob(B.P), i, j, k, fb);
+      if (i >= 0) trans1_face<0, RS, SP>(B, g, cprob(B.P), i, j, k, fb);
+      if (j >= 0) trans1_face<1, RS, SP>(B, g, cprob(B.P), i, j, k, fb);
+      if (k >= 0) trans1_face<2, RS, SP>(B, g, cprob(B.P), i, j, k, fb);
     });
     count(&B.P->cnt[3], fb);
   });
@@ -954,9 +1036,10 @@ CTU_DEV void recon_eval(CProb* P, const Stencil& S, double phi, int xd, int nd, 
   if (dn[4] < sp) { dn[4] = sp; floors += fd; }
 }
 
-// The species edge values of a cell along D (the hydro flattening).
+// The species edge values of a cell along D (the hydro flattening), stored
+// unconditionally as the hydro states.
 template <int D, int LIM>
-CTU_DEV void recon_species(const BoxRec& B, const Geo& g, int xd, int o, int oh, double phi) {
+CTU_DEV void recon_species(const BoxRec& B, const Geo& g, int o, int oh, double phi) {
   const gdbl* __restrict__ q = g.q(B.scr);
   gdbl* __restrict__ ql = g.ql(B.scr, D);
   gdbl* __restrict__ qr = g.qr(B.scr, D);
@@ -964,8 +1047,8 @@ CTU_DEV void recon_species(const BoxRec& B, const Geo& g, int xd, int o, int oh,
   for (int is = 0; is < g.ns; ++is) {
     const gdbl* a = q + (6 + is) * g.gcomp + o;
     const Parab par = ppm_l<LIM>(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi);
-    if (xd <= B.n[D] - 1) __builtin_nontemporal_store(par.aR, &ql[(kNV + is) * g.hcomp + oh + sth]);
-    if (xd >= 0) __builtin_nontemporal_store(par.aL, &qr[(kNV + is) * g.hcomp + oh]);
+    __builtin_nontemporal_store(par.aR, &ql[(kNV + is) * g.hcomp + oh + sth]);
+    __builtin_nontemporal_store(par.aL, &qr[(kNV + is) * g.hcomp + oh]);
   }
 }
 
@@ -990,7 +1073,7 @@ __global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
       trace_load<D, false>(g, q, o, S);
       recon_eval<D, LIM>(P, S, phi, x[D], B.n[D], up, dn, floors);
       trace_store<D>(B, g, oh, up, dn);
-      if (g.ns > 0) recon_species<D, LIM>(B, g, x[D], o, oh, phi);
+      if (g.ns > 0) recon_species<D, LIM>(B, g, o, oh, phi);
     });
     count(&B.P->cnt[2], floors);
   });
@@ -1035,11 +1118,7 @@ __global__ __launch_bounds__(kBlock) void k_recon3(const Segs L) {
         if (d == 0) trace_store<0>(B, g, oh, up, dn);
         else trace_store<1>(B, g, oh, up, dn);
       }
-      if (g.ns > 0) {
-        recon_species<0, LIM>(B, g, i, o, oh, phi);
-        recon_species<1, LIM>(B, g, j, o, oh, phi);
-        recon_species<2, LIM>(B, g, k, o, oh, phi);
-      }
+      if (g.ns > 0) species3<LIM, false>(B, g, P, o, oh, phi);
     });
     count(&B.P->cnt[2], floors);
   });
@@ -1396,23 +1475,25 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStReconY: CTU_LIM(k_recon, 1); break;
     case kStReconZ: CTU_LIM(k_recon, 2); break;
     case kStMolUpdate: k_mol_update<<<grid, block, 0, s>>>(G, L.arr, L.out, L.comb, L.c, L.last); break;
-    case kStRecon3:
-      if (L.lim == 1) k_recon3<1><<<grid, block, 0, s>>>(G);
-      else if (L.lim == 2) k_recon3<2><<<grid, block, 0, s>>>(G);
-      else k_recon3<0><<<grid, block, 0, s>>>(G);
-      break;
+#define CTU_LIM3(K)                                                         \
+  (L.lim == 1   ? K<1><<<grid, block, 0, s>>>(G)                            \
+   : L.lim == 2 ? K<2><<<grid, block, 0, s>>>(G)                            \
+                : K<0><<<grid, block, 0, s>>>(G))
+    case kStRecon3: CTU_LIM3(k_recon3); break;
     case kStFlatten: k_flatten<<<grid, block, 0, s>>>(G); break;
     case kStTraceX: CTU_LIM(k_trace, 0); break;
     case kStTraceY: CTU_LIM(k_trace, 1); break;
     case kStTraceZ: CTU_LIM(k_trace, 2); break;
-    case kStTrace3:
-      if (L.lim == 1) k_trace3<1><<<grid, block, 0, s>>>(G);
-      else if (L.lim == 2) k_trace3<2><<<grid, block, 0, s>>>(G);
-      else k_trace3<0><<<grid, block, 0, s>>>(G);
-      break;
+    case kStTrace3: CTU_LIM3(k_trace3); break;
+#undef CTU_LIM3
     case kStT1All:
-      if (L.rs) k_trans1_all<1><<<grid, block, 0, s>>>(G);
-      else k_trans1_all<0><<<grid, block, 0, s>>>(G);
+      if (L.sp) {
+        if (L.rs) k_trans1_all<1, true><<<grid, block, 0, s>>>(G);
+        else k_trans1_all<0, true><<<grid, block, 0, s>>>(G);
+      } else {
+        if (L.rs) k_trans1_all<1, false><<<grid, block, 0, s>>>(G);
+        else k_trans1_all<0, false><<<grid, block, 0, s>>>(G);
+      }
       break;
 #define CTU_RS(K, D) (L.rs ? K<D, 1><<<grid, block, 0, s>>>(G) : K<D, 0><<<grid, block, 0, s>>>(G))
     case kStRiemX: CTU_RS(k_riemann, 0); break;
