@@ -17,7 +17,9 @@ constexpr int kSlots = 64;   // signal-speed max accumulators per problem (sprea
 // Work regions of a box (n valid cells per direction), as (origin, extent):
 //   kValid  cells [0, n)            kGrown cells [-4, n+4)   kCells1 cells [-1, n]
 //   kFaceD  faces [0, n] along D, cells [-1, n] across
-//   kFinD   faces [0, n] along D, cells [0, n) across
+//   kFinD   faces [0, n] along D, cells [0, n) across, with x over [-1, n]
+//           (whole rows of the halo-1 arrays: the threads off the faces
+//           store zeros, so a row is written in whole lines)
 //   kCells1T  cells [-1, n] like kCells1: the merged tracing's own region, so
 //   its work units can march through more planes than stage 1's (a block
 //   marching through consecutive planes finds the z stencils of the next
@@ -34,7 +36,9 @@ __host__ __device__ inline void region_of(int kind, const int n[3], int org[3], 
         if (d == kind - kFace0) { org[d] = 0; ext[d] = n[d] + 1; } else { org[d] = -1; ext[d] = n[d] + 2; }
         break;
       default:
-        if (d == kind - kFin0) { org[d] = 0; ext[d] = n[d] + 1; } else { org[d] = 0; ext[d] = n[d]; }
+        if (d == 0) { org[d] = -1; ext[d] = n[d] + 2; }
+        else if (d == kind - kFin0) { org[d] = 0; ext[d] = n[d] + 1; }
+        else { org[d] = 0; ext[d] = n[d]; }
         break;
     }
   }
@@ -183,8 +187,9 @@ __host__ __device__ inline int stage_region(int stage) {
     case kStTraceX: case kStTraceY: case kStTraceZ: return kCells1;
     case kStReconX: case kStReconY: case kStReconZ: return kCells1;
     case kStMolUpdate: return kValid;
-    case kStRiemX: case kStT1X: return kFace0;
-    case kStRiemY: case kStT1Y: return kFace1;
+    case kStRiemX: case kStRiemY: return kCells1;  // whole rows / planes of stores
+    case kStT1X: return kFace0;
+    case kStT1Y: return kFace1;
     case kStRiemZ: case kStT1Z: return kFace2;
     case kStT2X: return kFin0;
     case kStT2Y: return kFin1;

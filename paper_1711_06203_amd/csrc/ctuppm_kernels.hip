@@ -698,7 +698,10 @@ CTU_DEV void wall_mirror(int side, double L[5], double R[5]) {
   }
 }
 
-// Normal flux of every face 0..n along D (cells -1..n across).
+// Normal flux of every face 0..n along D (cells -1..n across).  Along x and
+// y the threads cover cells -1..n, so a wave writes whole rows (x) and whole
+// planes (y): the slot of face -1, which nothing reads, takes zeros instead
+// of leaving a partly written line in every row.
 template <int D, int RS>
 __global__ __launch_bounds__(kBlock) void k_riemann(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
@@ -707,9 +710,14 @@ __global__ __launch_bounds__(kBlock) void k_riemann(const Segs L) {
     const gdbl* __restrict__ ql = g.ql(B.scr, D);
     const gdbl* __restrict__ qr = g.qr(B.scr, D);
     gdbl* __restrict__ fn = g.fn(B.scr, D);
-    march(kFace0 + D, B, M, [&](int i, int j, int k) {
+    march(D == 2 ? kFace2 : kCells1, B, M, [&](int i, int j, int k) {
       const int o = g.h(i, j, k);
-      const int side = wall_side(B, D, D == 0 ? i : (D == 1 ? j : k));
+      const int fa = D == 0 ? i : (D == 1 ? j : k);
+      if (fa < 0) {
+        for (int m = 0; m < g.nv; ++m) fn[m * g.hcomp + o] = 0.0;
+        return;
+      }
+      const int side = wall_side(B, D, fa);
       double L[5], R[5], f[5];
 #pragma unroll
       for (int m = 0; m < 5; ++m) {
@@ -874,9 +882,10 @@ __global__ __launch_bounds__(kBlock) void k_trans1_all(const Segs L) {
 // Stage 2 at one face along A: the face states corrected by dt/(2 dx_B)
 // dF^{B|C} and then dt/(2 dx_C) dF^{C|B}, with (B, C) the cyclic successors of
 // A, then the final HLLC flux (global component order).  fb counts states that
-// fell back to the uncorrected ones.
+// fell back to the uncorrected ones.  Threads whose slot holds no face (on
+// false) store zeros with the same store instructions.
 template <int A, int RS>
-CTU_DEV void final_flux(const BoxRec& B, const Geo& g, CProb* P, int o, int fa, gdbl* __restrict__ ff,
+CTU_DEV void final_flux(const BoxRec& B, const Geo& g, CProb* P, int o, int fa, bool on, gdbl* __restrict__ ff,
                         int& fb) {
   constexpr int Bd = (A + 1) % 3, Cd = (A + 2) % 3;
   // F^{B|C}: pair index 2B + (C == B+1 ? 0 : 1); F^{C|B}: 2C + (B == C+1 ? 0 : 1)
@@ -889,49 +898,59 @@ CTU_DEV void final_flux(const BoxRec& B, const Geo& g, CProb* P, int o, int fa, 
   const gdbl* __restrict__ Fcb = g.f1(B.scr, pcb);
   const double c2b = P->dt2dx[Bd];
   const double c2c = P->dt2dx[Cd];
-  double sL[5], sR[5], UL[5], UR[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    sL[m] = ql[m * g.hcomp + o];
-    sR[m] = qr[m * g.hcomp + o];
-  }
-  to_cons<A>(sL, P->rgm1, UL);
-  to_cons<A>(sR, P->rgm1, UR);
   const int oL = o - sa, oR = o;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const gdbl* F1 = Fbc + m * g.hcomp;
-    const gdbl* F2 = Fcb + m * g.hcomp;
-    UL[m] = UL[m] - c2b * (F1[oL + sb] - F1[oL]);
-    UR[m] = UR[m] - c2b * (F1[oR + sb] - F1[oR]);
-    UL[m] = UL[m] - c2c * (F2[oL + sc] - F2[oL]);
-    UR[m] = UR[m] - c2c * (F2[oR + sc] - F2[oR]);
-  }
-  double tL[5], tR[5], f[5];
-  const int kL = to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
-  const int kR = to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
-  fb += kL + kR;
   const int side = wall_side(B, A, fa);
-  wall_mirror(side, tL, tR);
-  Wave W;
-  rflux<RS>(tL, tR, P, f, W);
+  double sL0 = 0.0, sR0 = 0.0, rL = 1.0, rR = 1.0, f[5] = {};
+  int kL = 0, kR = 0;
+  Wave W{};
+  if (on) {
+    double sL[5], sR[5], UL[5], UR[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      sL[m] = ql[m * g.hcomp + o];
+      sR[m] = qr[m * g.hcomp + o];
+    }
+    to_cons<A>(sL, P->rgm1, UL);
+    to_cons<A>(sR, P->rgm1, UR);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const gdbl* F1 = Fbc + m * g.hcomp;
+      const gdbl* F2 = Fcb + m * g.hcomp;
+      UL[m] = UL[m] - c2b * (F1[oL + sb] - F1[oL]);
+      UR[m] = UR[m] - c2b * (F1[oR + sb] - F1[oR]);
+      UL[m] = UL[m] - c2c * (F2[oL + sc] - F2[oL]);
+      UR[m] = UR[m] - c2c * (F2[oR + sc] - F2[oR]);
+    }
+    double tL[5], tR[5];
+    kL = to_prim_or_keep<A>(UL, sL, P->gm1, P->small_dens, P->small_pres, tL);
+    kR = to_prim_or_keep<A>(UR, sR, P->gm1, P->small_dens, P->small_pres, tR);
+    fb += kL + kR;
+    wall_mirror(side, tL, tR);
+    rflux<RS>(tL, tR, P, f, W);
+    sL0 = sL[0]; sR0 = sR[0]; rL = UL[0]; rR = UR[0];
+  }
   store_flux<A>(ff, g.hcomp, o, f);
   for (int is = 0; is < g.ns; ++is) {
     const int c = (kNV + is) * g.hcomp;
-    const gdbl* F1 = Fbc + c;
-    const gdbl* F2 = Fcb + c;
-    const double xL = ql[c + o], xR = qr[c + o];
-    double wL = sL[0] * xL, wR = sR[0] * xR;
-    wL = wL - c2b * (F1[oL + sb] - F1[oL]);
-    wR = wR - c2b * (F1[oR + sb] - F1[oR]);
-    wL = wL - c2c * (F2[oL + sc] - F2[oL]);
-    wR = wR - c2c * (F2[oR + sc] - F2[oR]);
-    const double yL = kL ? xL : wL / UL[0], yR = kR ? xR : wR / UR[0];
-    ff[c + o] = species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR);
+    double v = 0.0;
+    if (on) {
+      const gdbl* F1 = Fbc + c;
+      const gdbl* F2 = Fcb + c;
+      const double xL = ql[c + o], xR = qr[c + o];
+      double wL = sL0 * xL, wR = sR0 * xR;
+      wL = wL - c2b * (F1[oL + sb] - F1[oL]);
+      wR = wR - c2b * (F1[oR + sb] - F1[oR]);
+      wL = wL - c2c * (F2[oL + sc] - F2[oL]);
+      wR = wR - c2c * (F2[oR + sc] - F2[oR]);
+      const double yL = kL ? xL : wL / rL, yR = kR ? xR : wR / rR;
+      v = species_flux(W, side == 1 ? yR : yL, side == 2 ? yL : yR);
+    }
+    ff[c + o] = v;
   }
 }
 
-// Stage 2 along A over faces 0..n (cells 0..n-1 across): final fluxes.
+// Stage 2 along A over faces 0..n (cells 0..n-1 across): final fluxes; the
+// threads cover whole rows (x over -1..n) and store zeros off the faces.
 template <int A, int RS>
 __global__ __launch_bounds__(kBlock) void k_trans2(const Segs L) {
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
@@ -939,8 +958,9 @@ __global__ __launch_bounds__(kBlock) void k_trans2(const Segs L) {
     const Geo g(B.n, B.ns);
     gdbl* __restrict__ ff = g.ff(B.scr, A);
     int fb = 0;
+    const int ilast = A == 0 ? B.n[0] : B.n[0] - 1;  // last x index holding a face
     march(kFin0 + A, B, M, [&](int i, int j, int k) {
-      final_flux<A, RS>(B, g, P, g.h(i, j, k), A == 0 ? i : (A == 1 ? j : k), ff, fb);
+      final_flux<A, RS>(B, g, P, g.h(i, j, k), A == 0 ? i : (A == 1 ? j : k), i >= 0 && i <= ilast, ff, fb);
     });
     count(&B.P->cnt[3], (unsigned long long)fb);
   });
