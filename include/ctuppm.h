@@ -411,10 +411,12 @@ int ctuppm_set_wave_boxes(ctuppm_ctx* ctx, int boxes);
 
 /* Kernels of the cell stages: on (1, the default), the flattening and the
  * tracing (CTU) or the edge-value face states (method of lines) of the three
- * directions run in one kernel that reads each cell's primitives once, and
- * the first transverse stage of the three directions (CTU) in one kernel that
- * reads each normal flux array once; off (0), a flattening kernel and one
- * kernel per direction.  Results are the same bits either way (each face
+ * directions run in one kernel that reads each cell's primitives once (for
+ * CTU the passive species of the three directions follow in a kernel of
+ * their own, stage "species_xyz", launched only for problems with species),
+ * and the first transverse stage of the three directions (CTU) in one kernel
+ * that reads each normal flux array once; off (0), a flattening kernel and
+ * one kernel per direction.  Results are the same bits either way (each face
  * takes the same arithmetic); captured graphs are dropped. */
 int ctuppm_set_fused(ctuppm_ctx* ctx, int on);
 /* Measurement: the HBM bandwidth plain streaming reaches on this GPU, the
@@ -442,7 +444,8 @@ int ctuppm_set_tuning2(ctuppm_ctx* ctx, int blocks_per_cu, int zseg_batched, int
  * Stages that run over the same work region share the setting:
  * ctuppm_stage_planes returns the stage's setting and its group (stages with
  * equal groups share it).  Defaults: 2 for cons->prim, 4 for the merged
- * tracing and the merged method-of-lines face states, 1 elsewhere.  Problems
+ * tracing (and its species stage) and the merged method-of-lines face states,
+ * 1 elsewhere.  Problems
  * stepped together whose merged-tracing work units at that depth would number
  * fewer than 8 per CU run their stages left at the defaults with one plane
  * per unit (two for cons->prim); a value set here is used as given.  Results

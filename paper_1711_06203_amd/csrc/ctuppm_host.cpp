@@ -513,6 +513,7 @@ ProbDev* level_rec(Problem* P, int level) { return level == 0 ? P->dP : P->dPf; 
 // chunks for the ghost fill and the boundaries.
 int run_range(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int b0, int b1, bool timed,
               const StageArgs& A0 = StageArgs()) {
+  if (stage == kStSpec3 && !S->species) return CTUPPM_OK;  // the merged tracing's species stage
   SegRun R{c, s, stage, S->form != CTUPPM_FORM_PER_BOX, timed, A0};
   R.A.rs = S->riemann;
   R.A.lim = S->limiter;
@@ -1180,7 +1181,7 @@ int build_set(ctuppm_ctx* c, const std::vector<int>& pids, int form, StepSet** o
 // directions in another.  Both give the same bits.
 const int kCellStagesSplit[] = {kStFlatten, kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ,
                                 kStT1X, kStT1Y, kStT1Z, kStT2X, kStT2Y, kStT2Z, kStUpdate};
-const int kCellStagesFused[] = {kStTrace3, kStRiemX, kStRiemY, kStRiemZ, kStT1All,
+const int kCellStagesFused[] = {kStTrace3, kStSpec3, kStRiemX, kStRiemY, kStRiemZ, kStT1All,
                                 kStT2X, kStT2Y, kStT2Z, kStUpdate};
 
 std::vector<int> cell_stages(const ctuppm_ctx* c) {
@@ -2552,13 +2553,25 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
       case kStTrace3: {
         // q over the union of the three directions' stencils of cells -1..n
         // (cells -1..n extended by 2 along one direction at a time), phi
-        // written once, the face states of the three directions
+        // written once, the face states of the three directions; the hydro
+        // components only (the species are the species stage's)
         const double ext = (n0 + 6) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 6) * (n2 + 2) +
                            (n0 + 2) * (n1 + 2) * (n2 + 6) - 2 * cells1;
         // the flattening reads the pressure one cell further along each direction
         const double pext = (n0 + 8) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 8) * (n2 + 2) +
                             (n0 + 2) * (n1 + 2) * (n2 + 8) - 2 * cells1;
-        tot += (nq - 1) * W * ext + W * pext + W * cells1 + 2 * nv * W * (face(0) + face(1) + face(2));
+        tot += kNV * W * ext + W * pext + W * cells1 + 2 * kNV * W * (face(0) + face(1) + face(2));
+        break;
+      }
+      case kStSpec3: {
+        // each species over the union of its stencils, the face states of
+        // the three directions; phi, the three velocities and the sound speed
+        // of cells -1..n once
+        const double ns = P->prm.nspec;
+        if (ns == 0) break;
+        const double ext = (n0 + 6) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 6) * (n2 + 2) +
+                           (n0 + 2) * (n1 + 2) * (n2 + 6) - 2 * cells1;
+        tot += ns * W * ext + 5 * W * cells1 + 2 * ns * W * (face(0) + face(1) + face(2));
         break;
       }
       case kStRecon3: {

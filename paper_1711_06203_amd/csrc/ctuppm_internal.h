@@ -168,7 +168,7 @@ enum Stage : int {
   kStFill = 0, kStBcX, kStBcY, kStBcZ, kStC2P, kStCfl, kStC2POnly, kStDt, kStFlatten,
   kStTraceX, kStTraceY, kStTraceZ, kStRiemX, kStRiemY, kStRiemZ, kStT1X, kStT1Y, kStT1Z,
   kStT2X, kStT2Y, kStT2Z, kStUpdate, kStFlip,
-  kStReconX, kStReconY, kStReconZ, kStMolUpdate, kStTrace3, kStT1All, kStRecon3, kNumStages
+  kStReconX, kStReconY, kStReconZ, kStMolUpdate, kStTrace3, kStT1All, kStRecon3, kStSpec3, kNumStages
 };
 
 // State array a stage reads (fill, boundaries, cons->prim, MOL stages) or
@@ -183,7 +183,7 @@ __host__ __device__ inline int stage_region(int stage) {
     case kStCfl: return kValid;
     case kStFlatten: return kCells1;
     case kStT1All: return kCells1;
-    case kStTrace3: case kStRecon3: return kCells1T;
+    case kStTrace3: case kStRecon3: case kStSpec3: return kCells1T;
     case kStTraceX: case kStTraceY: case kStTraceZ: return kCells1;
     case kStReconX: case kStReconY: case kStReconZ: return kCells1;
     case kStMolUpdate: return kValid;
@@ -210,7 +210,7 @@ struct Launch {
   int last = 1;        // MOL update: the step's last stage (test hook applies)
   int rs = 0;          // Riemann solver of the flux stages: 0 HLLC, 1 two-shock
   int lim = 0;         // reconstruction variant: 0 CW84, 1 Colella & Sekora, 2 CW84 + contact steepening
-  int sp = 0;          // a problem of the launch carries passive species (merged stage 1)
+  int sp = 0;          // a problem of the launch carries passive species (merged tracing and stage 1)
 };
 
 hipError_t launch_stage(int stage, const Launch& L);

@@ -619,8 +619,9 @@ __global__ __launch_bounds__(kBlock) void k_trace(const Segs L) {
 // for a later load, so every global store of the cell is issued after its
 // last load.  Three waves per SIMD (the LDS allows four): the register
 // budget that keeps the species loop from lowering the occupancy to two.
+// spec = 0: the species are left to k_spec3.
 template <int LIM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace3(const Segs L) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace3(const Segs L, int spec) {
   // 40 KB: the up and dn states of x and y, [direction][component][thread];
   // volatile, so the compiler keeps them in LDS rather than in registers
   __shared__ double held_lds[2 * 10 * kBlock];
@@ -670,9 +671,93 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (d == 0) trace_store<0>(B, g, oh, up, dn);
         else trace_store<1>(B, g, oh, up, dn);
       }
-      if (g.ns > 0) species3<LIM, true>(B, g, P, o, oh, phi);
+      if (spec && g.ns > 0) species3<LIM, true>(B, g, P, o, oh, phi);
     });
     count(&B.P->cnt[2], floors);
+  });
+}
+
+// The passive species of the merged tracing in a kernel of their own (after
+// k_trace3, which stored the flattening coefficient): a thread takes its cell
+// column through the unit's planes, kSpecPlanes at a time, species by
+// species.  Along z it keeps the column's five stencil values in registers
+// and shifts them by one plane per step (a rolling window), so each species
+// value is loaded once per kSpecPlanes planes plus four halo planes, not
+// once for every cell whose z stencil holds it; the flattening coefficient,
+// velocities and sound speed of the planes are loaded once for all species.
+// The arithmetic is species3's, value for value.
+constexpr int kSpecPlanes = 4;
+template <int LIM>
+__global__ __launch_bounds__(kBlock) void k_spec3(const Segs L) {
+  // phi, u, v, w, c of each plane of a chunk, [plane][quantity][thread]
+  __shared__ double hyd_lds[kSpecPlanes * 5 * kBlock];
+  ldbl* hyd = (ldbl*)hyd_lds;
+  for_each_unit(L, [&](const March& M, const BoxRec& B) {
+    const Geo g(B.n, B.ns);
+    if (g.ns == 0) return;
+    CProb* P = cprob(B.P);
+    int org[3], ext[3];
+    region_of(kCells1, B.n, org, ext);
+    const int t = threadIdx.x, it = M.start + t;
+    if (it >= M.end) return;
+    const int i = it % ext[0] + org[0];
+    const int j = it / ext[0] + org[1];
+    const gdbl* __restrict__ q = g.q(B.scr);
+    const gdbl* __restrict__ phiv = g.phi(B.scr);
+    const int gx = g.gx, gpl = g.gplane;
+    for (int z0 = M.z0; z0 < M.z1; z0 += kSpecPlanes) {
+      const int nz = min(kSpecPlanes, M.z1 - z0);
+      const int o0 = g.g(i, j, z0), oh0 = g.h(i, j, z0);
+      for (int p = 0; p < nz; ++p) {
+        const int o = o0 + p * gpl;
+        hyd[(5 * p) * kBlock + t] = phiv[oh0 + p * g.hplane];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) hyd[(5 * p + 1 + d) * kBlock + t] = q[(1 + d) * g.gcomp + o];
+        hyd[(5 * p + 4) * kBlock + t] = q[5 * g.gcomp + o];
+      }
+      // a plane's loads: v[0] the value two planes up, v[1..4] the x
+      // neighbours -2, -1, +1, +2, v[5..8] the y neighbours
+      auto plane_loads = [&](const gdbl* a, int o, double v[9]) {
+        v[0] = a[o + 2 * gpl];
+        v[1] = a[o - 2]; v[2] = a[o - 1]; v[3] = a[o + 1]; v[4] = a[o + 2];
+        v[5] = a[o - 2 * gx]; v[6] = a[o - gx]; v[7] = a[o + gx]; v[8] = a[o + 2 * gx];
+      };
+#pragma unroll 1
+      for (int is = 0; is < g.ns; ++is) {
+        const gdbl* a = q + (6 + is) * g.gcomp;
+        // the z window at the first plane: values at z0-2, z0-1, z0, z0+1
+        double w0 = a[o0 - 2 * gpl], w1 = a[o0 - gpl], w2 = a[o0], w3 = a[o0 + gpl];
+        double cur[9], nxt[9];
+        plane_loads(a, o0, cur);
+#pragma unroll 1
+        for (int p = 0; p < nz; ++p) {
+          // the next plane's loads go out before this plane's stores
+          if (p + 1 < nz) plane_loads(a, o0 + (p + 1) * gpl, nxt);
+          const double phi = hyd[(5 * p) * kBlock + t], cs = hyd[(5 * p + 4) * kBlock + t];
+          const Parab pr[3] = {ppm_l<LIM>(cur[1], cur[2], w2, cur[3], cur[4], phi),
+                               ppm_l<LIM>(cur[5], cur[6], w2, cur[7], cur[8], phi),
+                               ppm_l<LIM>(w0, w1, w2, w3, cur[0], phi)};
+          const int oh = oh0 + p * g.hplane;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double un = hyd[(5 * p + 1 + d) * kBlock + t], dtdx = P->dtdx[d];
+            const double lm = un - cs, l0 = un, lp = un + cs;
+            gdbl* __restrict__ ql = g.ql(B.scr, d);
+            gdbl* __restrict__ qr = g.qr(B.scr, d);
+            __builtin_nontemporal_store(species_up(pr[d], lp, l0, fabs(lp) * dtdx, fabs(l0) * dtdx),
+                                        &ql[(kNV + is) * g.hcomp + oh + g.hstride(d)]);
+            __builtin_nontemporal_store(species_dn(pr[d], lm, l0, fabs(lm) * dtdx, fabs(l0) * dtdx),
+                                        &qr[(kNV + is) * g.hcomp + oh]);
+          }
+          // shift the window one plane up
+          w0 = w1; w1 = w2; w2 = w3; w3 = cur[0];
+          if (p + 1 < nz) {
+#pragma unroll
+            for (int m = 0; m < 9; ++m) cur[m] = nxt[m];
+          }
+        }
+      }
+    }
   });
 }
 
@@ -1470,7 +1555,7 @@ const char* stage_name(int s) {
       "fill", "bc_x", "bc_y", "bc_z", "cons2prim_cfl", "cfl", "cons2prim", "dt", "flatten",
       "trace_x", "trace_y", "trace_z", "riemann_x", "riemann_y", "riemann_z",
       "trans1_x", "trans1_y", "trans1_z", "trans2_x", "trans2_y", "trans2_z", "update", "flip",
-      "recon_x", "recon_y", "recon_z", "mol_update", "trace_xyz", "trans1_xyz", "recon_xyz"};
+      "recon_x", "recon_y", "recon_z", "mol_update", "trace_xyz", "trans1_xyz", "recon_xyz", "species_xyz"};
   return (s >= 0 && s < kNumStages) ? names[s] : "?";
 }
 
@@ -1504,7 +1589,15 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStTraceX: CTU_LIM(k_trace, 0); break;
     case kStTraceY: CTU_LIM(k_trace, 1); break;
     case kStTraceZ: CTU_LIM(k_trace, 2); break;
-    case kStTrace3: CTU_LIM3(k_trace3); break;
+    case kStTrace3: {
+      // species go to k_spec3 when the launch holds problems with them
+      const int spec = L.sp ? 0 : 1;
+      if (L.lim == 1) k_trace3<1><<<grid, block, 0, s>>>(G, spec);
+      else if (L.lim == 2) k_trace3<2><<<grid, block, 0, s>>>(G, spec);
+      else k_trace3<0><<<grid, block, 0, s>>>(G, spec);
+      break;
+    }
+    case kStSpec3: CTU_LIM3(k_spec3); break;
 #undef CTU_LIM3
     case kStT1All:
       if (L.sp) {
