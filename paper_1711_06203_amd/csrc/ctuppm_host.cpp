@@ -442,6 +442,7 @@ struct StageArgs {
   int rs = 0;
   int lim = 0;
   int sp = 0;
+  int mol = 0;
 };
 
 // Launch one stage over a segment list with optional timing.
@@ -460,6 +461,7 @@ int launch_segs(ctuppm_ctx* c, hipStream_t s, int stage, const Segs& G, bool per
   L.rs = A.rs;
   L.lim = A.lim;
   L.sp = A.sp;
+  L.mol = A.mol;
   hipEvent_t a = nullptr, b = nullptr;
   if (timed) {
     a = take_event(c);
@@ -513,11 +515,12 @@ ProbDev* level_rec(Problem* P, int level) { return level == 0 ? P->dP : P->dPf; 
 // chunks for the ghost fill and the boundaries.
 int run_range(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int b0, int b1, bool timed,
               const StageArgs& A0 = StageArgs()) {
-  if (stage == kStSpec3 && !S->species) return CTUPPM_OK;  // the merged tracing's species stage
+  if (stage == kStSpec3 && !S->species) return CTUPPM_OK;  // species stage of the merged kernels
   SegRun R{c, s, stage, S->form != CTUPPM_FORM_PER_BOX, timed, A0};
   R.A.rs = S->riemann;
   R.A.lim = S->limiter;
   R.A.sp = S->species;
+  R.A.mol = S->scheme != 0;
   const int rf = rec_form(S->form), zv = S->zvar;
   for (size_t ip = 0; ip < S->probs.size(); ++ip) {
     const int off = S->box_off[ip], nb = S->box_off[ip + 1] - off;
@@ -1227,7 +1230,7 @@ int enqueue_mol(ctuppm_ctx* c, StepSet* S, hipStream_t s, bool timed, int guard)
   const int nst = S->scheme == 1 ? 2 : 3;
   // face states: flattening and the three directions in one kernel (fused,
   // the default) or one kernel each
-  static const std::vector<int> fused = {kStRecon3, kStRiemX, kStRiemY, kStRiemZ};
+  static const std::vector<int> fused = {kStRecon3, kStSpec3, kStRiemX, kStRiemY, kStRiemZ};
   static const std::vector<int> split = {kStFlatten, kStReconX, kStReconY, kStReconZ, kStRiemX, kStRiemY, kStRiemZ};
   const std::vector<int>& cells = c->fused ? fused : split;
   int rc;
@@ -2567,21 +2570,23 @@ int ctuppm_stage_bytes(ctuppm_ctx* c, int pid, int stage, double* bytes) {
         // each species over the union of its stencils, the face states of
         // the three directions; phi, the three velocities and the sound speed
         // of cells -1..n once
+        // (the method of lines: phi only, per Runge-Kutta stage)
         const double ns = P->prm.nspec;
         if (ns == 0) break;
         const double ext = (n0 + 6) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 6) * (n2 + 2) +
                            (n0 + 2) * (n1 + 2) * (n2 + 6) - 2 * cells1;
-        tot += ns * W * ext + 5 * W * cells1 + 2 * ns * W * (face(0) + face(1) + face(2));
+        tot += nst * (ns * W * ext + (scheme ? 1 : 5) * W * cells1 + 2 * ns * W * (face(0) + face(1) + face(2)));
         break;
       }
       case kStRecon3: {
         // as the merged tracing, per Runge-Kutta stage: the union of the three
-        // directions' stencils, the flattening's pressures, phi, the face states
+        // directions' stencils, the flattening's pressures, phi, the face
+        // states (hydro components; the species are the species stage's)
         const double ext = (n0 + 6) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 6) * (n2 + 2) +
                            (n0 + 2) * (n1 + 2) * (n2 + 6) - 2 * cells1;
         const double pext = (n0 + 8) * (n1 + 2) * (n2 + 2) + (n0 + 2) * (n1 + 8) * (n2 + 2) +
                             (n0 + 2) * (n1 + 2) * (n2 + 8) - 2 * cells1;
-        tot += nst * ((nq - 1) * W * ext + W * pext + W * cells1 + 2 * nv * W * (face(0) + face(1) + face(2)));
+        tot += nst * (kNV * W * ext + W * pext + W * cells1 + 2 * kNV * W * (face(0) + face(1) + face(2)));
         break;
       }
       case kStT1All:

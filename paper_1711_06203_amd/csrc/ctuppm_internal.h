@@ -211,6 +211,7 @@ struct Launch {
   int rs = 0;          // Riemann solver of the flux stages: 0 HLLC, 1 two-shock
   int lim = 0;         // reconstruction variant: 0 CW84, 1 Colella & Sekora, 2 CW84 + contact steepening
   int sp = 0;          // a problem of the launch carries passive species (merged tracing and stage 1)
+  int mol = 0;         // method-of-lines scheme (the species stage stores edge values)
 };
 
 hipError_t launch_stage(int stage, const Launch& L);

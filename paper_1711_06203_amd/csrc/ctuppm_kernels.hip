@@ -677,8 +677,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   });
 }
 
-// The passive species of the merged tracing in a kernel of their own (after
-// k_trace3, which stored the flattening coefficient): a thread takes its cell
+// The passive species of the merged tracing (TRACE) or of the merged
+// method-of-lines face states in a kernel of their own (after k_trace3 or
+// k_recon3, which stored the flattening coefficient): a thread takes its cell
 // column through the unit's planes, kSpecPlanes at a time, species by
 // species.  Along z it keeps the column's five stencil values in registers
 // and shifts them by one plane per step (a rolling window), so each species
@@ -687,7 +688,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 // velocities and sound speed of the planes are loaded once for all species.
 // The arithmetic is species3's, value for value.
 constexpr int kSpecPlanes = 4;
-template <int LIM>
+template <int LIM, bool TRACE>
 __global__ __launch_bounds__(kBlock) void k_spec3(const Segs L) {
   // phi, u, v, w, c of each plane of a chunk, [plane][quantity][thread]
   __shared__ double hyd_lds[kSpecPlanes * 5 * kBlock];
@@ -711,9 +712,11 @@ __global__ __launch_bounds__(kBlock) void k_spec3(const Segs L) {
       for (int p = 0; p < nz; ++p) {
         const int o = o0 + p * gpl;
         hyd[(5 * p) * kBlock + t] = phiv[oh0 + p * g.hplane];
+        if (TRACE) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) hyd[(5 * p + 1 + d) * kBlock + t] = q[(1 + d) * g.gcomp + o];
-        hyd[(5 * p + 4) * kBlock + t] = q[5 * g.gcomp + o];
+          for (int d = 0; d < 3; ++d) hyd[(5 * p + 1 + d) * kBlock + t] = q[(1 + d) * g.gcomp + o];
+          hyd[(5 * p + 4) * kBlock + t] = q[5 * g.gcomp + o];
+        }
       }
       // a plane's loads: v[0] the value two planes up, v[1..4] the x
       // neighbours -2, -1, +1, +2, v[5..8] the y neighbours
@@ -733,21 +736,24 @@ __global__ __launch_bounds__(kBlock) void k_spec3(const Segs L) {
         for (int p = 0; p < nz; ++p) {
           // the next plane's loads go out before this plane's stores
           if (p + 1 < nz) plane_loads(a, o0 + (p + 1) * gpl, nxt);
-          const double phi = hyd[(5 * p) * kBlock + t], cs = hyd[(5 * p + 4) * kBlock + t];
+          const double phi = hyd[(5 * p) * kBlock + t], cs = TRACE ? hyd[(5 * p + 4) * kBlock + t] : 0.0;
           const Parab pr[3] = {ppm_l<LIM>(cur[1], cur[2], w2, cur[3], cur[4], phi),
                                ppm_l<LIM>(cur[5], cur[6], w2, cur[7], cur[8], phi),
                                ppm_l<LIM>(w0, w1, w2, w3, cur[0], phi)};
           const int oh = oh0 + p * g.hplane;
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const double un = hyd[(5 * p + 1 + d) * kBlock + t], dtdx = P->dtdx[d];
-            const double lm = un - cs, l0 = un, lp = un + cs;
+            double up = pr[d].aR, dn = pr[d].aL;  // method-of-lines edge values
+            if (TRACE) {
+              const double un = hyd[(5 * p + 1 + d) * kBlock + t], dtdx = P->dtdx[d];
+              const double lm = un - cs, l0 = un, lp = un + cs;
+              up = species_up(pr[d], lp, l0, fabs(lp) * dtdx, fabs(l0) * dtdx);
+              dn = species_dn(pr[d], lm, l0, fabs(lm) * dtdx, fabs(l0) * dtdx);
+            }
             gdbl* __restrict__ ql = g.ql(B.scr, d);
             gdbl* __restrict__ qr = g.qr(B.scr, d);
-            __builtin_nontemporal_store(species_up(pr[d], lp, l0, fabs(lp) * dtdx, fabs(l0) * dtdx),
-                                        &ql[(kNV + is) * g.hcomp + oh + g.hstride(d)]);
-            __builtin_nontemporal_store(species_dn(pr[d], lm, l0, fabs(lm) * dtdx, fabs(l0) * dtdx),
-                                        &qr[(kNV + is) * g.hcomp + oh]);
+            __builtin_nontemporal_store(up, &ql[(kNV + is) * g.hcomp + oh + g.hstride(d)]);
+            __builtin_nontemporal_store(dn, &qr[(kNV + is) * g.hcomp + oh]);
           }
           // shift the window one plane up
           w0 = w1; w1 = w2; w2 = w3; w3 = cur[0];
@@ -1187,9 +1193,10 @@ __global__ __launch_bounds__(kBlock) void k_recon(const Segs L) {
 // One thread per cell of -1..n: the flattening coefficient (also stored, for
 // stage dumps), then the method-of-lines face states along x, y and z from
 // the same primitives, read once; the states of x and y wait in LDS until the
-// loads of z have returned, as in the merged tracing.
+// loads of z have returned, as in the merged tracing.  spec = 0: the species
+// are left to k_spec3.
 template <int LIM>
-__global__ __launch_bounds__(kBlock) void k_recon3(const Segs L) {
+__global__ __launch_bounds__(kBlock) void k_recon3(const Segs L, int spec) {
   __shared__ double held_lds[2 * 10 * kBlock];
   ldbl* held = (ldbl*)held_lds;
   for_each_unit(L, [&](const March& M, const BoxRec& B) {
@@ -1223,7 +1230,7 @@ __global__ __launch_bounds__(kBlock) void k_recon3(const Segs L) {
         if (d == 0) trace_store<0>(B, g, oh, up, dn);
         else trace_store<1>(B, g, oh, up, dn);
       }
-      if (g.ns > 0) species3<LIM, false>(B, g, P, o, oh, phi);
+      if (spec && g.ns > 0) species3<LIM, false>(B, g, P, o, oh, phi);
     });
     count(&B.P->cnt[2], floors);
   });
@@ -1584,7 +1591,13 @@ hipError_t launch_stage(int stage, const Launch& L) {
   (L.lim == 1   ? K<1><<<grid, block, 0, s>>>(G)                            \
    : L.lim == 2 ? K<2><<<grid, block, 0, s>>>(G)                            \
                 : K<0><<<grid, block, 0, s>>>(G))
-    case kStRecon3: CTU_LIM3(k_recon3); break;
+    case kStRecon3: {
+      const int spec = L.sp ? 0 : 1;
+      if (L.lim == 1) k_recon3<1><<<grid, block, 0, s>>>(G, spec);
+      else if (L.lim == 2) k_recon3<2><<<grid, block, 0, s>>>(G, spec);
+      else k_recon3<0><<<grid, block, 0, s>>>(G, spec);
+      break;
+    }
     case kStFlatten: k_flatten<<<grid, block, 0, s>>>(G); break;
     case kStTraceX: CTU_LIM(k_trace, 0); break;
     case kStTraceY: CTU_LIM(k_trace, 1); break;
@@ -1597,7 +1610,17 @@ hipError_t launch_stage(int stage, const Launch& L) {
       else k_trace3<0><<<grid, block, 0, s>>>(G, spec);
       break;
     }
-    case kStSpec3: CTU_LIM3(k_spec3); break;
+    case kStSpec3:
+      if (L.mol) {
+        if (L.lim == 1) k_spec3<1, false><<<grid, block, 0, s>>>(G);
+        else if (L.lim == 2) k_spec3<2, false><<<grid, block, 0, s>>>(G);
+        else k_spec3<0, false><<<grid, block, 0, s>>>(G);
+      } else {
+        if (L.lim == 1) k_spec3<1, true><<<grid, block, 0, s>>>(G);
+        else if (L.lim == 2) k_spec3<2, true><<<grid, block, 0, s>>>(G);
+        else k_spec3<0, true><<<grid, block, 0, s>>>(G);
+      }
+      break;
 #undef CTU_LIM3
     case kStT1All:
       if (L.sp) {
