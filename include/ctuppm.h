@@ -411,9 +411,9 @@ int ctuppm_set_wave_boxes(ctuppm_ctx* ctx, int boxes);
 
 /* Kernels of the cell stages: on (1, the default), the flattening and the
  * tracing (CTU) or the edge-value face states (method of lines) of the three
- * directions run in one kernel that reads each cell's primitives once (for
- * CTU the passive species of the three directions follow in a kernel of
- * their own, stage "species_xyz", launched only for problems with species),
+ * directions run in one kernel that reads each cell's primitives once (the
+ * passive species of the three directions follow in a kernel of their own,
+ * stage "species_xyz", launched only for problems with species),
  * and the first transverse stage of the three directions (CTU) in one kernel
  * that reads each normal flux array once; off (0), a flattening kernel and
  * one kernel per direction.  Results are the same bits either way (each face
