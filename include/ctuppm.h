@@ -415,9 +415,11 @@ int ctuppm_set_wave_boxes(ctuppm_ctx* ctx, int boxes);
  * passive species of the three directions follow in a kernel of their own,
  * stage "species_xyz", launched only for problems with species),
  * and the first transverse stage of the three directions (CTU) in one kernel
- * that reads each normal flux array once; off (0), a flattening kernel and
- * one kernel per direction.  Results are the same bits either way (each face
- * takes the same arithmetic); captured graphs are dropped. */
+ * that reads each normal flux array once; 2, as 1 with the species traced
+ * inside the merged kernels (no species stage); off (0), a flattening kernel
+ * and one kernel per direction.  Results are the same bits in every mode
+ * (each face takes the same arithmetic); captured graphs are dropped.
+ * CTUPPM_EINVAL for another value. */
 int ctuppm_set_fused(ctuppm_ctx* ctx, int on);
 /* Measurement: the HBM bandwidth plain streaming reaches on this GPU, the
  * ceiling the stage kernels are compared with.  kind 0 copies `bytes` from src

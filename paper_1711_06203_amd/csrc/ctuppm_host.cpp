@@ -443,6 +443,7 @@ struct StageArgs {
   int lim = 0;
   int sp = 0;
   int mol = 0;
+  int spstage = 0;
 };
 
 // Launch one stage over a segment list with optional timing.
@@ -462,6 +463,7 @@ int launch_segs(ctuppm_ctx* c, hipStream_t s, int stage, const Segs& G, bool per
   L.lim = A.lim;
   L.sp = A.sp;
   L.mol = A.mol;
+  L.spstage = A.spstage;
   hipEvent_t a = nullptr, b = nullptr;
   if (timed) {
     a = take_event(c);
@@ -515,12 +517,16 @@ ProbDev* level_rec(Problem* P, int level) { return level == 0 ? P->dP : P->dPf; 
 // chunks for the ghost fill and the boundaries.
 int run_range(ctuppm_ctx* c, StepSet* S, hipStream_t s, int stage, int b0, int b1, bool timed,
               const StageArgs& A0 = StageArgs()) {
-  if (stage == kStSpec3 && !S->species) return CTUPPM_OK;  // species stage of the merged kernels
+  // the species stage of the merged kernels: for sets with species, unless
+  // the merged kernels trace them (fused mode 2)
+  const int spstage = S->species && c->fused == 1;
+  if (stage == kStSpec3 && !spstage) return CTUPPM_OK;
   SegRun R{c, s, stage, S->form != CTUPPM_FORM_PER_BOX, timed, A0};
   R.A.rs = S->riemann;
   R.A.lim = S->limiter;
   R.A.sp = S->species;
   R.A.mol = S->scheme != 0;
+  R.A.spstage = spstage;
   const int rf = rec_form(S->form), zv = S->zvar;
   for (size_t ip = 0; ip < S->probs.size(); ++ip) {
     const int off = S->box_off[ip], nb = S->box_off[ip + 1] - off;
@@ -2429,7 +2435,8 @@ int ctuppm_set_concurrency(ctuppm_ctx* c, int on) {
 
 int ctuppm_set_fused(ctuppm_ctx* c, int on) {
   if (!c) return CTUPPM_EINVAL;
-  c->fused = on ? 1 : 0;
+  if (on < 0 || on > 2) return fail(c, CTUPPM_EINVAL, "fused mode must be 0, 1 or 2");
+  c->fused = on;
   for (auto& kv : c->probs) drop_sets(c, kv.first);  // captured graphs hold the old kernels
   return CTUPPM_OK;
 }

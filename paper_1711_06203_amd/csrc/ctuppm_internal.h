@@ -212,6 +212,7 @@ struct Launch {
   int lim = 0;         // reconstruction variant: 0 CW84, 1 Colella & Sekora, 2 CW84 + contact steepening
   int sp = 0;          // a problem of the launch carries passive species (merged tracing and stage 1)
   int mol = 0;         // method-of-lines scheme (the species stage stores edge values)
+  int spstage = 0;     // the species stage traces the species (the merged kernels leave them)
 };
 
 hipError_t launch_stage(int stage, const Launch& L);

@@ -1592,7 +1592,7 @@ hipError_t launch_stage(int stage, const Launch& L) {
    : L.lim == 2 ? K<2><<<grid, block, 0, s>>>(G)                            \
                 : K<0><<<grid, block, 0, s>>>(G))
     case kStRecon3: {
-      const int spec = L.sp ? 0 : 1;
+      const int spec = L.spstage ? 0 : 1;
       if (L.lim == 1) k_recon3<1><<<grid, block, 0, s>>>(G, spec);
       else if (L.lim == 2) k_recon3<2><<<grid, block, 0, s>>>(G, spec);
       else k_recon3<0><<<grid, block, 0, s>>>(G, spec);
@@ -1603,8 +1603,8 @@ hipError_t launch_stage(int stage, const Launch& L) {
     case kStTraceY: CTU_LIM(k_trace, 1); break;
     case kStTraceZ: CTU_LIM(k_trace, 2); break;
     case kStTrace3: {
-      // species go to k_spec3 when the launch holds problems with them
-      const int spec = L.sp ? 0 : 1;
+      // species go to k_spec3 when the species stage runs
+      const int spec = L.spstage ? 0 : 1;
       if (L.lim == 1) k_trace3<1><<<grid, block, 0, s>>>(G, spec);
       else if (L.lim == 2) k_trace3<2><<<grid, block, 0, s>>>(G, spec);
       else k_trace3<0><<<grid, block, 0, s>>>(G, spec);

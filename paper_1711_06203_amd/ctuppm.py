@@ -210,10 +210,15 @@ class Context:
         del a, b
         return v.value
 
-    def set_fused(self, on: bool):
-        """CTU cell stages: tracing and transverse stage 1 of the three
-        directions in one kernel each (default) or one kernel per direction."""
-        self.call("ctuppm_set_fused", int(bool(on)))
+    def set_fused(self, on):
+        """Cell stages: tracing (or face states) and transverse stage 1 of the
+        three directions in one kernel each, the species in a stage of their
+        own (True or 1, the default); 2: the same with the species inside the
+        merged kernels; False or 0: one kernel per direction."""
+        mode = int(on)
+        if mode not in (0, 1, 2):
+            raise ValueError("fused mode must be 0, 1 or 2")
+        self.call("ctuppm_set_fused", mode)
 
     def set_concurrency(self, on: bool):
         """Graph form: run the three directions of each phase concurrently (default off)."""

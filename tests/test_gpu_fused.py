@@ -1,8 +1,9 @@
 """The merged kernels (CTU: flattening and tracing of x, y, z in one kernel,
 the first transverse stage of x, y, z in one kernel; method of lines:
-flattening and the face states of x, y, z in one kernel) against the
+flattening and the face states of x, y, z in one kernel; the species in a
+stage of their own, or inside the merged kernels) against the
 one-kernel-per-direction form: bitwise the same states for every scheme
-variant, boundary kind, box layout and the two-level step, and both equal
+variant, boundary kind, box layout and the two-level step, and all equal
 the oracle."""
 import numpy as np
 import pytest
@@ -55,12 +56,12 @@ def _run(ctx, prob, steps, form):
 def test_fused_equals_split_and_oracle(ctx, name):
     prob = CASES[name]()
     res = {}
-    for fused in (True, False):
+    for fused in (1, 2, 0):
         ctx.set_fused(fused)
         for form in (["batched", "graph"] if prob.fine_boxes else ["per_box", "batched", "graph"]):
             res[(fused, form)] = _run(ctx, prob, 3, form)
     ctx.set_fused(True)
-    ref = res[(True, "batched")]
+    ref = res[(1, "batched")]
     for key, got in res.items():
         assert all(np.array_equal(a, b) for a, b in zip(got, ref)), key
     if prob.fine_boxes:
@@ -69,3 +70,13 @@ def test_fused_equals_split_and_oracle(ctx, name):
     else:
         U, _, _ = oracle.run_problem(prob, 3)
         assert np.array_equal(ref[0], U)
+
+
+def test_fused_mode_refused(ctx):
+    from paper_1711_06203_amd import ctuppm
+    for bad in (3, -1):
+        with pytest.raises((ctuppm.CtuError, ValueError)):
+            ctx.set_fused(bad)
+    with pytest.raises(ctuppm.CtuError):
+        ctx.call("ctuppm_set_fused", 3)
+    ctx.set_fused(True)
